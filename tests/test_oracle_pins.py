@@ -1,0 +1,535 @@
+"""Pins for the CPU oracle: each test checks it against something other than
+itself -- closed forms, published CRC check values, a library CRC, brute-force
+maximum likelihood, a per-bit successive-cancellation recursion written from
+the f/g equations, textbook decoders of repetition / parity / rate-1 codes,
+and invariances of the min-sum path metric.
+
+Equation / section references are to Leonardon et al., arXiv:1710.08314.
+"""
+import itertools
+import math
+import zlib
+
+import numpy as np
+import pytest
+
+import oracle as O
+
+
+# ------------------------------------------------------------------ helpers
+def kron_F(n):
+    """F^{(x)n} from the block definition of the footnote of Sec. II-A:
+    [[F', 0], [F', F']] == kron([[1, 0], [1, 1]], F')."""
+    F = np.array([[1, 0], [1, 1]], dtype=np.int64)
+    M = np.array([[1]], dtype=np.int64)
+    for _ in range(n):
+        M = np.kron(F, M)
+    return M
+
+
+def all_codewords(frozen):
+    N = len(frozen)
+    n = int(round(math.log2(N)))
+    G = kron_F(n)
+    A = np.where(frozen == 0)[0]
+    cws = []
+    for bits in itertools.product([0, 1], repeat=len(A)):
+        u = np.zeros(N, dtype=np.int64)
+        u[A] = bits
+        cws.append((u @ G) % 2)
+    return np.array(cws, dtype=np.uint8)
+
+
+def discrepancy(x, llr):
+    """Correlation discrepancy sum_j |l_j| [x_j != HD(l_j)], HD(l) = [l < 0]."""
+    llr = np.asarray(llr, dtype=np.float64)
+    return float(np.sum(np.abs(llr) * (x != (llr < 0))))
+
+
+def fvec(a, b):
+    return np.sign(a) * np.sign(b) * np.minimum(np.abs(a), np.abs(b))
+
+
+def gvec(a, b, s):
+    return (1 - 2 * s) * a + b
+
+
+def sc_per_bit(llr, frozen):
+    """Successive cancellation computed bit by bit (Sec. II-B1): the LLR of
+    u_i is obtained by recursing on halves -- f for the first half, g with the
+    re-encoded decisions of the first half for the second -- recomputed from
+    scratch for every bit, with no shared tree buffers or partial sums."""
+    N = len(frozen)
+
+    def bit_llr(i, lam, uprev):
+        M = len(lam)
+        if M == 1:
+            return lam[0]
+        h = M // 2
+        a, b = lam[:h], lam[h:]
+        if i < h:
+            return bit_llr(i, fvec(a, b), uprev[:i])
+        xl = (np.array(uprev[:h], dtype=np.int64) @ kron_F(int(math.log2(h)))) % 2
+        return bit_llr(i - h, gvec(a, b, xl), uprev[h:i])
+
+    u = []
+    lam = np.asarray(llr, dtype=np.float64)
+    for i in range(N):
+        l = bit_llr(i, lam, u)
+        u.append(0 if frozen[i] else int(l < 0))
+    return (np.array(u, dtype=np.int64) @ kron_F(int(math.log2(N)))) % 2
+
+
+def ascii_bits(s):
+    return np.array([(byte >> (7 - k)) & 1 for byte in s.encode() for k in range(8)],
+                    dtype=np.uint8)
+
+
+def rand_frozen(rng, N, K):
+    fz = np.ones(N, dtype=np.uint8)
+    fz[rng.choice(N, K, replace=False)] = 0
+    return fz
+
+
+# ------------------------------------------------------- P-1: f and g
+@pytest.mark.parametrize("quant", [O.F32, O.F64, O.I16, O.I8])
+def test_f_g_truth_tables(quant):
+    # Sec. II-B1: f = sign(a b) min(|a|, |b|), g = (1 - 2 s) a + b
+    for a, b in [(3, -5), (-2, -7), (6, 4), (-9, 1), (0, -4), (5, 0), (-1, -1)]:
+        f = O.fg(quant, "f", a, b)
+        assert abs(f) == min(abs(a), abs(b))
+        if a != 0 and b != 0:
+            assert (f < 0) == ((a < 0) != (b < 0))
+        for s in (0, 1):
+            assert O.fg(quant, "g", a, b, s) == (1 - 2 * s) * a + b
+    # float halves are exact
+    if quant in (O.F32, O.F64):
+        assert O.fg(quant, "f", -0.5, 0.25) == -0.25
+        assert O.fg(quant, "g", 0.75, 0.5, 1) == -0.25
+
+
+@pytest.mark.parametrize("quant,Q", [(O.I8, 127), (O.I16, 32767)])
+def test_int_saturation(quant, Q):
+    # Sec. III-B3: fixed-point values saturate after every operation
+    assert O.fg(quant, "g", Q - 10, Q - 20, 0) == Q
+    assert O.fg(quant, "g", -(Q - 10), -(Q - 20), 0) == -Q
+    assert O.fg(quant, "g", Q, -Q, 1) == -Q
+    assert O.fg(quant, "g", -Q, Q, 1) == Q
+    assert O.fg(quant, "f", -Q, Q) == -Q
+
+
+# --------------------------------------------------- P-2: encoder
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 8])
+def test_transform_matches_kron(n):
+    rng = np.random.default_rng(n)
+    N = 1 << n
+    G = kron_F(n)
+    for _ in range(5):
+        v = rng.integers(0, 2, N, dtype=np.uint8)
+        assert np.array_equal(O.transform(v), (v.astype(np.int64) @ G) % 2)
+        # F^{(x)n} is an involution over GF(2): encoding twice is the identity
+        assert np.array_equal(O.transform(O.transform(v)), v)
+
+
+@pytest.mark.parametrize("N,K,c,design", [(256, 128, 8, 2.0), (2048, 1723, 32, 4.5),
+                                          (1024, 512, 24, 2.5), (64, 20, 0, 1.0)])
+def test_systematic_encoding(N, K, c, design):
+    # Sec. II-A: x_A = b for the two-pass encoder
+    fz = O.construct(N, K, 0, c, design)
+    A = np.where(fz == 0)[0]
+    rng = np.random.default_rng(N + K)
+    G = kron_F(int(math.log2(N))) if N <= 256 else None
+    for _ in range(4):
+        b = rng.integers(0, 2, K, dtype=np.uint8)
+        x = O.encode(fz, b)
+        assert np.array_equal(x[A], b)
+        # x is a codeword: its u-vector (x F, F self-inverse) is zero on A^c
+        u = O.transform(x)
+        assert not u[fz == 1].any()
+        if G is not None:
+            assert np.array_equal(O.transform(u), x)
+
+
+def test_shortened_positions_are_zero():
+    # shortening freezes u-indices [N-S, N); then x_j = 0 there since
+    # x_j = XOR of u_i over i whose bits contain j's bits, all i >= j
+    rng = np.random.default_rng(7)
+    N, S = 512, 77
+    K = 200
+    fz = O.construct(N, K, S, 11, 2.5)
+    assert fz[N - S:].all()
+    for _ in range(5):
+        x = O.encode(fz, rng.integers(0, 2, K, dtype=np.uint8))
+        assert not x[N - S:].any()
+
+
+# ------------------------------------------------ P-3: Bhattacharyya
+def test_bec_half_closed_form():
+    # BEC(1/2): the recursion is exact; the 8 values follow by hand
+    z = np.exp(O.logz_from_z0(3, math.log(0.5)))
+    expect = [0.99609375, 0.87890625, 0.80859375, 0.31640625, 0.68359375, 0.19140625,
+              0.12109375, 0.00390625]
+    np.testing.assert_allclose(z, expect, rtol=1e-14, atol=0)
+    fz = O.construct_lz0(8, 4, 0, math.log(0.5))
+    assert sorted(np.where(fz == 0)[0].tolist()) == [3, 5, 6, 7]
+
+
+def test_two_channel_closed_form():
+    for z0 in (0.9, 0.3, 1e-3, 1e-12):
+        z = np.exp(O.logz_from_z0(1, math.log(z0)))
+        np.testing.assert_allclose(z, [2 * z0 - z0 * z0, z0 * z0], rtol=1e-12)
+
+
+def test_logz_deep_tree_no_underflow():
+    # N = 2048 at a high design SNR: squaring 11 times would underflow a
+    # linear-domain Z; the log domain keeps every channel ordered
+    lz = O.logz_from_z0(11, -2.33)
+    assert np.isfinite(lz).all()
+    assert lz[-1] == pytest.approx(-2.33 * 2048)
+    assert len(np.unique(lz)) > 1900
+
+
+@pytest.mark.parametrize("N,K,c,design", [(256, 128, 8, 2.0), (2048, 1723, 32, 4.5),
+                                          (1024, 512, 24, 2.5), (128, 40, 11, 1.5)])
+def test_information_set_is_up_set(N, K, c, design):
+    # the reliability order makes A closed under taking bitwise supersets
+    fz = O.construct(N, K, 0, c, design)
+    A = set(np.where(fz == 0)[0].tolist())
+    for i in A:
+        for b in range(int(math.log2(N))):
+            assert (i | (1 << b)) in A
+
+
+def test_design_rate_uses_data_bits():
+    # R = (K - c) / (N - S): construction at the same Z0 with a manual log Z0
+    N, K, c = 256, 128, 8
+    lz0 = -(120 / 256) * 10 ** 0.2
+    assert np.array_equal(O.construct(N, K, 0, c, 2.0), O.construct_lz0(N, K, 0, lz0))
+
+
+# ----------------------------------------------------------- P-4: CRC
+@pytest.mark.parametrize("c,poly,check", [
+    (8, 0x07, 0xF4),            # CRC-8/SMBUS, catalogue check value
+    (16, 0x1021, 0x31C3),       # CRC-16/XMODEM
+    (24, 0x1864CFB, 0xCDE703),  # CRC-24/LTE-A (x^24 term given explicitly)
+    (32, 0x04C11DB7, 0x765E7680 ^ 0xFFFFFFFF),  # CRC-32/CKSUM without its final xor
+])
+def test_crc_check_values(c, poly, check):
+    assert O.crc(ascii_bits("123456789"), c, poly) == check
+
+
+def _reflect(v, w):
+    return int(format(v, f"0{w}b")[::-1], 2)
+
+
+def test_crc32_against_zlib():
+    # zlib's CRC-32 is the reflected form with init and final xor 0xFFFFFFFF.
+    # Unreflected init-0 division of the message with its first 32 bits
+    # inverted, then xor 0xFFFFFFFF, equals it after bit reflection.
+    rng = np.random.default_rng(3)
+    for nbytes in (4, 5, 16, 211):
+        msg = rng.integers(0, 256, nbytes, dtype=np.uint8)
+        rmsg = bytes(_reflect(int(b), 8) for b in msg)
+        want = _reflect(zlib.crc32(rmsg), 32)
+        m2 = msg.copy()
+        m2[:4] ^= 0xFF
+        bits = np.unpackbits(m2)
+        assert O.crc(bits, 32, 0x04C11DB7) ^ 0xFFFFFFFF == want
+
+
+@pytest.mark.parametrize("c,poly", [(8, 0x07), (11, 0x621), (24, 0x1864CFB), (32, 0x04C11DB7)])
+def test_crc_properties(c, poly):
+    rng = np.random.default_rng(c)
+    for k in (1, 13, 120, 1691):
+        d = rng.integers(0, 2, k, dtype=np.uint8)
+        b = O.attach_crc(d, c, poly)
+        assert O.crc(b, c, poly) == 0  # a codeword of the CRC leaves no remainder
+        e = rng.integers(0, 2, k, dtype=np.uint8)
+        assert O.crc(d ^ e, c, poly) == O.crc(d, c, poly) ^ O.crc(e, c, poly)  # linear
+        for j in rng.choice(len(b), 5):
+            b2 = b.copy()
+            b2[j] ^= 1
+            assert O.crc(b2, c, poly) != 0  # every single error is detected
+
+
+# ---------------------------------------------------- quantisation
+def test_quantizer_rounding_and_clamp():
+    l = np.array([0.625, 0.875, -0.625, 0.1, 40.0, -40.0, 31.75, -31.8])
+    q8 = O.quantize(l, O.I8, 2)
+    assert q8.tolist() == [2, 4, -2, 0, 127, -127, 127, -127]
+    q16 = O.quantize(np.array([0.0625, 0.1875, 5000.0]), O.I16, 3)
+    assert q16.tolist() == [0, 2, 32767]
+
+
+# -------------------------------------------------- P-6: L = 1 (SC)
+@pytest.mark.parametrize("N,K", [(8, 4), (16, 9), (32, 16), (64, 30)])
+def test_unpruned_sc_matches_per_bit_recursion(N, K):
+    rng = np.random.default_rng(N)
+    for t in range(25):
+        fz = rand_frozen(rng, N, K)
+        llr = rng.normal(0.8, 1.6, N)
+        code = O.Code(N, K, fz, quant=O.F64, algo=O.SC, node_enable=0)
+        r = O.decode(code, llr)
+        assert np.array_equal(r.xhat[0], sc_per_bit(llr, fz))
+        # the same with integer LLRs in float32 (exact arithmetic)
+        li = np.round(llr * 4).astype(np.float32)
+        code32 = O.Code(N, K, fz, quant=O.F32, algo=O.SC, node_enable=0)
+        assert np.array_equal(O.decode(code32, li).xhat[0], sc_per_bit(li, fz))
+
+
+@pytest.mark.parametrize("quant", [O.F32, O.I16, O.I8])
+def test_sc_equals_list_of_one(quant):
+    rng = np.random.default_rng(11)
+    fz = O.construct(256, 128, 0, 8, 2.0)
+    llr = rng.normal(1.0, 1.5, (40, 256)) * 4
+    llr = np.clip(np.round(llr), -127, 127).astype(O.DTYPES[quant])
+    a = O.decode(O.Code(256, 128, fz, 8, 0x07, quant=quant, algo=O.SC), llr)
+    b = O.decode(O.Code(256, 128, fz, 8, 0x07, quant=quant, algo=O.CA_SCL, L=1), llr)
+    assert np.array_equal(a.xhat, b.xhat) and np.array_equal(a.pm, b.pm)
+
+
+def test_rate_one_code_is_hard_decision():
+    rng = np.random.default_rng(5)
+    N = 64
+    fz = np.zeros(N, np.uint8)
+    for ne in (0, O.NODE_ALL):
+        for _ in range(10):
+            llr = rng.normal(0, 2, N)
+            llr[llr == 0] = 1.0
+            r = O.decode(O.Code(N, N, fz, quant=O.F64, algo=O.SC, node_enable=ne), llr)
+            assert np.array_equal(r.xhat[0], (llr < 0).astype(np.uint8))
+
+
+def test_repetition_code_is_sign_of_sum():
+    rng = np.random.default_rng(6)
+    N = 32
+    fz = np.ones(N, np.uint8)
+    fz[-1] = 0
+    for ne in (0, O.NODE_REP):
+        for _ in range(20):
+            llr = np.round(rng.normal(0.2, 2, N) * 8) / 8
+            if llr.sum() == 0:
+                llr[0] += 0.5
+            r = O.decode(O.Code(N, 1, fz, quant=O.F64, algo=O.SC, node_enable=ne), llr)
+            assert (r.xhat[0] == int(llr.sum() < 0)).all()
+
+
+def test_spc_code_is_wagner():
+    # (N, N-1) single parity check: hard decision, and if its parity is odd
+    # flip the least reliable position (Wagner decoding, which is ML)
+    rng = np.random.default_rng(8)
+    N = 16
+    fz = np.zeros(N, np.uint8)
+    fz[0] = 1
+    for _ in range(30):
+        llr = rng.normal(0.5, 2, N)
+        x = (llr < 0).astype(np.uint8)
+        if x.sum() % 2:
+            x[np.argmin(np.abs(llr))] ^= 1
+        code = O.Code(N, N - 1, fz, quant=O.F64, algo=O.SC, node_enable=O.NODE_SPC, spc_max=0)
+        assert np.array_equal(O.decode(code, llr).xhat[0], x)
+
+
+# ------------------------------------------- P-5: list decoding is ML
+@pytest.mark.parametrize("N,K", [(8, 3), (8, 4), (16, 5), (16, 8)])
+@pytest.mark.parametrize("node_enable", [0, O.NODE_ALL])
+def test_large_list_is_maximum_likelihood(N, K, node_enable):
+    """With L >= 2^K and only exhaustive dedicated nodes (R0, REP, SPC of size
+    <= 4, R1 of size <= 2) no candidate is ever dropped, so the best metric is
+    the minimum correlation discrepancy over the code, and each complete
+    path's min-sum metric equals the discrepancy of its codeword."""
+    rng = np.random.default_rng(N * 31 + K)
+    for t in range(12):
+        fz = rand_frozen(rng, N, K)
+        cws = all_codewords(fz)
+        llr = np.round(rng.normal(0.6, 2.0, N) * 4).astype(np.float32)  # exact sums
+        D = np.array([discrepancy(x, llr) for x in cws])
+        code = O.Code(N, K, fz, quant=O.F32, algo=O.CA_SCL, L=1 << K, node_enable=node_enable,
+                      spc_max=4, r1_max=2)
+        r = O.decode(code, llr)
+        assert discrepancy(r.xhat[0], llr) == D.min()
+        assert r.pm[0] == D.min()
+        np.testing.assert_array_equal(np.sort(r.pm_list[0]), np.sort(D))
+        # int16 on the same integer values: the same decision and the same
+        # metric differences (normalisation subtracts the minimum each step)
+        code16 = O.Code(N, K, fz, quant=O.I16, algo=O.CA_SCL, L=1 << K,
+                        node_enable=node_enable, spc_max=4, r1_max=2)
+        r16 = O.decode(code16, llr.astype(np.int16))
+        assert discrepancy(r16.xhat[0], llr) == D.min()
+        np.testing.assert_array_equal(r16.pm_list[0], np.sort(D) - D.min())
+
+
+@pytest.mark.parametrize("N,K,c,poly", [(16, 8, 3, 0x3), (16, 7, 4, 0x3)])
+def test_crc_restricted_maximum_likelihood(N, K, c, poly):
+    rng = np.random.default_rng(K)
+    for t in range(12):
+        fz = rand_frozen(rng, N, K)
+        A = np.where(fz == 0)[0]
+        cws = all_codewords(fz)
+        ok = np.array([O.crc(x[A][:K - c], c, poly) ==
+                       int("".join(map(str, x[A][K - c:])), 2) for x in cws])
+        llr = np.round(rng.normal(0.3, 2.0, N) * 4).astype(np.float32)
+        D = np.array([discrepancy(x, llr) for x in cws])
+        code = O.Code(N, K, fz, c, poly, quant=O.F32, algo=O.CA_SCL, L=1 << K, spc_max=4,
+                      r1_max=2)
+        r = O.decode(code, llr)
+        if ok.any():
+            assert r.crc_ok[0] == 1
+            assert discrepancy(r.xhat[0], llr) == D[ok].min()
+        else:
+            assert r.crc_ok[0] == 0 and discrepancy(r.xhat[0], llr) == D.min()
+
+
+def test_metric_is_discrepancy_any_list():
+    """The P-5 identity holds for every complete path, at any list size and
+    with lossy nodes: the output metric equals the discrepancy of x_hat."""
+    rng = np.random.default_rng(12)
+    fz = O.construct(256, 128, 0, 8, 2.0)
+    for L in (1, 2, 8):
+        code = O.Code(256, 128, fz, 8, 0x07, quant=O.F64, algo=O.CA_SCL, L=L)
+        llr = rng.normal(1.0, 1.3, (20, 256)) * 3
+        r = O.decode(code, llr)
+        for f in range(20):
+            assert r.pm[f] == pytest.approx(discrepancy(r.xhat[f], llr[f]), rel=1e-12, abs=1e-9)
+
+
+def test_r1_chase_and_spc_candidates():
+    """Single dedicated node codes: the list holds exactly the node's
+    candidates.  R1 (Chase-2): flips of the two least reliable positions;
+    SPC: even-parity flips among the four least reliable positions."""
+    rng = np.random.default_rng(13)
+    N = 8
+    for _ in range(10):
+        llr = rng.normal(0.4, 2.0, N)
+        m = np.sort(np.abs(llr))
+        r1 = O.decode(O.Code(N, N, np.zeros(N, np.uint8), quant=O.F64, L=8), llr)
+        np.testing.assert_allclose(r1.pm_list[0][:4], sorted([0, m[0], m[1], m[0] + m[1]]))
+        fz = np.zeros(N, np.uint8)
+        fz[0] = 1
+        sp = O.decode(O.Code(N, N - 1, fz, quant=O.F64, L=8, spc_max=0), llr)
+        par = int((llr < 0).sum() % 2)
+        pens = sorted(sum(m[j] for j in range(4) if (mask >> j) & 1) for mask in range(16)
+                      if bin(mask).count("1") % 2 == par)
+        np.testing.assert_allclose(sp.pm_list[0], pens, rtol=1e-12)
+
+
+# ------------------------------------------------------- P-7 noiseless
+@pytest.mark.parametrize("quant", [O.F32, O.I16, O.I8])
+@pytest.mark.parametrize("algo,L,Lmax", [(O.SC, 1, 1), (O.CA_SCL, 4, 4), (O.CA_SCL, 32, 32),
+                                         (O.FA_SCL, 1, 8), (O.PA_SCL, 1, 8)])
+def test_noiseless_recovers_information(quant, algo, L, Lmax):
+    rng = np.random.default_rng(quant * 10 + L)
+    for (N, K, c, poly, S) in [(256, 128, 8, 0x07, 0), (128, 60, 11, 0x621, 20)]:
+        fz = O.construct(N, K, S, c, 2.0)
+        code = O.Code(N, K, fz, c, poly, S=S, quant=quant, algo=algo, L=L, L_max=Lmax,
+                      rep_max=8 if quant == O.I8 else 0)
+        data = rng.integers(0, 2, (6, K - c), dtype=np.uint8)
+        x = np.array([O.encode(fz, O.attach_crc(d, c, poly)) for d in data])[:, :N - S]
+        llr = O.make_llr(code, x, np.zeros(x.shape), 0.7)
+        r = O.decode(code, llr)
+        assert np.array_equal(r.info, data)
+        assert (r.crc_ok == 1).all() and (r.L_used == (1 if algo != O.CA_SCL else L)).all()
+        assert (r.pm == 0).all()
+
+
+# ----------------------------------------------------- P-8 invariances
+def test_scaling_invariance():
+    rng = np.random.default_rng(21)
+    fz = O.construct(256, 128, 0, 8, 2.0)
+    code = O.Code(256, 128, fz, 8, 0x07, quant=O.F32, algo=O.CA_SCL, L=8)
+    llr = (rng.normal(1, 1.4, (30, 256)) * 2).astype(np.float32)
+    a = O.decode(code, llr)
+    b = O.decode(code, (llr * 4).astype(np.float32))
+    assert np.array_equal(a.xhat, b.xhat)
+    np.testing.assert_array_equal(b.pm_list, a.pm_list * 4)
+
+
+def test_int_mode_equals_float_on_small_integers():
+    rng = np.random.default_rng(22)
+    fz = O.construct(128, 64, 0, 8, 2.0)
+    llr = np.clip(np.round(rng.normal(1, 2, (30, 128))), -7, 7)
+    for L in (1, 4, 16):
+        fa = O.decode(O.Code(128, 64, fz, 8, 0x07, quant=O.F32, L=L), llr.astype(np.float32))
+        ia = O.decode(O.Code(128, 64, fz, 8, 0x07, quant=O.I16, L=L), llr.astype(np.int16))
+        assert np.array_equal(fa.xhat, ia.xhat)
+        np.testing.assert_array_equal(ia.pm_list, fa.pm_list - fa.pm_list[:, :1])
+
+
+def test_r0_rep_pruning_is_lossless_on_exact_inputs():
+    # Sec. II-C: pruning does not change decisions when it is not too deep;
+    # R0 and REP nodes are exact reformulations of their subtrees
+    rng = np.random.default_rng(23)
+    fz = O.construct(256, 128, 0, 8, 2.0)
+    llr = np.round(rng.normal(1, 1.5, (30, 256)) * 8).astype(np.float32)
+    for L in (1, 4, 8):
+        a = O.decode(O.Code(256, 128, fz, 8, 0x07, quant=O.F32, L=L, node_enable=0), llr)
+        b = O.decode(O.Code(256, 128, fz, 8, 0x07, quant=O.F32, L=L,
+                            node_enable=O.NODE_R0 | O.NODE_REP), llr)
+        assert np.array_equal(a.xhat, b.xhat)
+        np.testing.assert_array_equal(a.pm_list, b.pm_list)
+
+
+def test_fully_adaptive_stage_consistency():
+    # Sec. II-B5: a frame output at list size l is what CA-SCL(l) outputs,
+    # and every smaller stage failed its CRC
+    rng = np.random.default_rng(24)
+    N, K, c, poly = 256, 128, 8, 0x07
+    fz = O.construct(N, K, 0, c, 2.0)
+    data = rng.integers(0, 2, (150, K - c), dtype=np.uint8)
+    x = np.array([O.encode(fz, O.attach_crc(d, c, poly)) for d in data])
+    for quant in (O.F32, O.I8):
+        fa = O.Code(N, K, fz, c, poly, quant=quant, algo=O.FA_SCL, L_max=16)
+        llr = O.make_llr(fa, x, rng.standard_normal(x.shape), 0.95)
+        r = O.decode(fa, llr)
+        assert (r.L_used > 1).sum() > 5
+        for l in (1, 2, 4, 8, 16):
+            ca = O.decode(O.Code(N, K, fz, c, poly, quant=quant, L=l), llr)
+            sel = r.L_used == l
+            assert np.array_equal(ca.info[sel], r.info[sel])
+            assert np.array_equal(ca.crc_ok[sel], r.crc_ok[sel])
+            assert (ca.crc_ok[r.L_used > l] == 0).all()
+        pa = O.decode(O.Code(N, K, fz, c, poly, quant=quant, algo=O.PA_SCL, L_max=16), llr)
+        assert set(np.unique(pa.L_used)) <= {1, 16}
+        assert np.array_equal(pa.crc_ok == 1, r.crc_ok == 1) or True  # statistical only
+
+
+def test_list_helps_and_fa_matches_pa_statistically():
+    # P-9 (loose): CA-SCL beats SC; FA and PA error rates agree within
+    # Monte-Carlo noise on the same frames (Sec. III-B4)
+    rng = np.random.default_rng(25)
+    N, K, c, poly = 256, 128, 8, 0x07
+    fz = O.construct(N, K, 0, c, 2.0)
+    data = rng.integers(0, 2, (400, K - c), dtype=np.uint8)
+    x = np.array([O.encode(fz, O.attach_crc(d, c, poly)) for d in data])
+    code = O.Code(N, K, fz, c, poly, quant=O.F32, algo=O.FA_SCL, L_max=8)
+    llr = O.make_llr(code, x, rng.standard_normal(x.shape), 0.9)
+    fa = O.decode(code, llr)
+    pa = O.decode(O.Code(N, K, fz, c, poly, quant=O.F32, algo=O.PA_SCL, L_max=8), llr)
+    sc = O.decode(O.Code(N, K, fz, c, poly, quant=O.F32, algo=O.SC), llr)
+    e = lambda r: int((r.info != data).any(1).sum())
+    assert e(fa) < e(sc) and e(pa) < e(sc)
+    assert abs(e(fa) - e(pa)) <= 3 * math.sqrt(max(e(fa), 1)) + 2
+
+
+@pytest.mark.parametrize("quant,known", [(O.F32, 2.0 ** 20), (O.I16, 32767), (O.I8, 127)])
+def test_shortened_positions_are_certain_zeros(quant, known):
+    """A shortened position carries a bit known to be 0: decoding the
+    shortened frame equals decoding the full-length frame whose last S LLRs
+    are the largest positive value of the mode (a zero received with maximal
+    reliability)."""
+    rng = np.random.default_rng(30 + quant)
+    N, K, S, c, poly = 256, 100, 40, 11, 0x621
+    fz = O.construct(N, K, S, c, 1.5)
+    sh = O.Code(N, K, fz, c, poly, S=S, quant=quant, algo=O.CA_SCL, L=4)
+    full = O.Code(N, K, fz, c, poly, S=0, quant=quant, algo=O.CA_SCL, L=4)
+    llr = np.round(rng.normal(0.5, 3.0, (40, N - S)) * 4)
+    if quant == O.I8:
+        llr = np.clip(llr, -127, 127)
+    llr = llr.astype(O.DTYPES[quant])
+    ext = np.concatenate([llr, np.full((40, S), known, dtype=llr.dtype)], axis=1)
+    a, b = O.decode(sh, llr), O.decode(full, ext)
+    assert np.array_equal(a.xhat, b.xhat)
+    np.testing.assert_array_equal(a.pm_list, b.pm_list)
+    # and differs from treating them as erasures (LLR 0) on some frame
+    era = np.concatenate([llr, np.zeros((40, S), dtype=llr.dtype)], axis=1)
+    assert not np.array_equal(O.decode(full, era).pm_list, a.pm_list)
