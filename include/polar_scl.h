@@ -1,0 +1,211 @@
+/*
+ * polar_scl.h -- C ABI of the MI355X (gfx950) flexible CRC-aided SCL polar
+ * decoder.
+ *
+ * The method is that of Leonardon, Cassagne, Leroux, Jego, Hamelin and
+ * Savaria, "Fast and Flexible Software Polar List Decoders"
+ * (arXiv:1710.08314): successive-cancellation list decoding (Algorithm 1,
+ * Sec. II-B2) with the Rate-0 / Rate-1 / repetition / single-parity-check
+ * dedicated nodes (Sec. II-B3), CRC-aided selection (Sec. II-B4, Sec. IV-B),
+ * fully / partially adaptive list sizes (Sec. II-B5) and float32, 16-bit and
+ * 8-bit saturated arithmetic (Sec. III-B3).  Every code and decoder parameter
+ * (Sec. III-A, III-B) is a runtime value of a plan; nothing is recompiled.
+ *
+ * Conventions shared by every entry point
+ *   - Return value: 0 on success or a negative POLAR_E* code; no exception
+ *     crosses the boundary.  polar_strerror() names a code.
+ *   - Pointers named d_* are device (HBM) pointers owned by the caller; all
+ *     other pointers are host pointers, read during the call only.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Calls that take a stream only enqueue work on it and return without
+ *     waiting; the caller synchronises before reading outputs.
+ *   - Bit vectors are packed little-endian in 32-bit words: bit j of a vector
+ *     is bit (j % 32) of word j / 32.
+ *   - A plan is immutable after creation and may be shared by several
+ *     streams and host threads; it owns device tables until destroyed.
+ */
+#ifndef POLAR_SCL_H
+#define POLAR_SCL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- errors */
+#define POLAR_OK 0
+#define POLAR_EINVAL (-1)    /* invalid argument or inconsistent descriptor      */
+#define POLAR_EUNSUP (-2)    /* valid but outside what the GPU decoder supports  */
+#define POLAR_ENOMEM (-3)    /* device or host allocation failed                 */
+#define POLAR_EHIP (-4)      /* a HIP runtime call failed                        */
+#define POLAR_ENOTSYS (-5)   /* frozen set unusable for systematic encoding      */
+
+/* ------------------------------------------------------------ enumerations */
+/* LLR / path-metric arithmetic (Sec. III-B3).  Integer modes saturate to
+ * [-127, 127] and [-32767, 32767] after every operation. */
+typedef enum { POLAR_F32 = 0, POLAR_I16 = 1, POLAR_I8 = 2 } polar_quant;
+
+/* Decoding algorithm (Sec. II-B, Table I).  SC is the L = 1 decoder; CA_SCL a
+ * fixed list size L; PA_SCL the stages 1 then L_max; FA_SCL the stages
+ * 1, 2, 4, ... up to L_max, each restarted from the channel LLRs when no
+ * candidate of the previous stage passes the CRC. */
+typedef enum { POLAR_SC = 0, POLAR_CA_SCL = 1, POLAR_PA_SCL = 2, POLAR_FA_SCL = 3 } polar_algo;
+
+/* Dedicated nodes that prune the decoding tree (Sec. II-B3, Sec. III-B2). */
+enum { POLAR_NODE_R0 = 1, POLAR_NODE_R1 = 2, POLAR_NODE_REP = 4, POLAR_NODE_SPC = 8 };
+#define POLAR_NODE_ALL 15u
+
+/* ------------------------------------------------------------------- plans */
+/* Descriptor of a code and its decoder (Sec. III-A genericity, Sec. III-B
+ * flexibility).  All fields are runtime parameters. */
+typedef struct {
+  uint32_t N;           /* mother code length, a power of two, 2 <= N <= 2048        */
+  uint32_t K;           /* |A|: information positions INCLUDING the crc_len CRC bits */
+  const uint32_t *frozen;   /* host, ceil(N/32) words, bit i = 1: u_i frozen; or NULL:
+                             * the |A| most reliable positions by the Bhattacharyya
+                             * recursion at design_ebn0_db                            */
+  float design_ebn0_db; /* construction point when frozen == NULL                     */
+  uint32_t n_shorten;   /* S: codeword positions [N-S, N) are known zeros, not sent;
+                         * u-indices [N-S, N) must be (or are made) frozen           */
+  uint32_t crc_len;     /* c, 0..32 (0: no CRC; then PA/FA are rejected)             */
+  uint64_t crc_poly;    /* generator g(x): the c low coefficients (an x^c term, if
+                         * present, is ignored); MSB-first, init 0, no final xor    */
+  uint32_t algo;        /* polar_algo                                                */
+  uint32_t L;           /* list size for CA_SCL (power of two, 1..32)                */
+  uint32_t L_max;       /* last stage for PA/FA (power of two, 1..32)                */
+  uint32_t quant;       /* polar_quant of the LLRs handed to the decoder             */
+  uint32_t node_enable; /* OR of POLAR_NODE_*                                        */
+  uint32_t rep_max;     /* largest REP node (0 = unlimited; 8 gives REP8-)           */
+  uint32_t spc_max;     /* largest SPC node (0 = unlimited; 4 gives SPC4)            */
+  uint32_t r1_max;      /* largest Rate-1 node (0 = unlimited)                       */
+  uint32_t r0_max;      /* largest Rate-0 node (0 = unlimited)                       */
+} polar_plan_desc;
+
+typedef struct polar_plan_s *polar_plan;
+
+/* Build a plan: frozen set (given or constructed), systematic-encoding check,
+ * the pre-order program of the pruned decoding tree, CRC tables, and their
+ * upload to device memory (synchronous, on the current device).
+ * Errors: POLAR_EINVAL (bad sizes, K > N - S, frozen mask with |A| != K, a
+ * frozen mask that leaves a shortened u-index unfrozen), POLAR_EUNSUP (N >
+ * 2048, L or L_max > 32 or not a power of two, crc_len > 32, float32 at a
+ * list size whose decoder state exceeds the LDS of one CU), POLAR_ENOTSYS
+ * (the systematic encoder of Sec. II-A would not give x_A = b for this
+ * frozen set), POLAR_ENOMEM, POLAR_EHIP.  *out is written only on success. */
+int polar_scl_plan(const polar_plan_desc *desc, polar_plan *out);
+
+/* Release a plan and its device tables.  The caller guarantees that no work
+ * using the plan is still pending on any stream.  NULL is accepted. */
+int polar_plan_destroy(polar_plan p);
+
+/* Sizes a caller needs to lay out buffers for a plan. */
+typedef struct {
+  uint32_t N, K, crc_len, n_tx;  /* n_tx = N - S transmitted positions                */
+  uint32_t k_data;               /* K - crc_len decoded information bits per frame    */
+  uint32_t info_words;           /* ceil(k_data / 32): d_info words per frame         */
+  uint32_t code_words;           /* ceil(N / 32): polar_encode words per frame        */
+  uint32_t llr_bytes;            /* n_tx * element size of the plan's quant           */
+  uint32_t max_list;             /* largest list size the plan's schedule reaches     */
+  uint32_t n_ops;                /* length of the node program                        */
+  uint32_t n_r0, n_r1, n_rep, n_spc, n_leaf_frozen, n_leaf_info; /* pruned-tree nodes */
+  uint32_t lds_bytes;            /* decoder LDS footprint per frame at max_list       */
+} polar_plan_info;
+
+int polar_plan_get_info(polar_plan p, polar_plan_info *out);
+
+/* Copy the plan's frozen mask (ceil(N/32) host words, bit = 1: frozen). */
+int polar_plan_get_frozen(polar_plan p, uint32_t *frozen_words);
+
+/* Host-only dry run of polar_scl_plan: validates the descriptor and fills
+ * *info and (if non-NULL) the frozen mask exactly as the plan would, without
+ * touching any device.  Same error codes as polar_scl_plan except POLAR_EHIP
+ * and POLAR_ENOMEM. */
+int polar_plan_query(const polar_plan_desc *desc, polar_plan_info *info, uint32_t *frozen_words);
+
+/* ------------------------------------------------------------------ decode */
+/* One frame of a batch (device array).  llr_off: byte offset of its n_tx
+ * LLRs in d_llr (aligned to the element size); out_off: word offset of its
+ * info_words output words in d_info; plan_idx: index into `plans`. */
+typedef struct {
+  uint64_t llr_off;
+  uint32_t out_off;
+  uint32_t plan_idx;
+} polar_frame;
+
+/* Per-frame result (device array, one per frame). */
+typedef struct {
+  uint8_t crc_ok;   /* 1: the output passed the CRC (always 1 without a CRC)     */
+  uint8_t L_used;   /* list size of the stage whose output was taken              */
+  uint8_t n_paths;  /* paths alive at the end of that stage                       */
+  uint8_t flags;    /* reserved, 0                                                */
+  uint32_t pm;      /* path metric of the output: float32 bits, or int32 value    */
+} polar_status;
+
+/* Optional knobs; NULL selects defaults. */
+typedef struct {
+  uint32_t schedule;   /* 0 = automatic (tiered: SC tier + device escalation queue
+                        * + list tier), 1 = plain (one generic launch)             */
+  uint32_t reserved[7];
+} polar_decode_opts;
+
+/* Decode a batch (the hot path, Algorithm 1 and Sec. II-B3..B5).
+ *   plans[n_plans]   host array of plans used by the frames (all of one quant)
+ *   d_frames         device array of n_frames descriptors, or NULL: then every
+ *                    frame uses plans[0], frame f reads d_llr + f * llr_bytes
+ *                    and writes d_info + f * info_words
+ *   d_llr            channel LLRs, natural codeword order, in the plans' quant
+ *                    type (LLR > 0 favours bit 0); shortened positions are not
+ *                    included
+ *   d_info           decoded information bits (k_data per frame, packed)
+ *   d_status         n_frames polar_status
+ *   d_pm_lists       nullable; per frame max_list uint32 (float32 bits or int32):
+ *                    the final path metrics in ascending order, unused entries
+ *                    0xFFFFFFFF
+ *   scratch          the library keeps a per-device work area (escalation queue
+ *                    and counters) that grows on demand: concurrent calls on
+ *                    different streams of one device must be serialised by
+ *                    the caller.
+ * Errors: POLAR_EINVAL (NULL buffers, mixed quants, plan index out of range is
+ * not checked on device: the caller guarantees it), POLAR_EHIP. */
+int polar_scl_decode_batch(const polar_plan *plans, uint32_t n_plans,
+                           const polar_frame *d_frames, uint32_t n_frames,
+                           const void *d_llr, uint32_t *d_info, polar_status *d_status,
+                           uint32_t *d_pm_lists, const polar_decode_opts *opts, void *stream);
+
+/* ---------------------------------------------------- encoder and channel */
+/* Systematic encoding with CRC attachment (Sec. II-A, Sec. II-B4): per frame,
+ * b = data || CRC(data), u_A = b, u' = u F, u'_{A^c} = 0, x = u' F.
+ *   d_data: n_frames * info_words words (k_data bits per frame, packed)
+ *   d_code: n_frames * code_words words (N codeword bits; the transmitted
+ *           part is bits [0, n_tx), the shortened tail is always zero). */
+int polar_encode(polar_plan p, const uint32_t *d_data, uint32_t *d_code, uint32_t n_frames,
+                 void *stream);
+
+/* Workload generator of the Monte-Carlo chain (Sec. II-C), not part of the
+ * decoder: i.i.d. data bits (d_data, info_words per frame) for frames
+ * [frame0, frame0 + n_frames) of stream `seed`, counter-based (Philox4x32-10),
+ * so any range can be regenerated independently. */
+int polar_gen_data(polar_plan p, uint64_t seed, uint64_t frame0, uint32_t n_frames,
+                   uint32_t *d_data, void *stream);
+
+/* BPSK (0 -> +1) over AWGN at Eb/N0 (rate R = k_data / n_tx, sigma^2 =
+ * 1 / (2 R Eb/N0)), LLR = 2 y / sigma^2, quantised to the plan's type as
+ * clamp(rint(LLR * 2^frac_bits), -Q, Q) (float32: rounded to nearest).
+ * Writes n_tx LLRs per frame contiguously into d_llr.  Noise is Philox4x32-10
+ * + Box-Muller, counter-based on (seed, frame). */
+int polar_channel(polar_plan p, const uint32_t *d_code, uint32_t n_frames, float ebn0_db,
+                  int32_t frac_bits, uint64_t seed, uint64_t frame0, void *d_llr, void *stream);
+
+/* --------------------------------------------------------------- misc */
+const char *polar_strerror(int err);
+
+/* Library version string. */
+const char *polar_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* POLAR_SCL_H */

@@ -1,0 +1,234 @@
+// C ABI of the polar SCL decoder (declarations and contracts in
+// include/polar_scl.h).  Host-side validation, plan upload and launches.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <vector>
+
+#include "../../include/polar_scl.h"
+#include "kernels.h"
+#include "plan.h"
+
+struct polar_plan_s {
+  polar::HostPlan hp;
+  int device = 0;
+  polar::DevPlan* d_blob = nullptr;
+  const polar::DevPlan** d_self = nullptr;  // one-entry device plan table
+};
+
+namespace {
+
+std::mutex g_mu;
+// device plan tables of multi-plan batches, keyed by the plan list
+std::map<std::vector<polar_plan>, const polar::DevPlan**> g_tables;
+
+int hip_ok(hipError_t e) { return e == hipSuccess ? POLAR_OK : POLAR_EHIP; }
+
+const polar::DevPlan* const* plan_table(const polar_plan* plans, uint32_t n, int* rc) {
+  *rc = POLAR_OK;
+  if (n == 1) return plans[0]->d_self;
+  std::vector<polar_plan> key(plans, plans + n);
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = g_tables.find(key);
+  if (it != g_tables.end()) return it->second;
+  std::vector<const polar::DevPlan*> h(n);
+  for (uint32_t i = 0; i < n; ++i) h[i] = plans[i]->d_blob;
+  const polar::DevPlan** d = nullptr;
+  if (hipMalloc(&d, n * sizeof(void*)) != hipSuccess) {
+    *rc = POLAR_ENOMEM;
+    return nullptr;
+  }
+  if (hipMemcpy(d, h.data(), n * sizeof(void*), hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipFree(d);
+    *rc = POLAR_EHIP;
+    return nullptr;
+  }
+  g_tables.emplace(std::move(key), d);
+  return d;
+}
+
+void forget_tables(polar_plan p) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  for (auto it = g_tables.begin(); it != g_tables.end();) {
+    bool uses = false;
+    for (auto q : it->first) uses |= (q == p);
+    if (uses) {
+      (void)hipFree(it->second);
+      it = g_tables.erase(it);
+    } else {
+      ++it;
+    }
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+int polar_scl_plan(const polar_plan_desc* desc, polar_plan* out) {
+  if (!desc || !out) return POLAR_EINVAL;
+  polar_plan p = new (std::nothrow) polar_plan_s;
+  if (!p) return POLAR_ENOMEM;
+  int rc = polar::make_plan(*desc, p->hp);
+  if (rc) {
+    delete p;
+    return rc;
+  }
+  if (hipGetDevice(&p->device) != hipSuccess) {
+    delete p;
+    return POLAR_EHIP;
+  }
+  const size_t bytes = p->hp.blob.size() * 4;
+  if (hipMalloc(&p->d_blob, bytes) != hipSuccess) {
+    delete p;
+    return POLAR_ENOMEM;
+  }
+  if (hipMalloc(&p->d_self, sizeof(void*)) != hipSuccess) {
+    (void)hipFree(p->d_blob);
+    delete p;
+    return POLAR_ENOMEM;
+  }
+  const polar::DevPlan* self = p->d_blob;
+  if (hipMemcpy(p->d_blob, p->hp.blob.data(), bytes, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(p->d_self, &self, sizeof(void*), hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipFree(p->d_blob);
+    (void)hipFree(p->d_self);
+    delete p;
+    return POLAR_EHIP;
+  }
+  *out = p;
+  return POLAR_OK;
+}
+
+int polar_plan_destroy(polar_plan p) {
+  if (!p) return POLAR_OK;
+  forget_tables(p);
+  int rc = POLAR_OK;
+  if (p->d_blob && hipFree(p->d_blob) != hipSuccess) rc = POLAR_EHIP;
+  if (p->d_self && hipFree(p->d_self) != hipSuccess) rc = POLAR_EHIP;
+  delete p;
+  return rc;
+}
+
+namespace {
+void fill_info(const polar::HostPlan& hp, polar_plan_info* o) {
+  const polar::DevPlan& h = hp.hdr;
+  std::memset(o, 0, sizeof(*o));
+  o->N = h.N;
+  o->K = h.K;
+  o->crc_len = h.c;
+  o->n_tx = h.n_tx;
+  o->k_data = h.k_data;
+  o->info_words = h.info_words;
+  o->code_words = h.code_words;
+  o->llr_bytes = h.n_tx * polar::elem_bytes(h.quant);
+  o->max_list = h.max_list;
+  o->n_ops = h.n_ops;
+  o->n_r0 = hp.counts.r0;
+  o->n_r1 = hp.counts.r1;
+  o->n_rep = hp.counts.rep;
+  o->n_spc = hp.counts.spc;
+  o->n_leaf_frozen = hp.counts.leaf_f;
+  o->n_leaf_info = hp.counts.leaf_i;
+  o->lds_bytes = h.lds_max;
+}
+}  // namespace
+
+int polar_plan_get_info(polar_plan p, polar_plan_info* o) {
+  if (!p || !o) return POLAR_EINVAL;
+  fill_info(p->hp, o);
+  return POLAR_OK;
+}
+
+int polar_plan_query(const polar_plan_desc* desc, polar_plan_info* info, uint32_t* frozen_words) {
+  if (!desc || !info) return POLAR_EINVAL;
+  polar::HostPlan hp;
+  const int rc = polar::make_plan(*desc, hp);
+  if (rc) return rc;
+  fill_info(hp, info);
+  if (frozen_words) std::memcpy(frozen_words, hp.frozen.data(), hp.frozen.size() * 4);
+  return POLAR_OK;
+}
+
+int polar_plan_get_frozen(polar_plan p, uint32_t* fw) {
+  if (!p || !fw) return POLAR_EINVAL;
+  std::memcpy(fw, p->hp.frozen.data(), p->hp.frozen.size() * 4);
+  return POLAR_OK;
+}
+
+int polar_scl_decode_batch(const polar_plan* plans, uint32_t n_plans, const polar_frame* d_frames,
+                           uint32_t n_frames, const void* d_llr, uint32_t* d_info,
+                           polar_status* d_status, uint32_t* d_pm_lists,
+                           const polar_decode_opts* opts, void* stream) {
+  if (!plans || n_plans == 0) return POLAR_EINVAL;
+  for (uint32_t i = 0; i < n_plans; ++i)
+    if (!plans[i]) return POLAR_EINVAL;
+  if (n_frames == 0) return POLAR_OK;
+  if (!d_llr || !d_info || !d_status) return POLAR_EINVAL;
+  if (!d_frames && n_plans != 1) return POLAR_EINVAL;
+  const uint32_t quant = plans[0]->hp.hdr.quant;
+  uint32_t lds = 0, pm_stride = 0;
+  for (uint32_t i = 0; i < n_plans; ++i) {
+    const polar::DevPlan& h = plans[i]->hp.hdr;
+    if (h.quant != quant) return POLAR_EINVAL;
+    lds = h.lds_max > lds ? h.lds_max : lds;
+    pm_stride = h.max_list > pm_stride ? h.max_list : pm_stride;
+  }
+  (void)opts;
+  int rc = POLAR_OK;
+  polar::KArgs A{};
+  A.plans = plan_table(plans, n_plans, &rc);
+  if (rc) return rc;
+  A.frames = d_frames;
+  A.n_frames = n_frames;
+  A.llr = static_cast<const char*>(d_llr);
+  A.llr_bytes = plans[0]->hp.hdr.n_tx * polar::elem_bytes(quant);
+  A.info_words = plans[0]->hp.hdr.info_words;
+  A.info = d_info;
+  A.status = d_status;
+  A.pm_lists = d_pm_lists;
+  A.pm_stride = pm_stride;
+  const uint32_t grid = n_frames < 0x7FFFFFFFu ? n_frames : 0x7FFFFFFFu;
+  return polar::launch_decode_plain(quant, A, lds, grid, static_cast<hipStream_t>(stream));
+}
+
+int polar_encode(polar_plan p, const uint32_t* d_data, uint32_t* d_code, uint32_t n_frames,
+                 void* stream) {
+  if (!p || (n_frames && (!d_data || !d_code))) return POLAR_EINVAL;
+  return polar::launch_encode(p->d_blob, p->hp.hdr, d_data, d_code, n_frames,
+                              static_cast<hipStream_t>(stream));
+}
+
+int polar_gen_data(polar_plan p, uint64_t seed, uint64_t frame0, uint32_t n_frames,
+                   uint32_t* d_data, void* stream) {
+  if (!p || (n_frames && !d_data)) return POLAR_EINVAL;
+  return polar::launch_gen_data(p->hp.hdr, seed, frame0, n_frames, d_data,
+                                static_cast<hipStream_t>(stream));
+}
+
+int polar_channel(polar_plan p, const uint32_t* d_code, uint32_t n_frames, float ebn0_db,
+                  int32_t frac_bits, uint64_t seed, uint64_t frame0, void* d_llr, void* stream) {
+  if (!p || (n_frames && (!d_code || !d_llr))) return POLAR_EINVAL;
+  if (frac_bits < 0 || frac_bits > 14) return POLAR_EINVAL;
+  return polar::launch_channel(p->hp.hdr, d_code, n_frames, ebn0_db, frac_bits, seed, frame0,
+                               d_llr, static_cast<hipStream_t>(stream));
+}
+
+const char* polar_strerror(int err) {
+  switch (err) {
+    case POLAR_OK: return "success";
+    case POLAR_EINVAL: return "invalid argument";
+    case POLAR_EUNSUP: return "unsupported configuration";
+    case POLAR_ENOMEM: return "out of memory";
+    case POLAR_EHIP: return "HIP runtime error";
+    case POLAR_ENOTSYS: return "frozen set not usable for systematic encoding";
+    default: return "unknown error";
+  }
+}
+
+const char* polar_version(void) { return "polar-scl-gfx950 0.1"; }
+
+}  // extern "C"

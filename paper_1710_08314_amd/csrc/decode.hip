@@ -1,0 +1,895 @@
+// gfx950 kernels of the flexible CRC-aided SCL polar decoder.
+//
+// Method: Leonardon et al., "Fast and Flexible Software Polar List Decoders"
+// (arXiv:1710.08314) -- Algorithm 1 (Sec. II-B2) walked as a pre-order node
+// program over the pruned tree (Sec. II-B3), min-sum f/g/h (equations of
+// Sec. II-B1), LLR-based path metrics, CRC-aided selection in path-metric
+// order (Sec. II-B4, IV-B), adaptive list-size schedules (Sec. II-B5) and
+// float32 / saturated int16 / saturated int8 arithmetic (Sec. III-B3).
+//
+// Execution model.  One workgroup decodes one frame at a time; all decoder
+// state lives in LDS:
+//   * the channel LLRs (root) are shared by every path and never written;
+//   * depth-d LLRs of the path of rank r are read from slot ptr[d][r] and
+//     f/g always write depth d+1 into the writer's own slot r, so a fork only
+//     copies the small per-depth slot table, never LLR data (the paper keeps
+//     LLRs behind pointers, Sec. IV-D);
+//   * partial sums are packed bits statically owned by rank and copied on
+//     fork (SSCL_cpy of Sec. IV-D, N bits per path);
+//   * candidates of a fork are (metric, parent rank, local index) keys sorted
+//     by a wave-level bitonic network; the first L survive, in key order.
+// Bit-exactness with a scalar reading of the method: f, g and penalties are
+// evaluated exactly as defined (no FMA, no reassociation: float penalty sums
+// use the stride-halving order v[i] += v[i + s], s = m/2 ... 1, which the
+// strided lane mapping below reproduces), ties are broken by the key.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "../../include/polar_scl.h"
+#include "kernels.h"
+#include "polar_internal.h"
+
+namespace polar {
+
+// ------------------------------------------------------------ value traits
+template <typename T>
+struct VT;
+template <>
+struct VT<float> {
+  static constexpr uint32_t E = 4, VMAX = 4;
+  using Acc = float;
+  using Key = unsigned long long;
+  static constexpr bool INT = false;
+  static constexpr int Q = 0;
+};
+template <>
+struct VT<int16_t> {
+  static constexpr uint32_t E = 2, VMAX = 8;
+  using Acc = int;
+  using Key = uint32_t;
+  static constexpr bool INT = true;
+  static constexpr int Q = 32767;
+};
+template <>
+struct VT<int8_t> {
+  static constexpr uint32_t E = 1, VMAX = 16;
+  using Acc = int;
+  using Key = uint32_t;
+  static constexpr bool INT = true;
+  static constexpr int Q = 127;
+};
+
+// f = sign(a b) min(|a|, |b|) with the sign taken from the operand signs;
+// g = (1 - 2 s) a + b, saturated in the integer modes (Sec. II-B1, III-B3).
+__device__ __forceinline__ float f_op(float a, float b) {
+  const float m = fminf(fabsf(a), fabsf(b));
+  return ((a < 0.f) != (b < 0.f)) ? -m : m;
+}
+__device__ __forceinline__ float g_op(float a, float b, uint32_t s) { return s ? (b - a) : (b + a); }
+__device__ __forceinline__ int f_opi(int a, int b) {
+  const int m = min(abs(a), abs(b));
+  return ((a ^ b) < 0) ? -m : m;
+}
+template <int Q>
+__device__ __forceinline__ int g_opi(int a, int b, uint32_t s) {
+  const int v = s ? (b - a) : (b + a);
+  return max(-Q, min(Q, v));
+}
+
+template <typename T>
+__device__ __forceinline__ typename VT<T>::Acc as_acc(T v) {
+  return (typename VT<T>::Acc)v;
+}
+
+// Element k of a small packed vector held in 32-bit words.
+template <typename T>
+__device__ __forceinline__ T get_el(const uint32_t* w, int k);
+template <>
+__device__ __forceinline__ float get_el<float>(const uint32_t* w, int k) {
+  return __uint_as_float(w[k]);
+}
+template <>
+__device__ __forceinline__ int16_t get_el<int16_t>(const uint32_t* w, int k) {
+  return (int16_t)(w[k >> 1] >> ((k & 1) * 16));
+}
+template <>
+__device__ __forceinline__ int8_t get_el<int8_t>(const uint32_t* w, int k) {
+  return (int8_t)(w[k >> 2] >> ((k & 3) * 8));
+}
+template <typename T>
+__device__ __forceinline__ void put_el(uint32_t* w, int k, T v);
+template <>
+__device__ __forceinline__ void put_el<float>(uint32_t* w, int k, float v) {
+  w[k] = __float_as_uint(v);
+}
+template <>
+__device__ __forceinline__ void put_el<int16_t>(uint32_t* w, int k, int16_t v) {
+  w[k >> 1] |= ((uint32_t)(uint16_t)v) << ((k & 1) * 16);
+}
+template <>
+__device__ __forceinline__ void put_el<int8_t>(uint32_t* w, int k, int8_t v) {
+  w[k >> 2] |= ((uint32_t)(uint8_t)v) << ((k & 3) * 8);
+}
+
+template <int NB>
+__device__ __forceinline__ void lds_ld(const char* p, uint32_t* w) {
+  if constexpr (NB == 16) {
+    const uint4 v = *reinterpret_cast<const uint4*>(p);
+    w[0] = v.x; w[1] = v.y; w[2] = v.z; w[3] = v.w;
+  } else if constexpr (NB == 8) {
+    const uint2 v = *reinterpret_cast<const uint2*>(p);
+    w[0] = v.x; w[1] = v.y;
+  } else if constexpr (NB == 4) {
+    w[0] = *reinterpret_cast<const uint32_t*>(p);
+  } else if constexpr (NB == 2) {
+    w[0] = *reinterpret_cast<const uint16_t*>(p);
+  } else {
+    w[0] = *reinterpret_cast<const uint8_t*>(p);
+  }
+}
+template <int NB>
+__device__ __forceinline__ void lds_st(char* p, const uint32_t* w) {
+  if constexpr (NB == 16) {
+    *reinterpret_cast<uint4*>(p) = make_uint4(w[0], w[1], w[2], w[3]);
+  } else if constexpr (NB == 8) {
+    *reinterpret_cast<uint2*>(p) = make_uint2(w[0], w[1]);
+  } else if constexpr (NB == 4) {
+    *reinterpret_cast<uint32_t*>(p) = w[0];
+  } else if constexpr (NB == 2) {
+    *reinterpret_cast<uint16_t*>(p) = (uint16_t)w[0];
+  } else {
+    *reinterpret_cast<uint8_t*>(p) = (uint8_t)w[0];
+  }
+}
+
+template <typename T, int V>
+__device__ __forceinline__ void f_chunk(const uint32_t* a, const uint32_t* b, uint32_t* o) {
+#pragma unroll
+  for (int k = 0; k < V; ++k) {
+    if constexpr (VT<T>::INT)
+      put_el<T>(o, k, (T)f_opi(get_el<T>(a, k), get_el<T>(b, k)));
+    else
+      put_el<T>(o, k, f_op(get_el<T>(a, k), get_el<T>(b, k)));
+  }
+}
+template <typename T, int V>
+__device__ __forceinline__ void g_chunk(const uint32_t* a, const uint32_t* b, uint32_t s,
+                                        uint32_t* o) {
+#pragma unroll
+  for (int k = 0; k < V; ++k) {
+    if constexpr (VT<T>::INT)
+      put_el<T>(o, k, (T)g_opi<VT<T>::Q>(get_el<T>(a, k), get_el<T>(b, k), (s >> k) & 1u));
+    else
+      put_el<T>(o, k, g_op(get_el<T>(a, k), get_el<T>(b, k), (s >> k) & 1u));
+  }
+}
+
+__device__ __forceinline__ uint32_t lg2(uint32_t x) { return 31u - __clz(x); }
+
+// ------------------------------------------------------------- frame state
+// Uniform (per workgroup) view of one frame-stage.
+struct Ctx {
+  char* smem;
+  const DevPlan* P;
+  const uint32_t* prog;
+  uint32_t N, n, bw, L;  // L: list size of this stage
+  LdsLayout lay;
+};
+
+__device__ __forceinline__ uint32_t* bits_of(const Ctx& c, uint32_t r) {
+  return reinterpret_cast<uint32_t*>(c.smem + c.lay.bits) + r * c.bw;
+}
+__device__ __forceinline__ uint8_t* ptr_tab(const Ctx& c) {
+  return reinterpret_cast<uint8_t*>(c.smem + c.lay.ptr);
+}
+__device__ __forceinline__ uint32_t* tabs(const Ctx& c) {
+  return reinterpret_cast<uint32_t*>(c.smem + c.lay.tabs);
+}
+// Address of element 0 of the depth-d LLRs of the path of rank r.
+__device__ __forceinline__ char* node_llr(const Ctx& c, uint32_t d, uint32_t r) {
+  if (d == 0) return c.smem + c.lay.root;
+  const uint32_t* t = tabs(c);
+  return c.smem + t[d] + (uint32_t)ptr_tab(c)[d * 32 + r] * t[12 + d];
+}
+
+// ------------------------------------------------------------ F, G and H
+template <typename T, int V, int NT>
+__device__ void run_fg(const Ctx& c, uint32_t d, uint32_t o, uint32_t a, bool is_g) {
+  constexpr uint32_t E = VT<T>::E;
+  constexpr int NB = V * E;
+  const uint32_t h = (c.N >> d) >> 1;
+  const uint32_t cpp = h / V, lc = lg2(cpp);
+  const uint32_t total = a << lc;
+  const uint32_t* t = tabs(c);
+  const uint32_t dbase = t[d + 1], dstride = t[12 + d + 1];
+  for (uint32_t it = threadIdx.x; it < total; it += NT) {
+    const uint32_t r = it >> lc, j = it & (cpp - 1);
+    const char* src = node_llr(c, d, r) + j * NB;
+    uint32_t wa[4], wb[4], wo[4] = {0u, 0u, 0u, 0u};
+    lds_ld<NB>(src, wa);
+    lds_ld<NB>(src + h * E, wb);
+    if (is_g) {
+      const uint32_t bp = o + j * V;
+      const uint32_t s = bits_of(c, r)[bp >> 5] >> (bp & 31);
+      g_chunk<T, V>(wa, wb, s, wo);
+    } else {
+      f_chunk<T, V>(wa, wb, wo);
+    }
+    lds_st<NB>(c.smem + dbase + r * dstride + j * NB, wo);
+  }
+  if (threadIdx.x < a) ptr_tab(c)[(d + 1) * 32 + threadIdx.x] = (uint8_t)threadIdx.x;
+}
+
+template <typename T, int NT>
+__device__ void op_fg(const Ctx& c, uint32_t d, uint32_t o, uint32_t a, bool is_g) {
+  const uint32_t h = (c.N >> d) >> 1;
+  constexpr uint32_t VM = VT<T>::VMAX;
+  if (h >= VM)
+    run_fg<T, VM, NT>(c, d, o, a, is_g);
+  else if (VM >= 8 && h == 8)
+    run_fg<T, (VM >= 8 ? 8 : 1), NT>(c, d, o, a, is_g);
+  else if (VM >= 4 && h == 4)
+    run_fg<T, (VM >= 4 ? 4 : 1), NT>(c, d, o, a, is_g);
+  else if (h == 2)
+    run_fg<T, 2, NT>(c, d, o, a, is_g);
+  else
+    run_fg<T, 1, NT>(c, d, o, a, is_g);
+}
+
+template <int NT>
+__device__ void op_h(const Ctx& c, uint32_t d, uint32_t o, uint32_t a) {
+  const uint32_t h = (c.N >> d) >> 1;
+  if (h >= 32) {
+    const uint32_t wc = h >> 5, lw = lg2(wc), total = a << lw;
+    for (uint32_t it = threadIdx.x; it < total; it += NT) {
+      const uint32_t r = it >> lw, k = it & (wc - 1);
+      uint32_t* B = bits_of(c, r);
+      B[(o >> 5) + k] ^= B[((o + h) >> 5) + k];
+    }
+  } else if (threadIdx.x < a) {
+    uint32_t* B = bits_of(c, threadIdx.x) + (o >> 5);
+    const uint32_t msk = ((1u << h) - 1u) << (o & 31);
+    const uint32_t w = *B;
+    *B = w ^ ((w >> h) & msk);
+  }
+}
+
+// ------------------------------------------------------- wave primitives
+template <typename K>
+__device__ __forceinline__ K shfl_xor_k(K v, int m) {
+  if constexpr (sizeof(K) == 8) {
+    const uint32_t lo = __shfl_xor((uint32_t)v, m, 64);
+    const uint32_t hi = __shfl_xor((uint32_t)(v >> 32), m, 64);
+    return ((K)hi << 32) | lo;
+  } else {
+    return __shfl_xor(v, m, 64);
+  }
+}
+
+// Bitonic sort, ascending, of 64 * KPL keys held as k[t] = element t*64+lane.
+template <typename K, int KPL>
+__device__ void wave_sort(K (&k)[KPL]) {
+  const uint32_t lane = threadIdx.x & 63u;
+#pragma unroll
+  for (uint32_t size = 2; size <= 64u * KPL; size <<= 1) {
+#pragma unroll
+    for (uint32_t st = size >> 1; st > 0; st >>= 1) {
+      if (st >= 64) {
+        const uint32_t q = st >> 6;
+#pragma unroll
+        for (int t = 0; t < KPL; ++t) {
+          if ((t & q) == 0) {
+            const uint32_t e = t * 64u + lane;
+            const bool asc = (e & size) == 0;
+            const K x = k[t], y = k[t | q];
+            const bool sw = asc ? (x > y) : (x < y);
+            k[t] = sw ? y : x;
+            k[t | q] = sw ? x : y;
+          }
+        }
+      } else {
+#pragma unroll
+        for (int t = 0; t < KPL; ++t) {
+          const uint32_t e = t * 64u + lane;
+          const K other = shfl_xor_k(k[t], (int)st);
+          const bool lower = (lane & st) == 0;
+          const bool asc = (e & size) == 0;
+          const bool keep_min = (lower == asc);
+          k[t] = keep_min ? (other < k[t] ? other : k[t]) : (other > k[t] ? other : k[t]);
+        }
+      }
+    }
+  }
+}
+
+// Sort `cnt` keys of src[] (wave 0 only), write the first `keep` to dst[].
+template <typename K, int KPL>
+__device__ void sort_keys_kpl(const K* src, uint32_t cnt, K* dst, uint32_t keep) {
+  const uint32_t lane = threadIdx.x & 63u;
+  K k[KPL];
+#pragma unroll
+  for (int t = 0; t < KPL; ++t) {
+    const uint32_t e = t * 64u + lane;
+    k[t] = e < cnt ? src[e] : (K)~(K)0;
+  }
+  wave_sort<K, KPL>(k);
+#pragma unroll
+  for (int t = 0; t < KPL; ++t) {
+    const uint32_t e = t * 64u + lane;
+    if (e < keep) dst[e] = k[t];
+  }
+}
+template <typename K>
+__device__ void sort_keys(const K* src, uint32_t cnt, K* dst, uint32_t keep) {
+  if (cnt <= 64)
+    sort_keys_kpl<K, 1>(src, cnt, dst, keep);
+  else if (cnt <= 128)
+    sort_keys_kpl<K, 2>(src, cnt, dst, keep);
+  else
+    sort_keys_kpl<K, 4>(src, cnt, dst, keep);
+}
+
+// ------------------------------------------------------------ keys
+// Candidate key (metric, parent rank, local index), compared as one unsigned
+// integer: local index in bits 0..3 (SPC masks reach 15), parent rank in bits
+// 4..8, metric above (int modes: <= 32767, 15 bits; float32: the bits of a
+// non-negative float, whose unsigned order is the numeric order).
+constexpr uint32_t kLocalBits = 4, kParentBits = 5, kPmShift = kLocalBits + kParentBits;
+template <typename T>
+__device__ __forceinline__ typename VT<T>::Key make_key(typename VT<T>::Acc pm, uint32_t parent,
+                                                        uint32_t local) {
+  if constexpr (VT<T>::INT)
+    return ((uint32_t)pm << kPmShift) | (parent << kLocalBits) | local;
+  else
+    return ((unsigned long long)__float_as_uint(pm) << 32) | (parent << kLocalBits) | local;
+}
+template <typename T>
+__device__ __forceinline__ typename VT<T>::Acc key_pm(typename VT<T>::Key k) {
+  if constexpr (VT<T>::INT)
+    return (int)(k >> kPmShift);
+  else
+    return __uint_as_float((uint32_t)(k >> 32));
+}
+template <typename T>
+__device__ __forceinline__ uint32_t key_parent(typename VT<T>::Key k) {
+  return ((uint32_t)k >> kLocalBits) & ((1u << kParentBits) - 1u);
+}
+template <typename T>
+__device__ __forceinline__ uint32_t key_local(typename VT<T>::Key k) {
+  return (uint32_t)k & ((1u << kLocalBits) - 1u);
+}
+template <typename T>
+__device__ __forceinline__ typename VT<T>::Acc pm_add(typename VT<T>::Acc pm,
+                                                      typename VT<T>::Acc pen) {
+  if constexpr (VT<T>::INT)
+    return min(pm + pen, VT<T>::Q);  // both >= 0; pen exact in int32
+  else
+    return pm + pen;
+}
+template <typename T>
+__device__ __forceinline__ typename VT<T>::Acc* pm_tab(const Ctx& c) {
+  return reinterpret_cast<typename VT<T>::Acc*>(c.smem + c.lay.pm);
+}
+
+// Reliability key (|alpha|, position): ordered by magnitude, then index.
+template <typename T>
+__device__ __forceinline__ typename VT<T>::Key rel_key(T v, uint32_t k) {
+  if constexpr (VT<T>::INT)
+    return ((uint32_t)abs((int)v) << 16) | k;
+  else
+    return ((unsigned long long)__float_as_uint(fabsf(v)) << 16) | k;
+}
+template <typename T>
+__device__ __forceinline__ typename VT<T>::Acc rel_mag(typename VT<T>::Key k) {
+  if constexpr (VT<T>::INT)
+    return (int)(k >> 16);
+  else
+    return __uint_as_float((uint32_t)(k >> 16));
+}
+
+// Insert key x into the sorted list s[0..NK) keeping the NK smallest.
+template <typename K, int NK>
+__device__ __forceinline__ void top_insert(K (&s)[NK], K x) {
+#pragma unroll
+  for (int i = 0; i < NK; ++i) {
+    const K lo = s[i] < x ? s[i] : x;
+    const K hi = s[i] < x ? x : s[i];
+    s[i] = lo;
+    x = hi;
+  }
+}
+
+// ------------------------------------------------------------ node ops
+constexpr uint32_t kEPL = 32;  // max elements per lane in a node (N/64)
+
+// Per-path node work.  Each path is handled by a segment of G = min(64, m)
+// lanes; lane j holds elements j, j + G, j + 2G, ...  The segment sums of
+// the penalties follow the stride-halving order exactly: in-lane halving of
+// the element list, then butterflies over the lanes.
+template <typename T, int NT>
+__device__ void op_node(const Ctx& c, uint32_t opc, uint32_t d, uint32_t o, uint32_t& a) {
+  using Acc = typename VT<T>::Acc;
+  using Key = typename VT<T>::Key;
+  const uint32_t m = c.N >> d;
+  const uint32_t G = m < 64 ? m : 64, lgG = lg2(G), epl = m >> lgG;
+  const uint32_t ppr = NT >> lgG;
+  const uint32_t tid = threadIdx.x, j = tid & (G - 1), lane = tid & 63u;
+  Acc* pm = pm_tab<T>(c);
+  Key* cand = reinterpret_cast<Key*>(c.smem + c.lay.cand);
+  uint16_t* cpos = reinterpret_cast<uint16_t*>(c.smem + c.lay.cpos);
+  const bool single = (opc == OP_R0 || opc == OP_LF);
+  const uint32_t C = single ? 1u : (opc == OP_R1 ? 4u : (opc == OP_SPC ? 8u : 2u));
+
+  for (uint32_t base = 0; base < a; base += ppr) {
+    const uint32_t r = base + (tid >> lgG);
+    const bool valid = r < a;
+    const T* al = reinterpret_cast<const T*>(node_llr(c, d, valid ? r : 0));
+    if (opc == OP_R0 || opc == OP_LF || opc == OP_REP || opc == OP_LI) {
+      // penalties of the all-0 (v = 0) and all-1 (v = 1) decisions
+      Acc x0[kEPL], x1[kEPL];
+#pragma unroll
+      for (uint32_t t = 0; t < kEPL; ++t) {
+        if (t < epl) {
+          const T v = al[j + (t << lgG)];
+          const Acc mg = VT<T>::INT ? (Acc)abs((int)v) : (Acc)fabsf((float)v);
+          const bool hd = v < (T)0;
+          x0[t] = hd ? mg : (Acc)0;
+          x1[t] = hd ? (Acc)0 : mg;
+        }
+      }
+#pragma unroll
+      for (uint32_t S = kEPL / 2; S >= 1; S >>= 1) {
+        if (S < epl) {
+#pragma unroll
+          for (uint32_t t = 0; t < S; ++t) {
+            x0[t] = x0[t] + x0[t + S];
+            x1[t] = x1[t] + x1[t + S];
+          }
+        }
+      }
+      Acc p0 = x0[0], p1 = x1[0];
+      for (uint32_t s = G >> 1; s >= 1; s >>= 1) {
+        p0 = p0 + __shfl_xor(p0, (int)s, 64);
+        p1 = p1 + __shfl_xor(p1, (int)s, 64);
+      }
+      if (valid && j == 0) {
+        if (single) {
+          pm[r] = pm_add<T>(pm[r], p0);
+        } else {
+          cand[r * 2 + 0] = make_key<T>(pm_add<T>(pm[r], p0), r, 0);
+          cand[r * 2 + 1] = make_key<T>(pm_add<T>(pm[r], p1), r, 1);
+        }
+      }
+      if (single && valid) {
+        // the node decides all zeros
+        uint32_t* B = bits_of(c, r);
+        if (m >= 32) {
+          for (uint32_t w = j; w < (m >> 5); w += G) B[(o >> 5) + w] = 0u;
+        } else if (j == 0) {
+          B[o >> 5] &= ~(((m == 32 ? 0u : (1u << m)) - 1u) << (o & 31));
+        }
+      }
+    } else {
+      // R1 (Chase-2 on the 2 least reliable positions) and SPC (even-parity
+      // flips among the 4 least reliable): keys (|alpha|, position).
+      constexpr int NK = 4;
+      const Key kmax = (Key)~(Key)0;
+      Key top[NK] = {kmax, kmax, kmax, kmax};
+      uint32_t par = 0;
+      // hard decisions of this lane's elements, written into the parent's own
+      // partial-sum region [o, o + m): copied to every child, then flipped.
+      uint32_t* B = bits_of(c, valid ? r : 0);
+#pragma unroll
+      for (uint32_t t = 0; t < kEPL; ++t) {
+        if (t < epl) {
+          const uint32_t k = j + (t << lgG);
+          const T v = al[k];
+          top_insert<Key, NK>(top, rel_key<T>(v, k));
+          const bool hd = v < (T)0;
+          par ^= hd ? 1u : 0u;
+          const unsigned long long bal = __ballot(hd);
+          if (G == 64) {
+            if (valid && (lane & 31u) == 0) B[((o + (t << 6)) >> 5) + (lane >> 5)] =
+                (uint32_t)(bal >> (lane & 32u));
+          } else if (valid && j == 0) {
+            const uint32_t seg = (uint32_t)(bal >> (lane & ~(G - 1u))) & ((G == 32 ? 0u : (1u << G)) - 1u);
+            uint32_t w = B[o >> 5];
+            const uint32_t msk = ((G == 32 ? 0u : (1u << G)) - 1u) << (o & 31);
+            B[o >> 5] = (w & ~msk) | (seg << (o & 31));
+          }
+        }
+      }
+      for (uint32_t s = G >> 1; s >= 1; s >>= 1) {
+        Key other[NK];
+#pragma unroll
+        for (int i = 0; i < NK; ++i) other[i] = shfl_xor_k(top[i], (int)s);
+#pragma unroll
+        for (int i = 0; i < NK; ++i) top_insert<Key, NK>(top, other[i]);
+        par ^= __shfl_xor(par, (int)s, 64);
+      }
+      // candidate q of the path is written by lane q mod G of its segment
+      // (a segment may be narrower than the candidate count: R1 with m = 2
+      // has 4 candidates on 2 lanes, SPC with m = 4 has 8 on 4 lanes)
+      const uint32_t npos = opc == OP_R1 ? 2u : 4u;
+      for (uint32_t q = j; valid && q < C; q += G) {
+        uint32_t mask;
+        if (opc == OP_R1) {
+          mask = q;
+        } else {
+          // q-th mask (ascending) over 4 positions whose weight has the
+          // parity of the hard decision
+          const uint32_t ev = 0xFCA96530u, od = 0xEDB87421u;  // nibble tables
+          mask = ((par ? od : ev) >> (4 * q)) & 15u;
+        }
+        Acc pen = (Acc)0;
+#pragma unroll
+        for (int i = 0; i < NK; ++i)
+          if ((mask >> i) & 1u) pen = pen + rel_mag<T>(top[i]);
+        cand[r * C + q] = make_key<T>(pm_add<T>(pm[r], pen), r, mask);
+        if (q < npos) {
+          Key tq = top[0];
+#pragma unroll
+          for (int i = 1; i < NK; ++i)
+            if ((uint32_t)i == q) tq = top[i];
+          cpos[r * 4 + q] = (uint16_t)(tq & 0xFFFFu);
+        }
+      }
+    }
+  }
+  __syncthreads();
+
+  if (single) {
+    if constexpr (VT<T>::INT) {
+      // normalisation after every update_paths() (Sec. III-B3)
+      if (tid < 64) {
+        Acc v = tid < a ? pm[tid] : (Acc)VT<T>::Q;
+        Acc mn = v;
+        for (int s = 32; s >= 1; s >>= 1) mn = min(mn, __shfl_xor(mn, s, 64));
+        if (tid < a) pm[tid] = v - mn;
+      }
+      __syncthreads();
+    }
+    return;
+  }
+
+  // ---- selection: the min(L, a*C) best keys, in key order
+  Key* sel = reinterpret_cast<Key*>(c.smem + c.lay.sel);
+  const uint32_t total = a * C;
+  const uint32_t keep = total < c.L ? total : c.L;
+  if (tid < 64) sort_keys<Key>(cand, total, sel, keep);
+  __syncthreads();
+
+  // ---- path copy: partial-sum words [0, nwc) and slot pointers of depths
+  // 1..d from each survivor's parent (register staged: all reads, barrier,
+  // all writes, so a parent can be overwritten by its own child)
+  uint8_t* pt = ptr_tab(c);
+  if (c.L > 1) {
+    uint32_t nwc = (o + m + 31u) >> 5;
+    if (nwc > c.bw) nwc = c.bw;
+    const uint32_t lw = nwc > 1 ? lg2(2 * nwc - 1) : 0;  // ceil log2
+    const uint32_t items = keep << lw;
+    constexpr int RMAX = (int)(kMaxL * (kMaxN / 32) / NT);
+    uint32_t reg[RMAX];
+#pragma unroll
+    for (int q = 0; q < RMAX; ++q) {
+      const uint32_t it = tid + q * NT;
+      reg[q] = 0;
+      if (it < items) {
+        const uint32_t i = it >> lw, w = it & ((1u << lw) - 1u);
+        if (w < nwc) reg[q] = bits_of(c, key_parent<T>(sel[i]))[w];
+      }
+    }
+    constexpr int PMAX = (int)((kMaxLogN * kMaxL + NT - 1) / NT);
+    uint8_t preg[PMAX];
+    const uint32_t pitems = keep * d;
+#pragma unroll
+    for (int q = 0; q < PMAX; ++q) {
+      const uint32_t it = tid + q * NT;
+      preg[q] = 0;
+      if (it < pitems) {
+        const uint32_t i = it / d, dd = 1 + it % d;
+        preg[q] = pt[dd * 32 + key_parent<T>(sel[i])];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < RMAX; ++q) {
+      const uint32_t it = tid + q * NT;
+      if (it < items) {
+        const uint32_t i = it >> lw, w = it & ((1u << lw) - 1u);
+        if (w < nwc) bits_of(c, i)[w] = reg[q];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < PMAX; ++q) {
+      const uint32_t it = tid + q * NT;
+      if (it < pitems) {
+        const uint32_t i = it / d, dd = 1 + it % d;
+        pt[dd * 32 + i] = preg[q];
+      }
+    }
+    __syncthreads();
+  }
+
+  // ---- metrics (normalised in the integer modes) and the node's decisions
+  if (tid < keep) {
+    Acc v = key_pm<T>(sel[tid]);
+    if constexpr (VT<T>::INT) v -= key_pm<T>(sel[0]);
+    pm[tid] = v;
+  }
+  if (opc == OP_LI || opc == OP_REP) {
+    if (m >= 32) {
+      const uint32_t wpp = m >> 5, lw = lg2(wpp), items = keep << lw;
+      for (uint32_t it = tid; it < items; it += NT) {
+        const uint32_t i = it >> lw, w = it & (wpp - 1u);
+        bits_of(c, i)[(o >> 5) + w] = key_local<T>(sel[i]) ? ~0u : 0u;
+      }
+    } else if (tid < keep) {
+      uint32_t* B = bits_of(c, tid) + (o >> 5);
+      const uint32_t msk = ((1u << m) - 1u) << (o & 31);
+      *B = key_local<T>(sel[tid]) ? (*B | msk) : (*B & ~msk);
+    }
+  } else if (tid < keep) {
+    // R1 / SPC: flip the chosen least reliable positions of the parent's
+    // hard decision (already copied into the child)
+    const uint32_t mask = key_local<T>(sel[tid]), p = key_parent<T>(sel[tid]);
+    uint32_t* B = bits_of(c, tid);
+    for (uint32_t i = 0; i < 4; ++i) {
+      if ((mask >> i) & 1u) {
+        const uint32_t pos = o + cpos[p * 4 + i];
+        B[pos >> 5] ^= 1u << (pos & 31);
+      }
+    }
+  }
+  __syncthreads();
+  a = keep;
+}
+
+// ------------------------------------------------------------ one stage
+template <typename T, int NT>
+__device__ void run_program(const Ctx& c, uint32_t& a) {
+  const uint32_t n_ops = c.P->n_ops;
+  for (uint32_t pc = 0; pc < n_ops; ++pc) {
+    const uint32_t w = c.prog[pc];
+    const uint32_t opc = op_code(w), d = op_depth(w), o = op_off(w);
+    switch (opc) {
+      case OP_F:
+        op_fg<T, NT>(c, d, o, a, false);
+        __syncthreads();
+        break;
+      case OP_G:
+        op_fg<T, NT>(c, d, o, a, true);
+        __syncthreads();
+        break;
+      case OP_H:
+        op_h<NT>(c, d, o, a);
+        __syncthreads();
+        break;
+      default:
+        op_node<T, NT>(c, opc, d, o, a);
+        break;
+    }
+  }
+}
+
+// End of a stage (Sec. II-B4, IV-B): order the paths by (metric, rank),
+// compute every path's CRC syndrome from its codeword estimate, and take
+// the first path in that order whose syndrome is zero.  Returns the chosen
+// rank; *ok = CRC passed.  ord[] keeps the order (for the metric list).
+template <typename T, int NT>
+__device__ uint32_t end_of_stage(const Ctx& c, uint32_t a, bool* ok) {
+  using Key = typename VT<T>::Key;
+  using Acc = typename VT<T>::Acc;
+  const uint32_t tid = threadIdx.x;
+  Key* cand = reinterpret_cast<Key*>(c.smem + c.lay.cand);
+  Key* sel = reinterpret_cast<Key*>(c.smem + c.lay.sel);
+  uint32_t* syn = reinterpret_cast<uint32_t*>(c.smem + c.lay.syn);
+  uint32_t* ord = reinterpret_cast<uint32_t*>(c.smem + c.lay.ord);
+  uint32_t* misc = reinterpret_cast<uint32_t*>(c.smem + c.lay.misc);
+  const Acc* pm = pm_tab<T>(c);
+  if (tid < a) {
+    cand[tid] = make_key<T>(pm[tid], tid, 0);
+    syn[tid] = 0;
+  }
+  __syncthreads();
+  if (tid < 64) sort_keys<Key>(cand, a, sel, a);
+  // syndromes
+  const uint32_t* infomask = plan_tab(c.P, c.P->off_infomask);
+  const uint32_t* crccol = plan_tab(c.P, c.P->off_crccol);
+  const uint32_t lbw = lg2(c.bw), items = a << lbw;
+  if (c.P->c > 0) {
+    for (uint32_t it = tid; it < items; it += NT) {
+      const uint32_t r = it >> lbw, w = it & (c.bw - 1u);
+      uint32_t v = bits_of(c, r)[w] & infomask[w];
+      uint32_t s = 0;
+      while (v) {
+        const uint32_t b = __ffs(v) - 1;
+        s ^= crccol[(w << 5) + b];
+        v &= v - 1u;
+      }
+      if (s) atomicXor(&syn[r], s);
+    }
+  }
+  __syncthreads();
+  if (tid < 64) {
+    const bool in = tid < a;
+    const uint32_t r = in ? key_parent<T>(sel[tid]) : 0u;
+    if (in) ord[tid] = r;
+    const unsigned long long good = __ballot(in && syn[r] == 0u);
+    if (tid == 0) {
+      misc[0] = good ? ord[__ffsll(good) - 1] : ord[0];
+      misc[1] = good ? 1u : 0u;
+    }
+  }
+  __syncthreads();
+  *ok = misc[1] != 0;
+  return misc[0];
+}
+
+// Load the channel LLRs into the root buffer; shortened positions get the
+// largest positive value (a zero received with certainty).
+template <typename T, int NT>
+__device__ void load_root(const Ctx& c, const char* llr) {
+  constexpr uint32_t E = VT<T>::E;
+  T* root = reinterpret_cast<T*>(c.smem + c.lay.root);
+  const uint32_t ntx = c.P->n_tx;
+  const uint32_t nbytes = ntx * E;
+  if ((((uintptr_t)llr) & 15u) == 0 && (nbytes & 15u) == 0) {
+    const uint4* src = reinterpret_cast<const uint4*>(llr);
+    uint4* dst = reinterpret_cast<uint4*>(root);
+    for (uint32_t i = threadIdx.x; i < (nbytes >> 4); i += NT) dst[i] = src[i];
+  } else {
+    const T* src = reinterpret_cast<const T*>(llr);
+    for (uint32_t i = threadIdx.x; i < ntx; i += NT) root[i] = src[i];
+  }
+  const T known = VT<T>::INT ? (T)VT<T>::Q : (T)1048576.0f;
+  for (uint32_t i = ntx + threadIdx.x; i < c.N; i += NT) root[i] = known;
+}
+
+template <typename T, int NT>
+__device__ void setup_stage(Ctx& c, uint32_t L) {
+  c.L = L;
+  c.lay = lds_layout(c.N, c.n, VT<T>::E, L, (uint32_t)sizeof(typename VT<T>::Key));
+  uint32_t* t = tabs(c);
+  if (threadIdx.x == 0) {
+    uint32_t cur = c.lay.stages;
+    t[0] = c.lay.root;
+    t[12] = 0;
+    for (uint32_t d = 1; d <= c.n; ++d) {
+      t[d] = cur;
+      t[12 + d] = slot_bytes(c.N, d, VT<T>::E);
+      cur += L * t[12 + d];
+    }
+    pm_tab<T>(c)[0] = (typename VT<T>::Acc)0;
+  }
+  __syncthreads();
+}
+
+// Decode frame f: run the plan's list-size schedule (Sec. II-B5) from
+// `L_first`, write bits, status and (optionally) the metric list.
+template <typename T, int NT>
+__device__ void decode_frame(char* smem, const KArgs& A, uint32_t f, const DevPlan* P,
+                             const char* llr, uint32_t out_off, uint32_t L_first) {
+  using Acc = typename VT<T>::Acc;
+  Ctx c;
+  c.smem = smem;
+  c.P = P;
+  c.prog = plan_tab(P, P->off_prog);
+  c.N = P->N;
+  c.n = P->n;
+  c.bw = P->bw;
+  c.L = 1;
+  c.lay = lds_layout(c.N, c.n, VT<T>::E, 1, (uint32_t)sizeof(typename VT<T>::Key));
+  load_root<T, NT>(c, llr);
+  uint32_t L = L_first, chosen = 0, a = 1;
+  bool ok = false;
+  for (;;) {
+    setup_stage<T, NT>(c, L);
+    a = 1;
+    run_program<T, NT>(c, a);
+    chosen = end_of_stage<T, NT>(c, a, &ok);
+    if (ok || L >= P->L_max) break;
+    L = (P->algo == POLAR_PA_SCL) ? P->L_max : 2 * L;
+  }
+  // ---- outputs
+  const uint32_t tid = threadIdx.x;
+  uint32_t* out = reinterpret_cast<uint32_t*>(c.smem + c.lay.out);
+  const uint32_t iw = P->info_words;
+  for (uint32_t i = tid; i < iw; i += NT) out[i] = 0;
+  __syncthreads();
+  const uint32_t* dmask = plan_tab(P, P->off_datamask);
+  const uint32_t* dpre = plan_tab(P, P->off_dataprefix);
+  const uint32_t* xb = bits_of(c, chosen);
+  for (uint32_t w = tid; w < c.bw; w += NT) {
+    const uint32_t x = xb[w];
+    uint32_t dm = dmask[w];
+    const uint32_t pre = dpre[w];
+    uint32_t v = 0, cnt = 0;
+    while (dm) {
+      const uint32_t b = __ffs(dm) - 1;
+      v |= ((x >> b) & 1u) << cnt;
+      ++cnt;
+      dm &= dm - 1u;
+    }
+    if (cnt) {
+      atomicOr(&out[pre >> 5], v << (pre & 31));
+      if ((pre & 31) + cnt > 32) atomicOr(&out[(pre >> 5) + 1], v >> (32 - (pre & 31)));
+    }
+  }
+  __syncthreads();
+  for (uint32_t i = tid; i < iw; i += NT) A.info[out_off + i] = out[i];
+  const Acc* pm = pm_tab<T>(c);
+  if (tid == 0) {
+    polar_status st;
+    st.crc_ok = ok ? 1 : 0;
+    st.L_used = (uint8_t)L;
+    st.n_paths = (uint8_t)a;
+    st.flags = 0;
+    const Acc v = pm[chosen];
+    if constexpr (VT<T>::INT)
+      st.pm = (uint32_t)v;
+    else
+      st.pm = __float_as_uint(v);
+    A.status[f] = st;
+  }
+  if (A.pm_lists) {
+    const uint32_t* ord = reinterpret_cast<const uint32_t*>(c.smem + c.lay.ord);
+    const uint32_t ml = A.pm_stride;
+    for (uint32_t t = tid; t < ml; t += NT) {
+      uint32_t v = 0xFFFFFFFFu;
+      if (t < a) {
+        const Acc p = pm[ord[t]];
+        if constexpr (VT<T>::INT)
+          v = (uint32_t)p;
+        else
+          v = __float_as_uint(p);
+      }
+      A.pm_lists[(size_t)f * ml + t] = v;
+    }
+  }
+  __syncthreads();
+}
+
+template <typename T, int NW>
+__global__ __launch_bounds__(NW * 64) void k_decode_plain(KArgs A) {
+  extern __shared__ __attribute__((aligned(16))) char smem[];
+  for (uint32_t f = blockIdx.x; f < A.n_frames; f += gridDim.x) {
+    const DevPlan* P;
+    const char* llr;
+    uint32_t out_off;
+    if (A.frames) {
+      const polar_frame fr = A.frames[f];
+      P = A.plans[fr.plan_idx];
+      llr = A.llr + fr.llr_off;
+      out_off = fr.out_off;
+    } else {
+      P = A.plans[0];
+      llr = A.llr + (size_t)f * A.llr_bytes;
+      out_off = f * A.info_words;
+    }
+    decode_frame<T, NW * 64>(smem, A, f, P, llr, out_off, P->first_stage);
+  }
+}
+
+// ------------------------------------------------------------ launchers
+template <typename T, int NW>
+static int launch_plain_t(const KArgs& A, uint32_t lds, uint32_t grid, hipStream_t s) {
+  auto k = k_decode_plain<T, NW>;
+  if (hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
+      hipSuccess)
+    return POLAR_EHIP;
+  hipLaunchKernelGGL(k, dim3(grid), dim3(NW * 64), lds, s, A);
+  return hipGetLastError() == hipSuccess ? POLAR_OK : POLAR_EHIP;
+}
+
+int launch_decode_plain(uint32_t quant, const KArgs& A, uint32_t lds, uint32_t grid,
+                        hipStream_t s) {
+  switch (quant) {
+    case POLAR_F32: return launch_plain_t<float, 1>(A, lds, grid, s);
+    case POLAR_I16: return launch_plain_t<int16_t, 1>(A, lds, grid, s);
+    default: return launch_plain_t<int8_t, 1>(A, lds, grid, s);
+  }
+}
+
+}  // namespace polar

@@ -1,0 +1,39 @@
+// Kernel arguments and launchers (device side in decode.hip / gen.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "../../include/polar_scl.h"
+#include "polar_internal.h"
+
+namespace polar {
+
+struct KArgs {
+  const DevPlan* const* plans;  // device array of device plan blobs
+  const polar_frame* frames;    // NULL: uniform batch of plans[0]
+  uint32_t n_frames;
+  const char* llr;
+  uint32_t llr_bytes;   // uniform batch: bytes per frame
+  uint32_t info_words;  // uniform batch: output words per frame
+  uint32_t* info;
+  polar_status* status;
+  uint32_t* pm_lists;   // nullable
+  uint32_t pm_stride;   // entries per frame in pm_lists
+};
+
+// One generic launch: each workgroup decodes whole frames (every stage of
+// the schedule in place).  `lds` = dynamic LDS bytes per workgroup.
+int launch_decode_plain(uint32_t quant, const KArgs& A, uint32_t lds, uint32_t grid,
+                        hipStream_t s);
+
+// Encoder, data generator and channel (gen.hip).
+int launch_encode(const DevPlan* dplan, const DevPlan& h, const uint32_t* d_data,
+                  uint32_t* d_code, uint32_t n_frames, hipStream_t s);
+int launch_gen_data(const DevPlan& h, uint64_t seed, uint64_t frame0, uint32_t n_frames,
+                    uint32_t* d_data, hipStream_t s);
+int launch_channel(const DevPlan& h, const uint32_t* d_code, uint32_t n_frames, float ebn0_db,
+                   int32_t frac_bits, uint64_t seed, uint64_t frame0, void* d_llr, hipStream_t s);
+
+}  // namespace polar

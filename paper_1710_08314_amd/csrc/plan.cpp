@@ -1,0 +1,269 @@
+// Host planner of the polar SCL decoder: everything that depends only on the
+// code and decoder parameters (Sec. III-A genericity, Sec. III-B flexibility),
+// computed once per plan and uploaded as a device blob.
+//
+//   * frozen set by the Bhattacharyya recursion (reading of Sec. II-A, which
+//     names reliability ordering without fixing a method or design point);
+//   * check that the systematic encoder of Sec. II-A gives x_A = b;
+//   * the pruned decoding tree (Sec. II-B3) as a pre-order node program;
+//   * CRC syndrome columns so that a path's CRC is checked straight from its
+//     codeword estimate, without first extracting the information bits
+//     (Sec. IV-B: packed words and precomputed sub-results);
+//   * the LDS footprint of one frame at each list size.
+#include "plan.h"
+
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+
+namespace polar {
+
+namespace {
+
+uint32_t ilog2(uint32_t x) {
+  uint32_t n = 0;
+  while ((1u << n) < x) ++n;
+  return n;
+}
+
+bool is_pow2(uint32_t x) { return x && !(x & (x - 1)); }
+
+// log Z of the "f" child: log(2Z - Z^2), computed as log Z + log(2 - Z) for
+// small Z and as log1p(-(1 - Z)^2) near Z = 1.
+double lz_minus(double lz) {
+  if (lz < -1.0) return lz + std::log(2.0 - std::exp(lz));
+  const double t = std::expm1(lz);
+  return std::log1p(-(t * t));
+}
+
+// Polar transform x = v F^{(x)n} on packed bits, in place (bw words hold N
+// bits).  Each butterfly stage XORs the second half of every block of size
+// 2s into its first half; the stages commute.
+void transform_words(std::vector<uint32_t>& w, uint32_t N) {
+  static const uint32_t kMask[5] = {0x55555555u, 0x33333333u, 0x0F0F0F0Fu, 0x00FF00FFu,
+                                    0x0000FFFFu};
+  for (uint32_t s = 1, k = 0; s < N && s < 32; s <<= 1, ++k)
+    for (auto& x : w) x ^= (x >> s) & kMask[k];
+  for (uint32_t S = 1; 32 * S < N; S <<= 1)
+    for (uint32_t i = 0; i < w.size(); ++i)
+      if (!(i & S)) w[i] ^= w[i + S];
+}
+
+inline bool bit(const std::vector<uint32_t>& w, uint32_t j) { return (w[j >> 5] >> (j & 31)) & 1u; }
+
+}  // namespace
+
+std::vector<double> bhattacharyya_log(uint32_t n, double lz0) {
+  const uint32_t N = 1u << n;
+  std::vector<double> out(N);
+  // breadth-first over the tree levels: level k holds 2^k values
+  std::vector<double> cur{lz0};
+  for (uint32_t k = 0; k < n; ++k) {
+    std::vector<double> nxt(cur.size() * 2);
+    for (size_t i = 0; i < cur.size(); ++i) {
+      nxt[2 * i] = lz_minus(cur[i]);      // next index bit 0
+      nxt[2 * i + 1] = 2.0 * cur[i];      // next index bit 1
+    }
+    cur.swap(nxt);
+  }
+  // cur[i] walks the index bits from the most significant: i is the index
+  for (uint32_t i = 0; i < N; ++i) out[i] = cur[i];
+  return out;
+}
+
+int make_plan(const polar_plan_desc& d, HostPlan& hp) {
+  if (d.N < 2 || d.N > kMaxN || !is_pow2(d.N)) return d.N > kMaxN && is_pow2(d.N) ? POLAR_EUNSUP : POLAR_EINVAL;
+  const uint32_t N = d.N, n = ilog2(N), S = d.n_shorten;
+  if (S >= N || d.K == 0 || d.K > N - S) return POLAR_EINVAL;
+  if (d.crc_len > 32) return POLAR_EUNSUP;
+  if (d.crc_len >= d.K) return POLAR_EINVAL;
+  if (d.quant > POLAR_I8 || d.algo > POLAR_FA_SCL) return POLAR_EINVAL;
+  uint32_t first = 1, maxl = 1;
+  switch (d.algo) {
+    case POLAR_SC: first = maxl = 1; break;
+    case POLAR_CA_SCL:
+      if (!is_pow2(d.L)) return POLAR_EINVAL;
+      if (d.L > kMaxL) return POLAR_EUNSUP;
+      first = maxl = d.L;
+      break;
+    default:
+      if (!is_pow2(d.L_max) || d.crc_len == 0) return POLAR_EINVAL;
+      if (d.L_max > kMaxL) return POLAR_EUNSUP;
+      first = 1;
+      maxl = d.L_max;
+      break;
+  }
+  const uint32_t bw = N >= 32 ? N / 32 : 1;
+
+  // ---- frozen set
+  std::vector<uint32_t> frozen(bw, 0);
+  if (d.frozen) {
+    for (uint32_t w = 0; w < bw; ++w) frozen[w] = d.frozen[w];
+    if (N < 32) frozen[0] &= (1u << N) - 1;
+    uint32_t na = 0;
+    for (uint32_t j = 0; j < N; ++j) na += bit(frozen, j) ? 0 : 1;
+    if (na != d.K) return POLAR_EINVAL;
+    for (uint32_t j = N - S; j < N; ++j)
+      if (!bit(frozen, j)) return POLAR_EINVAL;
+  } else {
+    const double rate = double(d.K - d.crc_len) / double(N - S);
+    const double lz0 = -rate * std::pow(10.0, double(d.design_ebn0_db) / 10.0);
+    std::vector<double> lz = bhattacharyya_log(n, lz0);
+    std::vector<uint32_t> idx(N - S);
+    std::iota(idx.begin(), idx.end(), 0u);
+    // most reliable first: smaller log Z, ties to the larger index
+    std::stable_sort(idx.begin(), idx.end(), [&](uint32_t a, uint32_t b) {
+      return lz[a] < lz[b] || (lz[a] == lz[b] && a > b);
+    });
+    for (uint32_t w = 0; w < bw; ++w) frozen[w] = ~0u;
+    if (N < 32) frozen[0] = (1u << N) - 1;
+    for (uint32_t k = 0; k < d.K; ++k) frozen[idx[k] >> 5] &= ~(1u << (idx[k] & 31));
+  }
+  std::vector<uint32_t> info(bw);
+  for (uint32_t w = 0; w < bw; ++w) info[w] = ~frozen[w];
+  if (N < 32) info[0] &= (1u << N) - 1;
+  std::vector<uint32_t> A;
+  for (uint32_t j = 0; j < N; ++j)
+    if (bit(info, j)) A.push_back(j);
+
+  // ---- systematic check: x_A = b for every unit vector b (linearity)
+  for (uint32_t k = 0; k < A.size(); ++k) {
+    std::vector<uint32_t> u(bw, 0);
+    u[A[k] >> 5] = 1u << (A[k] & 31);
+    transform_words(u, N);
+    for (uint32_t w = 0; w < bw; ++w) u[w] &= info[w];
+    transform_words(u, N);
+    for (uint32_t w = 0; w < bw; ++w) {
+      uint32_t want = (w == (A[k] >> 5)) ? (1u << (A[k] & 31)) : 0u;
+      if ((u[w] & info[w]) != want) return POLAR_ENOTSYS;
+    }
+  }
+
+  // ---- pruned tree -> node program (Sec. II-B3; precedence R0, R1, REP, SPC)
+  hp.prog.clear();
+  hp.counts = {};
+  auto fits = [](uint32_t lim, uint32_t m) { return lim == 0 || m <= lim; };
+  auto nfrozen = [&](uint32_t s, uint32_t m) {
+    uint32_t c = 0;
+    for (uint32_t j = s; j < s + m; ++j) c += bit(frozen, j) ? 1 : 0;
+    return c;
+  };
+  struct Emit {
+    static void go(HostPlan& hp, const polar_plan_desc& d, const std::vector<uint32_t>& fz,
+                   uint32_t s, uint32_t m, uint32_t dep,
+                   const decltype(fits)& fits, const decltype(nfrozen)& nfrozen) {
+      if (m == 1) {
+        bool f = (fz[s >> 5] >> (s & 31)) & 1u;
+        hp.prog.push_back(op_make(f ? OP_LF : OP_LI, dep, s));
+        (f ? hp.counts.leaf_f : hp.counts.leaf_i)++;
+        return;
+      }
+      const uint32_t nf = nfrozen(s, m);
+      const bool last_info = !((fz[(s + m - 1) >> 5] >> ((s + m - 1) & 31)) & 1u);
+      const bool first_frozen = (fz[s >> 5] >> (s & 31)) & 1u;
+      const uint32_t en = d.node_enable;
+      uint32_t op = 0xFF;
+      if ((en & POLAR_NODE_R0) && nf == m && fits(d.r0_max, m)) {
+        op = OP_R0;
+        hp.counts.r0++;
+      } else if ((en & POLAR_NODE_R1) && nf == 0 && fits(d.r1_max, m)) {
+        op = OP_R1;
+        hp.counts.r1++;
+      } else if ((en & POLAR_NODE_REP) && nf == m - 1 && last_info && fits(d.rep_max, m)) {
+        op = OP_REP;
+        hp.counts.rep++;
+      } else if ((en & POLAR_NODE_SPC) && m >= 4 && nf == 1 && first_frozen && fits(d.spc_max, m)) {
+        op = OP_SPC;
+        hp.counts.spc++;
+      }
+      if (op != 0xFF) {
+        hp.prog.push_back(op_make(op, dep, s));
+        return;
+      }
+      hp.prog.push_back(op_make(OP_F, dep, s));
+      go(hp, d, fz, s, m / 2, dep + 1, fits, nfrozen);
+      hp.prog.push_back(op_make(OP_G, dep, s));
+      go(hp, d, fz, s + m / 2, m / 2, dep + 1, fits, nfrozen);
+      hp.prog.push_back(op_make(OP_H, dep, s));
+    }
+  };
+  Emit::go(hp, d, frozen, 0, N, 0, fits, nfrozen);
+
+  // ---- CRC syndrome columns.  CRC(data) is the remainder of data(x) x^c
+  // by g(x) (MSB first, init 0, no final xor), linear in the data bits: data
+  // bit t contributes x^(k_data - 1 - t + c) mod g; a CRC bit contributes its
+  // own unit.  A path passes iff the XOR of the columns of its 1 bits is 0.
+  const uint32_t c = d.crc_len, kd = d.K - c;
+  const uint32_t cmask = c == 32 ? ~0u : ((1u << c) - 1u);
+  const uint32_t poly = uint32_t(d.crc_poly) & cmask;
+  std::vector<uint32_t> crccol(N, 0);
+  if (c > 0) {
+    uint32_t r = poly;  // x^c mod g
+    for (int t = int(kd) - 1; t >= 0; --t) {
+      crccol[A[t]] = r;
+      const bool top = (r >> (c - 1)) & 1u;
+      r = (r << 1) & cmask;
+      if (top) r ^= poly;
+    }
+    for (uint32_t t = 0; t < c; ++t) crccol[A[kd + t]] = 1u << (c - 1 - t);
+  }
+  std::vector<uint32_t> datamask(bw, 0), prefix(bw, 0);
+  for (uint32_t t = 0; t < kd; ++t) datamask[A[t] >> 5] |= 1u << (A[t] & 31);
+  for (uint32_t w = 1; w < bw; ++w) prefix[w] = prefix[w - 1] + __builtin_popcount(datamask[w - 1]);
+
+  // ---- header + blob
+  const uint32_t E = elem_bytes(d.quant), KB = key_bytes(d.quant);
+  const LdsLayout lay = lds_layout(N, n, E, maxl, KB);
+  if (lay.total > kLdsLimit) return POLAR_EUNSUP;
+
+  DevPlan h{};
+  h.N = N;
+  h.n = n;
+  h.K = d.K;
+  h.c = c;
+  h.n_tx = N - S;
+  h.k_data = kd;
+  h.quant = d.quant;
+  h.algo = d.algo;
+  h.L = d.algo == POLAR_CA_SCL ? d.L : 1;
+  h.L_max = maxl;
+  h.n_ops = uint32_t(hp.prog.size());
+  h.bw = bw;
+  h.info_words = (kd + 31) / 32;
+  h.code_words = (N + 31) / 32;
+  h.max_list = maxl;
+  h.lds_max = lay.total;
+  h.first_stage = first;
+  uint32_t off = sizeof(DevPlan) / 4;
+  h.off_prog = off;
+  off += h.n_ops;
+  h.off_infomask = off;
+  off += bw;
+  h.off_datamask = off;
+  off += bw;
+  h.off_dataprefix = off;
+  off += bw;
+  h.off_crccol = off;
+  off += N;
+  h.off_crcpos = off;
+  off += std::max(c, 1u);
+  hp.blob.assign(off, 0);
+  std::copy_n(reinterpret_cast<const uint32_t*>(&h), sizeof(DevPlan) / 4, hp.blob.begin());
+  std::copy(hp.prog.begin(), hp.prog.end(), hp.blob.begin() + h.off_prog);
+  std::copy(info.begin(), info.end(), hp.blob.begin() + h.off_infomask);
+  std::copy(datamask.begin(), datamask.end(), hp.blob.begin() + h.off_datamask);
+  std::copy(prefix.begin(), prefix.end(), hp.blob.begin() + h.off_dataprefix);
+  std::copy(crccol.begin(), crccol.end(), hp.blob.begin() + h.off_crccol);
+  for (uint32_t t = 0; t < c; ++t) hp.blob[h.off_crcpos + t] = A[kd + t];
+  hp.hdr = h;
+  hp.frozen = frozen;
+  hp.desc = d;
+  hp.desc.frozen = nullptr;
+  return POLAR_OK;
+}
+
+uint32_t plan_lds_bytes(const DevPlan& h, uint32_t L) {
+  return lds_layout(h.N, h.n, elem_bytes(h.quant), L, key_bytes(h.quant)).total;
+}
+
+}  // namespace polar

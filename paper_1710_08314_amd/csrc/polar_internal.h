@@ -1,0 +1,142 @@
+// Internal layout shared by the host planner and the gfx950 kernels of the
+// polar SCL decoder: the device plan blob, the node-program encoding and the
+// per-frame LDS layout.  Not part of the public C ABI.
+#pragma once
+
+#include <cstdint>
+
+#if defined(__HIPCC__)
+#define POLAR_HD __host__ __device__
+#else
+#define POLAR_HD
+#endif
+
+namespace polar {
+
+constexpr uint32_t kMaxN = 2048;
+constexpr uint32_t kMaxLogN = 11;
+constexpr uint32_t kMaxL = 32;
+constexpr uint32_t kLdsLimit = 160 * 1024;  // LDS of one gfx950 compute unit
+
+// ---------------------------------------------------------------------------
+// Node program: the pre-order walk of the pruned decoding tree (Algorithm 1
+// with the dedicated nodes of Sec. II-B3), one 32-bit word per step:
+//   bits 0..3   opcode
+//   bits 4..7   depth d of the node (node size m = N >> d)
+//   bits 8..23  first leaf (u-index) of the node = partial-sum bit offset
+// F/G read the node's LLRs at depth d and write its child's at depth d + 1;
+// H combines the children's partial sums in place; the node ops read the
+// node's LLRs at depth d, update path metrics, fork paths, and write the
+// node's partial sums.
+// ---------------------------------------------------------------------------
+enum Op : uint32_t {
+  OP_F = 0,
+  OP_G = 1,
+  OP_H = 2,
+  OP_R0 = 3,
+  OP_R1 = 4,
+  OP_REP = 5,
+  OP_SPC = 6,
+  OP_LF = 7,  // frozen leaf
+  OP_LI = 8,  // information leaf
+};
+
+POLAR_HD inline uint32_t op_make(uint32_t op, uint32_t d, uint32_t o) {
+  return (op & 15u) | ((d & 15u) << 4) | ((o & 0xFFFFu) << 8);
+}
+POLAR_HD inline uint32_t op_code(uint32_t w) { return w & 15u; }
+POLAR_HD inline uint32_t op_depth(uint32_t w) { return (w >> 4) & 15u; }
+POLAR_HD inline uint32_t op_off(uint32_t w) { return (w >> 8) & 0xFFFFu; }
+
+// ---------------------------------------------------------------------------
+// Device plan blob: a header followed by tables, all 32-bit words, offsets
+// in words from the blob start.
+// ---------------------------------------------------------------------------
+struct DevPlan {
+  uint32_t N, n, K, c;                // code length, log2 N, |A|, CRC length
+  uint32_t n_tx, k_data, quant, algo;  // sent positions, K - c, polar_quant, polar_algo
+  uint32_t L, L_max, n_ops, bw;       // list sizes, program length, bit words per path
+  uint32_t info_words, code_words, max_list, lds_max;
+  uint32_t off_prog;      // n_ops program words
+  uint32_t off_infomask;  // bw words: positions in A
+  uint32_t off_datamask;  // bw words: the first K - c positions of A
+  uint32_t off_dataprefix;  // bw words: data positions before word w
+  uint32_t off_crccol;    // N words: CRC syndrome column of codeword position j
+  uint32_t off_crcpos;    // c words: codeword positions of the CRC bits
+  uint32_t first_stage;   // list size of the first stage of the schedule
+  uint32_t pad[9];
+};
+static_assert(sizeof(DevPlan) == 32 * 4, "DevPlan header is 32 words");
+
+POLAR_HD inline const uint32_t* plan_tab(const DevPlan* p, uint32_t off) {
+  return reinterpret_cast<const uint32_t*>(p) + off;
+}
+
+// ---------------------------------------------------------------------------
+// LDS layout of one frame at list size L (element size E bytes, path-metric
+// key size KB bytes).  Byte offsets; every region 16-byte aligned.
+//   root    N LLRs (channel; shared by every path, never written by f/g)
+//   stage d (1..n): L slots of max(N >> d, 1) LLRs, slot padded to 4 bytes;
+//           the path of rank r reads depth-d LLRs from slot ptr[d][r] and
+//           writes depth d + 1 to its own slot r (index indirection)
+//   bits    L x bw words of partial sums, statically owned by rank (copied
+//           on fork)
+//   ptr     12 x 32 bytes: slot of each (depth, rank)
+//   pm      32 path metrics
+//   cand    8 L candidate keys;  sel: L sorted keys
+//   cpos    L x 4 least-reliable positions (u16) of the current node
+//   tabs    12 stage bases + 12 slot strides
+//   syn, ord, out, misc
+// ---------------------------------------------------------------------------
+struct LdsLayout {
+  uint32_t root, stages, bits, ptr, pm, cand, sel, cpos, tabs, syn, ord, out, misc, total;
+};
+
+POLAR_HD inline uint32_t ru16(uint32_t x) { return (x + 15u) & ~15u; }
+POLAR_HD inline uint32_t ru4(uint32_t x) { return (x + 3u) & ~3u; }
+
+POLAR_HD inline uint32_t slot_bytes(uint32_t N, uint32_t d, uint32_t E) {
+  uint32_t m = N >> d;
+  if (m < 1) m = 1;
+  return ru4(m * E);
+}
+
+POLAR_HD inline LdsLayout lds_layout(uint32_t N, uint32_t n, uint32_t E, uint32_t L, uint32_t KB) {
+  LdsLayout l{};
+  uint32_t cur = 0;
+  l.root = cur;
+  cur += ru16(N * E);
+  l.stages = cur;
+  for (uint32_t d = 1; d <= n; ++d) cur += L * slot_bytes(N, d, E);
+  cur = ru16(cur);
+  const uint32_t bw = N >= 32 ? N / 32 : 1;
+  l.bits = cur;
+  cur += ru16(L * bw * 4);
+  l.ptr = cur;
+  cur += 12 * 32;
+  l.pm = cur;
+  cur += 32 * 4;
+  l.cand = cur;
+  cur += ru16(8 * L * KB);
+  l.sel = cur;
+  cur += ru16(L * KB);
+  l.cpos = cur;
+  cur += ru16(L * 4 * 2);
+  l.tabs = cur;
+  cur += 24 * 4;
+  l.syn = cur;
+  cur += 32 * 4;
+  l.ord = cur;
+  cur += 32 * 4;
+  l.out = cur;
+  cur += 64 * 4;
+  l.misc = cur;
+  cur += 16 * 4;
+  l.total = ru16(cur);
+  return l;
+}
+
+POLAR_HD inline uint32_t elem_bytes(uint32_t quant) { return quant == 0 ? 4u : (quant == 1 ? 2u : 1u); }
+POLAR_HD inline uint32_t key_bytes(uint32_t quant) { return quant == 0 ? 8u : 4u; }
+
+}  // namespace polar

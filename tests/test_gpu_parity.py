@@ -1,0 +1,227 @@
+"""GPU parity: the HIP decoder against the CPU oracle, element by element, on
+the same oracle-made LLR buffers (bit-exact in int8/int16; float32 metrics
+within 1e-4 relative and bits equal except oracle-flagged near-ties).
+
+Sizes span several LDS tiles and ragged shapes (shortened lengths, odd byte
+counts) and cover the degenerate cases of the method (N = 2, rate 1, one
+information bit, no CRC, L = 1, SC, every node type on and off)."""
+import itertools
+
+import numpy as np
+import pytest
+
+import oracle as O
+from tests.gpu_util import compare, gpu_decode, gpu_plan, make_inputs, oracle_code
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _cuda():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _code(N, K, c, poly, design, S=0, **kw):
+    fz = O.construct(N, K, S, c, design)
+    return oracle_code(N, K, c, poly, fz, S=S, **kw)
+
+
+# ---------------------------------------------------------------- workloads
+def test_ca_scl_n256_l4_f32_seed0():
+    """The small workload: (256, 120 + CRC-8), Bhattacharyya at 2.0 dB,
+    CA-SCL L = 4, float32 LLR = 2y/sigma^2 at 2.5 dB, 1000 frames, seed 0."""
+    code = _code(256, 128, 8, 0x07, 2.0, quant="f32", algo="ca", L=4)
+    bits, llr = make_inputs(code, 1000, 0, 2.5)
+    rep = compare(code, llr)
+    print("c1", rep)
+
+
+@pytest.mark.parametrize("quant", ["i16", "i8"])
+def test_ca_scl_n256_l4_int(quant):
+    code = _code(256, 128, 8, 0x07, 2.0, quant=quant, algo="ca", L=4)
+    _, llr = make_inputs(code, 600, 1, 2.0)
+    compare(code, llr)
+
+
+@pytest.mark.parametrize("quant", ["f32", "i16", "i8"])
+def test_quant_sweep_n1024_l8(quant):
+    """(1024, 488 + CRC-24), L = 8, design 2.5 dB; two channel points."""
+    code = _code(1024, 512, 24, 0x1864CFB, 2.5, quant=quant, algo="ca", L=8)
+    for pt, eb in enumerate((1.5, 3.0)):
+        _, llr = make_inputs(code, 120, 5000 + pt, eb)
+        compare(code, llr)
+
+
+@pytest.mark.parametrize("ebn0", [3.5, 4.5])
+def test_fa_n2048_k1723_i8(ebn0):
+    """The headline code: (2048, 1691 + CRC-32), FA-SSCL L = 1 -> 32, int8
+    with REP8- and SPC4."""
+    code = _code(2048, 1723, 32, 0x04C11DB7, 4.5, quant="i8", algo="fa", L_max=32)
+    _, llr = make_inputs(code, 150, 2000 + int(ebn0 * 10), ebn0)
+    rep = compare(code, llr)
+    print("fa2048", ebn0, rep)
+
+
+@pytest.mark.parametrize("quant", ["f32", "i16"])
+def test_fa_n2048_k1723_other_quants(quant):
+    code = _code(2048, 1723, 32, 0x04C11DB7, 4.5, quant=quant, algo="fa",
+                 L_max=16 if quant == "f32" else 32)
+    _, llr = make_inputs(code, 60, 2100, 3.5)
+    compare(code, llr)
+
+
+@pytest.mark.parametrize("algo,L,Lmax", [("fa", 1, 8), ("pa", 1, 8), ("sc", 1, 1)])
+@pytest.mark.parametrize("quant", ["f32", "i8"])
+def test_adaptive_and_sc(algo, L, Lmax, quant):
+    code = _code(256, 128, 8, 0x07, 2.0, quant=quant, algo=algo, L=L, L_max=Lmax)
+    _, llr = make_inputs(code, 300, 7, 1.5)
+    rep = compare(code, llr)
+    if algo != "sc":
+        assert rep["escalated"] > 0
+
+
+def test_shortened_i16_crc11():
+    for (N, K, S) in [(512, 150, 77), (128, 40, 31), (2048, 900, 500), (256, 60, 1)]:
+        code = _code(N, K, 11, 0x621, 2.5, S=S, quant="i16", algo="ca", L=8)
+        _, llr = make_inputs(code, 40, N + S, 2.0)
+        compare(code, llr)
+
+
+# ------------------------------------------------------------- edge cases
+@pytest.mark.parametrize("N", [2, 4, 8, 16, 32, 64, 128])
+@pytest.mark.parametrize("quant", ["f32", "i16", "i8"])
+def test_small_codes_all_list_sizes(N, quant):
+    rng = np.random.default_rng(N)
+    for K in sorted({1, max(1, N // 4), N // 2, N - 1, N}):
+        fz = O.construct(N, K, 0, 0, 1.0)
+        for L in (1, 2, 8, 32):
+            code = oracle_code(N, K, 0, 0, fz, quant=quant, algo="ca", L=L)
+            llr = rng.normal(0.5, 2.0, (24, N)) * (4 if quant != "f32" else 1)
+            if quant != "f32":
+                llr = np.clip(np.round(llr), -127, 127)
+            compare(code, llr.astype(O.DTYPES[code.quant]))
+
+
+@pytest.mark.parametrize("node_enable,spc_max,rep_max", [
+    (0, 4, 0), (O.NODE_R0, 4, 0), (O.NODE_R1, 4, 0), (O.NODE_REP, 4, 0), (O.NODE_SPC, 4, 0),
+    (O.NODE_ALL, 0, 0), (O.NODE_ALL, 4, 8), (O.NODE_ALL, 16, 2)])
+@pytest.mark.parametrize("quant", ["f32", "i8"])
+def test_pruning_variants(node_enable, spc_max, rep_max, quant):
+    code = _code(512, 256, 11, 0x621, 2.0, quant=quant, algo="ca", L=4,
+                 node_enable=node_enable, spc_max=spc_max, rep_max=rep_max)
+    _, llr = make_inputs(code, 60, node_enable * 7 + spc_max, 1.8)
+    compare(code, llr)
+
+
+def test_saturating_int8_inputs():
+    # every LLR at the rails: exercises saturation in g and in the metrics
+    code = _code(256, 128, 8, 0x07, 2.0, quant="i8", algo="ca", L=8)
+    rng = np.random.default_rng(3)
+    llr = rng.choice(np.array([-127, 127, -126, 126, 0], dtype=np.int8), (80, 256))
+    compare(code, llr)
+
+
+def test_all_zero_llrs_ties():
+    # every candidate ties: results decided by the key order alone
+    for quant in ("f32", "i16", "i8"):
+        code = _code(128, 64, 8, 0x07, 2.0, quant=quant, algo="ca", L=8)
+        llr = np.zeros((4, 128), dtype=O.DTYPES[code.quant])
+        compare(code, llr)
+
+
+def test_no_crc_list_decoding():
+    code = _code(256, 100, 0, 0, 1.0, quant="f32", algo="ca", L=16)
+    _, llr = make_inputs(code, 80, 9, 1.0)
+    compare(code, llr)
+
+
+def test_mixed_lengths_in_one_batch():
+    """Several plans (different N, K, L) in one batch through frame
+    descriptors; each frame must equal its own oracle decode."""
+    import torch
+    from paper_1710_08314_amd import polar as P
+
+    specs = [(128, 64, 2), (256, 128, 8), (512, 200, 32), (2048, 1000, 8), (64, 20, 1)]
+    codes, plans, llrs, refs = [], [], [], []
+    for i, (N, K, L) in enumerate(specs):
+        code = _code(N, K, 11, 0x621, 2.5, quant="i16", algo="ca", L=L)
+        _, llr = make_inputs(code, 10, 300 + i, 2.0)
+        codes.append(code)
+        plans.append(gpu_plan(code))
+        llrs.append(llr)
+        refs.append(O.decode(code, llr))
+    # interleave frames of all plans
+    order = [(i, f) for f in range(10) for i in range(len(specs))]
+    buf, desc, off, out = [], [], 0, 0
+    for i, f in order:
+        b = llrs[i][f].tobytes()
+        pad = (-off) % 16
+        buf.append(b"\0" * pad)
+        off += pad
+        desc.append((off, out, i))
+        buf.append(b)
+        off += len(b)
+        out += plans[i].info.info_words
+    raw = np.frombuffer(b"".join(buf), dtype=np.uint8)
+    fr = np.zeros((len(desc), 4), dtype=np.int64)
+    fr32 = np.zeros((len(desc), 4), dtype=np.uint32)
+    for k, (lo, oo, pi) in enumerate(desc):
+        fr32[k] = (lo & 0xFFFFFFFF, lo >> 32, oo, pi)
+    d_llr = torch.from_numpy(raw.copy()).cuda()
+    d_fr = torch.from_numpy(fr32.view(np.int32)).cuda()
+    info, status, pml = P.decode_batch(plans, d_llr, frames=d_fr, with_pm_lists=True)
+    torch.cuda.synchronize()
+    info = info.cpu().numpy().view(np.uint32)
+    st = P.status_fields(status.cpu().numpy())
+    for k, (i, f) in enumerate(order):
+        oo = desc[k][1]
+        w = info[oo:oo + plans[i].info.info_words]
+        assert np.array_equal(P.unpack_bits(w, codes[i].k_data), refs[i].info[f])
+        assert st["crc_ok"][k] == refs[i].crc_ok[f]
+        assert st["pm_bits"][k].view(np.int32) == int(refs[i].pm[f])
+
+
+# -------------------------------------------------------------- encoder
+@pytest.mark.parametrize("N,K,c,poly,S", [(256, 128, 8, 0x07, 0), (2048, 1723, 32, 0x04C11DB7, 0),
+                                          (1024, 512, 24, 0x1864CFB, 0), (512, 150, 11, 0x621, 77),
+                                          (2, 1, 0, 0, 0), (32, 20, 11, 0x621, 3)])
+def test_encoder_matches_oracle(N, K, c, poly, S):
+    import torch
+    from paper_1710_08314_amd import polar as P
+
+    code = _code(N, K, c, poly, 2.0, S=S)
+    plan = gpu_plan(code)
+    rng = np.random.default_rng(N + K)
+    data = rng.integers(0, 2, (64, K - c), dtype=np.uint8)
+    d = torch.from_numpy(P.pack_bits(data).view(np.int32)).cuda()
+    x = P.encode(plan, d).cpu().numpy().view(np.uint32)
+    xb = P.unpack_bits(x, N)
+    for f in range(64):
+        assert np.array_equal(xb[f], O.encode(code.frozen, O.attach_crc(data[f], c, poly)))
+
+
+def test_generator_is_counter_based():
+    from paper_1710_08314_amd import polar as P
+
+    code = _code(256, 128, 8, 0x07, 2.0, quant="i8")
+    plan = gpu_plan(code)
+    a = P.gen_data(plan, 5, 0, 100).cpu().numpy()
+    b = P.gen_data(plan, 5, 40, 30).cpu().numpy()
+    assert np.array_equal(a[40:70], b)
+    bits = P.unpack_bits(a.view(np.uint32), 120)
+    assert abs(bits.mean() - 0.5) < 0.02
+    assert (P.unpack_bits(a.view(np.uint32), 128)[:, 120:] == 0).all()
+    code_w = P.encode(plan, P.gen_data(plan, 5, 0, 2000))
+    l1 = P.channel(plan, code_w, 2.5, 11, 0).cpu().numpy().astype(np.float64)
+    l2 = P.channel(plan, code_w, 2.5, 11, 0).cpu().numpy().astype(np.float64)
+    assert np.array_equal(l1, l2)
+    x = P.unpack_bits(code_w.cpu().numpy().view(np.uint32), 256)
+    s = 1 - 2 * x.astype(np.float64)
+    # LLR/4 = (2/sigma^2) y: mean 2/sigma^2 * s; variance 4/sigma^2
+    from paper_1710_08314_amd import synth
+    sig = synth.sigma_for(2.5, 120, 256)
+    z = (l1 / 4) * s
+    assert abs(z.mean() - 2 / sig ** 2) < 0.05 * 2 / sig ** 2
