@@ -145,9 +145,13 @@ typedef struct {
 
 /* Optional knobs; NULL selects defaults. */
 typedef struct {
-  uint32_t schedule;   /* 0 = automatic (tiered: SC tier + device escalation queue
-                        * + list tier), 1 = plain (one generic launch)             */
-  uint32_t reserved[7];
+  uint32_t schedule;   /* 0 = automatic, 1 = plain (one generic launch in which each
+                        * workgroup runs whole frames, every stage in place)      */
+  uint32_t flags;      /* reserved, 0                                             */
+  uint64_t *d_times;   /* nullable device array, 2 per frame: the device realtime
+                        * counter (polar_device_clock_khz) when the frame's decode
+                        * starts and when its outputs are written                 */
+  uint32_t reserved[4];
 } polar_decode_opts;
 
 /* Decode a batch (the hot path, Algorithm 1 and Sec. II-B3..B5).
@@ -198,7 +202,22 @@ int polar_gen_data(polar_plan p, uint64_t seed, uint64_t frame0, uint32_t n_fram
 int polar_channel(polar_plan p, const uint32_t *d_code, uint32_t n_frames, float ebn0_db,
                   int32_t frac_bits, uint64_t seed, uint64_t frame0, void *d_llr, void *stream);
 
+/* Algorithmic work of one decoding stage of plan p at list size L, counted
+ * from the node program and the deterministic growth of the active list
+ * (a <- min(L, a * candidates) at every forking node): f and g LLR updates
+ * (m/2 per path per node), h partial-sum updates (m/2 per path), node-level
+ * penalty terms (m per path per dedicated node or leaf), candidate sorting
+ * (C ceil(log2 C) comparisons for C candidates) and the final CRC checks
+ * (|A| bits per surviving path).  *ops receives the element-operation count
+ * (host only; no device work).  POLAR_EINVAL for L not a power of two or
+ * above 32. */
+int polar_plan_stage_work(polar_plan p, uint32_t L, uint64_t *ops);
+
 /* --------------------------------------------------------------- misc */
+/* Frequency of the device realtime counter used by d_times, in kHz, for the
+ * current device. */
+int polar_device_clock_khz(uint32_t *khz);
+
 const char *polar_strerror(int err);
 
 /* Library version string. */

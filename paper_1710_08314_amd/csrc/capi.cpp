@@ -22,6 +22,41 @@ struct polar_plan_s {
 namespace {
 
 std::mutex g_mu;
+// per-device escalation queue of the tiered schedule (grown on demand)
+struct Scratch {
+  uint32_t* q = nullptr;
+  size_t cap = 0;  // frame slots
+  int cus = 0;
+};
+std::map<int, Scratch> g_scratch;
+
+int device_scratch(size_t frames, uint32_t** q, int* cus) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return POLAR_EHIP;
+  std::lock_guard<std::mutex> lk(g_mu);
+  Scratch& sc = g_scratch[dev];
+  if (sc.cus == 0) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      return POLAR_EHIP;
+    sc.cus = v > 0 ? v : 1;
+  }
+  if (sc.cap < frames) {
+    if (sc.q) {
+      // the previous queue may still be in use by work queued on any stream
+      if (hipDeviceSynchronize() != hipSuccess) return POLAR_EHIP;
+      (void)hipFree(sc.q);
+      sc.q = nullptr;
+      sc.cap = 0;
+    }
+    const size_t want = frames < 4096 ? 4096 : frames;
+    if (hipMalloc(&sc.q, (want + 2) * sizeof(uint32_t)) != hipSuccess) return POLAR_ENOMEM;
+    sc.cap = want;
+  }
+  *q = sc.q;
+  *cus = sc.cus;
+  return POLAR_OK;
+}
 // device plan tables of multi-plan batches, keyed by the plan list
 std::map<std::vector<polar_plan>, const polar::DevPlan**> g_tables;
 
@@ -177,7 +212,6 @@ int polar_scl_decode_batch(const polar_plan* plans, uint32_t n_plans, const pola
     lds = h.lds_max > lds ? h.lds_max : lds;
     pm_stride = h.max_list > pm_stride ? h.max_list : pm_stride;
   }
-  (void)opts;
   int rc = POLAR_OK;
   polar::KArgs A{};
   A.plans = plan_table(plans, n_plans, &rc);
@@ -191,8 +225,35 @@ int polar_scl_decode_batch(const polar_plan* plans, uint32_t n_plans, const pola
   A.status = d_status;
   A.pm_lists = d_pm_lists;
   A.pm_stride = pm_stride;
+  A.times = opts ? opts->d_times : nullptr;
   const uint32_t grid = n_frames < 0x7FFFFFFFu ? n_frames : 0x7FFFFFFFu;
-  return polar::launch_decode_plain(quant, A, lds, grid, static_cast<hipStream_t>(stream));
+  const hipStream_t st = static_cast<hipStream_t>(stream);
+  const uint32_t schedule = opts ? opts->schedule : 0;
+  if (schedule == 1) return polar::launch_decode_plain(quant, A, lds, grid, st);
+  if (schedule != 0) return POLAR_EINVAL;
+  // tiered: SC tier if any plan starts at L = 1; list tier if any frame can
+  // need a list (a plan whose largest list exceeds 1)
+  polar::TierPlan tp{};
+  uint32_t lds_sc = 0;
+  for (uint32_t i = 0; i < n_plans; ++i) {
+    const polar::DevPlan& h = plans[i]->hp.hdr;
+    if (h.first_stage == 1) tp.run_sc = true;
+    if (h.max_list > 1) tp.run_list = true;
+    const uint32_t l1 = polar::plan_lds_bytes(h, 1);
+    lds_sc = l1 > lds_sc ? l1 : lds_sc;
+  }
+  uint32_t* q = nullptr;
+  int cus = 1;
+  rc = device_scratch(n_frames, &q, &cus);
+  if (rc) return rc;
+  tp.lds_sc = lds_sc;
+  tp.lds_list = lds;
+  tp.grid_sc = grid;
+  uint32_t per_cu = polar::kLdsLimit / (lds ? lds : 1);
+  per_cu = per_cu < 1 ? 1 : (per_cu > 4 ? 4 : per_cu);
+  const uint64_t gl = (uint64_t)cus * per_cu;
+  tp.grid_list = (uint32_t)(gl < n_frames ? gl : n_frames);
+  return polar::launch_decode_tiered(quant, A, tp, q, st);
 }
 
 int polar_encode(polar_plan p, const uint32_t* d_data, uint32_t* d_code, uint32_t n_frames,
@@ -215,6 +276,22 @@ int polar_channel(polar_plan p, const uint32_t* d_code, uint32_t n_frames, float
   if (frac_bits < 0 || frac_bits > 14) return POLAR_EINVAL;
   return polar::launch_channel(p->hp.hdr, d_code, n_frames, ebn0_db, frac_bits, seed, frame0,
                                d_llr, static_cast<hipStream_t>(stream));
+}
+
+int polar_plan_stage_work(polar_plan p, uint32_t L, uint64_t* ops) {
+  if (!p || !ops || L == 0 || L > polar::kMaxL || (L & (L - 1))) return POLAR_EINVAL;
+  *ops = polar::stage_work(p->hp, L);
+  return POLAR_OK;
+}
+
+int polar_device_clock_khz(uint32_t* khz) {
+  if (!khz) return POLAR_EINVAL;
+  int dev = 0, v = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return POLAR_EHIP;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeWallClockRate, dev) != hipSuccess)
+    return POLAR_EHIP;
+  *khz = (uint32_t)v;
+  return POLAR_OK;
 }
 
 const char* polar_strerror(int err) {

@@ -320,10 +320,36 @@ __device__ void sort_keys_kpl(const K* src, uint32_t cnt, K* dst, uint32_t keep)
     if (e < keep) dst[e] = k[t];
   }
 }
+// Up to 64 keys: a bitonic network over the first P = 2^ceil(log2 cnt) lanes
+// only (the network on an aligned power-of-two block is self-contained);
+// when a single survivor is kept, a min-reduction instead.
+template <typename K>
+__device__ void sort_keys_small(const K* src, uint32_t cnt, K* dst, uint32_t keep) {
+  const uint32_t lane = threadIdx.x & 63u;
+  uint32_t P = 1;
+  while (P < cnt) P <<= 1;
+  K k = lane < cnt ? src[lane] : (K)~(K)0;
+  if (keep == 1) {
+    for (uint32_t st = 1; st < P; st <<= 1) {
+      const K o = shfl_xor_k(k, (int)st);
+      k = o < k ? o : k;
+    }
+    if (lane == 0) dst[0] = k;
+    return;
+  }
+  for (uint32_t size = 2; size <= P; size <<= 1) {
+    for (uint32_t st = size >> 1; st > 0; st >>= 1) {
+      const K o = shfl_xor_k(k, (int)st);
+      const bool keep_min = ((lane & st) == 0) == ((lane & size) == 0);
+      k = keep_min ? (o < k ? o : k) : (o > k ? o : k);
+    }
+  }
+  if (lane < keep) dst[lane] = k;
+}
 template <typename K>
 __device__ void sort_keys(const K* src, uint32_t cnt, K* dst, uint32_t keep) {
   if (cnt <= 64)
-    sort_keys_kpl<K, 1>(src, cnt, dst, keep);
+    sort_keys_small<K>(src, cnt, dst, keep);
   else if (cnt <= 128)
     sort_keys_kpl<K, 2>(src, cnt, dst, keep);
   else
@@ -767,10 +793,13 @@ __device__ void setup_stage(Ctx& c, uint32_t L) {
 }
 
 // Decode frame f: run the plan's list-size schedule (Sec. II-B5) from
-// `L_first`, write bits, status and (optionally) the metric list.
+// `L_first`.  A frame whose stage at list size >= L_stop fails the CRC while
+// a larger stage remains is left for the list tier: returns false and writes
+// nothing.  Otherwise writes bits, status, the metric list and the end stamp.
 template <typename T, int NT>
-__device__ void decode_frame(char* smem, const KArgs& A, uint32_t f, const DevPlan* P,
-                             const char* llr, uint32_t out_off, uint32_t L_first) {
+__device__ bool decode_frame(char* smem, const KArgs& A, uint32_t f, const DevPlan* P,
+                             const char* llr, uint32_t out_off, uint32_t L_first,
+                             uint32_t L_stop) {
   using Acc = typename VT<T>::Acc;
   Ctx c;
   c.smem = smem;
@@ -790,6 +819,7 @@ __device__ void decode_frame(char* smem, const KArgs& A, uint32_t f, const DevPl
     run_program<T, NT>(c, a);
     chosen = end_of_stage<T, NT>(c, a, &ok);
     if (ok || L >= P->L_max) break;
+    if (L >= L_stop) return false;
     L = (P->algo == POLAR_PA_SCL) ? P->L_max : 2 * L;
   }
   // ---- outputs
@@ -832,6 +862,7 @@ __device__ void decode_frame(char* smem, const KArgs& A, uint32_t f, const DevPl
     else
       st.pm = __float_as_uint(v);
     A.status[f] = st;
+    if (A.times) A.times[2 * (size_t)f + 1] = wall_clock64();
   }
   if (A.pm_lists) {
     const uint32_t* ord = reinterpret_cast<const uint32_t*>(c.smem + c.lay.ord);
@@ -849,8 +880,25 @@ __device__ void decode_frame(char* smem, const KArgs& A, uint32_t f, const DevPl
     }
   }
   __syncthreads();
+  return true;
 }
 
+__device__ __forceinline__ void frame_of(const KArgs& A, uint32_t f, const DevPlan*& P,
+                                         const char*& llr, uint32_t& out_off) {
+  if (A.frames) {
+    const polar_frame fr = A.frames[f];
+    P = A.plans[fr.plan_idx];
+    llr = A.llr + fr.llr_off;
+    out_off = fr.out_off;
+  } else {
+    P = A.plans[0];
+    llr = A.llr + (size_t)f * A.llr_bytes;
+    out_off = f * A.info_words;
+  }
+}
+
+// Plain schedule: each workgroup runs whole frames, every stage in place,
+// with LDS sized for the largest list.
 template <typename T, int NW>
 __global__ __launch_bounds__(NW * 64) void k_decode_plain(KArgs A) {
   extern __shared__ __attribute__((aligned(16))) char smem[];
@@ -858,27 +906,77 @@ __global__ __launch_bounds__(NW * 64) void k_decode_plain(KArgs A) {
     const DevPlan* P;
     const char* llr;
     uint32_t out_off;
-    if (A.frames) {
-      const polar_frame fr = A.frames[f];
-      P = A.plans[fr.plan_idx];
-      llr = A.llr + fr.llr_off;
-      out_off = fr.out_off;
-    } else {
-      P = A.plans[0];
-      llr = A.llr + (size_t)f * A.llr_bytes;
-      out_off = f * A.info_words;
+    frame_of(A, f, P, llr, out_off);
+    if (A.times && threadIdx.x == 0) A.times[2 * (size_t)f] = wall_clock64();
+    decode_frame<T, NW * 64>(smem, A, f, P, llr, out_off, P->first_stage, 0xFFFFFFFFu);
+  }
+}
+
+// Escalation queue (device scratch): [0] frames queued, [1] next to take,
+// [2 ..] frame indices.
+__global__ void k_queue_reset(uint32_t* q) {
+  if (threadIdx.x < 2) q[threadIdx.x] = 0;
+}
+
+// SC tier: one wave per frame with the L = 1 footprint.  Frames of adaptive
+// plans that fail the CRC at L = 1, and frames of fixed-list plans, go to the
+// escalation queue without a host round trip.
+template <typename T>
+__global__ __launch_bounds__(64) void k_decode_sc(KArgs A, uint32_t* queue) {
+  extern __shared__ __attribute__((aligned(16))) char smem[];
+  for (uint32_t f = blockIdx.x; f < A.n_frames; f += gridDim.x) {
+    const DevPlan* P;
+    const char* llr;
+    uint32_t out_off;
+    frame_of(A, f, P, llr, out_off);
+    if (A.times && threadIdx.x == 0) A.times[2 * (size_t)f] = wall_clock64();
+    bool done = false;
+    if (P->first_stage == 1) done = decode_frame<T, 64>(smem, A, f, P, llr, out_off, 1, 1);
+    if (!done && threadIdx.x == 0) {
+      const uint32_t slot = atomicAdd(&queue[0], 1u);
+      queue[2 + slot] = f;
     }
-    decode_frame<T, NW * 64>(smem, A, f, P, llr, out_off, P->first_stage);
+  }
+}
+
+// List tier: persistent workgroups take frames from the escalation queue (or,
+// in direct mode, every frame) and run the remaining stages.
+template <typename T, int NW>
+__global__ __launch_bounds__(NW * 64) void k_decode_list(KArgs A, uint32_t* queue, int direct) {
+  extern __shared__ __attribute__((aligned(16))) char smem[];
+  __shared__ uint32_t s_idx;
+  const uint32_t total = direct ? A.n_frames : queue[0];
+  for (;;) {
+    if (threadIdx.x == 0) s_idx = atomicAdd(&queue[1], 1u);
+    __syncthreads();
+    const uint32_t idx = s_idx;
+    __syncthreads();
+    if (idx >= total) break;
+    const uint32_t f = direct ? idx : queue[2 + idx];
+    const DevPlan* P;
+    const char* llr;
+    uint32_t out_off;
+    frame_of(A, f, P, llr, out_off);
+    if (direct && A.times && threadIdx.x == 0) A.times[2 * (size_t)f] = wall_clock64();
+    uint32_t L0 = P->first_stage;
+    if (!direct && L0 == 1) L0 = (P->algo == POLAR_PA_SCL) ? P->L_max : 2;
+    decode_frame<T, NW * 64>(smem, A, f, P, llr, out_off, L0, 0xFFFFFFFFu);
   }
 }
 
 // ------------------------------------------------------------ launchers
+template <typename K>
+static int set_lds(K k, uint32_t lds) {
+  return hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)lds) == hipSuccess
+             ? POLAR_OK
+             : POLAR_EHIP;
+}
+
 template <typename T, int NW>
 static int launch_plain_t(const KArgs& A, uint32_t lds, uint32_t grid, hipStream_t s) {
   auto k = k_decode_plain<T, NW>;
-  if (hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
-      hipSuccess)
-    return POLAR_EHIP;
+  if (set_lds(k, lds)) return POLAR_EHIP;
   hipLaunchKernelGGL(k, dim3(grid), dim3(NW * 64), lds, s, A);
   return hipGetLastError() == hipSuccess ? POLAR_OK : POLAR_EHIP;
 }
@@ -889,6 +987,32 @@ int launch_decode_plain(uint32_t quant, const KArgs& A, uint32_t lds, uint32_t g
     case POLAR_F32: return launch_plain_t<float, 1>(A, lds, grid, s);
     case POLAR_I16: return launch_plain_t<int16_t, 1>(A, lds, grid, s);
     default: return launch_plain_t<int8_t, 1>(A, lds, grid, s);
+  }
+}
+
+template <typename T, int NW>
+static int launch_tiered_t(const KArgs& A, const TierPlan& tp, uint32_t* queue, hipStream_t s) {
+  hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, s, queue);
+  if (tp.run_sc) {
+    auto k = k_decode_sc<T>;
+    if (set_lds(k, tp.lds_sc)) return POLAR_EHIP;
+    hipLaunchKernelGGL(k, dim3(tp.grid_sc), dim3(64), tp.lds_sc, s, A, queue);
+  }
+  if (tp.run_list) {
+    auto k = k_decode_list<T, NW>;
+    if (set_lds(k, tp.lds_list)) return POLAR_EHIP;
+    hipLaunchKernelGGL(k, dim3(tp.grid_list), dim3(NW * 64), tp.lds_list, s, A, queue,
+                       tp.run_sc ? 0 : 1);
+  }
+  return hipGetLastError() == hipSuccess ? POLAR_OK : POLAR_EHIP;
+}
+
+int launch_decode_tiered(uint32_t quant, const KArgs& A, const TierPlan& tp, uint32_t* queue,
+                         hipStream_t s) {
+  switch (quant) {
+    case POLAR_F32: return launch_tiered_t<float, 1>(A, tp, queue, s);
+    case POLAR_I16: return launch_tiered_t<int16_t, 1>(A, tp, queue, s);
+    default: return launch_tiered_t<int8_t, 1>(A, tp, queue, s);
   }
 }
 

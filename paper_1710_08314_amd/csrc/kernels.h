@@ -21,12 +21,24 @@ struct KArgs {
   polar_status* status;
   uint32_t* pm_lists;   // nullable
   uint32_t pm_stride;   // entries per frame in pm_lists
+  uint64_t* times;      // nullable: realtime stamps, start and end per frame
 };
 
 // One generic launch: each workgroup decodes whole frames (every stage of
 // the schedule in place).  `lds` = dynamic LDS bytes per workgroup.
 int launch_decode_plain(uint32_t quant, const KArgs& A, uint32_t lds, uint32_t grid,
                         hipStream_t s);
+
+// Tiered schedule: an SC tier (L = 1 footprint, one wave per frame) that
+// pushes CRC failures of adaptive plans (and fixed-list frames) to a device
+// escalation queue, then a persistent list tier that drains it.  Without an
+// SC tier the list tier takes every frame directly.
+struct TierPlan {
+  bool run_sc, run_list;
+  uint32_t lds_sc, lds_list, grid_sc, grid_list;
+};
+int launch_decode_tiered(uint32_t quant, const KArgs& A, const TierPlan& tp, uint32_t* queue,
+                         hipStream_t s);
 
 // Encoder, data generator and channel (gen.hip).
 int launch_encode(const DevPlan* dplan, const DevPlan& h, const uint32_t* d_data,

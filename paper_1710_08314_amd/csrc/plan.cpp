@@ -214,7 +214,7 @@ int make_plan(const polar_plan_desc& d, HostPlan& hp) {
   // ---- header + blob
   const uint32_t E = elem_bytes(d.quant), KB = key_bytes(d.quant);
   const LdsLayout lay = lds_layout(N, n, E, maxl, KB);
-  if (lay.total > kLdsLimit) return POLAR_EUNSUP;
+  if (lay.total > kLdsLimit - 1024) return POLAR_EUNSUP;  // headroom for static LDS
 
   DevPlan h{};
   h.N = N;
@@ -260,6 +260,39 @@ int make_plan(const polar_plan_desc& d, HostPlan& hp) {
   hp.desc = d;
   hp.desc.frozen = nullptr;
   return POLAR_OK;
+}
+
+uint64_t stage_work(const HostPlan& hp, uint32_t L) {
+  const uint32_t N = hp.hdr.N;
+  uint64_t ops = 0, a = 1;
+  auto clog2 = [](uint64_t x) {
+    uint64_t k = 0;
+    while ((1ull << k) < x) ++k;
+    return k;
+  };
+  for (uint32_t w : hp.prog) {
+    const uint32_t op = op_code(w), m = N >> op_depth(w);
+    uint64_t C = 1;
+    switch (op) {
+      case OP_F:
+      case OP_G:
+      case OP_H: ops += a * (m / 2); continue;
+      case OP_R0:
+      case OP_LF: C = 1; break;
+      case OP_LI:
+      case OP_REP: C = 2; break;
+      case OP_R1: C = 4; break;
+      default: C = 8; break;
+    }
+    ops += a * m;
+    if (C > 1) {
+      const uint64_t tot = a * C;
+      ops += tot * clog2(tot);
+      a = std::min<uint64_t>(L, tot);
+    }
+  }
+  ops += a * hp.hdr.K + a * clog2(a);
+  return ops;
 }
 
 uint32_t plan_lds_bytes(const DevPlan& h, uint32_t L) {

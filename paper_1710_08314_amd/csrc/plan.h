@@ -29,6 +29,9 @@ std::vector<double> bhattacharyya_log(uint32_t n, double lz0);
 // a negative POLAR_E* code.
 int make_plan(const polar_plan_desc& d, HostPlan& hp);
 
+// Algorithmic element operations of one decoding stage at list size L.
+uint64_t stage_work(const HostPlan& hp, uint32_t L);
+
 // LDS bytes of one frame of this plan at list size L.
 uint32_t plan_lds_bytes(const DevPlan& h, uint32_t L);
 

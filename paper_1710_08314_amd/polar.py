@@ -54,13 +54,15 @@ class _Info(ctypes.Structure):
 
 
 class _Opts(ctypes.Structure):
-    _fields_ = [("schedule", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 7)]
+    _fields_ = [("schedule", ctypes.c_uint32), ("flags", ctypes.c_uint32),
+                ("d_times", ctypes.c_void_p), ("reserved", ctypes.c_uint32 * 4)]
 
 
 EXPORTS = ["polar_scl_plan", "polar_plan_destroy", "polar_plan_get_info", "polar_plan_get_frozen",
            "polar_plan_query",
            "polar_scl_decode_batch", "polar_encode", "polar_gen_data", "polar_channel",
-           "polar_strerror", "polar_version"]
+           "polar_plan_stage_work", "polar_device_clock_khz", "polar_strerror",
+           "polar_version"]
 
 
 def _load():
@@ -77,6 +79,8 @@ def _load():
     L.polar_encode.argtypes = [vp, vp, vp, u32, vp]
     L.polar_gen_data.argtypes = [vp, u64, u64, u32, vp, vp]
     L.polar_channel.argtypes = [vp, vp, u32, ctypes.c_float, i32, u64, u64, vp, vp]
+    L.polar_plan_stage_work.argtypes = [vp, u32, ctypes.POINTER(ctypes.c_uint64)]
+    L.polar_device_clock_khz.argtypes = [ctypes.POINTER(ctypes.c_uint32)]
     L.polar_strerror.argtypes = [ctypes.c_int]
     L.polar_strerror.restype = ctypes.c_char_p
     L.polar_version.restype = ctypes.c_char_p
@@ -203,6 +207,12 @@ class Plan:
     def handle(self):
         return self._h
 
+    def stage_work(self, L: int) -> int:
+        """Algorithmic element operations of one stage at list size L."""
+        v = ctypes.c_uint64()
+        _check(lib.polar_plan_stage_work(self._h, L, ctypes.byref(v)), "polar_plan_stage_work")
+        return int(v.value)
+
     def frozen(self) -> np.ndarray:
         w = np.zeros(self.info.code_words, dtype=np.uint32)
         _check(lib.polar_plan_get_frozen(self._h, w.ctypes.data), "polar_plan_get_frozen")
@@ -226,8 +236,14 @@ def llr_dtype(quant):
     return {F32: torch.float32, I16: torch.int16, I8: torch.int8}[quant]
 
 
+def device_clock_khz() -> int:
+    v = ctypes.c_uint32()
+    _check(lib.polar_device_clock_khz(ctypes.byref(v)), "polar_device_clock_khz")
+    return int(v.value)
+
+
 def decode_batch(plans, llr, frames=None, n_frames=None, with_pm_lists=False, schedule=0,
-                 stream=None):
+                 stream=None, times=None):
     """polar_scl_decode_batch.  `plans`: Plan or list of Plan; `llr`: device
     tensor (uniform batch: [F, n_tx] of the plan's dtype; with `frames`: any
     byte buffer).  Returns (info [F, info_words] int32, status [F, 8] uint8,
@@ -249,7 +265,7 @@ def decode_batch(plans, llr, frames=None, n_frames=None, with_pm_lists=False, sc
     status = torch.empty((n_frames, 8), dtype=torch.uint8, device=dev)
     pml = torch.empty((n_frames, ml), dtype=torch.int32, device=dev) if with_pm_lists else None
     arr = (ctypes.c_void_p * len(plans))(*[p.handle.value for p in plans])
-    opts = _Opts(schedule)
+    opts = _Opts(schedule, 0, times.data_ptr() if times is not None else None)
     _check(lib.polar_scl_decode_batch(arr, len(plans), _dptr(frames), n_frames, _dptr(llr),
                                       _dptr(info), _dptr(status), _dptr(pml),
                                       ctypes.byref(opts), _stream_ptr(stream)),
