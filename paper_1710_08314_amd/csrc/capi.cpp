@@ -239,7 +239,7 @@ int polar_scl_decode_batch(const polar_plan* plans, uint32_t n_plans, const pola
     const polar::DevPlan& h = plans[i]->hp.hdr;
     if (h.first_stage == 1) tp.run_sc = true;
     if (h.max_list > 1) tp.run_list = true;
-    const uint32_t l1 = polar::plan_lds_bytes(h, 1);
+    const uint32_t l1 = polar::sc_lds_bytes(h.N, polar::elem_bytes(h.quant));
     lds_sc = l1 > lds_sc ? l1 : lds_sc;
   }
   uint32_t* q = nullptr;

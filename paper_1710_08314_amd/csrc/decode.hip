@@ -27,145 +27,11 @@
 #include <cstdint>
 
 #include "../../include/polar_scl.h"
+#include "device_common.h"
 #include "kernels.h"
 #include "polar_internal.h"
 
 namespace polar {
-
-// ------------------------------------------------------------ value traits
-template <typename T>
-struct VT;
-template <>
-struct VT<float> {
-  static constexpr uint32_t E = 4, VMAX = 4;
-  using Acc = float;
-  using Key = unsigned long long;
-  static constexpr bool INT = false;
-  static constexpr int Q = 0;
-};
-template <>
-struct VT<int16_t> {
-  static constexpr uint32_t E = 2, VMAX = 8;
-  using Acc = int;
-  using Key = uint32_t;
-  static constexpr bool INT = true;
-  static constexpr int Q = 32767;
-};
-template <>
-struct VT<int8_t> {
-  static constexpr uint32_t E = 1, VMAX = 16;
-  using Acc = int;
-  using Key = uint32_t;
-  static constexpr bool INT = true;
-  static constexpr int Q = 127;
-};
-
-// f = sign(a b) min(|a|, |b|) with the sign taken from the operand signs;
-// g = (1 - 2 s) a + b, saturated in the integer modes (Sec. II-B1, III-B3).
-__device__ __forceinline__ float f_op(float a, float b) {
-  const float m = fminf(fabsf(a), fabsf(b));
-  return ((a < 0.f) != (b < 0.f)) ? -m : m;
-}
-__device__ __forceinline__ float g_op(float a, float b, uint32_t s) { return s ? (b - a) : (b + a); }
-__device__ __forceinline__ int f_opi(int a, int b) {
-  const int m = min(abs(a), abs(b));
-  return ((a ^ b) < 0) ? -m : m;
-}
-template <int Q>
-__device__ __forceinline__ int g_opi(int a, int b, uint32_t s) {
-  const int v = s ? (b - a) : (b + a);
-  return max(-Q, min(Q, v));
-}
-
-template <typename T>
-__device__ __forceinline__ typename VT<T>::Acc as_acc(T v) {
-  return (typename VT<T>::Acc)v;
-}
-
-// Element k of a small packed vector held in 32-bit words.
-template <typename T>
-__device__ __forceinline__ T get_el(const uint32_t* w, int k);
-template <>
-__device__ __forceinline__ float get_el<float>(const uint32_t* w, int k) {
-  return __uint_as_float(w[k]);
-}
-template <>
-__device__ __forceinline__ int16_t get_el<int16_t>(const uint32_t* w, int k) {
-  return (int16_t)(w[k >> 1] >> ((k & 1) * 16));
-}
-template <>
-__device__ __forceinline__ int8_t get_el<int8_t>(const uint32_t* w, int k) {
-  return (int8_t)(w[k >> 2] >> ((k & 3) * 8));
-}
-template <typename T>
-__device__ __forceinline__ void put_el(uint32_t* w, int k, T v);
-template <>
-__device__ __forceinline__ void put_el<float>(uint32_t* w, int k, float v) {
-  w[k] = __float_as_uint(v);
-}
-template <>
-__device__ __forceinline__ void put_el<int16_t>(uint32_t* w, int k, int16_t v) {
-  w[k >> 1] |= ((uint32_t)(uint16_t)v) << ((k & 1) * 16);
-}
-template <>
-__device__ __forceinline__ void put_el<int8_t>(uint32_t* w, int k, int8_t v) {
-  w[k >> 2] |= ((uint32_t)(uint8_t)v) << ((k & 3) * 8);
-}
-
-template <int NB>
-__device__ __forceinline__ void lds_ld(const char* p, uint32_t* w) {
-  if constexpr (NB == 16) {
-    const uint4 v = *reinterpret_cast<const uint4*>(p);
-    w[0] = v.x; w[1] = v.y; w[2] = v.z; w[3] = v.w;
-  } else if constexpr (NB == 8) {
-    const uint2 v = *reinterpret_cast<const uint2*>(p);
-    w[0] = v.x; w[1] = v.y;
-  } else if constexpr (NB == 4) {
-    w[0] = *reinterpret_cast<const uint32_t*>(p);
-  } else if constexpr (NB == 2) {
-    w[0] = *reinterpret_cast<const uint16_t*>(p);
-  } else {
-    w[0] = *reinterpret_cast<const uint8_t*>(p);
-  }
-}
-template <int NB>
-__device__ __forceinline__ void lds_st(char* p, const uint32_t* w) {
-  if constexpr (NB == 16) {
-    *reinterpret_cast<uint4*>(p) = make_uint4(w[0], w[1], w[2], w[3]);
-  } else if constexpr (NB == 8) {
-    *reinterpret_cast<uint2*>(p) = make_uint2(w[0], w[1]);
-  } else if constexpr (NB == 4) {
-    *reinterpret_cast<uint32_t*>(p) = w[0];
-  } else if constexpr (NB == 2) {
-    *reinterpret_cast<uint16_t*>(p) = (uint16_t)w[0];
-  } else {
-    *reinterpret_cast<uint8_t*>(p) = (uint8_t)w[0];
-  }
-}
-
-template <typename T, int V>
-__device__ __forceinline__ void f_chunk(const uint32_t* a, const uint32_t* b, uint32_t* o) {
-#pragma unroll
-  for (int k = 0; k < V; ++k) {
-    if constexpr (VT<T>::INT)
-      put_el<T>(o, k, (T)f_opi(get_el<T>(a, k), get_el<T>(b, k)));
-    else
-      put_el<T>(o, k, f_op(get_el<T>(a, k), get_el<T>(b, k)));
-  }
-}
-template <typename T, int V>
-__device__ __forceinline__ void g_chunk(const uint32_t* a, const uint32_t* b, uint32_t s,
-                                        uint32_t* o) {
-#pragma unroll
-  for (int k = 0; k < V; ++k) {
-    if constexpr (VT<T>::INT)
-      put_el<T>(o, k, (T)g_opi<VT<T>::Q>(get_el<T>(a, k), get_el<T>(b, k), (s >> k) & 1u));
-    else
-      put_el<T>(o, k, g_op(get_el<T>(a, k), get_el<T>(b, k), (s >> k) & 1u));
-  }
-}
-
-__device__ __forceinline__ uint32_t lg2(uint32_t x) { return 31u - __clz(x); }
 
 // ------------------------------------------------------------- frame state
 // Uniform (per workgroup) view of one frame-stage.
@@ -256,17 +122,6 @@ __device__ void op_h(const Ctx& c, uint32_t d, uint32_t o, uint32_t a) {
 }
 
 // ------------------------------------------------------- wave primitives
-template <typename K>
-__device__ __forceinline__ K shfl_xor_k(K v, int m) {
-  if constexpr (sizeof(K) == 8) {
-    const uint32_t lo = __shfl_xor((uint32_t)v, m, 64);
-    const uint32_t hi = __shfl_xor((uint32_t)(v >> 32), m, 64);
-    return ((K)hi << 32) | lo;
-  } else {
-    return __shfl_xor(v, m, 64);
-  }
-}
-
 // Bitonic sort, ascending, of 64 * KPL keys held as k[t] = element t*64+lane.
 template <typename K, int KPL>
 __device__ void wave_sort(K (&k)[KPL]) {
@@ -722,18 +577,15 @@ __device__ uint32_t end_of_stage(const Ctx& c, uint32_t a, bool* ok) {
   if (tid < 64) sort_keys<Key>(cand, a, sel, a);
   // syndromes
   const uint32_t* infomask = plan_tab(c.P, c.P->off_infomask);
-  const uint32_t* crccol = plan_tab(c.P, c.P->off_crccol);
+  const uint32_t* nib = plan_tab(c.P, c.P->off_crcnib);
   const uint32_t lbw = lg2(c.bw), items = a << lbw;
+  const uint32_t nq = c.N >= 32 ? 8u : (c.N + 3) / 4;
   if (c.P->c > 0) {
     for (uint32_t it = tid; it < items; it += NT) {
       const uint32_t r = it >> lbw, w = it & (c.bw - 1u);
-      uint32_t v = bits_of(c, r)[w] & infomask[w];
+      const uint32_t v = bits_of(c, r)[w] & infomask[w];
       uint32_t s = 0;
-      while (v) {
-        const uint32_t b = __ffs(v) - 1;
-        s ^= crccol[(w << 5) + b];
-        v &= v - 1u;
-      }
+      for (uint32_t q = 0; q < nq; ++q) s ^= nib[((w * 8 + q) << 4) + ((v >> (4 * q)) & 15u)];
       if (s) atomicXor(&syn[r], s);
     }
   }
@@ -918,27 +770,6 @@ __global__ void k_queue_reset(uint32_t* q) {
   if (threadIdx.x < 2) q[threadIdx.x] = 0;
 }
 
-// SC tier: one wave per frame with the L = 1 footprint.  Frames of adaptive
-// plans that fail the CRC at L = 1, and frames of fixed-list plans, go to the
-// escalation queue without a host round trip.
-template <typename T>
-__global__ __launch_bounds__(64) void k_decode_sc(KArgs A, uint32_t* queue) {
-  extern __shared__ __attribute__((aligned(16))) char smem[];
-  for (uint32_t f = blockIdx.x; f < A.n_frames; f += gridDim.x) {
-    const DevPlan* P;
-    const char* llr;
-    uint32_t out_off;
-    frame_of(A, f, P, llr, out_off);
-    if (A.times && threadIdx.x == 0) A.times[2 * (size_t)f] = wall_clock64();
-    bool done = false;
-    if (P->first_stage == 1) done = decode_frame<T, 64>(smem, A, f, P, llr, out_off, 1, 1);
-    if (!done && threadIdx.x == 0) {
-      const uint32_t slot = atomicAdd(&queue[0], 1u);
-      queue[2 + slot] = f;
-    }
-  }
-}
-
 // List tier: persistent workgroups take frames from the escalation queue (or,
 // in direct mode, every frame) and run the remaining stages.
 template <typename T, int NW>
@@ -994,9 +825,9 @@ template <typename T, int NW>
 static int launch_tiered_t(const KArgs& A, const TierPlan& tp, uint32_t* queue, hipStream_t s) {
   hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, s, queue);
   if (tp.run_sc) {
-    auto k = k_decode_sc<T>;
-    if (set_lds(k, tp.lds_sc)) return POLAR_EHIP;
-    hipLaunchKernelGGL(k, dim3(tp.grid_sc), dim3(64), tp.lds_sc, s, A, queue);
+    const int rc = launch_decode_sc(VT<T>::INT ? (sizeof(T) == 2 ? POLAR_I16 : POLAR_I8) : POLAR_F32,
+                                    A, tp.lds_sc, tp.grid_sc, queue, s);
+    if (rc) return rc;
   }
   if (tp.run_list) {
     auto k = k_decode_list<T, NW>;

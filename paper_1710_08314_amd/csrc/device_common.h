@@ -1,0 +1,159 @@
+// Device helpers shared by the decoder kernels: value traits of the three
+// arithmetic modes, the f / g node updates, packed element access, LDS vector
+// access and wave shuffles.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace polar {
+
+// ------------------------------------------------------------ value traits
+template <typename T>
+struct VT;
+template <>
+struct VT<float> {
+  static constexpr uint32_t E = 4, VMAX = 4;
+  using Acc = float;
+  using Key = unsigned long long;
+  static constexpr bool INT = false;
+  static constexpr int Q = 0;
+};
+template <>
+struct VT<int16_t> {
+  static constexpr uint32_t E = 2, VMAX = 8;
+  using Acc = int;
+  using Key = uint32_t;
+  static constexpr bool INT = true;
+  static constexpr int Q = 32767;
+};
+template <>
+struct VT<int8_t> {
+  static constexpr uint32_t E = 1, VMAX = 16;
+  using Acc = int;
+  using Key = uint32_t;
+  static constexpr bool INT = true;
+  static constexpr int Q = 127;
+};
+
+// f = sign(a b) min(|a|, |b|) with the sign taken from the operand signs;
+// g = (1 - 2 s) a + b, saturated in the integer modes (Sec. II-B1, III-B3).
+__device__ __forceinline__ float f_op(float a, float b) {
+  const float m = fminf(fabsf(a), fabsf(b));
+  return ((a < 0.f) != (b < 0.f)) ? -m : m;
+}
+__device__ __forceinline__ float g_op(float a, float b, uint32_t s) { return s ? (b - a) : (b + a); }
+__device__ __forceinline__ int f_opi(int a, int b) {
+  const int m = min(abs(a), abs(b));
+  return ((a ^ b) < 0) ? -m : m;
+}
+template <int Q>
+__device__ __forceinline__ int g_opi(int a, int b, uint32_t s) {
+  const int v = s ? (b - a) : (b + a);
+  return max(-Q, min(Q, v));
+}
+
+template <typename T>
+__device__ __forceinline__ typename VT<T>::Acc as_acc(T v) {
+  return (typename VT<T>::Acc)v;
+}
+
+// Element k of a small packed vector held in 32-bit words.
+template <typename T>
+__device__ __forceinline__ T get_el(const uint32_t* w, int k);
+template <>
+__device__ __forceinline__ float get_el<float>(const uint32_t* w, int k) {
+  return __uint_as_float(w[k]);
+}
+template <>
+__device__ __forceinline__ int16_t get_el<int16_t>(const uint32_t* w, int k) {
+  return (int16_t)(w[k >> 1] >> ((k & 1) * 16));
+}
+template <>
+__device__ __forceinline__ int8_t get_el<int8_t>(const uint32_t* w, int k) {
+  return (int8_t)(w[k >> 2] >> ((k & 3) * 8));
+}
+template <typename T>
+__device__ __forceinline__ void put_el(uint32_t* w, int k, T v);
+template <>
+__device__ __forceinline__ void put_el<float>(uint32_t* w, int k, float v) {
+  w[k] = __float_as_uint(v);
+}
+template <>
+__device__ __forceinline__ void put_el<int16_t>(uint32_t* w, int k, int16_t v) {
+  w[k >> 1] |= ((uint32_t)(uint16_t)v) << ((k & 1) * 16);
+}
+template <>
+__device__ __forceinline__ void put_el<int8_t>(uint32_t* w, int k, int8_t v) {
+  w[k >> 2] |= ((uint32_t)(uint8_t)v) << ((k & 3) * 8);
+}
+
+template <int NB>
+__device__ __forceinline__ void lds_ld(const char* p, uint32_t* w) {
+  if constexpr (NB == 16) {
+    const uint4 v = *reinterpret_cast<const uint4*>(p);
+    w[0] = v.x; w[1] = v.y; w[2] = v.z; w[3] = v.w;
+  } else if constexpr (NB == 8) {
+    const uint2 v = *reinterpret_cast<const uint2*>(p);
+    w[0] = v.x; w[1] = v.y;
+  } else if constexpr (NB == 4) {
+    w[0] = *reinterpret_cast<const uint32_t*>(p);
+  } else if constexpr (NB == 2) {
+    w[0] = *reinterpret_cast<const uint16_t*>(p);
+  } else {
+    w[0] = *reinterpret_cast<const uint8_t*>(p);
+  }
+}
+template <int NB>
+__device__ __forceinline__ void lds_st(char* p, const uint32_t* w) {
+  if constexpr (NB == 16) {
+    *reinterpret_cast<uint4*>(p) = make_uint4(w[0], w[1], w[2], w[3]);
+  } else if constexpr (NB == 8) {
+    *reinterpret_cast<uint2*>(p) = make_uint2(w[0], w[1]);
+  } else if constexpr (NB == 4) {
+    *reinterpret_cast<uint32_t*>(p) = w[0];
+  } else if constexpr (NB == 2) {
+    *reinterpret_cast<uint16_t*>(p) = (uint16_t)w[0];
+  } else {
+    *reinterpret_cast<uint8_t*>(p) = (uint8_t)w[0];
+  }
+}
+
+template <typename T, int V>
+__device__ __forceinline__ void f_chunk(const uint32_t* a, const uint32_t* b, uint32_t* o) {
+#pragma unroll
+  for (int k = 0; k < V; ++k) {
+    if constexpr (VT<T>::INT)
+      put_el<T>(o, k, (T)f_opi(get_el<T>(a, k), get_el<T>(b, k)));
+    else
+      put_el<T>(o, k, f_op(get_el<T>(a, k), get_el<T>(b, k)));
+  }
+}
+template <typename T, int V>
+__device__ __forceinline__ void g_chunk(const uint32_t* a, const uint32_t* b, uint32_t s,
+                                        uint32_t* o) {
+#pragma unroll
+  for (int k = 0; k < V; ++k) {
+    if constexpr (VT<T>::INT)
+      put_el<T>(o, k, (T)g_opi<VT<T>::Q>(get_el<T>(a, k), get_el<T>(b, k), (s >> k) & 1u));
+    else
+      put_el<T>(o, k, g_op(get_el<T>(a, k), get_el<T>(b, k), (s >> k) & 1u));
+  }
+}
+
+__device__ __forceinline__ uint32_t lg2(uint32_t x) { return 31u - __clz(x); }
+
+// ------------------------------------------------------- wave primitives
+template <typename K>
+__device__ __forceinline__ K shfl_xor_k(K v, int m) {
+  if constexpr (sizeof(K) == 8) {
+    const uint32_t lo = __shfl_xor((uint32_t)v, m, 64);
+    const uint32_t hi = __shfl_xor((uint32_t)(v >> 32), m, 64);
+    return ((K)hi << 32) | lo;
+  } else {
+    return __shfl_xor(v, m, 64);
+  }
+}
+
+}  // namespace polar

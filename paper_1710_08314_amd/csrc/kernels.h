@@ -39,6 +39,9 @@ struct TierPlan {
 };
 int launch_decode_tiered(uint32_t quant, const KArgs& A, const TierPlan& tp, uint32_t* queue,
                          hipStream_t s);
+// The SC tier kernel alone (sc.hip); `lds` = sc_lds_bytes of the largest N.
+int launch_decode_sc(uint32_t quant, const KArgs& A, uint32_t lds, uint32_t grid, uint32_t* queue,
+                     hipStream_t s);
 
 // Encoder, data generator and channel (gen.hip).
 int launch_encode(const DevPlan* dplan, const DevPlan& h, const uint32_t* d_data,

@@ -247,6 +247,9 @@ int make_plan(const polar_plan_desc& d, HostPlan& hp) {
   off += N;
   h.off_crcpos = off;
   off += std::max(c, 1u);
+  const uint32_t nnib = (N + 3) / 4;
+  h.off_crcnib = off;
+  off += nnib * 16;
   hp.blob.assign(off, 0);
   std::copy_n(reinterpret_cast<const uint32_t*>(&h), sizeof(DevPlan) / 4, hp.blob.begin());
   std::copy(hp.prog.begin(), hp.prog.end(), hp.blob.begin() + h.off_prog);
@@ -255,6 +258,15 @@ int make_plan(const polar_plan_desc& d, HostPlan& hp) {
   std::copy(prefix.begin(), prefix.end(), hp.blob.begin() + h.off_dataprefix);
   std::copy(crccol.begin(), crccol.end(), hp.blob.begin() + h.off_crccol);
   for (uint32_t t = 0; t < c; ++t) hp.blob[h.off_crcpos + t] = A[kd + t];
+  // nibble table of the syndrome columns (Sec. IV-B: a table of
+  // precomputed sub-results lets the CRC advance several bits per lookup)
+  for (uint32_t q = 0; q < nnib; ++q)
+    for (uint32_t e = 0; e < 16; ++e) {
+      uint32_t v = 0;
+      for (uint32_t b = 0; b < 4; ++b)
+        if (((e >> b) & 1u) && 4 * q + b < N) v ^= crccol[4 * q + b];
+      hp.blob[h.off_crcnib + q * 16 + e] = v;
+    }
   hp.hdr = h;
   hp.frozen = frozen;
   hp.desc = d;

@@ -64,7 +64,9 @@ struct DevPlan {
   uint32_t off_crccol;    // N words: CRC syndrome column of codeword position j
   uint32_t off_crcpos;    // c words: codeword positions of the CRC bits
   uint32_t first_stage;   // list size of the first stage of the schedule
-  uint32_t pad[9];
+  uint32_t off_crcnib;    // ceil(N/4) x 16 words: XOR of the CRC columns of every
+                          // 4-bit pattern at each nibble position of the codeword
+  uint32_t pad[8];
 };
 static_assert(sizeof(DevPlan) == 32 * 4, "DevPlan header is 32 words");
 
@@ -135,6 +137,21 @@ POLAR_HD inline LdsLayout lds_layout(uint32_t N, uint32_t n, uint32_t E, uint32_
   l.total = ru16(cur);
   return l;
 }
+
+// LDS layout of the L = 1 tier for one frame: root N LLRs, the LLRs of the
+// nodes of size >= 128 at depths 1, 2, ... (depth d at root_bytes +
+// E (N - N / 2^(d-1))), partial sums (N bits), output staging.
+POLAR_HD inline uint32_t sc_root_bytes(uint32_t N, uint32_t E) { return ru16(N * E); }
+POLAR_HD inline uint32_t sc_stage_base(uint32_t N, uint32_t d, uint32_t E) {
+  return sc_root_bytes(N, E) + E * (N - (N >> (d - 1)));
+}
+POLAR_HD inline uint32_t sc_bits_off(uint32_t N, uint32_t E) {
+  return ru16(sc_root_bytes(N, E) + E * N);
+}
+POLAR_HD inline uint32_t sc_out_off(uint32_t N, uint32_t E) {
+  return sc_bits_off(N, E) + ru16((N >= 64 ? N / 8 : 8));
+}
+POLAR_HD inline uint32_t sc_lds_bytes(uint32_t N, uint32_t E) { return sc_out_off(N, E) + 64 * 4; }
 
 POLAR_HD inline uint32_t elem_bytes(uint32_t quant) { return quant == 0 ? 4u : (quant == 1 ? 2u : 1u); }
 POLAR_HD inline uint32_t key_bytes(uint32_t quant) { return quant == 0 ? 8u : 4u; }
