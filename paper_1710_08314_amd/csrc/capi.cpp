@@ -29,6 +29,7 @@ struct Scratch {
   int cus = 0;
 };
 std::map<int, Scratch> g_scratch;
+thread_local size_t g_cap_current = 0;
 
 int device_scratch(size_t frames, uint32_t** q, int* cus) {
   int dev = 0;
@@ -50,13 +51,18 @@ int device_scratch(size_t frames, uint32_t** q, int* cus) {
       sc.cap = 0;
     }
     const size_t want = frames < 4096 ? 4096 : frames;
-    if (hipMalloc(&sc.q, (want + 2) * sizeof(uint32_t)) != hipSuccess) return POLAR_ENOMEM;
+    // two queues of (want + 2) words each
+    if (hipMalloc(&sc.q, 2 * (want + 2) * sizeof(uint32_t)) != hipSuccess) return POLAR_ENOMEM;
     sc.cap = want;
   }
   *q = sc.q;
   *cus = sc.cus;
+  g_cap_current = sc.cap;
   return POLAR_OK;
 }
+
+// capacity (frame slots) of the queues returned by the last device_scratch()
+size_t device_queue_cap() { return g_cap_current; }
 // device plan tables of multi-plan batches, keyed by the plan list
 std::map<std::vector<polar_plan>, const polar::DevPlan**> g_tables;
 
@@ -231,14 +237,29 @@ int polar_scl_decode_batch(const polar_plan* plans, uint32_t n_plans, const pola
   const uint32_t schedule = opts ? opts->schedule : 0;
   if (schedule == 1) return polar::launch_decode_plain(quant, A, lds, grid, st);
   if (schedule != 0) return POLAR_EINVAL;
-  // tiered: SC tier if any plan starts at L = 1; list tier if any frame can
-  // need a list (a plan whose largest list exceeds 1)
+  // tiered schedule: SC tier if any plan starts at L = 1; list tier A if any
+  // plan has a stage of list size 2..4; list tier B if any plan has a stage
+  // above 4 (the stages of a plan: SC {1}, CA {L}, PA {1, L_max}, FA {1, 2,
+  // 4, ..., L_max})
   polar::TierPlan tp{};
-  uint32_t lds_sc = 0;
+  uint32_t lds_sc = 0, lds_a = 0;
   for (uint32_t i = 0; i < n_plans; ++i) {
     const polar::DevPlan& h = plans[i]->hp.hdr;
     if (h.first_stage == 1) tp.run_sc = true;
-    if (h.max_list > 1) tp.run_list = true;
+    const bool fa = h.algo == POLAR_FA_SCL;
+    const bool has_a = (h.first_stage > 1 && h.first_stage <= polar::kTierALmax) ||
+                       (h.first_stage == 1 && h.max_list > 1 &&
+                        (fa || h.max_list <= polar::kTierALmax));
+    // list tier A is used for single-plan batches only: a batch of several
+    // plans goes from the SC tier straight to list tier B (which then runs
+    // every remaining stage)
+    if (has_a && n_plans == 1) {
+      tp.run_a = true;
+      const uint32_t la = h.max_list < polar::kTierALmax ? h.max_list : polar::kTierALmax;
+      const uint32_t b = polar::plan_lds_bytes(h, la);
+      lds_a = b > lds_a ? b : lds_a;
+    }
+    if (h.max_list > polar::kTierALmax || (n_plans > 1 && h.max_list > 1)) tp.run_b = true;
     const uint32_t l1 = polar::sc_lds_bytes(h.N, polar::elem_bytes(h.quant));
     lds_sc = l1 > lds_sc ? l1 : lds_sc;
   }
@@ -246,14 +267,19 @@ int polar_scl_decode_batch(const polar_plan* plans, uint32_t n_plans, const pola
   int cus = 1;
   rc = device_scratch(n_frames, &q, &cus);
   if (rc) return rc;
+  auto persistent = [&](uint32_t lds_wg, uint32_t max_per_cu) {
+    uint32_t per_cu = polar::kLdsLimit / (lds_wg ? lds_wg : 1);
+    per_cu = per_cu < 1 ? 1 : (per_cu > max_per_cu ? max_per_cu : per_cu);
+    const uint64_t g = (uint64_t)cus * per_cu;
+    return (uint32_t)(g < n_frames ? g : n_frames);
+  };
   tp.lds_sc = lds_sc;
-  tp.lds_list = lds;
   tp.grid_sc = grid;
-  uint32_t per_cu = polar::kLdsLimit / (lds ? lds : 1);
-  per_cu = per_cu < 1 ? 1 : (per_cu > 4 ? 4 : per_cu);
-  const uint64_t gl = (uint64_t)cus * per_cu;
-  tp.grid_list = (uint32_t)(gl < n_frames ? gl : n_frames);
-  return polar::launch_decode_tiered(quant, A, tp, q, st);
+  tp.lds_a = lds_a;
+  tp.grid_a = persistent(lds_a, 16);
+  tp.lds_b = lds;
+  tp.grid_b = persistent(lds, 4);
+  return polar::launch_decode_tiered(quant, A, tp, q, q + 2 + device_queue_cap(), st);
 }
 
 int polar_encode(polar_plan p, const uint32_t* d_data, uint32_t* d_code, uint32_t n_frames,

@@ -211,6 +211,30 @@ __device__ void sort_keys(const K* src, uint32_t cnt, K* dst, uint32_t keep) {
     sort_keys_kpl<K, 4>(src, cnt, dst, keep);
 }
 
+// Selection by rank counting (more than 64 candidates): every thread takes a
+// candidate, counts the smaller keys (keys are unique), and a candidate of
+// rank < keep lands at sel[rank].  The candidate count is then a multiple of
+// 4 (four or eight candidates per path), so keys are read 16 bytes at a time.
+template <typename K, int NT>
+__device__ void rank_select(const K* cand, uint32_t total, K* sel, uint32_t keep) {
+  constexpr uint32_t PER = 16 / sizeof(K);
+  const uint4* c4 = reinterpret_cast<const uint4*>(cand);
+  for (uint32_t i = threadIdx.x; i < total; i += NT) {
+    const K k = cand[i];
+    uint32_t rank = 0;
+    for (uint32_t q = 0; q < total / PER; ++q) {
+      const uint4 v = c4[q];
+      if constexpr (sizeof(K) == 4) {
+        rank += (v.x < k) + (v.y < k) + (v.z < k) + (v.w < k);
+      } else {
+        const K a = ((K)v.y << 32) | v.x, b = ((K)v.w << 32) | v.z;
+        rank += (a < k) + (b < k);
+      }
+    }
+    if (rank < keep) sel[rank] = k;
+  }
+}
+
 // ------------------------------------------------------------ keys
 // Candidate key (metric, parent rank, local index), compared as one unsigned
 // integer: local index in bits 0..3 (SPC masks reach 15), parent rank in bits
@@ -284,12 +308,140 @@ __device__ __forceinline__ void top_insert(K (&s)[NK], K x) {
 // ------------------------------------------------------------ node ops
 constexpr uint32_t kEPL = 32;  // max elements per lane in a node (N/64)
 
-// Per-path node work.  Each path is handled by a segment of G = min(64, m)
-// lanes; lane j holds elements j, j + G, j + 2G, ...  The segment sums of
-// the penalties follow the stride-halving order exactly: in-lane halving of
-// the element list, then butterflies over the lanes.
+// Candidate q of a path: the local index (R1: the Chase-2 mask q; SPC: the
+// q-th mask, ascending, over the 4 least reliable positions whose weight has
+// the parity of the hard decision) and its penalty.
+template <typename T>
+__device__ __forceinline__ void node_candidate(uint32_t opc, uint32_t q, uint32_t par,
+                                               const typename VT<T>::Key (&top)[4],
+                                               uint32_t* mask_out,
+                                               typename VT<T>::Acc* pen_out) {
+  using Acc = typename VT<T>::Acc;
+  uint32_t mask;
+  if (opc == OP_R1) {
+    mask = q;
+  } else {
+    const uint32_t ev = 0xFCA96530u, od = 0xEDB87421u;  // nibble tables
+    mask = ((par ? od : ev) >> (4 * q)) & 15u;
+  }
+  Acc pen = (Acc)0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+    if ((mask >> i) & 1u) pen = pen + rel_mag<T>(top[i]);
+  *mask_out = mask;
+  *pen_out = pen;
+}
+
+// Per-path statistics of a dedicated node or leaf in the integer modes.
+// Integer penalty sums are exact, so any lane assignment gives the same
+// result: each path gets a segment of G lanes with G as large as possible
+// while every active path fits one round (lane j of a segment holds elements
+// j, j + G, ...).  Writes the candidate keys (or, for single-candidate nodes,
+// the updated metric and zero decisions) and, for R1 / SPC, the hard
+// decisions into the parent's own partial-sum region [o, o + m).
 template <typename T, int NT>
-__device__ void op_node(const Ctx& c, uint32_t opc, uint32_t d, uint32_t o, uint32_t& a) {
+__device__ void node_stats_int(const Ctx& c, uint32_t opc, uint32_t d, uint32_t o, uint32_t a,
+                               uint32_t C) {
+  using Key = typename VT<T>::Key;
+  const uint32_t m = c.N >> d;
+  uint32_t G = 64;
+  while (G > 1 && G * a > (uint32_t)NT) G >>= 1;
+  if (G > m) G = m;
+  const uint32_t lgG = lg2(G), epl = m >> lgG, ppr = NT >> lgG;
+  const uint32_t tid = threadIdx.x, j = tid & (G - 1);
+  int* pm = pm_tab<T>(c);
+  Key* cand = reinterpret_cast<Key*>(c.smem + c.lay.cand);
+  uint16_t* cpos = reinterpret_cast<uint16_t*>(c.smem + c.lay.cpos);
+  const bool single = (opc == OP_R0 || opc == OP_LF);
+  const bool chase = (opc == OP_R1 || opc == OP_SPC);
+  for (uint32_t base = 0; base < a; base += ppr) {
+    const uint32_t r = base + (tid >> lgG);
+    const bool valid = r < a;
+    const T* al = reinterpret_cast<const T*>(node_llr(c, d, valid ? r : 0));
+    int p0 = 0, p1 = 0;
+    uint32_t par = 0;
+    Key top[4] = {~0u, ~0u, ~0u, ~0u};
+    for (uint32_t t = 0; t < epl; ++t) {
+      const uint32_t k = j + (t << lgG);
+      const int v = al[k];
+      const int mg = abs(v);
+      if (v < 0) {
+        p0 += mg;
+        par ^= 1u;
+      } else {
+        p1 += mg;
+      }
+      if (chase) top_insert<Key, 4>(top, ((uint32_t)mg << 16) | k);
+    }
+    for (uint32_t s = G >> 1; s >= 1; s >>= 1) {
+      p0 += __shfl_xor(p0, (int)s, 64);
+      p1 += __shfl_xor(p1, (int)s, 64);
+      if (chase) {
+        Key other[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) other[i] = __shfl_xor(top[i], (int)s, 64);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) top_insert<Key, 4>(top, other[i]);
+        par ^= __shfl_xor(par, (int)s, 64);
+      }
+    }
+    if (!valid) continue;
+    if (single) {
+      if (j == 0) pm[r] = pm_add<T>(pm[r], p0);
+      uint32_t* B = bits_of(c, r);
+      if (m >= 32) {
+        for (uint32_t w = j; w < (m >> 5); w += G) B[(o >> 5) + w] = 0u;
+      } else if (j == 0) {
+        B[o >> 5] &= ~(((1u << m) - 1u) << (o & 31));
+      }
+    } else if (!chase) {
+      if (j == 0) {
+        cand[r * 2 + 0] = make_key<T>(pm_add<T>(pm[r], p0), r, 0);
+        cand[r * 2 + 1] = make_key<T>(pm_add<T>(pm[r], p1), r, 1);
+      }
+    } else {
+      const uint32_t npos = opc == OP_R1 ? 2u : 4u;
+      for (uint32_t q = j; q < C; q += G) {
+        uint32_t mask;
+        int pen;
+        node_candidate<T>(opc, q, par, top, &mask, &pen);
+        cand[r * C + q] = make_key<T>(pm_add<T>(pm[r], pen), r, mask);
+        if (q < npos) {
+          Key tq = top[0];
+#pragma unroll
+          for (int i = 1; i < 4; ++i)
+            if ((uint32_t)i == q) tq = top[i];
+          cpos[r * 4 + q] = (uint16_t)(tq & 0xFFFFu);
+        }
+      }
+    }
+  }
+  if (chase) {
+    // hard decisions, one 32-bit word (or the m < 32 bits) per item
+    const uint32_t nw = m >= 32 ? (m >> 5) : 1u, lnw = lg2(nw), nb = m >= 32 ? 32u : m;
+    for (uint32_t it = tid; it < (a << lnw); it += NT) {
+      const uint32_t r = it >> lnw, w = it & (nw - 1u);
+      const T* al = reinterpret_cast<const T*>(node_llr(c, d, r)) + (w << 5);
+      uint32_t hv = 0;
+      for (uint32_t b = 0; b < nb; ++b) hv |= (al[b] < (T)0 ? 1u : 0u) << b;
+      uint32_t* B = bits_of(c, r);
+      if (m >= 32) {
+        B[(o >> 5) + w] = hv;
+      } else {
+        const uint32_t msk = ((1u << m) - 1u) << (o & 31);
+        B[o >> 5] = (B[o >> 5] & ~msk) | (hv << (o & 31));
+      }
+    }
+  }
+}
+
+// Per-path node work (float32).  Each path is handled by a segment of
+// G = min(64, m) lanes; lane j holds elements j, j + G, j + 2G, ...  The
+// segment sums of the penalties follow the stride-halving order exactly:
+// in-lane halving of the element list, then butterflies over the lanes.
+template <typename T, int NT>
+__device__ void node_stats_float(const Ctx& c, uint32_t opc, uint32_t d, uint32_t o, uint32_t a,
+                                 uint32_t C) {
   using Acc = typename VT<T>::Acc;
   using Key = typename VT<T>::Key;
   const uint32_t m = c.N >> d;
@@ -300,7 +452,6 @@ __device__ void op_node(const Ctx& c, uint32_t opc, uint32_t d, uint32_t o, uint
   Key* cand = reinterpret_cast<Key*>(c.smem + c.lay.cand);
   uint16_t* cpos = reinterpret_cast<uint16_t*>(c.smem + c.lay.cpos);
   const bool single = (opc == OP_R0 || opc == OP_LF);
-  const uint32_t C = single ? 1u : (opc == OP_R1 ? 4u : (opc == OP_SPC ? 8u : 2u));
 
   for (uint32_t base = 0; base < a; base += ppr) {
     const uint32_t r = base + (tid >> lgG);
@@ -395,18 +546,8 @@ __device__ void op_node(const Ctx& c, uint32_t opc, uint32_t d, uint32_t o, uint
       const uint32_t npos = opc == OP_R1 ? 2u : 4u;
       for (uint32_t q = j; valid && q < C; q += G) {
         uint32_t mask;
-        if (opc == OP_R1) {
-          mask = q;
-        } else {
-          // q-th mask (ascending) over 4 positions whose weight has the
-          // parity of the hard decision
-          const uint32_t ev = 0xFCA96530u, od = 0xEDB87421u;  // nibble tables
-          mask = ((par ? od : ev) >> (4 * q)) & 15u;
-        }
-        Acc pen = (Acc)0;
-#pragma unroll
-        for (int i = 0; i < NK; ++i)
-          if ((mask >> i) & 1u) pen = pen + rel_mag<T>(top[i]);
+        Acc pen;
+        node_candidate<T>(opc, q, par, top, &mask, &pen);
         cand[r * C + q] = make_key<T>(pm_add<T>(pm[r], pen), r, mask);
         if (q < npos) {
           Key tq = top[0];
@@ -418,6 +559,26 @@ __device__ void op_node(const Ctx& c, uint32_t opc, uint32_t d, uint32_t o, uint
       }
     }
   }
+}
+
+// A dedicated node or leaf for every active path (update_paths(),
+// Algorithm 1): candidates, selection of the min(L, a C) best keys in key
+// order, path copy, metrics and the node's decisions.
+template <typename T, int NT, int LMAX>
+__device__ void op_node(const Ctx& c, uint32_t opc, uint32_t d, uint32_t o, uint32_t& a) {
+  using Acc = typename VT<T>::Acc;
+  using Key = typename VT<T>::Key;
+  const uint32_t m = c.N >> d;
+  const uint32_t tid = threadIdx.x;
+  Acc* pm = pm_tab<T>(c);
+  Key* cand = reinterpret_cast<Key*>(c.smem + c.lay.cand);
+  uint16_t* cpos = reinterpret_cast<uint16_t*>(c.smem + c.lay.cpos);
+  const bool single = (opc == OP_R0 || opc == OP_LF);
+  const uint32_t C = single ? 1u : (opc == OP_R1 ? 4u : (opc == OP_SPC ? 8u : 2u));
+  if constexpr (VT<T>::INT)
+    node_stats_int<T, NT>(c, opc, d, o, a, C);
+  else
+    node_stats_float<T, NT>(c, opc, d, o, a, C);
   __syncthreads();
 
   if (single) {
@@ -438,7 +599,11 @@ __device__ void op_node(const Ctx& c, uint32_t opc, uint32_t d, uint32_t o, uint
   Key* sel = reinterpret_cast<Key*>(c.smem + c.lay.sel);
   const uint32_t total = a * C;
   const uint32_t keep = total < c.L ? total : c.L;
-  if (tid < 64) sort_keys<Key>(cand, total, sel, keep);
+  if (total <= 64) {
+    if (tid < 64) sort_keys_small<Key>(cand, total, sel, keep);
+  } else {
+    rank_select<Key, NT>(cand, total, sel, keep);
+  }
   __syncthreads();
 
   // ---- path copy: partial-sum words [0, nwc) and slot pointers of depths
@@ -450,7 +615,7 @@ __device__ void op_node(const Ctx& c, uint32_t opc, uint32_t d, uint32_t o, uint
     if (nwc > c.bw) nwc = c.bw;
     const uint32_t lw = nwc > 1 ? lg2(2 * nwc - 1) : 0;  // ceil log2
     const uint32_t items = keep << lw;
-    constexpr int RMAX = (int)(kMaxL * (kMaxN / 32) / NT);
+    constexpr int RMAX = (int)((LMAX * (kMaxN / 32) + NT - 1) / NT);
     uint32_t reg[RMAX];
 #pragma unroll
     for (int q = 0; q < RMAX; ++q) {
@@ -461,7 +626,7 @@ __device__ void op_node(const Ctx& c, uint32_t opc, uint32_t d, uint32_t o, uint
         if (w < nwc) reg[q] = bits_of(c, key_parent<T>(sel[i]))[w];
       }
     }
-    constexpr int PMAX = (int)((kMaxLogN * kMaxL + NT - 1) / NT);
+    constexpr int PMAX = (int)((kMaxLogN * LMAX + NT - 1) / NT);
     uint8_t preg[PMAX];
     const uint32_t pitems = keep * d;
 #pragma unroll
@@ -528,7 +693,7 @@ __device__ void op_node(const Ctx& c, uint32_t opc, uint32_t d, uint32_t o, uint
 }
 
 // ------------------------------------------------------------ one stage
-template <typename T, int NT>
+template <typename T, int NT, int LMAX>
 __device__ void run_program(const Ctx& c, uint32_t& a) {
   const uint32_t n_ops = c.P->n_ops;
   for (uint32_t pc = 0; pc < n_ops; ++pc) {
@@ -548,7 +713,7 @@ __device__ void run_program(const Ctx& c, uint32_t& a) {
         __syncthreads();
         break;
       default:
-        op_node<T, NT>(c, opc, d, o, a);
+        op_node<T, NT, LMAX>(c, opc, d, o, a);
         break;
     }
   }
@@ -648,7 +813,7 @@ __device__ void setup_stage(Ctx& c, uint32_t L) {
 // `L_first`.  A frame whose stage at list size >= L_stop fails the CRC while
 // a larger stage remains is left for the list tier: returns false and writes
 // nothing.  Otherwise writes bits, status, the metric list and the end stamp.
-template <typename T, int NT>
+template <typename T, int NT, int LMAX>
 __device__ bool decode_frame(char* smem, const KArgs& A, uint32_t f, const DevPlan* P,
                              const char* llr, uint32_t out_off, uint32_t L_first,
                              uint32_t L_stop) {
@@ -668,7 +833,7 @@ __device__ bool decode_frame(char* smem, const KArgs& A, uint32_t f, const DevPl
   for (;;) {
     setup_stage<T, NT>(c, L);
     a = 1;
-    run_program<T, NT>(c, a);
+    run_program<T, NT, LMAX>(c, a);
     chosen = end_of_stage<T, NT>(c, a, &ok);
     if (ok || L >= P->L_max) break;
     if (L >= L_stop) return false;
@@ -760,38 +925,58 @@ __global__ __launch_bounds__(NW * 64) void k_decode_plain(KArgs A) {
     uint32_t out_off;
     frame_of(A, f, P, llr, out_off);
     if (A.times && threadIdx.x == 0) A.times[2 * (size_t)f] = wall_clock64();
-    decode_frame<T, NW * 64>(smem, A, f, P, llr, out_off, P->first_stage, 0xFFFFFFFFu);
+    decode_frame<T, NW * 64, kMaxL>(smem, A, f, P, llr, out_off, P->first_stage, 0xFFFFFFFFu);
   }
 }
 
-// Escalation queue (device scratch): [0] frames queued, [1] next to take,
+// Escalation queues (device scratch): [0] frames queued, [1] next to take,
 // [2 ..] frame indices.
-__global__ void k_queue_reset(uint32_t* q) {
-  if (threadIdx.x < 2) q[threadIdx.x] = 0;
+__global__ void k_queue_reset(uint32_t* q1, uint32_t* q2) {
+  if (threadIdx.x < 2) {
+    q1[threadIdx.x] = 0;
+    q2[threadIdx.x] = 0;
+  }
 }
 
-// List tier: persistent workgroups take frames from the escalation queue (or,
-// in direct mode, every frame) and run the remaining stages.
-template <typename T, int NW>
-__global__ __launch_bounds__(NW * 64) void k_decode_list(KArgs A, uint32_t* queue, int direct) {
+// First stage of a frame's schedule above L_done (Sec. II-B5): the plan's
+// first stage if not yet run, else L_max (partially adaptive) or 2 L_done
+// (fully adaptive).
+__device__ __forceinline__ uint32_t next_stage(const DevPlan* P, uint32_t L_done) {
+  if (P->first_stage > L_done) return P->first_stage;
+  if (P->algo == POLAR_PA_SCL) return P->L_max;
+  return 2 * L_done;
+}
+
+// List tier: persistent workgroups take frames from q_in (or, in direct mode,
+// every frame), run the stages of their schedule in (L_done, L_hi], and pass
+// the frames that still fail the CRC on to q_out.
+template <typename T, int NW, int LMAX>
+__global__ __launch_bounds__(NW * 64) void k_decode_list(KArgs A, uint32_t* q_in, uint32_t* q_out,
+                                                         int direct, uint32_t L_done,
+                                                         uint32_t L_hi) {
   extern __shared__ __attribute__((aligned(16))) char smem[];
   __shared__ uint32_t s_idx;
-  const uint32_t total = direct ? A.n_frames : queue[0];
+  // a queue never holds more frames than the batch
+  const uint32_t total = direct ? A.n_frames : min(q_in[0], A.n_frames);
   for (;;) {
-    if (threadIdx.x == 0) s_idx = atomicAdd(&queue[1], 1u);
+    if (threadIdx.x == 0) s_idx = atomicAdd(&q_in[1], 1u);
     __syncthreads();
     const uint32_t idx = s_idx;
     __syncthreads();
     if (idx >= total) break;
-    const uint32_t f = direct ? idx : queue[2 + idx];
+    const uint32_t f = direct ? idx : q_in[2 + idx];
     const DevPlan* P;
     const char* llr;
     uint32_t out_off;
     frame_of(A, f, P, llr, out_off);
     if (direct && A.times && threadIdx.x == 0) A.times[2 * (size_t)f] = wall_clock64();
-    uint32_t L0 = P->first_stage;
-    if (!direct && L0 == 1) L0 = (P->algo == POLAR_PA_SCL) ? P->L_max : 2;
-    decode_frame<T, NW * 64>(smem, A, f, P, llr, out_off, L0, 0xFFFFFFFFu);
+    const uint32_t L0 = next_stage(P, L_done);
+    bool done = false;
+    if (L0 <= L_hi) done = decode_frame<T, NW * 64, LMAX>(smem, A, f, P, llr, out_off, L0, L_hi);
+    if (!done && threadIdx.x == 0) {
+      const uint32_t slot = atomicAdd(&q_out[0], 1u);
+      q_out[2 + slot] = f;
+    }
   }
 }
 
@@ -821,29 +1006,44 @@ int launch_decode_plain(uint32_t quant, const KArgs& A, uint32_t lds, uint32_t g
   }
 }
 
-template <typename T, int NW>
-static int launch_tiered_t(const KArgs& A, const TierPlan& tp, uint32_t* queue, hipStream_t s) {
-  hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, s, queue);
+template <typename T>
+static int launch_tiered_t(const KArgs& A, const TierPlan& tp, uint32_t* q1, uint32_t* q2,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, s, q1, q2);
+  uint32_t* q_cur = q1;
+  int direct = 1;
+  uint32_t L_done = 0;
   if (tp.run_sc) {
     const int rc = launch_decode_sc(VT<T>::INT ? (sizeof(T) == 2 ? POLAR_I16 : POLAR_I8) : POLAR_F32,
-                                    A, tp.lds_sc, tp.grid_sc, queue, s);
+                                    A, tp.lds_sc, tp.grid_sc, q1, s);
     if (rc) return rc;
+    direct = 0;
+    L_done = 1;
   }
-  if (tp.run_list) {
-    auto k = k_decode_list<T, NW>;
-    if (set_lds(k, tp.lds_list)) return POLAR_EHIP;
-    hipLaunchKernelGGL(k, dim3(tp.grid_list), dim3(NW * 64), tp.lds_list, s, A, queue,
-                       tp.run_sc ? 0 : 1);
+  if (tp.run_a) {
+    auto k = k_decode_list<T, 1, (int)kTierALmax>;
+    if (set_lds(k, tp.lds_a)) return POLAR_EHIP;
+    hipLaunchKernelGGL(k, dim3(tp.grid_a), dim3(64), tp.lds_a, s, A, q_cur, q2, direct, L_done,
+                       kTierALmax);
+    q_cur = q2;
+    direct = 0;
+    L_done = kTierALmax;
+  }
+  if (tp.run_b) {
+    auto k = k_decode_list<T, kListWaves, (int)kMaxL>;
+    if (set_lds(k, tp.lds_b)) return POLAR_EHIP;
+    hipLaunchKernelGGL(k, dim3(tp.grid_b), dim3(kListWaves * 64), tp.lds_b, s, A, q_cur,
+                       q_cur == q1 ? q2 : q1, direct, L_done, kMaxL);
   }
   return hipGetLastError() == hipSuccess ? POLAR_OK : POLAR_EHIP;
 }
 
-int launch_decode_tiered(uint32_t quant, const KArgs& A, const TierPlan& tp, uint32_t* queue,
-                         hipStream_t s) {
+int launch_decode_tiered(uint32_t quant, const KArgs& A, const TierPlan& tp, uint32_t* q1,
+                         uint32_t* q2, hipStream_t s) {
   switch (quant) {
-    case POLAR_F32: return launch_tiered_t<float, 1>(A, tp, queue, s);
-    case POLAR_I16: return launch_tiered_t<int16_t, 1>(A, tp, queue, s);
-    default: return launch_tiered_t<int8_t, 1>(A, tp, queue, s);
+    case POLAR_F32: return launch_tiered_t<float>(A, tp, q1, q2, s);
+    case POLAR_I16: return launch_tiered_t<int16_t>(A, tp, q1, q2, s);
+    default: return launch_tiered_t<int8_t>(A, tp, q1, q2, s);
   }
 }
 

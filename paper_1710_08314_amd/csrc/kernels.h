@@ -29,16 +29,22 @@ struct KArgs {
 int launch_decode_plain(uint32_t quant, const KArgs& A, uint32_t lds, uint32_t grid,
                         hipStream_t s);
 
-// Tiered schedule: an SC tier (L = 1 footprint, one wave per frame) that
-// pushes CRC failures of adaptive plans (and fixed-list frames) to a device
-// escalation queue, then a persistent list tier that drains it.  Without an
-// SC tier the list tier takes every frame directly.
+// Tiered schedule.  SC tier: one wave per frame with the L = 1 footprint,
+// pushing the CRC failures of adaptive plans (and untouched fixed-list
+// frames) to queue 1.  List tier A: one wave per frame with the L = 4
+// footprint, stages of L <= 4, failures to queue 2.  List tier B: several
+// waves per frame with the largest footprint, the remaining stages.  Each
+// tier's kernel is persistent and drains its input queue; a tier whose
+// predecessors did not run takes every frame directly.
+constexpr int kListWaves = 4;       // waves per frame in list tier B
+constexpr uint32_t kTierALmax = 4;  // largest list size of list tier A
+
 struct TierPlan {
-  bool run_sc, run_list;
-  uint32_t lds_sc, lds_list, grid_sc, grid_list;
+  bool run_sc, run_a, run_b;
+  uint32_t lds_sc, lds_a, lds_b, grid_sc, grid_a, grid_b;
 };
-int launch_decode_tiered(uint32_t quant, const KArgs& A, const TierPlan& tp, uint32_t* queue,
-                         hipStream_t s);
+int launch_decode_tiered(uint32_t quant, const KArgs& A, const TierPlan& tp, uint32_t* q1,
+                         uint32_t* q2, hipStream_t s);
 // The SC tier kernel alone (sc.hip); `lds` = sc_lds_bytes of the largest N.
 int launch_decode_sc(uint32_t quant, const KArgs& A, uint32_t lds, uint32_t grid, uint32_t* queue,
                      hipStream_t s);
