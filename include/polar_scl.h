@@ -143,11 +143,17 @@ typedef struct {
   uint32_t pm;      /* path metric of the output: float32 bits, or int32 value    */
 } polar_status;
 
+/* opts->flags: record HIP events on `stream` around every kernel launch of
+ * the call (see polar_last_tier_ms). */
+#define POLAR_OPT_TIER_TIMING 1u
+
 /* Optional knobs; NULL selects defaults. */
 typedef struct {
-  uint32_t schedule;   /* 0 = automatic, 1 = plain (one generic launch in which each
-                        * workgroup runs whole frames, every stage in place)      */
-  uint32_t flags;      /* reserved, 0                                             */
+  uint32_t schedule;   /* 0 = automatic (tiered: an L = 1 tier, then list tiers fed
+                        * by device escalation queues), 1 = plain (one generic
+                        * launch in which each workgroup runs whole frames, every
+                        * stage in place)                                          */
+  uint32_t flags;      /* OR of POLAR_OPT_*                                         */
   uint64_t *d_times;   /* nullable device array, 2 per frame: the device realtime
                         * counter (polar_device_clock_khz) when the frame's decode
                         * starts and when its outputs are written                 */
@@ -212,6 +218,13 @@ int polar_channel(polar_plan p, const uint32_t *d_code, uint32_t n_frames, float
  * (host only; no device work).  POLAR_EINVAL for L not a power of two or
  * above 32. */
 int polar_plan_stage_work(polar_plan p, uint32_t L, uint64_t *ops);
+
+/* Kernel durations (ms) of the last polar_scl_decode_batch call made with
+ * POLAR_OPT_TIER_TIMING on this host thread: ms[0] the L = 1 tier, ms[1] list
+ * tier A (L <= 4), ms[2] list tier B, ms[3] the plain kernel; 0 for a kernel
+ * that did not run.  Waits for the recorded events.  POLAR_EINVAL if no timed
+ * call was made. */
+int polar_last_tier_ms(float ms[4]);
 
 /* --------------------------------------------------------------- misc */
 /* Frequency of the device realtime counter used by d_times, in kHz, for the

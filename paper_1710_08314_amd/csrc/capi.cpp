@@ -61,6 +61,22 @@ int device_scratch(size_t frames, uint32_t** q, int* cus) {
   return POLAR_OK;
 }
 
+// events of the last timed call on this host thread: before the first
+// kernel, after the SC tier, after list tier A, after list tier B; and which
+// ran (plain schedule: [0] .. [3] bracket the one kernel)
+struct TierTiming {
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  bool ran[3] = {false, false, false};
+  bool plain = false, valid = false;
+};
+thread_local TierTiming g_timing;
+
+hipEvent_t* timing_events() {
+  for (auto& e : g_timing.ev)
+    if (!e && hipEventCreate(&e) != hipSuccess) return nullptr;
+  return g_timing.ev;
+}
+
 // capacity (frame slots) of the queues returned by the last device_scratch()
 size_t device_queue_cap() { return g_cap_current; }
 // device plan tables of multi-plan batches, keyed by the plan list
@@ -235,7 +251,19 @@ int polar_scl_decode_batch(const polar_plan* plans, uint32_t n_plans, const pola
   const uint32_t grid = n_frames < 0x7FFFFFFFu ? n_frames : 0x7FFFFFFFu;
   const hipStream_t st = static_cast<hipStream_t>(stream);
   const uint32_t schedule = opts ? opts->schedule : 0;
-  if (schedule == 1) return polar::launch_decode_plain(quant, A, lds, grid, st);
+  const bool timed = opts && (opts->flags & POLAR_OPT_TIER_TIMING);
+  hipEvent_t* ev = timed ? timing_events() : nullptr;
+  if (timed && !ev) return POLAR_EHIP;
+  if (schedule == 1) {
+    if (ev) (void)hipEventRecord(ev[0], st);
+    rc = polar::launch_decode_plain(quant, A, lds, grid, st);
+    if (ev) {
+      (void)hipEventRecord(ev[3], st);
+      g_timing.plain = true;
+      g_timing.valid = rc == POLAR_OK;
+    }
+    return rc;
+  }
   if (schedule != 0) return POLAR_EINVAL;
   // tiered schedule: SC tier if any plan starts at L = 1; list tier A if any
   // plan has a stage of list size 2..4; list tier B if any plan has a stage
@@ -279,7 +307,36 @@ int polar_scl_decode_batch(const polar_plan* plans, uint32_t n_plans, const pola
   tp.grid_a = persistent(lds_a, 16);
   tp.lds_b = lds;
   tp.grid_b = persistent(lds, 4);
-  return polar::launch_decode_tiered(quant, A, tp, q, q + 2 + device_queue_cap(), st);
+  rc = polar::launch_decode_tiered(quant, A, tp, q, q + 2 + device_queue_cap(), st, ev);
+  if (ev) {
+    g_timing.ran[0] = tp.run_sc;
+    g_timing.ran[1] = tp.run_a;
+    g_timing.ran[2] = tp.run_b;
+    g_timing.plain = false;
+    g_timing.valid = rc == POLAR_OK;
+  }
+  return rc;
+}
+
+int polar_last_tier_ms(float ms[4]) {
+  if (!ms || !g_timing.valid) return POLAR_EINVAL;
+  for (int i = 0; i < 4; ++i) ms[i] = 0.f;
+  float v = 0.f;
+  if (g_timing.plain) {
+    if (hipEventSynchronize(g_timing.ev[3]) != hipSuccess ||
+        hipEventElapsedTime(&v, g_timing.ev[0], g_timing.ev[3]) != hipSuccess)
+      return POLAR_EHIP;
+    ms[3] = v;
+    return POLAR_OK;
+  }
+  if (hipEventSynchronize(g_timing.ev[3]) != hipSuccess) return POLAR_EHIP;
+  for (int i = 0; i < 3; ++i) {
+    if (!g_timing.ran[i]) continue;
+    if (hipEventElapsedTime(&v, g_timing.ev[i], g_timing.ev[i + 1]) != hipSuccess)
+      return POLAR_EHIP;
+    ms[i] = v;
+  }
+  return POLAR_OK;
 }
 
 int polar_encode(polar_plan p, const uint32_t* d_data, uint32_t* d_code, uint32_t n_frames,

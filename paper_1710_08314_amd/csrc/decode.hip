@@ -1008,8 +1008,9 @@ int launch_decode_plain(uint32_t quant, const KArgs& A, uint32_t lds, uint32_t g
 
 template <typename T>
 static int launch_tiered_t(const KArgs& A, const TierPlan& tp, uint32_t* q1, uint32_t* q2,
-                           hipStream_t s) {
+                           hipStream_t s, hipEvent_t* ev) {
   hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, s, q1, q2);
+  if (ev) (void)hipEventRecord(ev[0], s);
   uint32_t* q_cur = q1;
   int direct = 1;
   uint32_t L_done = 0;
@@ -1020,6 +1021,7 @@ static int launch_tiered_t(const KArgs& A, const TierPlan& tp, uint32_t* q1, uin
     direct = 0;
     L_done = 1;
   }
+  if (ev) (void)hipEventRecord(ev[1], s);
   if (tp.run_a) {
     auto k = k_decode_list<T, 1, (int)kTierALmax>;
     if (set_lds(k, tp.lds_a)) return POLAR_EHIP;
@@ -1029,21 +1031,23 @@ static int launch_tiered_t(const KArgs& A, const TierPlan& tp, uint32_t* q1, uin
     direct = 0;
     L_done = kTierALmax;
   }
+  if (ev) (void)hipEventRecord(ev[2], s);
   if (tp.run_b) {
     auto k = k_decode_list<T, kListWaves, (int)kMaxL>;
     if (set_lds(k, tp.lds_b)) return POLAR_EHIP;
     hipLaunchKernelGGL(k, dim3(tp.grid_b), dim3(kListWaves * 64), tp.lds_b, s, A, q_cur,
                        q_cur == q1 ? q2 : q1, direct, L_done, kMaxL);
   }
+  if (ev) (void)hipEventRecord(ev[3], s);
   return hipGetLastError() == hipSuccess ? POLAR_OK : POLAR_EHIP;
 }
 
 int launch_decode_tiered(uint32_t quant, const KArgs& A, const TierPlan& tp, uint32_t* q1,
-                         uint32_t* q2, hipStream_t s) {
+                         uint32_t* q2, hipStream_t s, hipEvent_t* ev) {
   switch (quant) {
-    case POLAR_F32: return launch_tiered_t<float>(A, tp, q1, q2, s);
-    case POLAR_I16: return launch_tiered_t<int16_t>(A, tp, q1, q2, s);
-    default: return launch_tiered_t<int8_t>(A, tp, q1, q2, s);
+    case POLAR_F32: return launch_tiered_t<float>(A, tp, q1, q2, s, ev);
+    case POLAR_I16: return launch_tiered_t<int16_t>(A, tp, q1, q2, s, ev);
+    default: return launch_tiered_t<int8_t>(A, tp, q1, q2, s, ev);
   }
 }
 

@@ -43,8 +43,10 @@ struct TierPlan {
   bool run_sc, run_a, run_b;
   uint32_t lds_sc, lds_a, lds_b, grid_sc, grid_a, grid_b;
 };
+// ev (nullable): 4 events recorded before the first tier and after the SC
+// tier, list tier A and list tier B.
 int launch_decode_tiered(uint32_t quant, const KArgs& A, const TierPlan& tp, uint32_t* q1,
-                         uint32_t* q2, hipStream_t s);
+                         uint32_t* q2, hipStream_t s, hipEvent_t* ev);
 // The SC tier kernel alone (sc.hip); `lds` = sc_lds_bytes of the largest N.
 int launch_decode_sc(uint32_t quant, const KArgs& A, uint32_t lds, uint32_t grid, uint32_t* queue,
                      hipStream_t s);

@@ -61,7 +61,8 @@ class _Opts(ctypes.Structure):
 EXPORTS = ["polar_scl_plan", "polar_plan_destroy", "polar_plan_get_info", "polar_plan_get_frozen",
            "polar_plan_query",
            "polar_scl_decode_batch", "polar_encode", "polar_gen_data", "polar_channel",
-           "polar_plan_stage_work", "polar_device_clock_khz", "polar_strerror",
+           "polar_plan_stage_work", "polar_device_clock_khz", "polar_last_tier_ms",
+           "polar_strerror",
            "polar_version"]
 
 
@@ -81,6 +82,7 @@ def _load():
     L.polar_channel.argtypes = [vp, vp, u32, ctypes.c_float, i32, u64, u64, vp, vp]
     L.polar_plan_stage_work.argtypes = [vp, u32, ctypes.POINTER(ctypes.c_uint64)]
     L.polar_device_clock_khz.argtypes = [ctypes.POINTER(ctypes.c_uint32)]
+    L.polar_last_tier_ms.argtypes = [ctypes.POINTER(ctypes.c_float)]
     L.polar_strerror.argtypes = [ctypes.c_int]
     L.polar_strerror.restype = ctypes.c_char_p
     L.polar_version.restype = ctypes.c_char_p
@@ -242,8 +244,19 @@ def device_clock_khz() -> int:
     return int(v.value)
 
 
+OPT_TIER_TIMING = 1
+TIER_NAMES = ("sc", "list_a", "list_b", "plain")
+
+
+def last_tier_ms():
+    """polar_last_tier_ms: kernel durations of the last timed decode_batch."""
+    v = (ctypes.c_float * 4)()
+    _check(lib.polar_last_tier_ms(v), "polar_last_tier_ms")
+    return dict(zip(TIER_NAMES, [float(x) for x in v]))
+
+
 def decode_batch(plans, llr, frames=None, n_frames=None, with_pm_lists=False, schedule=0,
-                 stream=None, times=None):
+                 stream=None, times=None, tier_timing=False):
     """polar_scl_decode_batch.  `plans`: Plan or list of Plan; `llr`: device
     tensor (uniform batch: [F, n_tx] of the plan's dtype; with `frames`: any
     byte buffer).  Returns (info [F, info_words] int32, status [F, 8] uint8,
@@ -265,7 +278,8 @@ def decode_batch(plans, llr, frames=None, n_frames=None, with_pm_lists=False, sc
     status = torch.empty((n_frames, 8), dtype=torch.uint8, device=dev)
     pml = torch.empty((n_frames, ml), dtype=torch.int32, device=dev) if with_pm_lists else None
     arr = (ctypes.c_void_p * len(plans))(*[p.handle.value for p in plans])
-    opts = _Opts(schedule, 0, times.data_ptr() if times is not None else None)
+    opts = _Opts(schedule, OPT_TIER_TIMING if tier_timing else 0,
+                 times.data_ptr() if times is not None else None)
     _check(lib.polar_scl_decode_batch(arr, len(plans), _dptr(frames), n_frames, _dptr(llr),
                                       _dptr(info), _dptr(status), _dptr(pml),
                                       ctypes.byref(opts), _stream_ptr(stream)),
