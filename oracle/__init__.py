@@ -85,6 +85,8 @@ def lib():
                                        vp, i32]
         L.orc_decode_batch.restype = i32
         L.orc_nodes.argtypes = [ctypes.POINTER(_Cfg), vp, vp, vp, i32]
+        L.orc_make_frames.argtypes = [ctypes.POINTER(_Cfg), i32, vp, vp, dbl, i32, vp]
+        L.orc_make_frames.restype = i32
         L.orc_nodes.restype = i32
         _lib = L
     return _lib
@@ -259,6 +261,20 @@ def nodes(code: Code):
 
 def default_frac(quant: int) -> int:
     return {I8: 2, I16: 3}.get(quant, 0)
+
+
+def make_frames(code: Code, data: np.ndarray, noise: np.ndarray, sigma: float,
+                frac: int | None = None) -> np.ndarray:
+    """CRC + systematic encoding + BPSK/AWGN + quantisation of data [F, K - c]
+    with noise [F, N - S]: LLRs [F, N - S] of the mode's dtype (batched in C)."""
+    frac = default_frac(code.quant) if frac is None else frac
+    data = np.ascontiguousarray(data, dtype=np.uint8)
+    noise = np.ascontiguousarray(noise, dtype=np.float64)
+    F = data.shape[0]
+    out = np.zeros((F, code.n_tx), dtype=DTYPES[code.quant])
+    cfg = code.cfg()
+    lib().orc_make_frames(ctypes.byref(cfg), F, _p(data), _p(noise), float(sigma), frac, _p(out))
+    return out
 
 
 def make_llr(code: Code, x_tx: np.ndarray, noise: np.ndarray, sigma: float,

@@ -685,6 +685,26 @@ int max_list(const orc_cfg* c) {
 
 extern "C" {
 
+// Batch helpers of the Monte-Carlo chain (test-input generation): frame f
+// has kd data bits data[f * kd ...], gets b = data || CRC, the systematic
+// codeword, then BPSK/AWGN LLRs of its first N - S positions quantised to
+// the mode (noise[f * (N - S) ...] standard normals).  `out` holds
+// (N - S) values of the mode per frame.
+int orc_make_frames(const orc_cfg* c, int n, const uint8_t* data, const double* noise,
+                    double sigma, int frac, void* out) {
+  const int N = c->N, ntx = c->N - c->S, kd = c->K - c->crc_len;
+  std::vector<uint8_t> b(c->K), x(N);
+  std::vector<double> l(ntx);
+  const size_t es = elem_size(c->quant);
+  for (int f = 0; f < n; ++f) {
+    orc_attach_crc(data + (size_t)f * kd, kd, c->crc_len, c->crc_poly, b.data());
+    orc_encode(N, c->frozen, b.data(), x.data());
+    orc_bpsk_awgn_llr(x.data(), ntx, noise + (size_t)f * ntx, sigma, l.data());
+    orc_quantize(l.data(), ntx, c->quant, frac, (char*)out + (size_t)f * ntx * es);
+  }
+  return 0;
+}
+
 // Decode one frame.  `llr` holds N - S values of the mode's type (float,
 // int16, int8 or double), natural codeword order.  `info` receives K - c
 // bytes (0/1); `xhat` (nullable) N bytes; `pm_list` (nullable) up to the
