@@ -16,6 +16,7 @@ latency per point, and the CPU oracle timed on a bounded host-made sample.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -32,6 +33,15 @@ WORKLOAD = dict(name="fa_sscl_n2048_k1723_crc32_lmax32_i8", N=2048, K=1723, crc_
 # MI355X: 256 CUs x 64 vector lanes per clock x 2.4 GHz (no FMA, no packing)
 VALU_PEAK_OPS = 256 * 64 * 2.4e9
 PAPER_CONTEXT_MBPS = {3.5: 24.4, 4.0: 227.3, 4.5: 425.9}  # one i5-6600K core, 8-bit FA
+# counter summaries (HBM bytes per launch) and the sources each kernel is built from
+TRAFFIC_FILES = {"k_sc<int8>": "hbm_traffic_k_sc_fa2048_i8.md",
+                 "k_decode_list<int8,1,4>": "hbm_traffic_list_a_fa2048_i8.md",
+                 "k_decode_list<int8,4,32>": "hbm_traffic_list_b_fa2048_i8.md"}
+KERNEL_SOURCES = {"k_sc<int8>": ["sc.hip", "device_common.h", "kernels.h", "polar_internal.h"],
+                  "k_decode_list<int8,1,4>": ["decode.hip", "device_common.h", "kernels.h",
+                                              "polar_internal.h"],
+                  "k_decode_list<int8,4,32>": ["decode.hip", "device_common.h", "kernels.h",
+                                               "polar_internal.h"]}
 
 
 def wilson(k, n, z=1.96):
@@ -84,6 +94,49 @@ def cpu_baseline(points, frames_per_point, threads):
             "per_point_mbps": per}
 
 
+def calib_copy(nbytes):
+    """A plain elementwise kernel of known traffic: y = -x over int32, reading
+    and writing `nbytes` each, run three times.  Its FETCH_SIZE / WRITE_SIZE
+    readings scale the decoder kernel's counters to bytes."""
+    import torch
+
+    n = nbytes // 4
+    x = torch.ones(n, dtype=torch.int32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        torch.neg(x, out=y)
+    torch.cuda.synchronize()
+    print(json.dumps({"calib_copy_bytes": n * 4, "dispatches": 3}))
+
+
+def kernel_source_hash(files):
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(ROOT, "paper_1710_08314_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary,
+    or None when there is none or the kernel's sources changed since."""
+    path = os.path.join(ROOT, "profiles", TRAFFIC_FILES.get(kernel, "-"))
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and line.startswith("- "):
+                k, v = line[2:].split(":", 1)
+                vals[k.strip()] = v.strip().strip("`")
+    if vals.get("source_sha256") != kernel_source_hash(KERNEL_SOURCES[kernel]):
+        return None
+    try:
+        return int(vals["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -96,7 +149,12 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--compare-plain", type=int, default=1,
                     help="also time the plain one-launch form once per point")
+    ap.add_argument("--calib-copy", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device copy of BYTES (HBM counter calibration)")
     args = ap.parse_args()
+    if args.calib_copy:
+        calib_copy(args.calib_copy)
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU: the decoder shards frames across GPUs with no "
               "collective, so only --gpus 1 is measured", file=sys.stderr)
@@ -238,7 +296,8 @@ def main():
     dom = max(tiers, key=lambda t: tiers[t]["launch_ms"])
     roofline = {"bound": "alu", "achieved": tiers[dom]["achieved"],
                 "peak": round(VALU_PEAK_OPS / 1e12, 2), "unit": "Tops/s",
-                "frac": tiers[dom]["frac"], "traffic": None, "kernel": tiers[dom]["kernel"],
+                "frac": tiers[dom]["frac"], "traffic": measured_traffic(tiers[dom]["kernel"]),
+                "kernel": tiers[dom]["kernel"],
                 "work_per_launch_ops": tiers[dom]["work_per_launch_ops"],
                 "launch_ms": tiers[dom]["launch_ms"], "tiers": tiers}
 
