@@ -146,11 +146,22 @@ typedef struct {
 /* opts->flags: record HIP events on `stream` around every kernel launch of
  * the call (see polar_last_tier_ms). */
 #define POLAR_OPT_TIER_TIMING 1u
+/* opts->flags: for a batch of fixed-list plans (class schedule, below), time
+ * the candidate schedules on this very batch the first time its plan list is
+ * seen, keep the fastest in the library's schedule cache (keyed by the plan
+ * list) and use it from then on.  The call then blocks until the candidates
+ * have run; its outputs are those of the chosen schedule (every candidate
+ * computes the same outputs).  Not usable under graph capture. */
+#define POLAR_OPT_AUTOTUNE 2u
 
 /* Optional knobs; NULL selects defaults. */
 typedef struct {
-  uint32_t schedule;   /* 0 = automatic (tiered: an L = 1 tier, then list tiers fed
-                        * by device escalation queues), 1 = plain (one generic
+  uint32_t schedule;   /* 0 = automatic: a batch of fixed-list plans (CA-SCL, SC)
+                        * with several plans uses the class schedule -- frames
+                        * split by list size and code length, one persistent
+                        * kernel per class sized for that class; otherwise the
+                        * tiered schedule -- an L = 1 tier, then list tiers fed
+                        * by device escalation queues.  1 = plain (one generic
                         * launch in which each workgroup runs whole frames, every
                         * stage in place)                                          */
   uint32_t flags;      /* OR of POLAR_OPT_*                                         */
@@ -221,10 +232,34 @@ int polar_plan_stage_work(polar_plan p, uint32_t L, uint64_t *ops);
 
 /* Kernel durations (ms) of the last polar_scl_decode_batch call made with
  * POLAR_OPT_TIER_TIMING on this host thread: ms[0] the L = 1 tier, ms[1] list
- * tier A (L <= 4), ms[2] list tier B, ms[3] the plain kernel; 0 for a kernel
- * that did not run.  Waits for the recorded events.  POLAR_EINVAL if no timed
- * call was made. */
-int polar_last_tier_ms(float ms[4]);
+ * tier A (L <= 4), ms[2] list tier B, ms[3] the plain kernel, ms[4] the
+ * kernels of the class schedule together; 0 for what did not run.  Waits for
+ * the recorded events.  POLAR_EINVAL if no timed call was made. */
+int polar_last_tier_ms(float ms[5]);
+
+/* Text description of the class schedule the library would use for this
+ * plan list (classes, kernel variant, LDS bytes and workgroups of each, and
+ * whether it came from POLAR_OPT_AUTOTUNE), NUL-terminated, truncated to
+ * `len` bytes.  POLAR_EINVAL for an empty or NULL list or a list that does
+ * not use the class schedule. */
+int polar_schedule_describe(const polar_plan *plans, uint32_t n_plans, char *buf, uint32_t len);
+
+/* ------------------------------------------------------------ HIP graphs */
+/* A decode of fixed buffers captured once into a HIP graph and replayed:
+ * polar_graph_create takes the arguments of polar_scl_decode_batch (same
+ * meaning; opts->flags may not contain POLAR_OPT_TIER_TIMING or
+ * POLAR_OPT_AUTOTUNE, a schedule cached by an earlier autotuned call is
+ * used) and records the launches of one decode, with a work area of its own,
+ * into an executable graph; polar_graph_launch replays it on `stream`,
+ * decoding whatever the buffers hold at that time.  Buffers and plans must
+ * outlive the graph.  Replays of one graph must not overlap. */
+typedef struct polar_graph_s *polar_graph;
+int polar_graph_create(const polar_plan *plans, uint32_t n_plans, const polar_frame *d_frames,
+                       uint32_t n_frames, const void *d_llr, uint32_t *d_info,
+                       polar_status *d_status, uint32_t *d_pm_lists,
+                       const polar_decode_opts *opts, polar_graph *out);
+int polar_graph_launch(polar_graph g, void *stream);
+int polar_graph_destroy(polar_graph g);
 
 /* --------------------------------------------------------------- misc */
 /* Frequency of the device realtime counter used by d_times, in kHz, for the

@@ -2,7 +2,10 @@
 // include/polar_scl.h).  Host-side validation, plan upload and launches.
 #include <hip/hip_runtime.h>
 
+#include <cstdio>
 #include <cstring>
+#include <iterator>
+#include <string>
 #include <map>
 #include <mutex>
 #include <new>
@@ -22,18 +25,33 @@ struct polar_plan_s {
 namespace {
 
 std::mutex g_mu;
-// per-device escalation queue of the tiered schedule (grown on demand)
+
+// Work area of one decode: queue 1 and queue 2 of the tiered schedule (cap + 2
+// words each: [0] frames queued, [1] next to take, then frame indices) and
+// the per-class counters of the class schedule.
+size_t work_words(size_t cap) { return 2 * (cap + 2) + polar::kMaxClasses; }
+struct Work {
+  uint32_t* q1 = nullptr;
+  uint32_t* q2 = nullptr;
+  uint32_t* heads = nullptr;
+};
+Work work_view(uint32_t* base, size_t cap) {
+  Work w;
+  w.q1 = base;
+  w.q2 = base + cap + 2;
+  w.heads = base + 2 * (cap + 2);
+  return w;
+}
+
+// per-device shared work area (grown on demand) and compute-unit count
 struct Scratch {
   uint32_t* q = nullptr;
   size_t cap = 0;  // frame slots
   int cus = 0;
 };
 std::map<int, Scratch> g_scratch;
-thread_local size_t g_cap_current = 0;
 
-int device_scratch(size_t frames, uint32_t** q, int* cus) {
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return POLAR_EHIP;
+int device_cus(int dev, int* cus) {
   std::lock_guard<std::mutex> lk(g_mu);
   Scratch& sc = g_scratch[dev];
   if (sc.cus == 0) {
@@ -42,32 +60,39 @@ int device_scratch(size_t frames, uint32_t** q, int* cus) {
       return POLAR_EHIP;
     sc.cus = v > 0 ? v : 1;
   }
+  *cus = sc.cus;
+  return POLAR_OK;
+}
+
+int device_scratch(size_t frames, Work* w) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return POLAR_EHIP;
+  std::lock_guard<std::mutex> lk(g_mu);
+  Scratch& sc = g_scratch[dev];
   if (sc.cap < frames) {
     if (sc.q) {
-      // the previous queue may still be in use by work queued on any stream
+      // the previous area may still be in use by work queued on any stream
       if (hipDeviceSynchronize() != hipSuccess) return POLAR_EHIP;
       (void)hipFree(sc.q);
       sc.q = nullptr;
       sc.cap = 0;
     }
     const size_t want = frames < 4096 ? 4096 : frames;
-    // two queues of (want + 2) words each
-    if (hipMalloc(&sc.q, 2 * (want + 2) * sizeof(uint32_t)) != hipSuccess) return POLAR_ENOMEM;
+    if (hipMalloc(&sc.q, work_words(want) * sizeof(uint32_t)) != hipSuccess) return POLAR_ENOMEM;
     sc.cap = want;
   }
-  *q = sc.q;
-  *cus = sc.cus;
-  g_cap_current = sc.cap;
+  *w = work_view(sc.q, sc.cap);
   return POLAR_OK;
 }
 
-// events of the last timed call on this host thread: before the first
-// kernel, after the SC tier, after list tier A, after list tier B; and which
-// ran (plain schedule: [0] .. [3] bracket the one kernel)
+// events of the last timed call on this host thread: [0] before the first
+// kernel, [1] after the SC tier, [2] after list tier A, [3] after list tier B
+// (plain schedule: [0] and [3] bracket the one kernel); [4], [5] bracket the
+// kernels of the class schedule
 struct TierTiming {
-  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  hipEvent_t ev[6] = {};
   bool ran[3] = {false, false, false};
-  bool plain = false, valid = false;
+  bool plain = false, classes = false, valid = false;
 };
 thread_local TierTiming g_timing;
 
@@ -77,8 +102,24 @@ hipEvent_t* timing_events() {
   return g_timing.ev;
 }
 
-// capacity (frame slots) of the queues returned by the last device_scratch()
-size_t device_queue_cap() { return g_cap_current; }
+// kernel attributes are set once per device, outside any capture
+std::map<int, bool> g_attr_done;
+int ensure_attributes(int dev) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (g_attr_done[dev]) return POLAR_OK;
+  const int rc = polar::init_kernel_attributes();
+  if (rc == POLAR_OK) g_attr_done[dev] = true;
+  return rc;
+}
+
+// class-schedule choices, per plan list
+struct ClassConfig {
+  uint32_t l8_kernel = polar::CK_W2_L8;  // kernel of the L = 5..8 plans
+  uint32_t split_n = 1;                   // classes split by code length
+  bool tuned = false;
+};
+std::map<std::vector<polar_plan>, ClassConfig> g_sched;
+
 // device plan tables of multi-plan batches, keyed by the plan list
 std::map<std::vector<polar_plan>, const polar::DevPlan**> g_tables;
 
@@ -109,6 +150,11 @@ const polar::DevPlan* const* plan_table(const polar_plan* plans, uint32_t n, int
 
 void forget_tables(polar_plan p) {
   std::lock_guard<std::mutex> lk(g_mu);
+  for (auto it = g_sched.begin(); it != g_sched.end();) {
+    bool uses = false;
+    for (auto q : it->first) uses |= (q == p);
+    it = uses ? g_sched.erase(it) : std::next(it);
+  }
   for (auto it = g_tables.begin(); it != g_tables.end();) {
     bool uses = false;
     for (auto q : it->first) uses |= (q == p);
@@ -134,7 +180,7 @@ int polar_scl_plan(const polar_plan_desc* desc, polar_plan* out) {
     delete p;
     return rc;
   }
-  if (hipGetDevice(&p->device) != hipSuccess) {
+  if (hipGetDevice(&p->device) != hipSuccess || ensure_attributes(p->device) != POLAR_OK) {
     delete p;
     return POLAR_EHIP;
   }
@@ -216,63 +262,233 @@ int polar_plan_get_frozen(polar_plan p, uint32_t* fw) {
   return POLAR_OK;
 }
 
-int polar_scl_decode_batch(const polar_plan* plans, uint32_t n_plans, const polar_frame* d_frames,
-                           uint32_t n_frames, const void* d_llr, uint32_t* d_info,
-                           polar_status* d_status, uint32_t* d_pm_lists,
-                           const polar_decode_opts* opts, void* stream) {
+}  // extern "C"
+
+namespace {
+
+// A validated batch: kernel arguments and what the schedules need.
+struct Batch {
+  polar::KArgs A{};
+  uint32_t quant = 0, lds = 0;
+  bool fixed_list = true;  // every plan has one stage (SC or CA-SCL)
+  std::vector<polar_plan> plans;
+};
+
+int prepare(const polar_plan* plans, uint32_t n_plans, const polar_frame* d_frames,
+            uint32_t n_frames, const void* d_llr, uint32_t* d_info, polar_status* d_status,
+            uint32_t* d_pm_lists, const polar_decode_opts* opts, Batch* b) {
   if (!plans || n_plans == 0) return POLAR_EINVAL;
   for (uint32_t i = 0; i < n_plans; ++i)
     if (!plans[i]) return POLAR_EINVAL;
-  if (n_frames == 0) return POLAR_OK;
   if (!d_llr || !d_info || !d_status) return POLAR_EINVAL;
   if (!d_frames && n_plans != 1) return POLAR_EINVAL;
-  const uint32_t quant = plans[0]->hp.hdr.quant;
-  uint32_t lds = 0, pm_stride = 0;
+  b->quant = plans[0]->hp.hdr.quant;
+  uint32_t pm_stride = 0;
   for (uint32_t i = 0; i < n_plans; ++i) {
     const polar::DevPlan& h = plans[i]->hp.hdr;
-    if (h.quant != quant) return POLAR_EINVAL;
-    lds = h.lds_max > lds ? h.lds_max : lds;
+    if (h.quant != b->quant) return POLAR_EINVAL;
+    b->lds = h.lds_max > b->lds ? h.lds_max : b->lds;
     pm_stride = h.max_list > pm_stride ? h.max_list : pm_stride;
+    if (h.algo != POLAR_SC && h.algo != POLAR_CA_SCL) b->fixed_list = false;
   }
+  b->plans.assign(plans, plans + n_plans);
   int rc = POLAR_OK;
-  polar::KArgs A{};
+  polar::KArgs& A = b->A;
   A.plans = plan_table(plans, n_plans, &rc);
   if (rc) return rc;
   A.frames = d_frames;
   A.n_frames = n_frames;
   A.llr = static_cast<const char*>(d_llr);
-  A.llr_bytes = plans[0]->hp.hdr.n_tx * polar::elem_bytes(quant);
+  A.llr_bytes = plans[0]->hp.hdr.n_tx * polar::elem_bytes(b->quant);
   A.info_words = plans[0]->hp.hdr.info_words;
   A.info = d_info;
   A.status = d_status;
   A.pm_lists = d_pm_lists;
   A.pm_stride = pm_stride;
   A.times = opts ? opts->d_times : nullptr;
-  const uint32_t grid = n_frames < 0x7FFFFFFFu ? n_frames : 0x7FFFFFFFu;
-  const hipStream_t st = static_cast<hipStream_t>(stream);
-  const uint32_t schedule = opts ? opts->schedule : 0;
-  const bool timed = opts && (opts->flags & POLAR_OPT_TIER_TIMING);
+  return POLAR_OK;
+}
+
+bool uses_classes(const Batch& b, uint32_t schedule) {
+  return schedule == 0 && b.fixed_list && b.plans.size() > 1 && b.A.frames != nullptr;
+}
+
+// persistent grid: as many workgroups as the CUs hold (LDS-limited, at most
+// `max_per_cu`), never more than frames
+uint32_t persistent_grid(int cus, uint32_t lds_wg, uint32_t max_per_cu, uint32_t n_frames) {
+  uint32_t per_cu = polar::kLdsLimit / (lds_wg ? lds_wg : 1);
+  per_cu = per_cu < 1 ? 1 : (per_cu > max_per_cu ? max_per_cu : per_cu);
+  const uint64_t g = (uint64_t)cus * per_cu;
+  return (uint32_t)(g < n_frames ? g : n_frames);
+}
+
+// Classes of a fixed-list batch: kernel by list size, then (optionally) by
+// code length, each with the LDS of its largest member.
+int build_classes(const Batch& b, const ClassConfig& cfg, int cus,
+                  std::vector<polar::ClassLaunch>* out) {
+  static const uint32_t nb_split[5] = {0, 256, 512, 1024, polar::kMaxN};
+  static const uint32_t nb_one[2] = {0, polar::kMaxN};
+  const uint32_t* nb = cfg.split_n ? nb_split : nb_one;
+  const uint32_t n_nc = cfg.split_n ? 4 : 1;
+  auto kernel_of = [&](uint32_t L) -> uint32_t {
+    if (L <= 1) return polar::CK_SC;
+    if (L <= 4) return polar::CK_W1_L4;
+    if (L <= 8) return cfg.l8_kernel;
+    return polar::CK_W4_L32;
+  };
+  // [kernel][n class] -> lds
+  uint32_t lds[4][4] = {};
+  bool used[4][4] = {};
+  for (polar_plan p : b.plans) {
+    const polar::DevPlan& h = p->hp.hdr;
+    const uint32_t k = kernel_of(h.first_stage);
+    uint32_t c = 0;
+    while (c + 1 < n_nc && h.N > nb[c + 1]) ++c;
+    const uint32_t need = k == polar::CK_SC ? polar::sc_lds_bytes(h.N, polar::elem_bytes(h.quant))
+                                            : polar::plan_lds_bytes(h, h.first_stage);
+    used[k][c] = true;
+    lds[k][c] = need > lds[k][c] ? need : lds[k][c];
+  }
+  out->clear();
+  const uint32_t n_frames = b.A.n_frames;
+  for (uint32_t k = 0; k < 4; ++k)
+    for (uint32_t c = 0; c < n_nc; ++c) {
+      if (!used[k][c]) continue;
+      polar::ClassLaunch cl{};
+      cl.kernel = k;
+      cl.sel.on = 1;
+      cl.sel.nmin = nb[c] + 1;
+      cl.sel.nmax = nb[c + 1];
+      if (k == polar::CK_SC) {
+        cl.sel.lmin = cl.sel.lmax = 1;
+      } else if (k == polar::CK_W1_L4) {
+        cl.sel.lmin = 2;
+        cl.sel.lmax = 4;
+      } else if (k == polar::CK_W2_L8) {
+        cl.sel.lmin = 5;
+        cl.sel.lmax = 8;
+      } else {
+        cl.sel.lmin = cfg.l8_kernel == polar::CK_W4_L32 ? 5 : 9;
+        cl.sel.lmax = polar::kMaxL;
+      }
+      cl.lds = lds[k][c];
+      if (k == polar::CK_SC)
+        cl.grid = n_frames;  // one wave per frame, frames outside the class exit at once
+      else
+        cl.grid = persistent_grid(cus, cl.lds, k == polar::CK_W1_L4 ? 16 : (k == polar::CK_W2_L8 ? 8 : 4),
+                                  (n_frames + 63) / 64 * 64);
+      out->push_back(cl);
+    }
+  return out->size() <= polar::kMaxClasses ? POLAR_OK : POLAR_EUNSUP;
+}
+
+const char* kernel_name(uint32_t k) {
+  switch (k) {
+    case polar::CK_SC: return "sc";
+    case polar::CK_W1_L4: return "w1_l4";
+    case polar::CK_W2_L8: return "w2_l8";
+    default: return "w4_l32";
+  }
+}
+
+ClassConfig cached_config(const std::vector<polar_plan>& key, bool* found) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = g_sched.find(key);
+  *found = it != g_sched.end();
+  return *found ? it->second : ClassConfig{};
+}
+
+// The class schedule; with `autotune` and no cached choice, every candidate
+// is timed on this batch and the fastest is cached (and its outputs kept).
+int run_classes(const Batch& b, const Work& w, hipStream_t st, bool autotune, hipEvent_t ev0,
+                hipEvent_t ev1) {
+  int dev = 0, cus = 1;
+  if (hipGetDevice(&dev) != hipSuccess) return POLAR_EHIP;
+  int rc = device_cus(dev, &cus);
+  if (rc) return rc;
+  bool found = false;
+  ClassConfig cfg = cached_config(b.plans, &found);
+  std::vector<polar::ClassLaunch> cls;
+  if (autotune && !found) {
+    static const ClassConfig cands[4] = {{polar::CK_W2_L8, 1, true},
+                                         {polar::CK_W4_L32, 1, true},
+                                         {polar::CK_W2_L8, 0, true},
+                                         {polar::CK_W4_L32, 0, true}};
+    hipEvent_t e[2] = {nullptr, nullptr};
+    if (hipEventCreate(&e[0]) != hipSuccess || hipEventCreate(&e[1]) != hipSuccess) {
+      if (e[0]) (void)hipEventDestroy(e[0]);
+      return POLAR_EHIP;
+    }
+    float best = 1e30f;
+    uint32_t best_i = 0;
+    for (uint32_t i = 0; i < 4 && rc == POLAR_OK; ++i) {
+      rc = build_classes(b, cands[i], cus, &cls);
+      if (rc) break;
+      rc = polar::launch_decode_classes(b.quant, b.A, cls.data(), (uint32_t)cls.size(), w.heads,
+                                        st, e[0], e[1]);
+      float ms = 0.f;
+      if (rc == POLAR_OK && (hipEventSynchronize(e[1]) != hipSuccess ||
+                             hipEventElapsedTime(&ms, e[0], e[1]) != hipSuccess))
+        rc = POLAR_EHIP;
+      if (rc == POLAR_OK && ms < best) {
+        best = ms;
+        best_i = i;
+      }
+    }
+    (void)hipEventDestroy(e[0]);
+    (void)hipEventDestroy(e[1]);
+    if (rc) return rc;
+    cfg = cands[best_i];
+    {
+      std::lock_guard<std::mutex> lk(g_mu);
+      g_sched[b.plans] = cfg;
+    }
+  }
+  rc = build_classes(b, cfg, cus, &cls);
+  if (rc) return rc;
+  return polar::launch_decode_classes(b.quant, b.A, cls.data(), (uint32_t)cls.size(), w.heads, st,
+                                      ev0, ev1);
+}
+
+// Launch one decode of a prepared batch on `st` with work area `w`.
+int launch_batch(const Batch& b, uint32_t schedule, const Work& w, hipStream_t st, bool timed,
+                 bool autotune) {
+  const polar::KArgs& A = b.A;
+  const uint32_t n_frames = A.n_frames;
   hipEvent_t* ev = timed ? timing_events() : nullptr;
   if (timed && !ev) return POLAR_EHIP;
+  int rc = POLAR_OK;
   if (schedule == 1) {
+    const uint32_t grid = n_frames < 0x7FFFFFFFu ? n_frames : 0x7FFFFFFFu;
     if (ev) (void)hipEventRecord(ev[0], st);
-    rc = polar::launch_decode_plain(quant, A, lds, grid, st);
+    rc = polar::launch_decode_plain(b.quant, A, b.lds, grid, st);
     if (ev) {
       (void)hipEventRecord(ev[3], st);
       g_timing.plain = true;
+      g_timing.classes = false;
       g_timing.valid = rc == POLAR_OK;
     }
     return rc;
   }
   if (schedule != 0) return POLAR_EINVAL;
+  if (uses_classes(b, schedule)) {
+    rc = run_classes(b, w, st, autotune, ev ? ev[4] : nullptr, ev ? ev[5] : nullptr);
+    if (ev) {
+      g_timing.plain = false;
+      g_timing.classes = true;
+      g_timing.valid = rc == POLAR_OK;
+    }
+    return rc;
+  }
   // tiered schedule: SC tier if any plan starts at L = 1; list tier A if any
   // plan has a stage of list size 2..4; list tier B if any plan has a stage
   // above 4 (the stages of a plan: SC {1}, CA {L}, PA {1, L_max}, FA {1, 2,
   // 4, ..., L_max})
+  const uint32_t n_plans = (uint32_t)b.plans.size();
   polar::TierPlan tp{};
   uint32_t lds_sc = 0, lds_a = 0;
-  for (uint32_t i = 0; i < n_plans; ++i) {
-    const polar::DevPlan& h = plans[i]->hp.hdr;
+  for (polar_plan p : b.plans) {
+    const polar::DevPlan& h = p->hp.hdr;
     if (h.first_stage == 1) tp.run_sc = true;
     const bool fa = h.algo == POLAR_FA_SCL;
     const bool has_a = (h.first_stage > 1 && h.first_stage <= polar::kTierALmax) ||
@@ -284,59 +500,191 @@ int polar_scl_decode_batch(const polar_plan* plans, uint32_t n_plans, const pola
     if (has_a && n_plans == 1) {
       tp.run_a = true;
       const uint32_t la = h.max_list < polar::kTierALmax ? h.max_list : polar::kTierALmax;
-      const uint32_t b = polar::plan_lds_bytes(h, la);
-      lds_a = b > lds_a ? b : lds_a;
+      const uint32_t lb = polar::plan_lds_bytes(h, la);
+      lds_a = lb > lds_a ? lb : lds_a;
     }
     if (h.max_list > polar::kTierALmax || (n_plans > 1 && h.max_list > 1)) tp.run_b = true;
     const uint32_t l1 = polar::sc_lds_bytes(h.N, polar::elem_bytes(h.quant));
     lds_sc = l1 > lds_sc ? l1 : lds_sc;
   }
-  uint32_t* q = nullptr;
-  int cus = 1;
-  rc = device_scratch(n_frames, &q, &cus);
+  int dev = 0, cus = 1;
+  if (hipGetDevice(&dev) != hipSuccess) return POLAR_EHIP;
+  rc = device_cus(dev, &cus);
   if (rc) return rc;
-  auto persistent = [&](uint32_t lds_wg, uint32_t max_per_cu) {
-    uint32_t per_cu = polar::kLdsLimit / (lds_wg ? lds_wg : 1);
-    per_cu = per_cu < 1 ? 1 : (per_cu > max_per_cu ? max_per_cu : per_cu);
-    const uint64_t g = (uint64_t)cus * per_cu;
-    return (uint32_t)(g < n_frames ? g : n_frames);
-  };
   tp.lds_sc = lds_sc;
-  tp.grid_sc = grid;
+  tp.grid_sc = n_frames < 0x7FFFFFFFu ? n_frames : 0x7FFFFFFFu;
   tp.lds_a = lds_a;
-  tp.grid_a = persistent(lds_a, 16);
-  tp.lds_b = lds;
-  tp.grid_b = persistent(lds, 4);
-  rc = polar::launch_decode_tiered(quant, A, tp, q, q + 2 + device_queue_cap(), st, ev);
+  tp.grid_a = persistent_grid(cus, lds_a, 16, n_frames);
+  tp.lds_b = b.lds;
+  tp.grid_b = persistent_grid(cus, b.lds, 4, n_frames);
+  rc = polar::launch_decode_tiered(b.quant, A, tp, w.q1, w.q2, st, ev);
   if (ev) {
     g_timing.ran[0] = tp.run_sc;
     g_timing.ran[1] = tp.run_a;
     g_timing.ran[2] = tp.run_b;
     g_timing.plain = false;
+    g_timing.classes = false;
     g_timing.valid = rc == POLAR_OK;
   }
   return rc;
 }
 
-int polar_last_tier_ms(float ms[4]) {
+}  // namespace
+
+extern "C" {
+
+int polar_scl_decode_batch(const polar_plan* plans, uint32_t n_plans, const polar_frame* d_frames,
+                           uint32_t n_frames, const void* d_llr, uint32_t* d_info,
+                           polar_status* d_status, uint32_t* d_pm_lists,
+                           const polar_decode_opts* opts, void* stream) {
+  if (!plans || n_plans == 0) return POLAR_EINVAL;
+  if (n_frames == 0) {
+    for (uint32_t i = 0; i < n_plans; ++i)
+      if (!plans[i]) return POLAR_EINVAL;
+    return POLAR_OK;
+  }
+  Batch b;
+  int rc = prepare(plans, n_plans, d_frames, n_frames, d_llr, d_info, d_status, d_pm_lists, opts,
+                   &b);
+  if (rc) return rc;
+  const uint32_t schedule = opts ? opts->schedule : 0;
+  if (schedule > 1) return POLAR_EINVAL;
+  Work w;
+  if (schedule == 0) {
+    rc = device_scratch(n_frames, &w);
+    if (rc) return rc;
+  }
+  const uint32_t flags = opts ? opts->flags : 0;
+  return launch_batch(b, schedule, w, static_cast<hipStream_t>(stream),
+                      (flags & POLAR_OPT_TIER_TIMING) != 0, (flags & POLAR_OPT_AUTOTUNE) != 0);
+}
+
+int polar_last_tier_ms(float ms[5]) {
   if (!ms || !g_timing.valid) return POLAR_EINVAL;
-  for (int i = 0; i < 4; ++i) ms[i] = 0.f;
+  for (int i = 0; i < 5; ++i) ms[i] = 0.f;
   float v = 0.f;
-  if (g_timing.plain) {
-    if (hipEventSynchronize(g_timing.ev[3]) != hipSuccess ||
-        hipEventElapsedTime(&v, g_timing.ev[0], g_timing.ev[3]) != hipSuccess)
+  hipEvent_t* ev = g_timing.ev;
+  if (g_timing.classes) {
+    if (hipEventSynchronize(ev[5]) != hipSuccess || hipEventElapsedTime(&v, ev[4], ev[5]) != hipSuccess)
       return POLAR_EHIP;
+    ms[4] = v;
+    return POLAR_OK;
+  }
+  if (hipEventSynchronize(ev[3]) != hipSuccess) return POLAR_EHIP;
+  if (g_timing.plain) {
+    if (hipEventElapsedTime(&v, ev[0], ev[3]) != hipSuccess) return POLAR_EHIP;
     ms[3] = v;
     return POLAR_OK;
   }
-  if (hipEventSynchronize(g_timing.ev[3]) != hipSuccess) return POLAR_EHIP;
   for (int i = 0; i < 3; ++i) {
     if (!g_timing.ran[i]) continue;
-    if (hipEventElapsedTime(&v, g_timing.ev[i], g_timing.ev[i + 1]) != hipSuccess)
-      return POLAR_EHIP;
+    if (hipEventElapsedTime(&v, ev[i], ev[i + 1]) != hipSuccess) return POLAR_EHIP;
     ms[i] = v;
   }
   return POLAR_OK;
+}
+
+int polar_schedule_describe(const polar_plan* plans, uint32_t n_plans, char* buf, uint32_t len) {
+  if (!plans || n_plans == 0 || !buf || len == 0) return POLAR_EINVAL;
+  for (uint32_t i = 0; i < n_plans; ++i)
+    if (!plans[i]) return POLAR_EINVAL;
+  Batch b;
+  b.plans.assign(plans, plans + n_plans);
+  for (polar_plan p : b.plans) {
+    const polar::DevPlan& h = p->hp.hdr;
+    if (h.algo != POLAR_SC && h.algo != POLAR_CA_SCL) b.fixed_list = false;
+  }
+  if (!b.fixed_list || n_plans < 2) return POLAR_EINVAL;
+  int dev = 0, cus = 1;
+  if (hipGetDevice(&dev) != hipSuccess) return POLAR_EHIP;
+  int rc = device_cus(dev, &cus);
+  if (rc) return rc;
+  bool found = false;
+  const ClassConfig cfg = cached_config(b.plans, &found);
+  b.A.n_frames = 1u << 20;  // grid sizes for a large batch
+  std::vector<polar::ClassLaunch> cls;
+  rc = build_classes(b, cfg, cus, &cls);
+  if (rc) return rc;
+  std::string t = "classes=" + std::to_string(cls.size()) +
+                  " l8=" + kernel_name(cfg.l8_kernel) + " split_n=" + std::to_string(cfg.split_n) +
+                  " tuned=" + std::to_string(found && cfg.tuned ? 1 : 0);
+  for (const auto& c : cls)
+    t += "; " + std::string(kernel_name(c.kernel)) + " L" + std::to_string(c.sel.lmin) + "-" +
+         std::to_string(c.sel.lmax) + " N" + std::to_string(c.sel.nmin) + "-" +
+         std::to_string(c.sel.nmax) + " lds=" + std::to_string(c.lds) + " wg=" + std::to_string(c.grid);
+  std::snprintf(buf, len, "%s", t.c_str());
+  return POLAR_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- graphs
+struct polar_graph_s {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  uint32_t* work = nullptr;
+};
+
+extern "C" {
+
+int polar_graph_destroy(polar_graph g) {
+  if (!g) return POLAR_OK;
+  int rc = POLAR_OK;
+  if (g->exec && hipGraphExecDestroy(g->exec) != hipSuccess) rc = POLAR_EHIP;
+  if (g->graph && hipGraphDestroy(g->graph) != hipSuccess) rc = POLAR_EHIP;
+  if (g->work && hipFree(g->work) != hipSuccess) rc = POLAR_EHIP;
+  delete g;
+  return rc;
+}
+
+int polar_graph_create(const polar_plan* plans, uint32_t n_plans, const polar_frame* d_frames,
+                       uint32_t n_frames, const void* d_llr, uint32_t* d_info,
+                       polar_status* d_status, uint32_t* d_pm_lists,
+                       const polar_decode_opts* opts, polar_graph* out) {
+  if (!out || n_frames == 0) return POLAR_EINVAL;
+  *out = nullptr;
+  const uint32_t flags = opts ? opts->flags : 0;
+  if (flags & (POLAR_OPT_TIER_TIMING | POLAR_OPT_AUTOTUNE)) return POLAR_EINVAL;
+  const uint32_t schedule = opts ? opts->schedule : 0;
+  if (schedule > 1) return POLAR_EINVAL;
+  Batch b;
+  int rc = prepare(plans, n_plans, d_frames, n_frames, d_llr, d_info, d_status, d_pm_lists, opts,
+                   &b);
+  if (rc) return rc;
+  polar_graph g = new (std::nothrow) polar_graph_s;
+  if (!g) return POLAR_ENOMEM;
+  if (hipMalloc(&g->work, work_words(n_frames) * sizeof(uint32_t)) != hipSuccess) {
+    delete g;
+    return POLAR_ENOMEM;
+  }
+  const Work w = work_view(g->work, n_frames);
+  hipStream_t s = nullptr;
+  if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
+    (void)polar_graph_destroy(g);
+    return POLAR_EHIP;
+  }
+  rc = POLAR_OK;
+  if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) rc = POLAR_EHIP;
+  if (rc == POLAR_OK) {
+    const int lr = launch_batch(b, schedule, w, s, false, false);
+    const hipError_t ec = hipStreamEndCapture(s, &g->graph);
+    rc = lr ? lr : (ec == hipSuccess ? POLAR_OK : POLAR_EHIP);
+  }
+  if (rc == POLAR_OK && hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0) != hipSuccess)
+    rc = POLAR_EHIP;
+  (void)hipStreamDestroy(s);
+  if (rc) {
+    (void)polar_graph_destroy(g);
+    return rc;
+  }
+  *out = g;
+  return POLAR_OK;
+}
+
+int polar_graph_launch(polar_graph g, void* stream) {
+  if (!g || !g->exec) return POLAR_EINVAL;
+  return hipGraphLaunch(g->exec, static_cast<hipStream_t>(stream)) == hipSuccess ? POLAR_OK
+                                                                                   : POLAR_EHIP;
 }
 
 int polar_encode(polar_plan p, const uint32_t* d_data, uint32_t* d_code, uint32_t n_frames,

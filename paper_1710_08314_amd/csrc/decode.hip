@@ -980,6 +980,52 @@ __global__ __launch_bounds__(NW * 64) void k_decode_list(KArgs A, uint32_t* q_in
   }
 }
 
+// Class schedule: persistent workgroups claim the frame descriptors 64 at a
+// time; wave 0 tests the 64 frames against the class (first stage and code
+// length of the frame's plan) and the workgroup decodes the matching ones,
+// each in its single stage.
+__device__ __forceinline__ bool in_class(const DevPlan* P, const ClassSel& sel) {
+  return P->first_stage >= sel.lmin && P->first_stage <= sel.lmax && P->N >= sel.nmin &&
+         P->N <= sel.nmax;
+}
+
+template <typename T, int NW, int LMAX>
+__global__ __launch_bounds__(NW * 64) void k_decode_class(KArgs A, uint32_t* head, ClassSel sel) {
+  extern __shared__ __attribute__((aligned(16))) char smem[];
+  __shared__ uint32_t s_base;
+  __shared__ unsigned long long s_mask;
+  for (;;) {
+    if (threadIdx.x == 0) s_base = atomicAdd(head, 64u);
+    __syncthreads();
+    const uint32_t base = s_base;
+    if (base >= A.n_frames) break;
+    if (threadIdx.x < 64) {
+      const uint32_t f = base + threadIdx.x;
+      bool m = false;
+      if (f < A.n_frames) m = in_class(A.plans[A.frames[f].plan_idx], sel);
+      const unsigned long long b = __ballot(m);
+      if (threadIdx.x == 0) s_mask = b;
+    }
+    __syncthreads();
+    unsigned long long mask = s_mask;
+    __syncthreads();
+    while (mask) {
+      const uint32_t f = base + (uint32_t)(__ffsll(mask) - 1);
+      mask &= mask - 1ull;
+      const DevPlan* P;
+      const char* llr;
+      uint32_t out_off;
+      frame_of(A, f, P, llr, out_off);
+      if (A.times && threadIdx.x == 0) A.times[2 * (size_t)f] = wall_clock64();
+      decode_frame<T, NW * 64, LMAX>(smem, A, f, P, llr, out_off, P->first_stage, 0xFFFFFFFFu);
+    }
+  }
+}
+
+__global__ void k_heads_reset(uint32_t* heads, uint32_t n) {
+  if (threadIdx.x < n) heads[threadIdx.x] = 0;
+}
+
 // ------------------------------------------------------------ launchers
 template <typename K>
 static int set_lds(K k, uint32_t lds) {
@@ -989,11 +1035,78 @@ static int set_lds(K k, uint32_t lds) {
              : POLAR_EHIP;
 }
 
+int sc_set_attributes(int lds);
+
+// Dynamic LDS every decoder kernel may request: the CU's LDS less room for the
+// kernels' own static variables (plans never need more, see plan_lds_bytes).
+constexpr uint32_t kDynLdsMax = kLdsLimit - 1024;
+
+template <typename T>
+static int set_attributes_t() {
+  int rc = POLAR_OK;
+  rc |= set_lds(k_decode_plain<T, 1>, kDynLdsMax);
+  rc |= set_lds(k_decode_list<T, 1, (int)kTierALmax>, kDynLdsMax);
+  rc |= set_lds(k_decode_list<T, kListWaves, (int)kMaxL>, kDynLdsMax);
+  rc |= set_lds(k_decode_class<T, 1, 4>, kDynLdsMax);
+  rc |= set_lds(k_decode_class<T, 2, 8>, kDynLdsMax);
+  rc |= set_lds(k_decode_class<T, 4, (int)kMaxL>, kDynLdsMax);
+  return rc ? POLAR_EHIP : POLAR_OK;
+}
+
+int init_kernel_attributes() {
+  if (set_attributes_t<float>() || set_attributes_t<int16_t>() || set_attributes_t<int8_t>())
+    return POLAR_EHIP;
+  return sc_set_attributes((int)kDynLdsMax);
+}
+
+template <typename T>
+static int launch_classes_t(const KArgs& A, const ClassLaunch* cls, uint32_t n_cls,
+                            uint32_t* heads, hipStream_t s) {
+  hipLaunchKernelGGL(k_heads_reset, dim3(1), dim3(64), 0, s, heads, n_cls);
+  const uint32_t quant = VT<T>::INT ? (sizeof(T) == 2 ? POLAR_I16 : POLAR_I8) : POLAR_F32;
+  for (uint32_t i = 0; i < n_cls; ++i) {
+    const ClassLaunch& c = cls[i];
+    switch (c.kernel) {
+      case CK_SC: {
+        const int rc = launch_decode_sc(quant, A, c.lds, c.grid, heads, c.sel, s);
+        if (rc) return rc;
+        break;
+      }
+      case CK_W1_L4:
+        hipLaunchKernelGGL((k_decode_class<T, 1, 4>), dim3(c.grid), dim3(64), c.lds, s, A,
+                           heads + i, c.sel);
+        break;
+      case CK_W2_L8:
+        hipLaunchKernelGGL((k_decode_class<T, 2, 8>), dim3(c.grid), dim3(128), c.lds, s, A,
+                           heads + i, c.sel);
+        break;
+      default:
+        hipLaunchKernelGGL((k_decode_class<T, 4, (int)kMaxL>), dim3(c.grid), dim3(256), c.lds, s,
+                           A, heads + i, c.sel);
+        break;
+    }
+  }
+  return hipGetLastError() == hipSuccess ? POLAR_OK : POLAR_EHIP;
+}
+
+int launch_decode_classes(uint32_t quant, const KArgs& A, const ClassLaunch* cls, uint32_t n_cls,
+                          uint32_t* heads, hipStream_t s, hipEvent_t ev_begin,
+                          hipEvent_t ev_end) {
+  if (n_cls > kMaxClasses) return POLAR_EINVAL;
+  if (ev_begin) (void)hipEventRecord(ev_begin, s);
+  int rc;
+  switch (quant) {
+    case POLAR_F32: rc = launch_classes_t<float>(A, cls, n_cls, heads, s); break;
+    case POLAR_I16: rc = launch_classes_t<int16_t>(A, cls, n_cls, heads, s); break;
+    default: rc = launch_classes_t<int8_t>(A, cls, n_cls, heads, s); break;
+  }
+  if (ev_end) (void)hipEventRecord(ev_end, s);
+  return rc;
+}
+
 template <typename T, int NW>
 static int launch_plain_t(const KArgs& A, uint32_t lds, uint32_t grid, hipStream_t s) {
-  auto k = k_decode_plain<T, NW>;
-  if (set_lds(k, lds)) return POLAR_EHIP;
-  hipLaunchKernelGGL(k, dim3(grid), dim3(NW * 64), lds, s, A);
+  hipLaunchKernelGGL((k_decode_plain<T, NW>), dim3(grid), dim3(NW * 64), lds, s, A);
   return hipGetLastError() == hipSuccess ? POLAR_OK : POLAR_EHIP;
 }
 
@@ -1016,16 +1129,14 @@ static int launch_tiered_t(const KArgs& A, const TierPlan& tp, uint32_t* q1, uin
   uint32_t L_done = 0;
   if (tp.run_sc) {
     const int rc = launch_decode_sc(VT<T>::INT ? (sizeof(T) == 2 ? POLAR_I16 : POLAR_I8) : POLAR_F32,
-                                    A, tp.lds_sc, tp.grid_sc, q1, s);
+                                    A, tp.lds_sc, tp.grid_sc, q1, ClassSel{}, s);
     if (rc) return rc;
     direct = 0;
     L_done = 1;
   }
   if (ev) (void)hipEventRecord(ev[1], s);
   if (tp.run_a) {
-    auto k = k_decode_list<T, 1, (int)kTierALmax>;
-    if (set_lds(k, tp.lds_a)) return POLAR_EHIP;
-    hipLaunchKernelGGL(k, dim3(tp.grid_a), dim3(64), tp.lds_a, s, A, q_cur, q2, direct, L_done,
+    hipLaunchKernelGGL((k_decode_list<T, 1, (int)kTierALmax>), dim3(tp.grid_a), dim3(64), tp.lds_a, s, A, q_cur, q2, direct, L_done,
                        kTierALmax);
     q_cur = q2;
     direct = 0;
@@ -1033,9 +1144,7 @@ static int launch_tiered_t(const KArgs& A, const TierPlan& tp, uint32_t* q1, uin
   }
   if (ev) (void)hipEventRecord(ev[2], s);
   if (tp.run_b) {
-    auto k = k_decode_list<T, kListWaves, (int)kMaxL>;
-    if (set_lds(k, tp.lds_b)) return POLAR_EHIP;
-    hipLaunchKernelGGL(k, dim3(tp.grid_b), dim3(kListWaves * 64), tp.lds_b, s, A, q_cur,
+    hipLaunchKernelGGL((k_decode_list<T, kListWaves, (int)kMaxL>), dim3(tp.grid_b), dim3(kListWaves * 64), tp.lds_b, s, A, q_cur,
                        q_cur == q1 ? q2 : q1, direct, L_done, kMaxL);
   }
   if (ev) (void)hipEventRecord(ev[3], s);

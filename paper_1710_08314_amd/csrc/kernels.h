@@ -48,8 +48,40 @@ struct TierPlan {
 int launch_decode_tiered(uint32_t quant, const KArgs& A, const TierPlan& tp, uint32_t* q1,
                          uint32_t* q2, hipStream_t s, hipEvent_t* ev);
 // The SC tier kernel alone (sc.hip); `lds` = sc_lds_bytes of the largest N.
+// With `sel` on, the kernel decodes only the frames of its class and skips
+// the others (no queue); otherwise frames of plans whose first stage is not
+// L = 1 are queued untouched.
+struct ClassSel {
+  uint32_t on;
+  uint32_t lmin, lmax;  // the plan's first stage (list size) in [lmin, lmax]
+  uint32_t nmin, nmax;  // the plan's code length in [nmin, nmax]
+};
 int launch_decode_sc(uint32_t quant, const KArgs& A, uint32_t lds, uint32_t grid, uint32_t* queue,
-                     hipStream_t s);
+                     const ClassSel& sel, hipStream_t s);
+
+// Class schedule of a batch of fixed-list plans (no escalation): the frames
+// are split into classes by list size and code length, and each class is
+// decoded by its own persistent kernel that walks the frame descriptors,
+// picks the frames of its class and runs their single stage.  No frame is
+// handed between kernels.  Kernel variants (waves per frame, largest list):
+enum ClassKernel : uint32_t {
+  CK_SC = 0,      // k_sc: L = 1, one wave per frame
+  CK_W1_L4 = 1,   // one wave, L <= 4
+  CK_W2_L8 = 2,   // two waves, L <= 8
+  CK_W4_L32 = 3,  // four waves, L <= 32
+};
+struct ClassLaunch {
+  uint32_t kernel;  // ClassKernel
+  ClassSel sel;
+  uint32_t lds, grid;
+};
+constexpr uint32_t kMaxClasses = 16;
+// heads: one counter per class, cleared by the first kernel of the launch.
+int launch_decode_classes(uint32_t quant, const KArgs& A, const ClassLaunch* cls, uint32_t n_cls,
+                          uint32_t* heads, hipStream_t s, hipEvent_t ev_begin, hipEvent_t ev_end);
+// Allow every decoder kernel the whole LDS of a CU (called once, outside any
+// graph capture); launches then pass their actual footprint.
+int init_kernel_attributes();
 
 // Encoder, data generator and channel (gen.hip).
 int launch_encode(const DevPlan* dplan, const DevPlan& h, const uint32_t* d_data,

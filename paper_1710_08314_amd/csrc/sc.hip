@@ -389,7 +389,7 @@ __device__ __forceinline__ void lds_op(char* smem, uint32_t N, uint32_t opc, uin
 // queued untouched; frames of adaptive plans whose L = 1 decision fails the
 // CRC are queued for the list tier; every other frame is finished here.
 template <typename T>
-__global__ __launch_bounds__(64) void k_sc(KArgs A, uint32_t* queue) {
+__global__ __launch_bounds__(64) void k_sc(KArgs A, uint32_t* queue, ClassSel sel) {
   extern __shared__ __attribute__((aligned(16))) char smem[];
   using V = typename Lane<T>::V;
   using Acc = typename VT<T>::Acc;
@@ -409,14 +409,19 @@ __global__ __launch_bounds__(64) void k_sc(KArgs A, uint32_t* queue) {
       llr = A.llr + (size_t)f * A.llr_bytes;
       out_off = f * A.info_words;
     }
-    if (A.times && lane == 0) A.times[2 * (size_t)f] = wall_clock64();
-    if (P->first_stage != 1) {
+    if (sel.on) {
+      // class schedule: only this class's frames, the others are left alone
+      if (P->first_stage < sel.lmin || P->first_stage > sel.lmax || P->N < sel.nmin ||
+          P->N > sel.nmax)
+        continue;
+    } else if (P->first_stage != 1) {
       if (lane == 0) {
         const uint32_t slot = atomicAdd(&queue[0], 1u);
         queue[2 + slot] = f;
       }
       continue;
     }
+    if (A.times && lane == 0) A.times[2 * (size_t)f] = wall_clock64();
     const uint32_t N = P->N, n = P->n, ntx = P->n_tx, n_ops = P->n_ops;
     const uint32_t* prog = plan_tab(P, P->off_prog);
     // ---- channel LLRs -> root (shortened tail: a zero known for certain)
@@ -523,22 +528,27 @@ __global__ __launch_bounds__(64) void k_sc(KArgs A, uint32_t* queue) {
 
 template <typename T>
 static int launch_sc_t(const KArgs& A, uint32_t lds, uint32_t grid, uint32_t* queue,
-                       hipStream_t s) {
-  auto k = k_sc<T>;
-  if (hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
-      hipSuccess)
-    return POLAR_EHIP;
-  hipLaunchKernelGGL(k, dim3(grid), dim3(64), lds, s, A, queue);
+                       const ClassSel& sel, hipStream_t s) {
+  hipLaunchKernelGGL(k_sc<T>, dim3(grid), dim3(64), lds, s, A, queue, sel);
   return hipGetLastError() == hipSuccess ? POLAR_OK : POLAR_EHIP;
 }
 
 int launch_decode_sc(uint32_t quant, const KArgs& A, uint32_t lds, uint32_t grid, uint32_t* queue,
-                     hipStream_t s) {
+                     const ClassSel& sel, hipStream_t s) {
   switch (quant) {
-    case POLAR_F32: return launch_sc_t<float>(A, lds, grid, queue, s);
-    case POLAR_I16: return launch_sc_t<int16_t>(A, lds, grid, queue, s);
-    default: return launch_sc_t<int8_t>(A, lds, grid, queue, s);
+    case POLAR_F32: return launch_sc_t<float>(A, lds, grid, queue, sel, s);
+    case POLAR_I16: return launch_sc_t<int16_t>(A, lds, grid, queue, sel, s);
+    default: return launch_sc_t<int8_t>(A, lds, grid, queue, sel, s);
   }
+}
+
+int sc_set_attributes(int lds) {
+  const void* ks[] = {(const void*)k_sc<float>, (const void*)k_sc<int16_t>,
+                      (const void*)k_sc<int8_t>};
+  for (const void* k : ks)
+    if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess)
+      return POLAR_EHIP;
+  return POLAR_OK;
 }
 
 }  // namespace polar

@@ -62,7 +62,8 @@ EXPORTS = ["polar_scl_plan", "polar_plan_destroy", "polar_plan_get_info", "polar
            "polar_plan_query",
            "polar_scl_decode_batch", "polar_encode", "polar_gen_data", "polar_channel",
            "polar_plan_stage_work", "polar_device_clock_khz", "polar_last_tier_ms",
-           "polar_strerror",
+           "polar_schedule_describe", "polar_graph_create", "polar_graph_launch",
+           "polar_graph_destroy", "polar_strerror",
            "polar_version"]
 
 
@@ -83,6 +84,10 @@ def _load():
     L.polar_plan_stage_work.argtypes = [vp, u32, ctypes.POINTER(ctypes.c_uint64)]
     L.polar_device_clock_khz.argtypes = [ctypes.POINTER(ctypes.c_uint32)]
     L.polar_last_tier_ms.argtypes = [ctypes.POINTER(ctypes.c_float)]
+    L.polar_schedule_describe.argtypes = [vp, u32, ctypes.c_char_p, u32]
+    L.polar_graph_create.argtypes = [vp, u32, vp, u32, vp, vp, vp, vp, vp, ctypes.POINTER(vp)]
+    L.polar_graph_launch.argtypes = [vp, vp]
+    L.polar_graph_destroy.argtypes = [vp]
     L.polar_strerror.argtypes = [ctypes.c_int]
     L.polar_strerror.restype = ctypes.c_char_p
     L.polar_version.restype = ctypes.c_char_p
@@ -245,28 +250,28 @@ def device_clock_khz() -> int:
 
 
 OPT_TIER_TIMING = 1
-TIER_NAMES = ("sc", "list_a", "list_b", "plain")
+OPT_AUTOTUNE = 2
+TIER_NAMES = ("sc", "list_a", "list_b", "plain", "classes")
 
 
 def last_tier_ms():
     """polar_last_tier_ms: kernel durations of the last timed decode_batch."""
-    v = (ctypes.c_float * 4)()
+    v = (ctypes.c_float * 5)()
     _check(lib.polar_last_tier_ms(v), "polar_last_tier_ms")
     return dict(zip(TIER_NAMES, [float(x) for x in v]))
 
 
-def decode_batch(plans, llr, frames=None, n_frames=None, with_pm_lists=False, schedule=0,
-                 stream=None, times=None, tier_timing=False):
-    """polar_scl_decode_batch.  `plans`: Plan or list of Plan; `llr`: device
-    tensor (uniform batch: [F, n_tx] of the plan's dtype; with `frames`: any
-    byte buffer).  Returns (info [F, info_words] int32, status [F, 8] uint8,
-    pm_lists [F, max_list] int32 or None)."""
+def schedule_describe(plans) -> str:
+    """polar_schedule_describe: the class schedule used for this plan list."""
+    arr = (ctypes.c_void_p * len(plans))(*[p.handle.value for p in plans])
+    buf = ctypes.create_string_buffer(4096)
+    _check(lib.polar_schedule_describe(arr, len(plans), buf, len(buf)), "polar_schedule_describe")
+    return buf.value.decode()
+
+
+def _outputs(plans, llr, frames, n_frames, with_pm_lists):
     import torch
 
-    if isinstance(plans, Plan):
-        plans = [plans]
-    if n_frames is None:
-        n_frames = frames.shape[0] if frames is not None else llr.shape[0]
     dev = llr.device
     iw = max(p.info.info_words for p in plans)
     ml = max(p.info.max_list for p in plans)
@@ -277,9 +282,58 @@ def decode_batch(plans, llr, frames=None, n_frames=None, with_pm_lists=False, sc
         info = torch.zeros((max(tot, 1),), dtype=torch.int32, device=dev)
     status = torch.empty((n_frames, 8), dtype=torch.uint8, device=dev)
     pml = torch.empty((n_frames, ml), dtype=torch.int32, device=dev) if with_pm_lists else None
+    return info, status, pml
+
+
+class Graph:
+    """polar_graph_*: one decode of fixed buffers captured into a HIP graph.
+    The output tensors are allocated here and rewritten by every replay."""
+
+    def __init__(self, plans, llr, frames=None, n_frames=None, with_pm_lists=False, schedule=0):
+        if isinstance(plans, Plan):
+            plans = [plans]
+        if n_frames is None:
+            n_frames = frames.shape[0] if frames is not None else llr.shape[0]
+        self._keep = (plans, llr, frames)
+        self.info, self.status, self.pm_lists = _outputs(plans, llr, frames, n_frames,
+                                                         with_pm_lists)
+        arr = (ctypes.c_void_p * len(plans))(*[p.handle.value for p in plans])
+        opts = _Opts(schedule, 0, None)
+        h = ctypes.c_void_p()
+        _check(lib.polar_graph_create(arr, len(plans), _dptr(frames), n_frames, _dptr(llr),
+                                      _dptr(self.info), _dptr(self.status), _dptr(self.pm_lists),
+                                      ctypes.byref(opts), ctypes.byref(h)), "polar_graph_create")
+        self._h = h
+
+    def launch(self, stream=None):
+        _check(lib.polar_graph_launch(self._h, _stream_ptr(stream)), "polar_graph_launch")
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib.polar_graph_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def decode_batch(plans, llr, frames=None, n_frames=None, with_pm_lists=False, schedule=0,
+                 stream=None, times=None, tier_timing=False, autotune=False):
+    """polar_scl_decode_batch.  `plans`: Plan or list of Plan; `llr`: device
+    tensor (uniform batch: [F, n_tx] of the plan's dtype; with `frames`: any
+    byte buffer).  Returns (info [F, info_words] int32, status [F, 8] uint8,
+    pm_lists [F, max_list] int32 or None)."""
+    if isinstance(plans, Plan):
+        plans = [plans]
+    if n_frames is None:
+        n_frames = frames.shape[0] if frames is not None else llr.shape[0]
+    info, status, pml = _outputs(plans, llr, frames, n_frames, with_pm_lists)
     arr = (ctypes.c_void_p * len(plans))(*[p.handle.value for p in plans])
-    opts = _Opts(schedule, OPT_TIER_TIMING if tier_timing else 0,
-                 times.data_ptr() if times is not None else None)
+    flags = (OPT_TIER_TIMING if tier_timing else 0) | (OPT_AUTOTUNE if autotune else 0)
+    opts = _Opts(schedule, flags, times.data_ptr() if times is not None else None)
     _check(lib.polar_scl_decode_batch(arr, len(plans), _dptr(frames), n_frames, _dptr(llr),
                                       _dptr(info), _dptr(status), _dptr(pml),
                                       ctypes.byref(opts), _stream_ptr(stream)),

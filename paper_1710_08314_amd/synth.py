@@ -86,3 +86,37 @@ C2 = Workload("fa_sscl_n2048_k1723_crc32_lmax32_i8", 2048, 1723, 32, 0x04C11DB7,
 # 5. Quantisation sweep (1024, 488 + CRC-24), L = 8.
 C5 = Workload("ca_scl_n1024_k512_crc24_l8", 1024, 512, 24, 0x1864CFB, 2.5, "f32", "ca", 8, 8,
               [1.0, 1.5, 2.0, 2.5, 3.0, 3.5, 4.0], 10_000_000, 5000)
+
+
+# 3. Batched uneven launch: every frame draws its own code and decoder.
+C3_N = (128, 256, 512, 1024, 2048)
+C3_RATES = (1 / 4, 1 / 3, 1 / 2, 2 / 3, 5 / 6)
+C3_L = (2, 8, 32)
+C3_CRC = (11, 0x621)
+C3_DESIGN_DB = 2.5
+C3_SHORTENED = 0.2  # fraction of frames shortened by S ~ U{1 .. N/4}
+
+
+def uneven_batch(seed: int, n: int):
+    """Per-frame draws of the uneven batch: N, rate, L, shortening S and
+    Eb/N0 ~ U[1, 4] dB.  Returns (codes, code_idx, ebn0): `codes` lists the
+    distinct (N, K, L, S) with K = round(rate (N - S)) = |A| including the
+    CRC, `code_idx[f]` the code of frame f."""
+    rng = np.random.Generator(np.random.Philox(np.random.SeedSequence([int(seed), 0xC3])))
+    N = rng.choice(np.array(C3_N), size=n)
+    r = rng.integers(0, len(C3_RATES), size=n)
+    L = rng.choice(np.array(C3_L), size=n)
+    short = rng.random(n) < C3_SHORTENED
+    S = np.where(short, rng.integers(1, N // 4 + 1), 0)
+    ebn0 = rng.uniform(1.0, 4.0, size=n)
+    K = np.rint(np.array(C3_RATES)[r] * (N - S)).astype(np.int64)
+    key = np.stack([N, K, L, S], axis=1)
+    codes, code_idx = np.unique(key, axis=0, return_inverse=True)
+    return [tuple(int(v) for v in c) for c in codes], code_idx.reshape(-1), ebn0
+
+
+def frame_draws(seed: int, f: int, k_data: int, n_tx: int):
+    """Data bits [k_data] and noise [n_tx] of frame f alone (a generator per
+    (seed, frame), for batches whose frames all differ in size)."""
+    rng = np.random.Generator(np.random.Philox(np.random.SeedSequence([int(seed), 0xF, int(f)])))
+    return rng.integers(0, 2, size=k_data, dtype=np.uint8), rng.standard_normal(size=n_tx)

@@ -106,3 +106,88 @@ def compare(code: O.Code, llr: np.ndarray, ref: O.Result | None = None, schedule
     exact = bool(bit_eq.all()) and np.array_equal(np.nan_to_num(g_list, nan=-1),
                                                    np.nan_to_num(ref.pm_list, nan=-1))
     return {"frames": F, "exact": exact, "fer_gpu": None, "escalated": int((ref.L_used > 1).sum())}
+
+
+C3_QUANT = "i16"
+
+
+def uneven_inputs(seed: int, n: int, with_codes_for=None):
+    """The uneven batch of n frames (per-frame N, rate, L, shortening, Eb/N0),
+    built on the host by the oracle.  Returns a dict: `specs` (N, K, L, S) per
+    plan, `codes` the oracle Code per plan, `plan_of` per frame, `data` per
+    frame (list), `raw` the LLR bytes (each frame 16-byte aligned), `desc`
+    [n, 4] uint32 frame descriptors (llr_off lo, hi, out_off, plan_idx) and
+    `out_off` per frame."""
+    specs, plan_of, ebn0 = synth.uneven_batch(seed, n)
+    c, poly = synth.C3_CRC
+    q = QMAP[C3_QUANT]
+    codes = []
+    for (N, K, L, S) in specs:
+        fz = O.construct(N, K, S, c, synth.C3_DESIGN_DB)
+        codes.append(oracle_code(N, K, c, poly, fz, S=S, quant=q, algo="ca", L=L))
+    es = np.dtype(O.DTYPES[q]).itemsize
+    offs = np.zeros(n, dtype=np.int64)
+    out_off = np.zeros(n, dtype=np.int64)
+    off = out = 0
+    for f in range(n):
+        cd = codes[plan_of[f]]
+        off = (off + 15) // 16 * 16
+        offs[f] = off
+        off += cd.n_tx * es
+        out_off[f] = out
+        out += (cd.k_data + 31) // 32
+    raw = np.zeros(off, dtype=np.uint8)
+    data = []
+    for f in range(n):
+        cd = codes[plan_of[f]]
+        b, z = synth.frame_draws(seed, f, cd.k_data, cd.n_tx)
+        sigma = synth.sigma_for(float(ebn0[f]), cd.k_data, cd.n_tx)
+        l = O.make_frames(cd, b[None, :], z[None, :], sigma)
+        raw[offs[f]:offs[f] + cd.n_tx * es] = l.view(np.uint8).reshape(-1)
+        data.append(b)
+    desc = np.zeros((n, 4), dtype=np.uint32)
+    desc[:, 0] = offs & 0xFFFFFFFF
+    desc[:, 1] = offs >> 32
+    desc[:, 2] = out_off
+    desc[:, 3] = plan_of
+    return {"specs": specs, "codes": codes, "plan_of": plan_of, "data": data, "raw": raw,
+            "desc": desc, "out_off": out_off, "ebn0": ebn0}
+
+
+def check_uneven(inp, info_words, status, sample, pm_lists=None):
+    """Frame-by-frame parity of the sampled frames of an uneven batch (int16:
+    bit-exact bits, path metric, CRC flag, list size and live paths)."""
+    from paper_1710_08314_amd import polar as P
+
+    st = P.status_fields(status)
+    by_plan = {}
+    for f in sample:
+        by_plan.setdefault(int(inp["plan_of"][f]), []).append(int(f))
+    es = np.dtype(O.DTYPES[QMAP[C3_QUANT]]).itemsize
+
+    def ref_of(item):
+        pi, fs = item
+        cd = inp["codes"][pi]
+        llr = np.stack([inp["raw"][inp["desc"][f, 0]:inp["desc"][f, 0] + cd.n_tx * es]
+                        .view(O.DTYPES[cd.quant]) for f in fs])
+        return pi, fs, O.decode(cd, llr)
+
+    import concurrent.futures as cf
+    import os
+
+    with cf.ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        refs = list(ex.map(ref_of, by_plan.items()))
+    for pi, fs, ref in refs:
+        cd = inp["codes"][pi]
+        for j, f in enumerate(fs):
+            w = info_words[inp["out_off"][f]:inp["out_off"][f] + (cd.k_data + 31) // 32]
+            bits = P.unpack_bits(w, cd.k_data)
+            assert np.array_equal(bits, ref.info[j]), f"frame {f} plan {inp['specs'][pi]}: bits"
+            assert st["crc_ok"][f] == ref.crc_ok[j], f"frame {f}: crc_ok"
+            assert st["L_used"][f] == ref.L_used[j], f"frame {f}: L_used"
+            assert st["n_paths"][f] == ref.n_pm[j], f"frame {f}: paths"
+            assert st["pm_bits"][f].view(np.int32) == int(ref.pm[j]), f"frame {f}: pm"
+            if pm_lists is not None:
+                k = int(ref.n_pm[j])
+                assert np.array_equal(pm_lists[f][:k].view(np.int32),
+                                      ref.pm_list[j][:k].astype(np.int32)), f"frame {f}: pm list"
