@@ -137,6 +137,256 @@ def measured_traffic(kernel):
         return None
 
 
+def bench_uneven(args):
+    """The batched uneven launch: 2^20 frames, each with its own (N, rate, L,
+    shortening) -- about 15,000 plans -- CRC-11, int16, decoded in one call by
+    the autotuned class schedule, then by a HIP-graph replay of it, then by
+    the plain one-launch form.  Inputs are generated on the device per plan
+    (data, systematic encoding, BPSK/AWGN at one Eb/N0 ~ U[1, 4] dB per plan:
+    the fixed-list decoders' work does not depend on the channel)."""
+    import torch
+
+    from paper_1710_08314_amd import polar as P
+    from paper_1710_08314_amd import synth
+
+    torch.cuda.set_device(0)
+    n = args.frames if args.frames != 1_000_000 else 1 << 20
+    specs, plan_of, _ = synth.uneven_batch(3000, n)
+    c, poly = synth.C3_CRC
+    t0 = time.perf_counter()
+    plans = [P.Plan(N, K, c, poly, design_ebn0_db=synth.C3_DESIGN_DB, n_shorten=S, algo=P.CA_SCL,
+                    L=L, quant=P.I16) for (N, K, L, S) in specs]
+    t_plan = time.perf_counter() - t0
+    counts = np.bincount(plan_of, minlength=len(plans))
+    # plan-major LLR regions, each frame slot padded to 16 bytes
+    strides = [((p.info.n_tx * 2 + 15) // 16) * 16 for p in plans]
+    region = np.zeros(len(plans) + 1, dtype=np.int64)
+    region[1:] = np.cumsum(counts * np.array(strides, dtype=np.int64))
+    d_llr = torch.empty(int(region[-1]), dtype=torch.uint8, device="cuda")
+    rng = np.random.default_rng(3001)
+    ebn0 = rng.uniform(1.0, 4.0, size=len(plans))
+    for i, p in enumerate(plans):
+        if counts[i] == 0:
+            continue
+        data = P.gen_data(p, 3002, 0, int(counts[i]))
+        code = P.encode(p, data)
+        llr = P.channel(p, code, float(ebn0[i]), 3003 + i, 0)
+        dst = d_llr[int(region[i]):int(region[i + 1])].view(int(counts[i]), strides[i])
+        dst[:, :p.info.n_tx * 2].copy_(llr.view(torch.uint8).view(int(counts[i]), -1))
+    # frame descriptors in draw order
+    slot = np.zeros(n, dtype=np.int64)
+    seen = np.zeros(len(plans), dtype=np.int64)
+    order = np.argsort(plan_of, kind="stable")
+    sorted_plans = plan_of[order]
+    starts = np.searchsorted(sorted_plans, np.arange(len(plans)))
+    rank = np.empty(n, dtype=np.int64)
+    rank[order] = np.arange(n) - starts[sorted_plans]
+    st_arr = np.array(strides, dtype=np.int64)
+    slot = region[plan_of] + rank * st_arr[plan_of]
+    iw = np.array([p.info.info_words for p in plans], dtype=np.int64)[plan_of]
+    out_off = np.concatenate([[0], np.cumsum(iw)[:-1]])
+    desc = np.zeros((n, 4), dtype=np.uint32)
+    desc[:, 0] = slot & 0xFFFFFFFF
+    desc[:, 1] = slot >> 32
+    desc[:, 2] = out_off
+    desc[:, 3] = plan_of
+    d_fr = torch.from_numpy(desc.view(np.int32)).cuda()
+    kd = np.array([p.info.k_data for p in plans], dtype=np.int64)
+    info_bits = int((kd[plan_of]).sum())
+    coded_bits = int(np.array([p.info.n_tx for p in plans])[plan_of].sum())
+    torch.cuda.synchronize()
+    t_gen = time.perf_counter() - t0 - t_plan
+    stream = torch.cuda.current_stream()
+
+    def timed(fn, reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ms = []
+        for _ in range(reps):
+            e0.record(stream)
+            fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        return float(np.mean(ms))
+
+    # autotune once (untimed), then the timed steps
+    t1 = time.perf_counter()
+    P.decode_batch(plans, d_llr, frames=d_fr, autotune=True, stream=stream)
+    torch.cuda.synchronize()
+    t_tune = time.perf_counter() - t1
+    sched = P.schedule_describe(plans)
+    for _ in range(args.warmup):
+        P.decode_batch(plans, d_llr, frames=d_fr, stream=stream)
+    torch.cuda.synchronize()
+    tw = time.perf_counter()
+    ms_batched = timed(lambda: P.decode_batch(plans, d_llr, frames=d_fr, stream=stream), args.steps)
+    elapsed = time.perf_counter() - tw
+    g = P.Graph(plans, d_llr, frames=d_fr)
+    g.launch(stream)
+    torch.cuda.synchronize()
+    ms_graph = timed(lambda: g.launch(stream), args.steps)
+    ms_plain = None
+    if args.compare_plain:
+        ms_plain = timed(lambda: P.decode_batch(plans, d_llr, frames=d_fr, schedule=1,
+                                                stream=stream), 1)
+    # batched latency from device stamps: completion - batch start, decode time
+    times = torch.zeros((n, 2), dtype=torch.int64, device="cuda")
+    P.decode_batch(plans, d_llr, frames=d_fr, times=times, stream=stream)
+    torch.cuda.synchronize()
+    khz = P.device_clock_khz()
+    t = times.cpu().numpy().astype(np.float64)
+    svc = (t[:, 1] - t[:, 0]) / khz * 1e3
+    done = (t[:, 1] - t[:, 0].min()) / khz * 1e3
+    Ls = np.array([s_[2] for s_ in specs])[plan_of]
+    per_L = {str(l): {"frames": int((Ls == l).sum()),
+                      "decode_p50_us": round(float(np.percentile(svc[Ls == l], 50)), 1),
+                      "decode_p99_us": round(float(np.percentile(svc[Ls == l], 99)), 1)}
+             for l in synth.C3_L}
+    mbps = lambda ms: round(info_bits / (ms / 1e3) / 1e6, 1)
+    out = {
+        "metric": "info Mb/s per MI355X at matched FER + p50/p99 decode latency, batched vs plain",
+        "value": round(info_bits * args.steps / elapsed / 1e6, 1), "unit": "Mb/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(elapsed / args.steps * 1e3, 2), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "i16", "data": "synthetic",
+        "config": {"workload": "uneven_batch_2p20_crc11_i16", "frames": n, "plans": len(plans),
+                   "info_bits": info_bits, "coded_bits": coded_bits,
+                   "schedule": sched, "autotune_s": round(t_tune, 2),
+                   "plan_setup_s": round(t_plan, 2), "input_gen_s": round(t_gen, 2),
+                   "batched_kernel_ms": round(ms_batched, 3), "batched_info_mbps": mbps(ms_batched),
+                   "graph_replay_ms": round(ms_graph, 3), "graph_info_mbps": mbps(ms_graph),
+                   "plain_ms": None if ms_plain is None else round(ms_plain, 3),
+                   "plain_info_mbps": None if ms_plain is None else mbps(ms_plain),
+                   "coded_mbps": round(coded_bits / (ms_batched / 1e3) / 1e6, 1),
+                   "latency": {"batch_completion_p50_us": round(float(np.percentile(done, 50)), 1),
+                               "batch_completion_p99_us": round(float(np.percentile(done, 99)), 1),
+                               "decode_p50_us": round(float(np.percentile(svc, 50)), 1),
+                               "decode_p99_us": round(float(np.percentile(svc, 99)), 1),
+                               "per_list_size": per_L}},
+    }
+    print(json.dumps(out))
+
+
+def bench_served(args):
+    """Served decoding: requests of mixed sizes (N in {32 .. 1024} with
+    P(N) ~ 1/N, K ~ U{12 .. N/2} incl. CRC-11, FA-SSCL L = 1 -> 8, Eb/N0 ~
+    U[0, 3] dB), pre-staged in HBM, released at Poisson arrival times of 0.5
+    to 8 M requests/s into the library's serving loop (continuous batching
+    over 4 HIP streams, frame budget), for float32 and int8 LLRs.  Latency is
+    host-observed completion minus scheduled arrival.  Beside it: the same
+    requests as one batch (device stamps) and as the plain one-launch form."""
+    import torch
+
+    from paper_1710_08314_amd import polar as P
+    from paper_1710_08314_amd import synth
+
+    torch.cuda.set_device(0)
+    n = args.frames if args.frames != 1_000_000 else 1_000_000
+    c, poly = synth.C4_CRC
+    stream = torch.cuda.current_stream()
+    results = {}
+    for quant in ("f32", "i8"):
+        qv = P.QUANT_NAMES[quant]
+        es = P.ELEM_BYTES[qv]
+        specs, plan_of, ebn0, _ = synth.served_requests(4100, n, 1.0e6)
+        plans = [P.Plan(N, K, c, poly, design_ebn0_db=synth.C4_DESIGN_DB, algo=P.FA_SCL,
+                        L_max=synth.C4_L_MAX, quant=qv) for (N, K) in specs]
+        # LLR pool: per plan, its requests sorted by Eb/N0 in 8 chunks, each
+        # generated at the chunk's median Eb/N0 (within ~0.2 dB of every draw)
+        strides = np.array([((p.info.n_tx * es + 15) // 16) * 16 for p in plans], dtype=np.int64)
+        slot = np.zeros(n, dtype=np.int64)
+        order = np.lexsort((ebn0, plan_of))
+        pool = int(strides[plan_of].sum())
+        d_llr = torch.empty(pool, dtype=torch.uint8, device="cuda")
+        off = 0
+        pos = 0
+        counts = np.bincount(plan_of, minlength=len(plans))
+        for i, p in enumerate(plans):
+            reqs = order[pos:pos + counts[i]]
+            pos += counts[i]
+            for ch in np.array_split(reqs, min(8, len(reqs))) if len(reqs) else []:
+                m = len(ch)
+                slot[ch] = off + np.arange(m) * strides[i]
+                data = P.gen_data(p, 4101, off, m)
+                code = P.encode(p, data)
+                llr = P.channel(p, code, float(np.median(ebn0[ch])), 4102, off)
+                dst = d_llr[off:off + m * int(strides[i])].view(m, int(strides[i]))
+                dst[:, :p.info.n_tx * es].copy_(llr.view(torch.uint8).view(m, -1))
+                off += m * int(strides[i])
+        iw = np.array([p.info.info_words for p in plans], dtype=np.int64)[plan_of]
+        out_off = np.concatenate([[0], np.cumsum(iw)[:-1]])
+        desc = np.zeros((n, 4), dtype=np.uint32)
+        desc[:, 0] = slot & 0xFFFFFFFF
+        desc[:, 1] = slot >> 32
+        desc[:, 2] = out_off
+        desc[:, 3] = plan_of
+        d_fr = torch.from_numpy(desc.view(np.int32)).cuda()
+        info_bits = int(np.array([p.info.k_data for p in plans], dtype=np.int64)[plan_of].sum())
+        n_words = int(iw.sum())
+        # one batch (not served), with device stamps, and the plain form
+        times = torch.zeros((n, 2), dtype=torch.int64, device="cuda")
+        P.decode_batch(plans, d_llr, frames=d_fr, stream=stream)  # warm-up, plan table
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        b_info, b_st, _ = P.decode_batch(plans, d_llr, frames=d_fr, stream=stream, times=times)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms_batch = e0.elapsed_time(e1)
+        khz = P.device_clock_khz()
+        t = times.cpu().numpy().astype(np.float64)
+        done = (t[:, 1] - t[:, 0].min()) / khz * 1e3
+        e0.record(stream)
+        P.decode_batch(plans, d_llr, frames=d_fr, schedule=1, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms_plain = e0.elapsed_time(e1)
+        hist = np.bincount(b_st[:, 1].cpu().numpy(), minlength=9)
+        per_rate = {}
+        srv = P.Server(n_slots=4, max_batch=16384, max_inflight=65536)
+        for k, rate in enumerate(synth.C4_RATES_MREQ):
+            rng = np.random.default_rng(4200 + k)
+            gaps = rng.exponential(1.0 / rate, size=n)  # us
+            arrival = np.cumsum(gaps) - gaps[0]
+            info = torch.zeros(max(n_words, 1), dtype=torch.int32, device="cuda")
+            status = torch.zeros((n, 8), dtype=torch.uint8, device="cuda")
+            torch.cuda.synchronize()
+            done_us, stats = srv.replay(plans, d_fr, arrival, d_llr, info, status)
+            torch.cuda.synchronize()
+            same = bool(torch.equal(status, b_st) and torch.equal(info[:n_words], b_info[:n_words]))
+            lat = done_us - arrival
+            per_rate[str(rate)] = {
+                "offered_mreq_s": rate, "served_mreq_s": round(n / stats["session_us"], 3),
+                "info_mbps": round(info_bits / stats["session_us"], 1),
+                "latency_p50_us": round(float(np.percentile(lat, 50)), 1),
+                "latency_p99_us": round(float(np.percentile(lat, 99)), 1),
+                "batches": stats["batches"], "mean_batch": round(stats["mean_batch"], 1),
+                "peak_inflight": stats["peak_inflight"], "results_equal_batch": same}
+            print(f"served {quant} {rate} Mreq/s: {per_rate[str(rate)]}", file=sys.stderr,
+                  flush=True)
+        srv.close()
+        results[quant] = {
+            "requests": n, "plans": len(plans), "info_bits": info_bits,
+            "L_used_hist": {str(l): int(hist[l]) for l in (1, 2, 4, 8) if hist[l]},
+            "batched": {"kernel_ms": round(ms_batch, 3),
+                        "info_mbps": round(info_bits / (ms_batch / 1e3) / 1e6, 1),
+                        "completion_p50_us": round(float(np.percentile(done, 50)), 1),
+                        "completion_p99_us": round(float(np.percentile(done, 99)), 1)},
+            "plain": {"kernel_ms": round(ms_plain, 3),
+                      "info_mbps": round(info_bits / (ms_plain / 1e3) / 1e6, 1)},
+            "served": per_rate}
+        del plans
+    best = max(results["i8"]["served"].values(), key=lambda v: v["info_mbps"])
+    out = {
+        "metric": "info Mb/s per MI355X at matched FER + p50/p99 decode latency, batched vs plain",
+        "value": best["info_mbps"], "unit": "Mb/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "i8", "data": "synthetic",
+        "config": {"workload": "served_fa_lmax8_crc11_n32_1024", "per_quant": results},
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -151,9 +401,17 @@ def main():
                     help="also time the plain one-launch form once per point")
     ap.add_argument("--calib-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (HBM counter calibration)")
+    ap.add_argument("--workload", default="headline", choices=["headline", "uneven", "served"],
+                    help="uneven: the batched uneven launch (2^20 frames of mixed codes); "
+                         "served: Poisson arrivals of mixed-size requests through the serving loop")
     args = ap.parse_args()
     if args.calib_copy:
         calib_copy(args.calib_copy)
+        return
+    if args.workload in ("uneven", "served"):
+        if args.gpus != 1:
+            sys.exit(2)
+        (bench_uneven if args.workload == "uneven" else bench_served)(args)
         return
     if args.gpus != 1:
         print("bench.py runs on one GPU: the decoder shards frames across GPUs with no "

@@ -41,6 +41,7 @@ extern "C" {
 #define POLAR_ENOMEM (-3)    /* device or host allocation failed                 */
 #define POLAR_EHIP (-4)      /* a HIP runtime call failed                        */
 #define POLAR_ENOTSYS (-5)   /* frozen set unusable for systematic encoding      */
+#define POLAR_EAGAIN (-6)    /* serving: no free slot or budget right now; poll  */
 
 /* ------------------------------------------------------------ enumerations */
 /* LLR / path-metric arithmetic (Sec. III-B3).  Integer modes saturate to
@@ -260,6 +261,58 @@ int polar_graph_create(const polar_plan *plans, uint32_t n_plans, const polar_fr
                        const polar_decode_opts *opts, polar_graph *out);
 int polar_graph_launch(polar_graph g, void *stream);
 int polar_graph_destroy(polar_graph g);
+
+/* -------------------------------------------------------------- serving */
+/* Continuous batching of decode requests on one device.  A server owns
+ * `n_slots` HIP streams, each with a work area for up to `max_batch` frames.
+ * A submitted batch (a range of a caller's frame descriptors whose LLRs are
+ * already in device memory) is admitted when a slot is free and the frames
+ * in flight stay within `max_inflight`; it is then enqueued at once on the
+ * slot's stream, so batches admitted while others run overlap on the device.
+ * All decoding, including the adaptive list escalation (Sec. II-B5), happens
+ * on the device without host round trips; the host only admits and polls. */
+typedef struct {
+  uint32_t n_slots;       /* concurrent batches (HIP streams), 1..64             */
+  uint32_t max_batch;     /* frames per batch                                    */
+  uint32_t max_inflight;  /* admission budget: frames admitted, not yet complete */
+  uint32_t reserved;
+} polar_server_config;
+
+typedef struct polar_server_s *polar_server;
+
+int polar_server_create(const polar_server_config *cfg, polar_server *out);
+
+/* Admit one batch: frames [first, first + count) of d_frames, decoded as by
+ * polar_scl_decode_batch with schedule 0 (outputs at the descriptors' out_off
+ * in d_info, statuses at d_status[first ..]).  Returns POLAR_OK and *slot, or
+ * POLAR_EAGAIN when no slot is free or the budget is full (nothing enqueued),
+ * POLAR_EINVAL when count exceeds max_batch.  `tag` is returned by poll. */
+int polar_server_submit(polar_server s, const polar_plan *plans, uint32_t n_plans,
+                        const polar_frame *d_frames, uint32_t first, uint32_t count,
+                        const void *d_llr, uint32_t *d_info, polar_status *d_status,
+                        uint64_t tag, uint32_t *slot);
+
+/* Non-blocking: the tags of batches that completed since the last poll
+ * (up to max), their slots freed.  *n receives the count. */
+int polar_server_poll(polar_server s, uint64_t *tags, uint32_t max, uint32_t *n);
+
+/* Frames admitted and not yet reported complete. */
+int polar_server_inflight(polar_server s, uint32_t *frames);
+
+int polar_server_destroy(polar_server s);
+
+/* Serving session over requests pre-staged in device memory: request r is
+ * frame r of d_frames and arrives at host time arrival_us[r] (microseconds
+ * after the call starts, non-decreasing).  The loop releases requests at
+ * their arrival times and, whenever a slot and budget are free, admits every
+ * released request not yet admitted (up to max_batch) as one batch; it polls
+ * completions and writes, per request, the host-observed completion time
+ * (us, same clock) to complete_us.  stats (nullable, 4 values): batches,
+ * mean frames per batch, largest frames in flight, session length in us. */
+int polar_serve_replay(polar_server s, const polar_plan *plans, uint32_t n_plans,
+                       const polar_frame *d_frames, uint32_t n_req, const double *arrival_us,
+                       const void *d_llr, uint32_t *d_info, polar_status *d_status,
+                       double *complete_us, double *stats);
 
 /* --------------------------------------------------------------- misc */
 /* Frequency of the device realtime counter used by d_times, in kHz, for the

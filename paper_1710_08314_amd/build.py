@@ -17,7 +17,7 @@ LIB = os.path.join(PKG, "libpolar_scl.so")
 BUILD_DIR = os.path.join(PKG, "_build")
 
 HIP_SOURCES = ["decode.hip", "sc.hip", "gen.hip"]
-CPP_SOURCES = ["plan.cpp", "capi.cpp"]
+CPP_SOURCES = ["plan.cpp", "capi.cpp", "server.cpp"]
 
 ARCH = os.environ.get("POLAR_OFFLOAD_ARCH", "gfx950")
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-fno-strict-aliasing", "-Wall",

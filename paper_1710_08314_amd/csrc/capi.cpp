@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "../../include/polar_scl.h"
+#include "batch.h"
 #include "kernels.h"
 #include "plan.h"
 
@@ -26,22 +27,10 @@ namespace {
 
 std::mutex g_mu;
 
-// Work area of one decode: queue 1 and queue 2 of the tiered schedule (cap + 2
-// words each: [0] frames queued, [1] next to take, then frame indices) and
-// the per-class counters of the class schedule.
-size_t work_words(size_t cap) { return 2 * (cap + 2) + polar::kMaxClasses; }
-struct Work {
-  uint32_t* q1 = nullptr;
-  uint32_t* q2 = nullptr;
-  uint32_t* heads = nullptr;
-};
-Work work_view(uint32_t* base, size_t cap) {
-  Work w;
-  w.q1 = base;
-  w.q2 = base + cap + 2;
-  w.heads = base + 2 * (cap + 2);
-  return w;
-}
+using polar::Work;
+using polar::work_view;
+using polar::work_words;
+using polar::Batch;
 
 // per-device shared work area (grown on demand) and compute-unit count
 struct Scratch {
@@ -264,15 +253,26 @@ int polar_plan_get_frozen(polar_plan p, uint32_t* fw) {
 
 }  // extern "C"
 
-namespace {
+namespace polar {
 
-// A validated batch: kernel arguments and what the schedules need.
-struct Batch {
-  polar::KArgs A{};
-  uint32_t quant = 0, lds = 0;
-  bool fixed_list = true;  // every plan has one stage (SC or CA-SCL)
-  std::vector<polar_plan> plans;
-};
+size_t work_words(size_t cap) { return cap + 2 + kMaxClasses; }
+
+Work work_view(uint32_t* base, size_t cap) {
+  Work w;
+  w.state = base;
+  w.tier_heads = base + cap;
+  w.heads = base + cap + 2;
+  return w;
+}
+
+}  // namespace polar
+
+namespace {
+using polar::launch_batch;
+using polar::prepare;
+}  // namespace
+
+namespace polar {
 
 int prepare(const polar_plan* plans, uint32_t n_plans, const polar_frame* d_frames,
             uint32_t n_frames, const void* d_llr, uint32_t* d_info, polar_status* d_status,
@@ -308,6 +308,10 @@ int prepare(const polar_plan* plans, uint32_t n_plans, const polar_frame* d_fram
   A.times = opts ? opts->d_times : nullptr;
   return POLAR_OK;
 }
+
+}  // namespace polar
+
+namespace {
 
 bool uses_classes(const Batch& b, uint32_t schedule) {
   return schedule == 0 && b.fixed_list && b.plans.size() > 1 && b.A.frames != nullptr;
@@ -450,6 +454,10 @@ int run_classes(const Batch& b, const Work& w, hipStream_t st, bool autotune, hi
                                       ev0, ev1);
 }
 
+}  // namespace
+
+namespace polar {
+
 // Launch one decode of a prepared batch on `st` with work area `w`.
 int launch_batch(const Batch& b, uint32_t schedule, const Work& w, hipStream_t st, bool timed,
                  bool autotune) {
@@ -484,7 +492,6 @@ int launch_batch(const Batch& b, uint32_t schedule, const Work& w, hipStream_t s
   // plan has a stage of list size 2..4; list tier B if any plan has a stage
   // above 4 (the stages of a plan: SC {1}, CA {L}, PA {1, L_max}, FA {1, 2,
   // 4, ..., L_max})
-  const uint32_t n_plans = (uint32_t)b.plans.size();
   polar::TierPlan tp{};
   uint32_t lds_sc = 0, lds_a = 0;
   for (polar_plan p : b.plans) {
@@ -494,16 +501,13 @@ int launch_batch(const Batch& b, uint32_t schedule, const Work& w, hipStream_t s
     const bool has_a = (h.first_stage > 1 && h.first_stage <= polar::kTierALmax) ||
                        (h.first_stage == 1 && h.max_list > 1 &&
                         (fa || h.max_list <= polar::kTierALmax));
-    // list tier A is used for single-plan batches only: a batch of several
-    // plans goes from the SC tier straight to list tier B (which then runs
-    // every remaining stage)
-    if (has_a && n_plans == 1) {
+    if (has_a) {
       tp.run_a = true;
       const uint32_t la = h.max_list < polar::kTierALmax ? h.max_list : polar::kTierALmax;
       const uint32_t lb = polar::plan_lds_bytes(h, la);
       lds_a = lb > lds_a ? lb : lds_a;
     }
-    if (h.max_list > polar::kTierALmax || (n_plans > 1 && h.max_list > 1)) tp.run_b = true;
+    if (h.max_list > polar::kTierALmax) tp.run_b = true;
     const uint32_t l1 = polar::sc_lds_bytes(h.N, polar::elem_bytes(h.quant));
     lds_sc = l1 > lds_sc ? l1 : lds_sc;
   }
@@ -517,7 +521,15 @@ int launch_batch(const Batch& b, uint32_t schedule, const Work& w, hipStream_t s
   tp.grid_a = persistent_grid(cus, lds_a, 16, n_frames);
   tp.lds_b = b.lds;
   tp.grid_b = persistent_grid(cus, b.lds, 4, n_frames);
-  rc = polar::launch_decode_tiered(b.quant, A, tp, w.q1, w.q2, st, ev);
+  // frames claimed at a time: 64 (one wave's worth of state words) when the
+  // batch spreads over the workgroups at least 8 times, fewer for small batches
+  auto chunk_of = [&](uint32_t grid) {
+    const uint64_t c = n_frames / ((uint64_t)(grid ? grid : 1) * 8);
+    return (uint32_t)(c < 1 ? 1 : (c > 64 ? 64 : c));
+  };
+  tp.chunk_a = chunk_of(tp.grid_a);
+  tp.chunk_b = chunk_of(tp.grid_b);
+  rc = polar::launch_decode_tiered(b.quant, A, tp, w.state, w.tier_heads, st, ev);
   if (ev) {
     g_timing.ran[0] = tp.run_sc;
     g_timing.ran[1] = tp.run_a;
@@ -733,6 +745,7 @@ const char* polar_strerror(int err) {
     case POLAR_ENOMEM: return "out of memory";
     case POLAR_EHIP: return "HIP runtime error";
     case POLAR_ENOTSYS: return "frozen set not usable for systematic encoding";
+    case POLAR_EAGAIN: return "no free serving slot or budget; poll and retry";
     default: return "unknown error";
   }
 }

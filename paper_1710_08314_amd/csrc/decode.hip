@@ -816,7 +816,7 @@ __device__ void setup_stage(Ctx& c, uint32_t L) {
 template <typename T, int NT, int LMAX>
 __device__ bool decode_frame(char* smem, const KArgs& A, uint32_t f, const DevPlan* P,
                              const char* llr, uint32_t out_off, uint32_t L_first,
-                             uint32_t L_stop) {
+                             uint32_t L_stop, uint32_t* L_last = nullptr) {
   using Acc = typename VT<T>::Acc;
   Ctx c;
   c.smem = smem;
@@ -836,7 +836,10 @@ __device__ bool decode_frame(char* smem, const KArgs& A, uint32_t f, const DevPl
     run_program<T, NT, LMAX>(c, a);
     chosen = end_of_stage<T, NT>(c, a, &ok);
     if (ok || L >= P->L_max) break;
-    if (L >= L_stop) return false;
+    if (L >= L_stop) {
+      if (L_last) *L_last = L;
+      return false;
+    }
     L = (P->algo == POLAR_PA_SCL) ? P->L_max : 2 * L;
   }
   // ---- outputs
@@ -929,54 +932,66 @@ __global__ __launch_bounds__(NW * 64) void k_decode_plain(KArgs A) {
   }
 }
 
-// Escalation queues (device scratch): [0] frames queued, [1] next to take,
-// [2 ..] frame indices.
-__global__ void k_queue_reset(uint32_t* q1, uint32_t* q2) {
-  if (threadIdx.x < 2) {
-    q1[threadIdx.x] = 0;
-    q2[threadIdx.x] = 0;
+// Per-frame state of the tiered schedule (device scratch): state[f] = the
+// list size of frame f's next stage, 0 once its outputs are written.  Every
+// frame starts at its plan's first stage; the two list-tier claim counters
+// start at zero.
+__global__ void k_state_init(KArgs A, uint32_t* state, uint32_t* heads) {
+  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < 2) heads[t] = 0;
+  for (uint32_t f = t; f < A.n_frames; f += gridDim.x * blockDim.x) {
+    const DevPlan* P = A.frames ? A.plans[A.frames[f].plan_idx] : A.plans[0];
+    state[f] = P->first_stage;
   }
 }
 
-// First stage of a frame's schedule above L_done (Sec. II-B5): the plan's
-// first stage if not yet run, else L_max (partially adaptive) or 2 L_done
-// (fully adaptive).
-__device__ __forceinline__ uint32_t next_stage(const DevPlan* P, uint32_t L_done) {
-  if (P->first_stage > L_done) return P->first_stage;
-  if (P->algo == POLAR_PA_SCL) return P->L_max;
-  return 2 * L_done;
-}
-
-// List tier: persistent workgroups take frames from q_in (or, in direct mode,
-// every frame), run the stages of their schedule in (L_done, L_hi], and pass
-// the frames that still fail the CRC on to q_out.
+// List tier: persistent workgroups claim the frames `chunk` (1..64) at a
+// time; wave 0 reads their state words and picks the frames whose next stage lies in
+// [L_lo, L_hi] (a ballot, shared through LDS with the other waves, so every
+// wave of the workgroup works on the same frames).  For each picked frame the
+// stages of its schedule up to L_hi run in place; its state becomes 0 when
+// its outputs are written, else the list size of its next stage.  Frame
+// indices come only from the claim counter, never from memory the device
+// wrote.
 template <typename T, int NW, int LMAX>
-__global__ __launch_bounds__(NW * 64) void k_decode_list(KArgs A, uint32_t* q_in, uint32_t* q_out,
-                                                         int direct, uint32_t L_done,
-                                                         uint32_t L_hi) {
+__global__ __launch_bounds__(NW * 64) void k_decode_list(KArgs A, uint32_t* state, uint32_t* head,
+                                                         uint32_t L_lo, uint32_t L_hi,
+                                                         uint32_t chunk) {
   extern __shared__ __attribute__((aligned(16))) char smem[];
-  __shared__ uint32_t s_idx;
-  // a queue never holds more frames than the batch
-  const uint32_t total = direct ? A.n_frames : min(q_in[0], A.n_frames);
+  __shared__ uint32_t s_base;
+  __shared__ unsigned long long s_mask;
+  __shared__ uint32_t s_L0[64];
   for (;;) {
-    if (threadIdx.x == 0) s_idx = atomicAdd(&q_in[1], 1u);
+    if (threadIdx.x == 0) s_base = atomicAdd(head, chunk);
     __syncthreads();
-    const uint32_t idx = s_idx;
-    __syncthreads();
-    if (idx >= total) break;
-    const uint32_t f = direct ? idx : q_in[2 + idx];
-    const DevPlan* P;
-    const char* llr;
-    uint32_t out_off;
-    frame_of(A, f, P, llr, out_off);
-    if (direct && A.times && threadIdx.x == 0) A.times[2 * (size_t)f] = wall_clock64();
-    const uint32_t L0 = next_stage(P, L_done);
-    bool done = false;
-    if (L0 <= L_hi) done = decode_frame<T, NW * 64, LMAX>(smem, A, f, P, llr, out_off, L0, L_hi);
-    if (!done && threadIdx.x == 0) {
-      const uint32_t slot = atomicAdd(&q_out[0], 1u);
-      q_out[2 + slot] = f;
+    const uint32_t base = s_base;
+    if (base >= A.n_frames) break;
+    if (threadIdx.x < 64) {
+      const uint32_t f = base + threadIdx.x;
+      const uint32_t L0 = (threadIdx.x < chunk && f < A.n_frames) ? state[f] : 0u;
+      s_L0[threadIdx.x] = L0;
+      const unsigned long long b = __ballot(L0 >= L_lo && L0 <= L_hi);
+      if (threadIdx.x == 0) s_mask = b;
     }
+    __syncthreads();
+    unsigned long long mask = s_mask;
+    while (mask) {
+      const uint32_t j = (uint32_t)(__ffsll(mask) - 1);
+      mask &= mask - 1ull;
+      const uint32_t f = base + j;
+      const uint32_t L0 = s_L0[j];
+      const DevPlan* P;
+      const char* llr;
+      uint32_t out_off;
+      frame_of(A, f, P, llr, out_off);
+      if (L0 == P->first_stage && A.times && threadIdx.x == 0)
+        A.times[2 * (size_t)f] = wall_clock64();
+      uint32_t L_last = L0;
+      const bool done =
+          decode_frame<T, NW * 64, LMAX>(smem, A, f, P, llr, out_off, L0, L_hi, &L_last);
+      if (threadIdx.x == 0) state[f] = done ? 0u : next_stage(P, L_last);
+    }
+    __syncthreads();
   }
 }
 
@@ -1120,43 +1135,35 @@ int launch_decode_plain(uint32_t quant, const KArgs& A, uint32_t lds, uint32_t g
 }
 
 template <typename T>
-static int launch_tiered_t(const KArgs& A, const TierPlan& tp, uint32_t* q1, uint32_t* q2,
+static int launch_tiered_t(const KArgs& A, const TierPlan& tp, uint32_t* state, uint32_t* heads,
                            hipStream_t s, hipEvent_t* ev) {
-  hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, s, q1, q2);
+  const uint32_t blocks = (A.n_frames + 255) / 256 < 2048 ? (A.n_frames + 255) / 256 : 2048;
+  hipLaunchKernelGGL(k_state_init, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, s, A, state, heads);
   if (ev) (void)hipEventRecord(ev[0], s);
-  uint32_t* q_cur = q1;
-  int direct = 1;
-  uint32_t L_done = 0;
   if (tp.run_sc) {
     const int rc = launch_decode_sc(VT<T>::INT ? (sizeof(T) == 2 ? POLAR_I16 : POLAR_I8) : POLAR_F32,
-                                    A, tp.lds_sc, tp.grid_sc, q1, ClassSel{}, s);
+                                    A, tp.lds_sc, tp.grid_sc, state, ClassSel{}, s);
     if (rc) return rc;
-    direct = 0;
-    L_done = 1;
   }
   if (ev) (void)hipEventRecord(ev[1], s);
-  if (tp.run_a) {
-    hipLaunchKernelGGL((k_decode_list<T, 1, (int)kTierALmax>), dim3(tp.grid_a), dim3(64), tp.lds_a, s, A, q_cur, q2, direct, L_done,
-                       kTierALmax);
-    q_cur = q2;
-    direct = 0;
-    L_done = kTierALmax;
-  }
+  if (tp.run_a)
+    hipLaunchKernelGGL((k_decode_list<T, 1, (int)kTierALmax>), dim3(tp.grid_a), dim3(64), tp.lds_a,
+                       s, A, state, heads, 2u, kTierALmax, tp.chunk_a);
   if (ev) (void)hipEventRecord(ev[2], s);
-  if (tp.run_b) {
-    hipLaunchKernelGGL((k_decode_list<T, kListWaves, (int)kMaxL>), dim3(tp.grid_b), dim3(kListWaves * 64), tp.lds_b, s, A, q_cur,
-                       q_cur == q1 ? q2 : q1, direct, L_done, kMaxL);
-  }
+  if (tp.run_b)
+    hipLaunchKernelGGL((k_decode_list<T, kListWaves, (int)kMaxL>), dim3(tp.grid_b),
+                       dim3(kListWaves * 64), tp.lds_b, s, A, state, heads + 1,
+                       tp.run_a ? kTierALmax + 1 : 2u, kMaxL, tp.chunk_b);
   if (ev) (void)hipEventRecord(ev[3], s);
   return hipGetLastError() == hipSuccess ? POLAR_OK : POLAR_EHIP;
 }
 
-int launch_decode_tiered(uint32_t quant, const KArgs& A, const TierPlan& tp, uint32_t* q1,
-                         uint32_t* q2, hipStream_t s, hipEvent_t* ev) {
+int launch_decode_tiered(uint32_t quant, const KArgs& A, const TierPlan& tp, uint32_t* state,
+                         uint32_t* heads, hipStream_t s, hipEvent_t* ev) {
   switch (quant) {
-    case POLAR_F32: return launch_tiered_t<float>(A, tp, q1, q2, s, ev);
-    case POLAR_I16: return launch_tiered_t<int16_t>(A, tp, q1, q2, s, ev);
-    default: return launch_tiered_t<int8_t>(A, tp, q1, q2, s, ev);
+    case POLAR_F32: return launch_tiered_t<float>(A, tp, state, heads, s, ev);
+    case POLAR_I16: return launch_tiered_t<int16_t>(A, tp, state, heads, s, ev);
+    default: return launch_tiered_t<int8_t>(A, tp, state, heads, s, ev);
   }
 }
 

@@ -29,34 +29,51 @@ struct KArgs {
 int launch_decode_plain(uint32_t quant, const KArgs& A, uint32_t lds, uint32_t grid,
                         hipStream_t s);
 
-// Tiered schedule.  SC tier: one wave per frame with the L = 1 footprint,
-// pushing the CRC failures of adaptive plans (and untouched fixed-list
-// frames) to queue 1.  List tier A: one wave per frame with the L = 4
-// footprint, stages of L <= 4, failures to queue 2.  List tier B: several
-// waves per frame with the largest footprint, the remaining stages.  Each
-// tier's kernel is persistent and drains its input queue; a tier whose
-// predecessors did not run takes every frame directly.
+// Tiered schedule.  A per-frame state word holds the list size of each
+// frame's next stage (0 once its outputs are written), initialised to its
+// plan's first stage.  SC tier: one wave per frame with the L = 1 footprint,
+// decodes the frames whose plan starts at L = 1.  List tier A: one wave per
+// frame with the L = 4 footprint, the frames whose next stage is 2..4, up to
+// L = 4.  List tier B: several waves per frame with the largest footprint,
+// the frames whose next stage is above A's range, to the end.  The list
+// tiers are persistent kernels that scan the state words 64 frames at a
+// time; a frame that leaves a tier unfinished carries its next stage in its
+// state word, so escalation needs no host round trip and no frame list.
 constexpr int kListWaves = 4;       // waves per frame in list tier B
 constexpr uint32_t kTierALmax = 4;  // largest list size of list tier A
 
 struct TierPlan {
   bool run_sc, run_a, run_b;
   uint32_t lds_sc, lds_a, lds_b, grid_sc, grid_a, grid_b;
+  uint32_t chunk_a, chunk_b;  // frames a list-tier workgroup claims at a time (1..64)
 };
+// state: n_frames words; heads: 2 claim counters (tiers A and B).
 // ev (nullable): 4 events recorded before the first tier and after the SC
 // tier, list tier A and list tier B.
-int launch_decode_tiered(uint32_t quant, const KArgs& A, const TierPlan& tp, uint32_t* q1,
-                         uint32_t* q2, hipStream_t s, hipEvent_t* ev);
+int launch_decode_tiered(uint32_t quant, const KArgs& A, const TierPlan& tp, uint32_t* state,
+                         uint32_t* heads, hipStream_t s, hipEvent_t* ev);
+
+#if defined(__HIPCC__)
+// First stage of a frame's schedule (Sec. II-B5) above L_done: the plan's
+// first stage if not yet run, else L_max (partially adaptive) or 2 L_done
+// (fully adaptive).
+__device__ __forceinline__ uint32_t next_stage(const DevPlan* P, uint32_t L_done) {
+  if (P->first_stage > L_done) return P->first_stage;
+  if (P->algo == POLAR_PA_SCL) return P->L_max;
+  return 2 * L_done;
+}
+#endif
+
 // The SC tier kernel alone (sc.hip); `lds` = sc_lds_bytes of the largest N.
 // With `sel` on, the kernel decodes only the frames of its class and skips
-// the others (no queue); otherwise frames of plans whose first stage is not
-// L = 1 are queued untouched.
+// the others (no state); otherwise it decodes the frames of plans that start
+// at L = 1 and records their state.
 struct ClassSel {
   uint32_t on;
   uint32_t lmin, lmax;  // the plan's first stage (list size) in [lmin, lmax]
   uint32_t nmin, nmax;  // the plan's code length in [nmin, nmax]
 };
-int launch_decode_sc(uint32_t quant, const KArgs& A, uint32_t lds, uint32_t grid, uint32_t* queue,
+int launch_decode_sc(uint32_t quant, const KArgs& A, uint32_t lds, uint32_t grid, uint32_t* state,
                      const ClassSel& sel, hipStream_t s);
 
 // Class schedule of a batch of fixed-list plans (no escalation): the frames

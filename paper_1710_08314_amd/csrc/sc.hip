@@ -1,7 +1,7 @@
 // L = 1 tier of the decoder on gfx950: successive cancellation over the
 // pruned tree (Sec. II-B1, II-B3) for every frame, one wave per frame, with
 // the CRC check of the fully / partially adaptive schedules (Sec. II-B5) and
-// a device escalation queue for the frames that need a list.
+// a per-frame state word for the frames that need a list.
 //
 // A list of one path never forks, so this tier keeps no candidate lists, no
 // path copies and no slot indirection.  Its layout follows the shape of the
@@ -385,11 +385,13 @@ __device__ __forceinline__ void lds_op(char* smem, uint32_t N, uint32_t opc, uin
 
 }  // namespace
 
-// One wave per frame.  Frames of fixed-list plans (first stage > 1) are
-// queued untouched; frames of adaptive plans whose L = 1 decision fails the
-// CRC are queued for the list tier; every other frame is finished here.
+// One wave per frame.  Tiered schedule (sel off): only frames whose plan
+// starts at L = 1 are decoded here; a frame of an adaptive plan whose L = 1
+// decision fails the CRC gets its next list size in state[f] (the list tiers
+// pick it up), every other decoded frame is finished here (state[f] = 0).
+// Class schedule (sel on): only the frames of the class, no state.
 template <typename T>
-__global__ __launch_bounds__(64) void k_sc(KArgs A, uint32_t* queue, ClassSel sel) {
+__global__ __launch_bounds__(64) void k_sc(KArgs A, uint32_t* state, ClassSel sel) {
   extern __shared__ __attribute__((aligned(16))) char smem[];
   using V = typename Lane<T>::V;
   using Acc = typename VT<T>::Acc;
@@ -415,11 +417,7 @@ __global__ __launch_bounds__(64) void k_sc(KArgs A, uint32_t* queue, ClassSel se
           P->N > sel.nmax)
         continue;
     } else if (P->first_stage != 1) {
-      if (lane == 0) {
-        const uint32_t slot = atomicAdd(&queue[0], 1u);
-        queue[2 + slot] = f;
-      }
-      continue;
+      continue;  // a list tier starts it (state[f] already holds its first stage)
     }
     if (A.times && lane == 0) A.times[2 * (size_t)f] = wall_clock64();
     const uint32_t N = P->N, n = P->n, ntx = P->n_tx, n_ops = P->n_ops;
@@ -473,14 +471,12 @@ __global__ __launch_bounds__(64) void k_sc(KArgs A, uint32_t* queue, ClassSel se
     }
     for (int s = 32; s >= 1; s >>= 1) syn ^= __shfl_xor(syn, s, 64);
     const bool ok = rfl(syn) == 0u;
-    if (!ok && P->L_max > 1) {
-      if (lane == 0) {
-        const uint32_t slot = atomicAdd(&queue[0], 1u);
-        queue[2 + slot] = f;
-      }
+    if (!ok && P->L_max > 1 && !sel.on) {
+      if (lane == 0) state[f] = next_stage(P, 1);
       __syncthreads();
       continue;
     }
+    if (!sel.on && lane == 0) state[f] = 0;
     // ---- outputs: information bits (data positions of A, ascending)
     uint32_t* out = reinterpret_cast<uint32_t*>(smem + sc_out_off(N, E));
     const uint32_t iw = P->info_words;
@@ -527,18 +523,18 @@ __global__ __launch_bounds__(64) void k_sc(KArgs A, uint32_t* queue, ClassSel se
 }
 
 template <typename T>
-static int launch_sc_t(const KArgs& A, uint32_t lds, uint32_t grid, uint32_t* queue,
+static int launch_sc_t(const KArgs& A, uint32_t lds, uint32_t grid, uint32_t* state,
                        const ClassSel& sel, hipStream_t s) {
-  hipLaunchKernelGGL(k_sc<T>, dim3(grid), dim3(64), lds, s, A, queue, sel);
+  hipLaunchKernelGGL(k_sc<T>, dim3(grid), dim3(64), lds, s, A, state, sel);
   return hipGetLastError() == hipSuccess ? POLAR_OK : POLAR_EHIP;
 }
 
-int launch_decode_sc(uint32_t quant, const KArgs& A, uint32_t lds, uint32_t grid, uint32_t* queue,
+int launch_decode_sc(uint32_t quant, const KArgs& A, uint32_t lds, uint32_t grid, uint32_t* state,
                      const ClassSel& sel, hipStream_t s) {
   switch (quant) {
-    case POLAR_F32: return launch_sc_t<float>(A, lds, grid, queue, sel, s);
-    case POLAR_I16: return launch_sc_t<int16_t>(A, lds, grid, queue, sel, s);
-    default: return launch_sc_t<int8_t>(A, lds, grid, queue, sel, s);
+    case POLAR_F32: return launch_sc_t<float>(A, lds, grid, state, sel, s);
+    case POLAR_I16: return launch_sc_t<int16_t>(A, lds, grid, state, sel, s);
+    default: return launch_sc_t<int8_t>(A, lds, grid, state, sel, s);
   }
 }
 

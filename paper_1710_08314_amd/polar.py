@@ -27,7 +27,9 @@ ELEM_BYTES = {F32: 4, I16: 2, I8: 1}
 
 ERRORS = {0: "success", -1: "invalid argument", -2: "unsupported configuration",
           -3: "out of memory", -4: "HIP runtime error",
-          -5: "frozen set not usable for systematic encoding"}
+          -5: "frozen set not usable for systematic encoding",
+          -6: "no free serving slot or budget"}
+EAGAIN = -6
 
 
 class PolarError(RuntimeError):
@@ -58,12 +60,19 @@ class _Opts(ctypes.Structure):
                 ("d_times", ctypes.c_void_p), ("reserved", ctypes.c_uint32 * 4)]
 
 
+class _ServerCfg(ctypes.Structure):
+    _fields_ = [("n_slots", ctypes.c_uint32), ("max_batch", ctypes.c_uint32),
+                ("max_inflight", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
 EXPORTS = ["polar_scl_plan", "polar_plan_destroy", "polar_plan_get_info", "polar_plan_get_frozen",
            "polar_plan_query",
            "polar_scl_decode_batch", "polar_encode", "polar_gen_data", "polar_channel",
            "polar_plan_stage_work", "polar_device_clock_khz", "polar_last_tier_ms",
            "polar_schedule_describe", "polar_graph_create", "polar_graph_launch",
-           "polar_graph_destroy", "polar_strerror",
+           "polar_graph_destroy", "polar_server_create", "polar_server_submit",
+           "polar_server_poll", "polar_server_inflight", "polar_server_destroy",
+           "polar_serve_replay", "polar_strerror",
            "polar_version"]
 
 
@@ -88,6 +97,13 @@ def _load():
     L.polar_graph_create.argtypes = [vp, u32, vp, u32, vp, vp, vp, vp, vp, ctypes.POINTER(vp)]
     L.polar_graph_launch.argtypes = [vp, vp]
     L.polar_graph_destroy.argtypes = [vp]
+    L.polar_server_create.argtypes = [ctypes.POINTER(_ServerCfg), ctypes.POINTER(vp)]
+    L.polar_server_submit.argtypes = [vp, vp, u32, vp, u32, u32, vp, vp, vp, u64,
+                                      ctypes.POINTER(u32)]
+    L.polar_server_poll.argtypes = [vp, ctypes.POINTER(u64), u32, ctypes.POINTER(u32)]
+    L.polar_server_inflight.argtypes = [vp, ctypes.POINTER(u32)]
+    L.polar_server_destroy.argtypes = [vp]
+    L.polar_serve_replay.argtypes = [vp, vp, u32, vp, u32, vp, vp, vp, vp, vp, vp]
     L.polar_strerror.argtypes = [ctypes.c_int]
     L.polar_strerror.restype = ctypes.c_char_p
     L.polar_version.restype = ctypes.c_char_p
@@ -311,6 +327,63 @@ class Graph:
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             lib.polar_graph_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """polar_server_*: continuous batching over `n_slots` HIP streams."""
+
+    def __init__(self, n_slots=4, max_batch=4096, max_inflight=16384):
+        cfg = _ServerCfg(n_slots, max_batch, max_inflight, 0)
+        h = ctypes.c_void_p()
+        _check(lib.polar_server_create(ctypes.byref(cfg), ctypes.byref(h)), "polar_server_create")
+        self._h = h
+
+    def submit(self, plans, frames, first, count, llr, info, status, tag=0):
+        """Admit frames [first, first + count); False when no slot or budget."""
+        arr = (ctypes.c_void_p * len(plans))(*[p.handle.value for p in plans])
+        slot = ctypes.c_uint32()
+        rc = lib.polar_server_submit(self._h, arr, len(plans), _dptr(frames), first, count,
+                                     _dptr(llr), _dptr(info), _dptr(status), tag,
+                                     ctypes.byref(slot))
+        if rc == EAGAIN:
+            return False
+        _check(rc, "polar_server_submit")
+        return True
+
+    def poll(self, max_tags=64):
+        tags = (ctypes.c_uint64 * max_tags)()
+        n = ctypes.c_uint32()
+        _check(lib.polar_server_poll(self._h, tags, max_tags, ctypes.byref(n)), "polar_server_poll")
+        return [int(tags[i]) for i in range(n.value)]
+
+    def inflight(self):
+        v = ctypes.c_uint32()
+        _check(lib.polar_server_inflight(self._h, ctypes.byref(v)), "polar_server_inflight")
+        return int(v.value)
+
+    def replay(self, plans, frames, arrival_us, llr, info, status):
+        """polar_serve_replay: returns (completion times in us, stats dict)."""
+        arr = (ctypes.c_void_p * len(plans))(*[p.handle.value for p in plans])
+        arrival = np.ascontiguousarray(arrival_us, dtype=np.float64)
+        n = len(arrival)
+        done = np.zeros(n, dtype=np.float64)
+        stats = np.zeros(4, dtype=np.float64)
+        _check(lib.polar_serve_replay(self._h, arr, len(plans), _dptr(frames), n,
+                                      arrival.ctypes.data, _dptr(llr), _dptr(info), _dptr(status),
+                                      done.ctypes.data, stats.ctypes.data), "polar_serve_replay")
+        return done, {"batches": int(stats[0]), "mean_batch": float(stats[1]),
+                      "peak_inflight": int(stats[2]), "session_us": float(stats[3])}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib.polar_server_destroy(self._h)
             self._h = ctypes.c_void_p()
 
     def __del__(self):

@@ -120,3 +120,28 @@ def frame_draws(seed: int, f: int, k_data: int, n_tx: int):
     (seed, frame), for batches whose frames all differ in size)."""
     rng = np.random.Generator(np.random.Philox(np.random.SeedSequence([int(seed), 0xF, int(f)])))
     return rng.integers(0, 2, size=k_data, dtype=np.uint8), rng.standard_normal(size=n_tx)
+
+
+# 4. Served decoding: Poisson arrivals of requests of mixed sizes.
+C4_N = (32, 64, 128, 256, 512, 1024)
+C4_CRC = (11, 0x621)
+C4_L_MAX = 8
+C4_DESIGN_DB = 1.5
+C4_RATES_MREQ = (0.5, 1.0, 2.0, 4.0, 8.0)
+
+
+def served_requests(seed: int, n: int, rate_per_s: float):
+    """n requests: N with P(N) proportional to 1/N, K ~ U{12 .. N/2} (|A|
+    including CRC-11), Eb/N0 ~ U[0, 3] dB and Poisson arrival times (us).
+    Returns (codes, code_idx, ebn0, arrival_us) with `codes` the distinct
+    (N, K)."""
+    rng = np.random.Generator(np.random.Philox(np.random.SeedSequence([int(seed), 0xC4])))
+    w = 1.0 / np.array(C4_N, dtype=np.float64)
+    N = rng.choice(np.array(C4_N), size=n, p=w / w.sum())
+    K = rng.integers(12, N // 2 + 1)
+    ebn0 = rng.uniform(0.0, 3.0, size=n)
+    gaps = rng.exponential(1e6 / rate_per_s, size=n)
+    arrival = np.cumsum(gaps) - gaps[0]
+    key = np.stack([N, K], axis=1)
+    codes, code_idx = np.unique(key, axis=0, return_inverse=True)
+    return [tuple(int(v) for v in c) for c in codes], code_idx.reshape(-1), ebn0, arrival

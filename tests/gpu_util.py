@@ -125,7 +125,17 @@ def uneven_inputs(seed: int, n: int, with_codes_for=None):
     for (N, K, L, S) in specs:
         fz = O.construct(N, K, S, c, synth.C3_DESIGN_DB)
         codes.append(oracle_code(N, K, c, poly, fz, S=S, quant=q, algo="ca", L=L))
-    es = np.dtype(O.DTYPES[q]).itemsize
+    out = pack_inputs(codes, plan_of, ebn0, seed)
+    out["specs"] = specs
+    return out
+
+
+def pack_inputs(codes, plan_of, ebn0, seed):
+    """Frames of mixed codes built on the host by the oracle (frame f: code
+    codes[plan_of[f]], Eb/N0 ebn0[f], draws synth.frame_draws(seed, f)),
+    packed for a multi-plan decode: each frame's LLRs 16-byte aligned."""
+    n = len(plan_of)
+    es = np.dtype(O.DTYPES[codes[0].quant]).itemsize
     offs = np.zeros(n, dtype=np.int64)
     out_off = np.zeros(n, dtype=np.int64)
     off = out = 0
@@ -150,8 +160,8 @@ def uneven_inputs(seed: int, n: int, with_codes_for=None):
     desc[:, 1] = offs >> 32
     desc[:, 2] = out_off
     desc[:, 3] = plan_of
-    return {"specs": specs, "codes": codes, "plan_of": plan_of, "data": data, "raw": raw,
-            "desc": desc, "out_off": out_off, "ebn0": ebn0}
+    return {"codes": codes, "plan_of": plan_of, "data": data, "raw": raw, "desc": desc,
+            "out_off": out_off, "ebn0": ebn0}
 
 
 def check_uneven(inp, info_words, status, sample, pm_lists=None):
