@@ -521,10 +521,11 @@ int launch_batch(const Batch& b, uint32_t schedule, const Work& w, hipStream_t s
   tp.grid_a = persistent_grid(cus, lds_a, 16, n_frames);
   tp.lds_b = b.lds;
   tp.grid_b = persistent_grid(cus, b.lds, 4, n_frames);
-  // frames claimed at a time: 64 (one wave's worth of state words) when the
-  // batch spreads over the workgroups at least 8 times, fewer for small batches
+  // frames claimed at a time: about n / (32 workgroups' worth), so that the
+  // frames a tier has to decode spread evenly over its workgroups; at most 64
+  // (one wave's worth of state words), at least 1
   auto chunk_of = [&](uint32_t grid) {
-    const uint64_t c = n_frames / ((uint64_t)(grid ? grid : 1) * 8);
+    const uint64_t c = n_frames / ((uint64_t)(grid ? grid : 1) * 32);
     return (uint32_t)(c < 1 ? 1 : (c > 64 ? 64 : c));
   };
   tp.chunk_a = chunk_of(tp.grid_a);

@@ -933,9 +933,9 @@ __global__ __launch_bounds__(NW * 64) void k_decode_plain(KArgs A) {
 }
 
 // Per-frame state of the tiered schedule (device scratch): state[f] = the
-// list size of frame f's next stage, 0 once its outputs are written.  Every
-// frame starts at its plan's first stage; the two list-tier claim counters
-// start at zero.
+// list size of frame f's next stage (a finished frame holds 0 or 1, which no
+// list tier takes).  Every frame starts at its plan's first stage; the two
+// list-tier claim counters start at zero.
 __global__ void k_state_init(KArgs A, uint32_t* state, uint32_t* heads) {
   const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t < 2) heads[t] = 0;

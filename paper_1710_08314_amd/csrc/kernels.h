@@ -30,8 +30,9 @@ int launch_decode_plain(uint32_t quant, const KArgs& A, uint32_t lds, uint32_t g
                         hipStream_t s);
 
 // Tiered schedule.  A per-frame state word holds the list size of each
-// frame's next stage (0 once its outputs are written), initialised to its
-// plan's first stage.  SC tier: one wave per frame with the L = 1 footprint,
+// frame's next stage, initialised to its plan's first stage; a finished
+// frame's word is 0 (list tiers) or stays 1 (SC tier), which no list tier
+// takes.  SC tier: one wave per frame with the L = 1 footprint,
 // decodes the frames whose plan starts at L = 1.  List tier A: one wave per
 // frame with the L = 4 footprint, the frames whose next stage is 2..4, up to
 // L = 4.  List tier B: several waves per frame with the largest footprint,

@@ -388,7 +388,8 @@ __device__ __forceinline__ void lds_op(char* smem, uint32_t N, uint32_t opc, uin
 // One wave per frame.  Tiered schedule (sel off): only frames whose plan
 // starts at L = 1 are decoded here; a frame of an adaptive plan whose L = 1
 // decision fails the CRC gets its next list size in state[f] (the list tiers
-// pick it up), every other decoded frame is finished here (state[f] = 0).
+// pick it up); every other decoded frame is finished here (its state keeps
+// the value 1, which no list tier takes).
 // Class schedule (sel on): only the frames of the class, no state.
 template <typename T>
 __global__ __launch_bounds__(64) void k_sc(KArgs A, uint32_t* state, ClassSel sel) {
@@ -476,7 +477,6 @@ __global__ __launch_bounds__(64) void k_sc(KArgs A, uint32_t* state, ClassSel se
       __syncthreads();
       continue;
     }
-    if (!sel.on && lane == 0) state[f] = 0;
     // ---- outputs: information bits (data positions of A, ascending)
     uint32_t* out = reinterpret_cast<uint32_t*>(smem + sc_out_off(N, E));
     const uint32_t iw = P->info_words;
