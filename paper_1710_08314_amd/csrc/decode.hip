@@ -695,9 +695,12 @@ __device__ void op_node(const Ctx& c, uint32_t opc, uint32_t d, uint32_t o, uint
 // ------------------------------------------------------------ one stage
 template <typename T, int NT, int LMAX>
 __device__ void run_program(const Ctx& c, uint32_t& a) {
-  const uint32_t n_ops = c.P->n_ops;
+  const uint32_t n_ops = uni(c.P->n_ops);
+  // the next op word is fetched while the current op runs
+  uint32_t w_next = n_ops ? c.prog[0] : 0u;
   for (uint32_t pc = 0; pc < n_ops; ++pc) {
-    const uint32_t w = c.prog[pc];
+    const uint32_t w = uni(w_next);
+    if (pc + 1 < n_ops) w_next = c.prog[pc + 1];
     const uint32_t opc = op_code(w), d = op_depth(w), o = op_off(w);
     switch (opc) {
       case OP_F:
@@ -741,11 +744,12 @@ __device__ uint32_t end_of_stage(const Ctx& c, uint32_t a, bool* ok) {
   __syncthreads();
   if (tid < 64) sort_keys<Key>(cand, a, sel, a);
   // syndromes
-  const uint32_t* infomask = plan_tab(c.P, c.P->off_infomask);
-  const uint32_t* nib = plan_tab(c.P, c.P->off_crcnib);
+  const uint32_t* infomask = plan_tab(c.P, uni(c.P->off_infomask));
+  const uint32_t* nib = plan_tab(c.P, uni(c.P->off_crcnib));
+  const uint32_t crc_len = uni(c.P->c);
   const uint32_t lbw = lg2(c.bw), items = a << lbw;
   const uint32_t nq = c.N >= 32 ? 8u : (c.N + 3) / 4;
-  if (c.P->c > 0) {
+  if (crc_len > 0) {
     for (uint32_t it = tid; it < items; it += NT) {
       const uint32_t r = it >> lbw, w = it & (c.bw - 1u);
       const uint32_t v = bits_of(c, r)[w] & infomask[w];
@@ -766,8 +770,8 @@ __device__ uint32_t end_of_stage(const Ctx& c, uint32_t a, bool* ok) {
     }
   }
   __syncthreads();
-  *ok = misc[1] != 0;
-  return misc[0];
+  *ok = uni(misc[1]) != 0;
+  return uni(misc[0]);
 }
 
 // Load the channel LLRs into the root buffer; shortened positions get the
@@ -776,7 +780,7 @@ template <typename T, int NT>
 __device__ void load_root(const Ctx& c, const char* llr) {
   constexpr uint32_t E = VT<T>::E;
   T* root = reinterpret_cast<T*>(c.smem + c.lay.root);
-  const uint32_t ntx = c.P->n_tx;
+  const uint32_t ntx = uni(c.P->n_tx);
   const uint32_t nbytes = ntx * E;
   if ((((uintptr_t)llr) & 15u) == 0 && (nbytes & 15u) == 0) {
     const uint4* src = reinterpret_cast<const uint4*>(llr);
@@ -818,38 +822,43 @@ __device__ bool decode_frame(char* smem, const KArgs& A, uint32_t f, const DevPl
                              const char* llr, uint32_t out_off, uint32_t L_first,
                              uint32_t L_stop, uint32_t* L_last = nullptr) {
   using Acc = typename VT<T>::Acc;
+  P = uni_ptr(P);
+  llr = uni_ptr(llr);
+  out_off = uni(out_off);
+  L_first = uni(L_first);
   Ctx c;
   c.smem = smem;
   c.P = P;
-  c.prog = plan_tab(P, P->off_prog);
-  c.N = P->N;
-  c.n = P->n;
-  c.bw = P->bw;
+  c.prog = uni_ptr(plan_tab(P, uni(P->off_prog)));
+  c.N = uni(P->N);
+  c.n = uni(P->n);
+  c.bw = uni(P->bw);
   c.L = 1;
   c.lay = lds_layout(c.N, c.n, VT<T>::E, 1, (uint32_t)sizeof(typename VT<T>::Key));
   load_root<T, NT>(c, llr);
   uint32_t L = L_first, chosen = 0, a = 1;
+  const uint32_t L_max = uni(P->L_max), algo = uni(P->algo);
   bool ok = false;
   for (;;) {
     setup_stage<T, NT>(c, L);
     a = 1;
     run_program<T, NT, LMAX>(c, a);
     chosen = end_of_stage<T, NT>(c, a, &ok);
-    if (ok || L >= P->L_max) break;
+    if (ok || L >= L_max) break;
     if (L >= L_stop) {
       if (L_last) *L_last = L;
       return false;
     }
-    L = (P->algo == POLAR_PA_SCL) ? P->L_max : 2 * L;
+    L = (algo == POLAR_PA_SCL) ? L_max : 2 * L;
   }
   // ---- outputs
   const uint32_t tid = threadIdx.x;
   uint32_t* out = reinterpret_cast<uint32_t*>(c.smem + c.lay.out);
-  const uint32_t iw = P->info_words;
+  const uint32_t iw = uni(P->info_words);
   for (uint32_t i = tid; i < iw; i += NT) out[i] = 0;
   __syncthreads();
-  const uint32_t* dmask = plan_tab(P, P->off_datamask);
-  const uint32_t* dpre = plan_tab(P, P->off_dataprefix);
+  const uint32_t* dmask = plan_tab(P, uni(P->off_datamask));
+  const uint32_t* dpre = plan_tab(P, uni(P->off_dataprefix));
   const uint32_t* xb = bits_of(c, chosen);
   for (uint32_t w = tid; w < c.bw; w += NT) {
     const uint32_t x = xb[w];
@@ -964,7 +973,7 @@ __global__ __launch_bounds__(NW * 64) void k_decode_list(KArgs A, uint32_t* stat
   for (;;) {
     if (threadIdx.x == 0) s_base = atomicAdd(head, chunk);
     __syncthreads();
-    const uint32_t base = s_base;
+    const uint32_t base = uni(s_base);
     if (base >= A.n_frames) break;
     if (threadIdx.x < 64) {
       const uint32_t f = base + threadIdx.x;
@@ -974,12 +983,12 @@ __global__ __launch_bounds__(NW * 64) void k_decode_list(KArgs A, uint32_t* stat
       if (threadIdx.x == 0) s_mask = b;
     }
     __syncthreads();
-    unsigned long long mask = s_mask;
+    uint64_t mask = uni64(s_mask);
     while (mask) {
-      const uint32_t j = (uint32_t)(__ffsll(mask) - 1);
+      const uint32_t j = (uint32_t)(__ffsll((unsigned long long)mask) - 1);
       mask &= mask - 1ull;
       const uint32_t f = base + j;
-      const uint32_t L0 = s_L0[j];
+      const uint32_t L0 = uni(s_L0[j]);
       const DevPlan* P;
       const char* llr;
       uint32_t out_off;
@@ -1012,7 +1021,7 @@ __global__ __launch_bounds__(NW * 64) void k_decode_class(KArgs A, uint32_t* hea
   for (;;) {
     if (threadIdx.x == 0) s_base = atomicAdd(head, 64u);
     __syncthreads();
-    const uint32_t base = s_base;
+    const uint32_t base = uni(s_base);
     if (base >= A.n_frames) break;
     if (threadIdx.x < 64) {
       const uint32_t f = base + threadIdx.x;
@@ -1022,10 +1031,10 @@ __global__ __launch_bounds__(NW * 64) void k_decode_class(KArgs A, uint32_t* hea
       if (threadIdx.x == 0) s_mask = b;
     }
     __syncthreads();
-    unsigned long long mask = s_mask;
+    uint64_t mask = uni64(s_mask);
     __syncthreads();
     while (mask) {
-      const uint32_t f = base + (uint32_t)(__ffsll(mask) - 1);
+      const uint32_t f = base + (uint32_t)(__ffsll((unsigned long long)mask) - 1);
       mask &= mask - 1ull;
       const DevPlan* P;
       const char* llr;

@@ -144,6 +144,19 @@ __device__ __forceinline__ void g_chunk(const uint32_t* a, const uint32_t* b, ui
 
 __device__ __forceinline__ uint32_t lg2(uint32_t x) { return 31u - __clz(x); }
 
+// Values that are the same in every lane (a frame's plan, its node program,
+// list sizes, loop bounds) are pinned to scalar registers, so that the
+// control flow built on them is scalar (s_cbranch_scc) rather than
+// exec-masked.  Call only where every lane of the wave is active.
+__device__ __forceinline__ uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ uint64_t uni64(uint64_t v) {
+  return ((uint64_t)uni((uint32_t)(v >> 32)) << 32) | uni((uint32_t)v);
+}
+template <typename Q>
+__device__ __forceinline__ Q* uni_ptr(Q* p) {
+  return reinterpret_cast<Q*>(uni64(reinterpret_cast<uint64_t>(p)));
+}
+
 // ------------------------------------------------------- wave primitives
 template <typename K>
 __device__ __forceinline__ K shfl_xor_k(K v, int m) {

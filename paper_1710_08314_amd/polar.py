@@ -14,6 +14,11 @@ from dataclasses import dataclass
 
 import numpy as np
 
+# PyTorch first: its wheel carries its own HIP runtime, and the library must
+# bind to the runtime PyTorch uses (loading the library first would put the
+# system runtime under PyTorch, which then sees no GPU).
+import torch  # noqa: F401
+
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libpolar_scl.so")
 
