@@ -47,6 +47,7 @@ class _Cfg(ctypes.Structure):
         ("quant", ctypes.c_int32), ("algo", ctypes.c_int32), ("L", ctypes.c_int32),
         ("L_max", ctypes.c_int32), ("node_enable", ctypes.c_int32), ("rep_max", ctypes.c_int32),
         ("spc_max", ctypes.c_int32), ("r1_max", ctypes.c_int32), ("r0_max", ctypes.c_int32),
+        ("P", ctypes.c_int32),
     ]
 
 
@@ -70,6 +71,10 @@ def lib():
         L.orc_construct.restype = i32
         L.orc_construct_lz0.argtypes = [i32, i32, i32, dbl, vp]
         L.orc_construct_lz0.restype = i32
+        L.orc_construct_p.argtypes = [i32, i32, i32, i32, i32, dbl, vp]
+        L.orc_construct_p.restype = i32
+        L.orc_construct_lz0p.argtypes = [i32, i32, i32, i32, dbl, vp]
+        L.orc_construct_lz0p.restype = i32
         L.orc_fg.argtypes = [i32, i32, dbl, dbl, i32]
         L.orc_fg.restype = dbl
         L.orc_transform.argtypes = [i32, vp, vp]
@@ -103,19 +108,21 @@ def logz_from_z0(n: int, lz0: float) -> np.ndarray:
     return out
 
 
-def construct(N: int, K: int, S: int, crc_len: int, design_ebn0_db: float) -> np.ndarray:
-    """Frozen mask (uint8, 1 = frozen) by the Bhattacharyya reading; K = |A|."""
+def construct(N: int, K: int, S: int, crc_len: int, design_ebn0_db: float,
+              P: int = 0) -> np.ndarray:
+    """Frozen mask (uint8, 1 = frozen) by the Bhattacharyya reading; K = |A|;
+    S shortened (last) and P punctured (first) codeword positions."""
     fz = np.zeros(N, dtype=np.uint8)
-    rc = lib().orc_construct(N, K, S, crc_len, float(design_ebn0_db), _p(fz))
+    rc = lib().orc_construct_p(N, K, S, P, crc_len, float(design_ebn0_db), _p(fz))
     if rc:
         raise ValueError("bad construction arguments")
     return fz
 
 
-def construct_lz0(N: int, K: int, S: int, lz0: float) -> np.ndarray:
+def construct_lz0(N: int, K: int, S: int, lz0: float, P: int = 0) -> np.ndarray:
     """Frozen mask from an explicit log Z0 of the underlying channel."""
     fz = np.zeros(N, dtype=np.uint8)
-    if lib().orc_construct_lz0(N, K, S, float(lz0), _p(fz)):
+    if lib().orc_construct_lz0p(N, K, S, P, float(lz0), _p(fz)):
         raise ValueError("bad construction arguments")
     return fz
 
@@ -187,16 +194,17 @@ class Code:
     spc_max: int = 4
     r1_max: int = 0
     r0_max: int = 0
+    P: int = 0  # punctured: the first P codeword positions are not sent
 
     def cfg(self) -> _Cfg:
         self._fz = np.ascontiguousarray(self.frozen, dtype=np.uint8)
         return _Cfg(self.N, self.K, self.crc_len, self.crc_poly, self._fz.ctypes.data, self.S,
                     self.quant, self.algo, self.L, self.L_max, self.node_enable, self.rep_max,
-                    self.spc_max, self.r1_max, self.r0_max)
+                    self.spc_max, self.r1_max, self.r0_max, self.P)
 
     @property
     def n_tx(self) -> int:
-        return self.N - self.S
+        return self.N - self.S - self.P
 
     @property
     def k_data(self) -> int:

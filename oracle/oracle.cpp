@@ -207,6 +207,7 @@ typedef struct {
   int32_t L_max;        // largest list size (PA / FA)
   int32_t node_enable;  // OR of ORC_NODE_*
   int32_t rep_max, spc_max, r1_max, r0_max;  // 0 = unlimited node size
+  int32_t P;            // punctured: codeword positions [0, P) not sent (LLR 0)
 } orc_cfg;
 
 typedef struct {
@@ -221,16 +222,20 @@ void orc_logz_z0(int n, double lz0, double* out) { logz_from_z0(n, lz0, out); }
 
 // Frozen set: the N - |A| least reliable u-indices are frozen, i.e. |A| most
 // reliable kept, ranked by (log Z ascending, index descending).  Shortened
-// u-indices [N-S, N) are frozen first.  Design point: Eb/N0 in dB with
-// R = (K - c) / (N - S) and Z0 = exp(-R Eb/N0).  Returns 0, or -1 on bad args.
-int orc_construct_lz0(int N, int K, int S, double lz0, uint8_t* frozen) {
+// u-indices [N-S, N) and punctured u-indices [0, P) are frozen first: x_j
+// is the XOR of the u_i with i a bitwise superset of j, so [N-S, N) (an
+// up-set) carries only known zeros and, with x_[0,P) (a down-set) not sent,
+// u_[0,P) cannot be recovered.  Design point: Eb/N0 in dB with
+// R = (K - c) / (N - S - P) and Z0 = exp(-R Eb/N0).  Returns 0, or -1 on bad
+// args.
+int orc_construct_lz0p(int N, int K, int S, int P, double lz0, uint8_t* frozen) {
   int n = 0;
   while ((1 << n) < N) ++n;
-  if ((1 << n) != N || K < 0 || S < 0 || K > N - S) return -1;
+  if ((1 << n) != N || K < 0 || S < 0 || P < 0 || K > N - S - P) return -1;
   std::vector<double> lz(N);
   logz_from_z0(n, lz0, lz.data());
   std::vector<int> idx;
-  for (int i = 0; i < N - S; ++i) idx.push_back(i);
+  for (int i = P; i < N - S; ++i) idx.push_back(i);
   std::sort(idx.begin(), idx.end(), [&](int a, int b) {
     if (lz[a] != lz[b]) return lz[a] < lz[b];
     return a > b;
@@ -240,10 +245,19 @@ int orc_construct_lz0(int N, int K, int S, double lz0, uint8_t* frozen) {
   return 0;
 }
 
+int orc_construct_lz0(int N, int K, int S, double lz0, uint8_t* frozen) {
+  return orc_construct_lz0p(N, K, S, 0, lz0, frozen);
+}
+
+int orc_construct_p(int N, int K, int S, int P, int crc_len, double design_ebn0_db,
+                    uint8_t* frozen) {
+  if (N - S - P <= 0) return -1;
+  const double rate = (double)(K - crc_len) / (double)(N - S - P);
+  return orc_construct_lz0p(N, K, S, P, -rate * std::pow(10.0, design_ebn0_db / 10.0), frozen);
+}
+
 int orc_construct(int N, int K, int S, int crc_len, double design_ebn0_db, uint8_t* frozen) {
-  if (N - S <= 0) return -1;
-  const double rate = (double)(K - crc_len) / (double)(N - S);
-  return orc_construct_lz0(N, K, S, -rate * std::pow(10.0, design_ebn0_db / 10.0), frozen);
+  return orc_construct_p(N, K, S, 0, crc_len, design_ebn0_db, frozen);
 }
 
 // f (op 0) or g (op 1, partial sum s) of the given mode on one pair, for the
@@ -606,11 +620,12 @@ template <class A>
 int decode_frame(const orc_cfg& c, const void* llr_in, uint8_t* info_out, uint8_t* xhat_out,
                  double* pm_list_out, orc_status* st) {
   using V = typename A::V;
-  const int N = c.N, Ntx = c.N - c.S;
+  const int N = c.N, P = c.P, Ntx = c.N - c.S - c.P;
   std::vector<V> chan(N);
   const V* src = (const V*)llr_in;
-  for (int i = 0; i < Ntx; ++i) chan[i] = src[i];
-  for (int i = Ntx; i < N; ++i) chan[i] = A::known();  // shortened: known zero bit
+  for (int i = 0; i < P; ++i) chan[i] = V(0);  // punctured: nothing received
+  for (int i = 0; i < Ntx; ++i) chan[P + i] = src[i];
+  for (int i = P + Ntx; i < N; ++i) chan[i] = A::known();  // shortened: known zero bit
   std::vector<int> stages = stage_schedule(c);
   std::vector<uint8_t> b_hat, x_hat;
   std::vector<double> pm_list;
@@ -643,11 +658,13 @@ int check_cfg(const orc_cfg* c) {
   int n = 0;
   while ((1 << n) < c->N) ++n;
   if (c->N < 1 || (1 << n) != c->N) return -1;
-  if (c->S < 0 || c->S >= c->N) return -1;
+  if (c->S < 0 || c->P < 0 || c->S + c->P >= c->N) return -1;
   int na = 0;
   for (int i = 0; i < c->N; ++i) na += c->frozen[i] ? 0 : 1;
   if (na != c->K || c->crc_len < 0 || c->crc_len > 64 || c->crc_len > c->K) return -1;
   for (int i = c->N - c->S; i < c->N; ++i)
+    if (!c->frozen[i]) return -1;
+  for (int i = 0; i < c->P; ++i)
     if (!c->frozen[i]) return -1;
   if (c->algo == ORC_CA_SCL && c->L < 1) return -1;
   if ((c->algo == ORC_PA_SCL || c->algo == ORC_FA_SCL) && (c->L_max < 1 || c->crc_len == 0))
@@ -687,19 +704,19 @@ extern "C" {
 
 // Batch helpers of the Monte-Carlo chain (test-input generation): frame f
 // has kd data bits data[f * kd ...], gets b = data || CRC, the systematic
-// codeword, then BPSK/AWGN LLRs of its first N - S positions quantised to
-// the mode (noise[f * (N - S) ...] standard normals).  `out` holds
-// (N - S) values of the mode per frame.
+// codeword, then BPSK/AWGN LLRs of its sent positions [P, N - S) quantised
+// to the mode (noise[f * ntx ...] standard normals, ntx = N - S - P).
+// `out` holds ntx values of the mode per frame.
 int orc_make_frames(const orc_cfg* c, int n, const uint8_t* data, const double* noise,
                     double sigma, int frac, void* out) {
-  const int N = c->N, ntx = c->N - c->S, kd = c->K - c->crc_len;
+  const int N = c->N, ntx = c->N - c->S - c->P, kd = c->K - c->crc_len;
   std::vector<uint8_t> b(c->K), x(N);
   std::vector<double> l(ntx);
   const size_t es = elem_size(c->quant);
   for (int f = 0; f < n; ++f) {
     orc_attach_crc(data + (size_t)f * kd, kd, c->crc_len, c->crc_poly, b.data());
     orc_encode(N, c->frozen, b.data(), x.data());
-    orc_bpsk_awgn_llr(x.data(), ntx, noise + (size_t)f * ntx, sigma, l.data());
+    orc_bpsk_awgn_llr(x.data() + c->P, ntx, noise + (size_t)f * ntx, sigma, l.data());
     orc_quantize(l.data(), ntx, c->quant, frac, (char*)out + (size_t)f * ntx * es);
   }
   return 0;

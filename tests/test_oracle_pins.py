@@ -533,3 +533,117 @@ def test_shortened_positions_are_certain_zeros(quant, known):
     # and differs from treating them as erasures (LLR 0) on some frame
     era = np.concatenate([llr, np.zeros((40, S), dtype=llr.dtype)], axis=1)
     assert not np.array_equal(O.decode(full, era).pm_list, a.pm_list)
+
+
+# ------------------------------------------------------------ puncturing
+def test_punctured_bits_only_reach_punctured_positions():
+    """x_j is the XOR of the u_i whose index is a bitwise superset of j
+    (the rows of F^{(x)n}), so u_i with i < P reaches only positions j <= i:
+    when x_[0,P) is not sent those bits are invisible, which is why the
+    construction freezes u_[0,P).  Checked on the generator matrix itself."""
+    for n in (3, 4, 5):
+        N = 1 << n
+        G = kron_F(n)
+        for P in range(1, N):
+            for i in range(P):
+                assert not G[i, P:].any()
+            # and every u_i with i >= P reaches some sent position
+            for i in range(P, N):
+                assert G[i, P:].any()
+
+
+@pytest.mark.parametrize("N,K,P", [(16, 6, 3), (16, 8, 5), (32, 10, 7), (32, 16, 11)])
+def test_punctured_construction_keeps_codewords_distinct(N, K, P):
+    """With u_[0,P) frozen, the 2^K codewords stay distinct on the sent
+    positions [P, N): maximum-likelihood decoding of the punctured code is
+    well posed.  The frozen set holds [0, P) and otherwise the most reliable
+    positions of the unpunctured ranking."""
+    fz = O.construct(N, K, 0, 0, 2.0, P=P)
+    assert fz[:P].all() and int((fz == 0).sum()) == K
+    sent = all_codewords(fz)[:, P:]
+    assert len({r.tobytes() for r in sent}) == 1 << K
+    # ranking among [P, N) matches the unpunctured construction's order
+    lz = O.logz_from_z0(int(math.log2(N)), -0.5)
+    A = np.where(fz == 0)[0]
+    fz_lz = O.construct_lz0(N, K, 0, -0.5, P=P)
+    rest = sorted(range(P, N), key=lambda i: (lz[i], -i))[:K]
+    assert sorted(rest) == list(np.where(fz_lz == 0)[0])
+    assert len(A) == K
+
+
+@pytest.mark.parametrize("quant", [O.F32, O.I16, O.I8])
+def test_punctured_positions_are_erasures(quant):
+    """A punctured position is a bit nobody received: decoding the punctured
+    frame equals decoding the full-length frame whose first P LLRs are 0."""
+    rng = np.random.default_rng(40 + quant)
+    N, K, P, c, poly = 256, 90, 37, 11, 0x621
+    fz = O.construct(N, K, 0, c, 1.5, P=P)
+    pu = O.Code(N, K, fz, c, poly, P=P, quant=quant, algo=O.CA_SCL, L=4)
+    full = O.Code(N, K, fz, c, poly, quant=quant, algo=O.CA_SCL, L=4)
+    llr = np.round(rng.normal(0.5, 3.0, (40, N - P)) * 4)
+    if quant == O.I8:
+        llr = np.clip(llr, -127, 127)
+    llr = llr.astype(O.DTYPES[quant])
+    ext = np.concatenate([np.zeros((40, P), dtype=llr.dtype), llr], axis=1)
+    a, b = O.decode(pu, llr), O.decode(full, ext)
+    assert np.array_equal(a.xhat, b.xhat)
+    np.testing.assert_array_equal(a.pm_list, b.pm_list)
+    # zeros placed at the end instead would change the result on some frame
+    tail = np.concatenate([llr, np.zeros((40, P), dtype=llr.dtype)], axis=1)
+    assert not np.array_equal(O.decode(full, tail).pm_list, a.pm_list)
+
+
+@pytest.mark.parametrize("N,K,P", [(16, 6, 3), (16, 5, 6)])
+def test_punctured_large_list_is_maximum_likelihood(N, K, P):
+    """With L >= 2^K the punctured decode is maximum likelihood over the sent
+    positions: its metric is the least discrepancy of x[P:] against the
+    received LLRs, attained by a unique codeword."""
+    rng = np.random.default_rng(N + P)
+    fz = O.construct(N, K, 0, 0, 2.0, P=P)
+    cws = all_codewords(fz)
+    for t in range(10):
+        llr = np.round(rng.normal(0.6, 2.0, N - P) * 4).astype(np.float32)
+        D = np.array([discrepancy(x[P:], llr) for x in cws])
+        code = O.Code(N, K, fz, P=P, quant=O.F32, algo=O.CA_SCL, L=1 << K, spc_max=4, r1_max=2)
+        r = O.decode(code, llr)
+        assert r.pm[0] == D.min()
+        assert discrepancy(r.xhat[0][P:], llr) == D.min()
+
+
+@pytest.mark.parametrize("quant", [O.F32, O.I16, O.I8])
+def test_punctured_noiseless_and_frame_slice(quant):
+    """Noiseless punctured frames decode to their data, and the sent LLRs are
+    BPSK of the codeword slice [P, N - S)."""
+    rng = np.random.default_rng(50 + quant)
+    N, K, S, P, c, poly = 512, 200, 30, 45, 11, 0x621
+    fz = O.construct(N, K, S, c, 2.0, P=P)
+    code = O.Code(N, K, fz, c, poly, S=S, P=P, quant=quant, algo=O.CA_SCL, L=4)
+    data = rng.integers(0, 2, (16, K - c), dtype=np.uint8)
+    noise = np.zeros((16, N - S - P))
+    llr = O.make_frames(code, data, noise, 0.5)
+    for f in range(4):
+        x = O.encode(fz, O.attach_crc(data[f], c, poly))
+        assert np.array_equal((llr[f] < 0).astype(np.uint8), x[P:N - S])
+    r = O.decode(code, llr)
+    assert np.array_equal(r.info, data) and (r.crc_ok == 1).all()
+
+
+@pytest.mark.parametrize("N,K,P,design", [(256, 96, 96, 1.0), (512, 192, 192, 3.0)])
+def test_punctured_construction_rate_and_forced_freeze(N, K, P, design):
+    """Puncturing changes the construction in two ways, both visible here:
+    the design rate is K / (N - P) (the sent length), and u_[0,P) is frozen
+    even where the unpunctured ranking would put information bits."""
+    n = int(math.log2(N))
+    fz = O.construct(N, K, 0, 0, design, P=P)
+    # the rate over sent positions: the same set as an explicit log Z0 at that
+    # rate, and a different set from the rate over all N positions
+    lz0 = -(K / (N - P)) * 10 ** (design / 10)
+    assert np.array_equal(fz, O.construct_lz0(N, K, 0, lz0, P=P))
+    assert not np.array_equal(fz, O.construct_lz0(N, K, 0, -(K / N) * 10 ** (design / 10), P=P))
+    # forced freeze: the unpunctured ranking has information bits below P
+    unp = O.construct_lz0(N, K, 0, lz0)
+    assert (unp[:P] == 0).any()
+    assert fz[:P].all()
+    lz = O.logz_from_z0(n, lz0)
+    best = sorted(range(P, N), key=lambda i: (lz[i], -i))[:K]
+    assert sorted(best) == list(np.where(fz == 0)[0])
