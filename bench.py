@@ -387,6 +387,65 @@ def bench_served(args):
     print(json.dumps(out))
 
 
+def bench_pruning(args):
+    """Tree pruning sweep (Sec. III-B2 / the node study of Sec. IV): the
+    headline code and decoder with the dedicated nodes enabled one family at a
+    time -- none, R0, +REP8-, +R1, +SPC4 (the default), then SPC of any size
+    and REP of any size -- reporting node-program length, throughput and FER
+    at 3.5 and 4.5 dB (10^6 frames each unless --frames is given)."""
+    import torch
+
+    from paper_1710_08314_amd import polar as P
+
+    torch.cuda.set_device(0)
+    W = WORKLOAD
+    F = args.frames
+    stream = torch.cuda.current_stream()
+    R0, R1, REP, SPC = P.NODE_R0, P.NODE_R1, P.NODE_REP, P.NODE_SPC
+    variants = [("none", 0, 8, 4), ("R0", R0, 8, 4), ("R0+REP8", R0 | REP, 8, 4),
+                ("R0+REP8+R1", R0 | REP | R1, 8, 4), ("R0+REP8+R1+SPC4", R0 | REP | R1 | SPC, 8, 4),
+                ("R0+REP8+R1+SPC(any)", R0 | REP | R1 | SPC, 8, 0),
+                ("R0+REP(any)+R1+SPC4", R0 | REP | R1 | SPC, 0, 4)]
+    # the channel is the same for every variant: generate with the default plan
+    base = P.Plan(W["N"], W["K"], W["crc_len"], W["crc_poly"], design_ebn0_db=W["design"],
+                  algo=P.FA_SCL, L_max=W["L_max"], quant=P.I8, rep_max=8, spc_max=4)
+    kd = base.info.k_data
+    points = {}
+    for i, eb in enumerate((3.5, 4.5)):
+        data = P.gen_data(base, 2000 + i, 0, F)
+        llr = P.channel(base, P.encode(base, data), eb, 3000 + i, 0, frac_bits=W["frac"])
+        points[eb] = (data, llr)
+    torch.cuda.synchronize()
+    rows = []
+    for name, enable, rep_max, spc_max in variants:
+        plan = P.Plan(W["N"], W["K"], W["crc_len"], W["crc_poly"], design_ebn0_db=W["design"],
+                      algo=P.FA_SCL, L_max=W["L_max"], quant=P.I8, node_enable=enable,
+                      rep_max=rep_max, spc_max=spc_max)
+        row = {"nodes": name, "n_ops": plan.info.n_ops, "r0": plan.info.n_r0, "r1": plan.info.n_r1,
+               "rep": plan.info.n_rep, "spc": plan.info.n_spc,
+               "leaves": plan.info.n_leaf_frozen + plan.info.n_leaf_info}
+        for eb, (data, llr) in points.items():
+            P.decode_batch(plan, llr, stream=stream)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            info, status, _ = P.decode_batch(plan, llr, stream=stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1)
+            fer = float((info != data).any(dim=1).float().mean().item())
+            row[str(eb)] = {"ms": round(ms, 3), "info_mbps": round(F * kd / (ms / 1e3) / 1e6, 1),
+                            "fer": fer}
+        rows.append(row)
+        print(f"pruning {row}", file=sys.stderr, flush=True)
+    out = {"metric": "info Mb/s per MI355X at matched FER + p50/p99 decode latency, batched vs plain",
+           "value": rows[4]["3.5"]["info_mbps"], "unit": "Mb/s", "n_gpus": 1, "steps": 1,
+           "warmup": 1, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "i8", "data": "synthetic",
+           "config": {"workload": "pruning_sweep_fa2048_k1723_i8", "frames_per_point": F,
+                      "variants": rows}}
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -401,17 +460,18 @@ def main():
                     help="also time the plain one-launch form once per point")
     ap.add_argument("--calib-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (HBM counter calibration)")
-    ap.add_argument("--workload", default="headline", choices=["headline", "uneven", "served"],
+    ap.add_argument("--workload", default="headline",
+                    choices=["headline", "uneven", "served", "pruning"],
                     help="uneven: the batched uneven launch (2^20 frames of mixed codes); "
                          "served: Poisson arrivals of mixed-size requests through the serving loop")
     args = ap.parse_args()
     if args.calib_copy:
         calib_copy(args.calib_copy)
         return
-    if args.workload in ("uneven", "served"):
+    if args.workload in ("uneven", "served", "pruning"):
         if args.gpus != 1:
             sys.exit(2)
-        (bench_uneven if args.workload == "uneven" else bench_served)(args)
+        {"uneven": bench_uneven, "served": bench_served, "pruning": bench_pruning}[args.workload](args)
         return
     if args.gpus != 1:
         print("bench.py runs on one GPU: the decoder shards frames across GPUs with no "

@@ -82,6 +82,9 @@ typedef struct {
   uint32_t spc_max;     /* largest SPC node (0 = unlimited; 4 gives SPC4)            */
   uint32_t r1_max;      /* largest Rate-1 node (0 = unlimited)                       */
   uint32_t r0_max;      /* largest Rate-0 node (0 = unlimited)                       */
+  uint32_t n_puncture;  /* P: codeword positions [0, P) are not sent and decode as
+                         * LLR 0; u-indices [0, P) must be (or are made) frozen; the
+                         * sent LLRs are positions [P, N - S)                         */
 } polar_plan_desc;
 
 typedef struct polar_plan_s *polar_plan;

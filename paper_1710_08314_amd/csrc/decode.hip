@@ -774,24 +774,26 @@ __device__ uint32_t end_of_stage(const Ctx& c, uint32_t a, bool* ok) {
   return uni(misc[0]);
 }
 
-// Load the channel LLRs into the root buffer; shortened positions get the
+// Load the channel LLRs into the root buffer: punctured positions [0, P)
+// received nothing (0), the sent ones follow, and shortened positions get the
 // largest positive value (a zero received with certainty).
 template <typename T, int NT>
 __device__ void load_root(const Ctx& c, const char* llr) {
   constexpr uint32_t E = VT<T>::E;
   T* root = reinterpret_cast<T*>(c.smem + c.lay.root);
-  const uint32_t ntx = uni(c.P->n_tx);
+  const uint32_t ntx = uni(c.P->n_tx), np = uni(c.P->n_punct);
   const uint32_t nbytes = ntx * E;
-  if ((((uintptr_t)llr) & 15u) == 0 && (nbytes & 15u) == 0) {
+  if ((((uintptr_t)llr) & 15u) == 0 && (nbytes & 15u) == 0 && ((np * E) & 15u) == 0) {
     const uint4* src = reinterpret_cast<const uint4*>(llr);
-    uint4* dst = reinterpret_cast<uint4*>(root);
+    uint4* dst = reinterpret_cast<uint4*>(root + np);
     for (uint32_t i = threadIdx.x; i < (nbytes >> 4); i += NT) dst[i] = src[i];
   } else {
     const T* src = reinterpret_cast<const T*>(llr);
-    for (uint32_t i = threadIdx.x; i < ntx; i += NT) root[i] = src[i];
+    for (uint32_t i = threadIdx.x; i < ntx; i += NT) root[np + i] = src[i];
   }
+  for (uint32_t i = threadIdx.x; i < np; i += NT) root[i] = (T)0;
   const T known = VT<T>::INT ? (T)VT<T>::Q : (T)1048576.0f;
-  for (uint32_t i = ntx + threadIdx.x; i < c.N; i += NT) root[i] = known;
+  for (uint32_t i = np + ntx + threadIdx.x; i < c.N; i += NT) root[i] = known;
 }
 
 template <typename T, int NT>

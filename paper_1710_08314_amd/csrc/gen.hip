@@ -119,9 +119,9 @@ __device__ __forceinline__ T quantise(float l, float scale, int Q) {
 }
 
 template <typename T>
-__global__ void k_channel(const uint32_t* code, uint32_t cw, uint32_t n_tx, uint32_t n_frames,
-                          float sigma, float llr_scale, float qscale, int Q, uint64_t seed,
-                          uint64_t frame0, T* out) {
+__global__ void k_channel(const uint32_t* code, uint32_t cw, uint32_t p0, uint32_t n_tx,
+                          uint32_t n_frames, float sigma, float llr_scale, float qscale, int Q,
+                          uint64_t seed, uint64_t frame0, T* out) {
   const uint32_t g4 = (n_tx + 3) / 4;
   const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (gid >= (uint64_t)n_frames * g4) return;
@@ -142,7 +142,8 @@ __global__ void k_channel(const uint32_t* code, uint32_t cw, uint32_t n_tx, uint
   for (int k = 0; k < 4; ++k) {
     const uint32_t i = g * 4 + k;
     if (i < n_tx) {
-      const float s = ((C[i >> 5] >> (i & 31)) & 1u) ? -1.f : 1.f;
+      const uint32_t j = p0 + i;  // sent positions start after the punctured ones
+      const float s = ((C[j >> 5] >> (j & 31)) & 1u) ? -1.f : 1.f;
       const float y = s + sigma * z[k];
       out[(size_t)f * n_tx + i] = quantise<T>(llr_scale * y, qscale, Q);
     }
@@ -179,17 +180,17 @@ int launch_channel(const DevPlan& h, const uint32_t* d_code, uint32_t n_frames, 
   switch (h.quant) {
     case POLAR_F32:
       hipLaunchKernelGGL(k_channel<float>, dim3(blocks), dim3(256), 0, s, d_code, h.code_words,
-                         h.n_tx, n_frames, (float)sigma, llr_scale, qscale, 0, seed, frame0,
+                         h.n_punct, h.n_tx, n_frames, (float)sigma, llr_scale, qscale, 0, seed, frame0,
                          (float*)d_llr);
       break;
     case POLAR_I16:
       hipLaunchKernelGGL(k_channel<int16_t>, dim3(blocks), dim3(256), 0, s, d_code, h.code_words,
-                         h.n_tx, n_frames, (float)sigma, llr_scale, qscale, 32767, seed, frame0,
+                         h.n_punct, h.n_tx, n_frames, (float)sigma, llr_scale, qscale, 32767, seed, frame0,
                          (int16_t*)d_llr);
       break;
     default:
       hipLaunchKernelGGL(k_channel<int8_t>, dim3(blocks), dim3(256), 0, s, d_code, h.code_words,
-                         h.n_tx, n_frames, (float)sigma, llr_scale, qscale, 127, seed, frame0,
+                         h.n_punct, h.n_tx, n_frames, (float)sigma, llr_scale, qscale, 127, seed, frame0,
                          (int8_t*)d_llr);
       break;
   }

@@ -73,8 +73,8 @@ std::vector<double> bhattacharyya_log(uint32_t n, double lz0) {
 
 int make_plan(const polar_plan_desc& d, HostPlan& hp) {
   if (d.N < 2 || d.N > kMaxN || !is_pow2(d.N)) return d.N > kMaxN && is_pow2(d.N) ? POLAR_EUNSUP : POLAR_EINVAL;
-  const uint32_t N = d.N, n = ilog2(N), S = d.n_shorten;
-  if (S >= N || d.K == 0 || d.K > N - S) return POLAR_EINVAL;
+  const uint32_t N = d.N, n = ilog2(N), S = d.n_shorten, Pn = d.n_puncture;
+  if (S >= N || Pn >= N - S || d.K == 0 || d.K > N - S - Pn) return POLAR_EINVAL;
   if (d.crc_len > 32) return POLAR_EUNSUP;
   if (d.crc_len >= d.K) return POLAR_EINVAL;
   if (d.quant > POLAR_I8 || d.algo > POLAR_FA_SCL) return POLAR_EINVAL;
@@ -105,12 +105,17 @@ int make_plan(const polar_plan_desc& d, HostPlan& hp) {
     if (na != d.K) return POLAR_EINVAL;
     for (uint32_t j = N - S; j < N; ++j)
       if (!bit(frozen, j)) return POLAR_EINVAL;
+    for (uint32_t j = 0; j < Pn; ++j)
+      if (!bit(frozen, j)) return POLAR_EINVAL;
   } else {
-    const double rate = double(d.K - d.crc_len) / double(N - S);
+    // rate over the sent positions; shortened u-indices [N-S, N) (their bits
+    // are known zeros) and punctured u-indices [0, P) (their bits reach only
+    // unsent positions) are frozen before ranking the rest
+    const double rate = double(d.K - d.crc_len) / double(N - S - Pn);
     const double lz0 = -rate * std::pow(10.0, double(d.design_ebn0_db) / 10.0);
     std::vector<double> lz = bhattacharyya_log(n, lz0);
-    std::vector<uint32_t> idx(N - S);
-    std::iota(idx.begin(), idx.end(), 0u);
+    std::vector<uint32_t> idx(N - S - Pn);
+    std::iota(idx.begin(), idx.end(), Pn);
     // most reliable first: smaller log Z, ties to the larger index
     std::stable_sort(idx.begin(), idx.end(), [&](uint32_t a, uint32_t b) {
       return lz[a] < lz[b] || (lz[a] == lz[b] && a > b);
@@ -221,7 +226,8 @@ int make_plan(const polar_plan_desc& d, HostPlan& hp) {
   h.n = n;
   h.K = d.K;
   h.c = c;
-  h.n_tx = N - S;
+  h.n_tx = N - S - Pn;
+  h.n_punct = Pn;
   h.k_data = kd;
   h.quant = d.quant;
   h.algo = d.algo;

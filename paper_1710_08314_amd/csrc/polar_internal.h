@@ -66,7 +66,9 @@ struct DevPlan {
   uint32_t first_stage;   // list size of the first stage of the schedule
   uint32_t off_crcnib;    // ceil(N/4) x 16 words: XOR of the CRC columns of every
                           // 4-bit pattern at each nibble position of the codeword
-  uint32_t pad[8];
+  uint32_t n_punct;       // P: codeword positions [0, P) not sent (LLR 0); the sent
+                          // positions are [P, P + n_tx)
+  uint32_t pad[7];
 };
 static_assert(sizeof(DevPlan) == 32 * 4, "DevPlan header is 32 words");
 

@@ -421,21 +421,23 @@ __global__ __launch_bounds__(64) void k_sc(KArgs A, uint32_t* state, ClassSel se
       continue;  // a list tier starts it (state[f] already holds its first stage)
     }
     if (A.times && lane == 0) A.times[2 * (size_t)f] = wall_clock64();
-    const uint32_t N = P->N, n = P->n, ntx = P->n_tx, n_ops = P->n_ops;
+    const uint32_t N = P->N, n = P->n, ntx = P->n_tx, n_ops = P->n_ops, np = P->n_punct;
     const uint32_t* prog = plan_tab(P, P->off_prog);
-    // ---- channel LLRs -> root (shortened tail: a zero known for certain)
+    // ---- channel LLRs -> root: punctured head [0, P) received nothing (0),
+    // sent positions [P, P + n_tx), shortened tail a zero known for certain
     T* root = reinterpret_cast<T*>(smem);
     const uint32_t nbytes = ntx * E;
-    if ((((uintptr_t)llr) & 15u) == 0 && (nbytes & 15u) == 0) {
+    if ((((uintptr_t)llr) & 15u) == 0 && (nbytes & 15u) == 0 && ((np * E) & 15u) == 0) {
       const uint4* s4 = reinterpret_cast<const uint4*>(llr);
-      uint4* d4 = reinterpret_cast<uint4*>(root);
+      uint4* d4 = reinterpret_cast<uint4*>(root + np);
       for (uint32_t i = lane; i < (nbytes >> 4); i += 64) d4[i] = s4[i];
     } else {
       const T* s1 = reinterpret_cast<const T*>(llr);
-      for (uint32_t i = lane; i < ntx; i += 64) root[i] = s1[i];
+      for (uint32_t i = lane; i < ntx; i += 64) root[np + i] = s1[i];
     }
+    for (uint32_t i = lane; i < np; i += 64) root[i] = (T)0;
     const T known = VT<T>::INT ? (T)VT<T>::Q : (T)1048576.0f;
-    for (uint32_t i = ntx + lane; i < N; i += 64) root[i] = known;
+    for (uint32_t i = np + ntx + lane; i < N; i += 64) root[i] = known;
     __syncthreads();
 
     Regs<T> R;

@@ -50,7 +50,8 @@ class _Desc(ctypes.Structure):
                 ("algo", ctypes.c_uint32), ("L", ctypes.c_uint32), ("L_max", ctypes.c_uint32),
                 ("quant", ctypes.c_uint32), ("node_enable", ctypes.c_uint32),
                 ("rep_max", ctypes.c_uint32), ("spc_max", ctypes.c_uint32),
-                ("r1_max", ctypes.c_uint32), ("r0_max", ctypes.c_uint32)]
+                ("r1_max", ctypes.c_uint32), ("r0_max", ctypes.c_uint32),
+                ("n_puncture", ctypes.c_uint32)]
 
 
 class _Info(ctypes.Structure):
@@ -186,7 +187,7 @@ class PlanInfo:
 
 
 def _desc(N, K, crc_len, crc_poly, frozen, design_ebn0_db, n_shorten, algo, L, L_max, quant,
-          node_enable, rep_max, spc_max, r1_max, r0_max):
+          node_enable, rep_max, spc_max, r1_max, r0_max, n_puncture=0):
     if isinstance(quant, str):
         quant = QUANT_NAMES[quant]
     if isinstance(algo, str):
@@ -196,16 +197,17 @@ def _desc(N, K, crc_len, crc_poly, frozen, design_ebn0_db, n_shorten, algo, L, L
     fw = pack_frozen(np.asarray(frozen, dtype=np.uint8)) if frozen is not None else None
     d = _Desc(N, K, fw.ctypes.data if fw is not None else None, float(design_ebn0_db), n_shorten,
               crc_len, crc_poly, algo, L, L_max, quant, node_enable, rep_max, spc_max, r1_max,
-              r0_max)
+              r0_max, n_puncture)
     return d, fw, quant, algo
 
 
 def plan_query(N, K, crc_len=0, crc_poly=0, frozen=None, design_ebn0_db=0.0, n_shorten=0,
                algo=CA_SCL, L=1, L_max=1, quant=F32, node_enable=NODE_ALL, rep_max=None,
-               spc_max=4, r1_max=0, r0_max=0):
+               spc_max=4, r1_max=0, r0_max=0, n_puncture=0):
     """polar_plan_query: host-only planning -> (PlanInfo, frozen uint8 mask)."""
     d, fw, quant, algo = _desc(N, K, crc_len, crc_poly, frozen, design_ebn0_db, n_shorten, algo,
-                               L, L_max, quant, node_enable, rep_max, spc_max, r1_max, r0_max)
+                               L, L_max, quant, node_enable, rep_max, spc_max, r1_max, r0_max,
+                               n_puncture)
     inf = _Info()
     out = np.zeros((N + 31) // 32, dtype=np.uint32)
     _check(lib.polar_plan_query(ctypes.byref(d), ctypes.byref(inf), out.ctypes.data),
@@ -218,10 +220,10 @@ class Plan:
 
     def __init__(self, N, K, crc_len=0, crc_poly=0, frozen=None, design_ebn0_db=0.0,
                  n_shorten=0, algo=CA_SCL, L=1, L_max=1, quant=F32, node_enable=NODE_ALL,
-                 rep_max=None, spc_max=4, r1_max=0, r0_max=0):
+                 rep_max=None, spc_max=4, r1_max=0, r0_max=0, n_puncture=0):
         d, self._fw, quant, algo = _desc(N, K, crc_len, crc_poly, frozen, design_ebn0_db,
                                          n_shorten, algo, L, L_max, quant, node_enable, rep_max,
-                                         spc_max, r1_max, r0_max)
+                                         spc_max, r1_max, r0_max, n_puncture)
         h = ctypes.c_void_p()
         _check(lib.polar_scl_plan(ctypes.byref(d), ctypes.byref(h)), "polar_scl_plan")
         self._h = h

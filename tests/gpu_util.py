@@ -21,13 +21,13 @@ PM_RTOL = 1e-4
 
 
 def oracle_code(N, K, c, poly, frozen, S=0, quant="f32", algo="ca", L=1, L_max=1,
-                node_enable=O.NODE_ALL, rep_max=None, spc_max=4, r1_max=0, r0_max=0):
+                node_enable=O.NODE_ALL, rep_max=None, spc_max=4, r1_max=0, r0_max=0, P=0):
     q = QMAP[quant] if isinstance(quant, str) else quant
     if rep_max is None:
         rep_max = 8 if q == O.I8 else 0
     return O.Code(N, K, frozen, c, poly, S=S, quant=q, algo=AMAP[algo] if isinstance(algo, str)
                   else algo, L=L, L_max=L_max, node_enable=node_enable, rep_max=rep_max,
-                  spc_max=spc_max, r1_max=r1_max, r0_max=r0_max)
+                  spc_max=spc_max, r1_max=r1_max, r0_max=r0_max, P=P)
 
 
 def make_inputs(code: O.Code, n: int, seed: int, ebn0_db: float, first: int = 0):
@@ -36,7 +36,7 @@ def make_inputs(code: O.Code, n: int, seed: int, ebn0_db: float, first: int = 0)
     x = np.zeros((n, code.n_tx), dtype=np.uint8)
     for f in range(n):
         b = O.attach_crc(bits[f], code.crc_len, code.crc_poly)
-        x[f] = O.encode(code.frozen, b)[:code.n_tx]
+        x[f] = O.encode(code.frozen, b)[code.P:code.P + code.n_tx]
     sigma = synth.sigma_for(ebn0_db, code.k_data, code.n_tx)
     return bits, O.make_llr(code, x, noise, sigma)
 
@@ -45,7 +45,7 @@ def gpu_plan(code: O.Code):
     from paper_1710_08314_amd import polar as P
 
     return P.Plan(code.N, code.K, code.crc_len, code.crc_poly, frozen=code.frozen,
-                  n_shorten=code.S, algo=code.algo, L=code.L, L_max=code.L_max, quant=code.quant,
+                  n_shorten=code.S, n_puncture=code.P, algo=code.algo, L=code.L, L_max=code.L_max, quant=code.quant,
                   node_enable=code.node_enable, rep_max=code.rep_max, spc_max=code.spc_max,
                   r1_max=code.r1_max, r0_max=code.r0_max)
 

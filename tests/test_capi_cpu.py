@@ -91,6 +91,8 @@ def test_explicit_frozen_mask_roundtrip():
     (dict(N=64, K=10, algo=P.FA_SCL, L_max=8), -1),  # FA without a CRC
     (dict(N=64, K=10, quant=7), -1),
     (dict(N=2048, K=1000, crc_len=11, algo=P.CA_SCL, L=32, quant=P.F32), -2),  # LDS
+    (dict(N=64, K=10, n_puncture=64), -1), (dict(N=64, K=10, n_shorten=20, n_puncture=44), -1),
+    (dict(N=64, K=30, n_shorten=20, n_puncture=20), -1),  # K > N - S - P
 ])
 def test_plan_errors(kw, code):
     with pytest.raises(P.PolarError) as e:
@@ -125,3 +127,20 @@ def test_given_mask_must_freeze_shortened_positions():
     fz[[31, 30, 29, 27]] = 0
     with pytest.raises(P.PolarError):
         P.plan_query(32, 4, frozen=fz, n_shorten=2)
+
+
+@pytest.mark.parametrize("N,K,c,design,S,Pn", [
+    (256, 90, 11, 1.5, 0, 37), (512, 192, 0, 3.0, 0, 192), (1024, 400, 24, 2.5, 100, 150),
+    (2048, 1000, 11, 2.5, 256, 300), (64, 20, 11, 1.0, 5, 9),
+])
+def test_punctured_frozen_set_matches_oracle(N, K, c, design, S, Pn):
+    """Puncturing: the plan's construction equals the oracle's, the sent
+    length is N - S - P, and a given frozen set must freeze [0, P)."""
+    info, fz = P.plan_query(N, K, c, 0x621, design_ebn0_db=design, n_shorten=S, n_puncture=Pn)
+    assert np.array_equal(fz, O.construct(N, K, S, c, design, P=Pn))
+    assert info.n_tx == N - S - Pn
+    bad = fz.copy()
+    j = int(np.where(fz[Pn:] == 0)[0][0]) + Pn
+    bad[j], bad[Pn - 1] = 1, 0  # an information bit inside the punctured head
+    with pytest.raises(P.PolarError):
+        P.plan_query(N, K, c, 0x621, frozen=bad, n_shorten=S, n_puncture=Pn)

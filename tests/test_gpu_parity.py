@@ -203,6 +203,43 @@ def test_encoder_matches_oracle(N, K, c, poly, S):
         assert np.array_equal(xb[f], O.encode(code.frozen, O.attach_crc(data[f], c, poly)))
 
 
+# ------------------------------------------------------------- puncturing
+PUNCTURED = [(256, 90, 0, 37, 11, 0x621, 1.5, 2.0), (1024, 400, 100, 150, 24, 0x1864CFB, 2.5, 2.5),
+             (64, 20, 5, 9, 11, 0x621, 1.0, 2.0), (512, 192, 0, 192, 11, 0x621, 3.0, 3.0)]
+
+
+@pytest.mark.parametrize("quant,algo,L,Lmax", [("i16", "ca", 8, 8), ("f32", "ca", 4, 4),
+                                               ("i8", "fa", 1, 16)])
+def test_punctured_codes(quant, algo, L, Lmax):
+    """Codes whose first P positions are not sent (LLR 0), with and without
+    shortening, against the oracle frame by frame."""
+    for (N, K, S, Pn, c, poly, design, eb) in PUNCTURED:
+        fz = O.construct(N, K, S, c, design, P=Pn)
+        code = oracle_code(N, K, c, poly, fz, S=S, P=Pn, quant=quant, algo=algo, L=L, L_max=Lmax)
+        _, llr = make_inputs(code, 150, 77 + N, eb)
+        compare(code, llr)
+
+
+def test_punctured_channel_sends_the_right_slice():
+    """polar_channel of a punctured, shortened plan sends positions
+    [P, N - S) of the codeword: noiseless-sign check at very high Eb/N0."""
+    import torch
+    from paper_1710_08314_amd import polar as P
+
+    N, K, S, Pn, c, poly = 512, 150, 40, 70, 11, 0x621
+    code = oracle_code(N, K, c, poly, O.construct(N, K, S, c, 2.0, P=Pn), S=S, P=Pn, quant="f32")
+    plan = gpu_plan(code)
+    rng = np.random.default_rng(3)
+    data = rng.integers(0, 2, (32, K - c), dtype=np.uint8)
+    d = torch.from_numpy(P.pack_bits(data).view(np.int32)).cuda()
+    x = P.encode(plan, d)
+    llr = P.channel(plan, x, 40.0, 5, 0).cpu().numpy()
+    assert llr.shape == (32, N - S - Pn)
+    for f in range(32):
+        cw = O.encode(code.frozen, O.attach_crc(data[f], c, poly))
+        assert np.array_equal((llr[f] < 0).astype(np.uint8), cw[Pn:N - S])
+
+
 def test_generator_is_counter_based():
     from paper_1710_08314_amd import polar as P
 
