@@ -21,6 +21,8 @@ struct Work {
   uint32_t* state = nullptr;
   uint32_t* tier_heads = nullptr;
   uint32_t* heads = nullptr;  // class schedule
+  char* spill = nullptr;      // depth-1 slots of spilled layouts (spill_need bytes)
+  uint64_t spill_bytes = 0;
 };
 size_t work_words(size_t cap);                // words of a work area for `cap` frames
 Work work_view(uint32_t* base, size_t cap);  // the regions of an area at `base`
@@ -38,6 +40,10 @@ struct Batch {
 int prepare(const polar_plan* plans, uint32_t n_plans, const polar_frame* d_frames,
             uint32_t n_frames, const void* d_llr, uint32_t* d_info, polar_status* d_status,
             uint32_t* d_pm_lists, const polar_decode_opts* opts, Batch* b);
+
+// Global memory the batch's spilled layouts need in a work area (0: none):
+// the depth-1 slots of one frame per workgroup that may hold such a frame.
+uint64_t spill_need(const Batch& b, int cus);
 
 // Enqueue one decode of `b` on `st` using work area `w` (schedule 0 automatic,
 // 1 plain; `timed`: tier events of this host thread; `autotune`: see

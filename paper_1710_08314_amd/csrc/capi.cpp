@@ -74,6 +74,34 @@ int device_scratch(size_t frames, Work* w) {
   return POLAR_OK;
 }
 
+// per-device buffer for the depth-1 slots of spilled layouts (grown on demand)
+struct SpillBuf {
+  char* p = nullptr;
+  uint64_t bytes = 0;
+};
+std::map<int, SpillBuf> g_spill;
+
+int device_spill(uint64_t bytes, Work* w) {
+  if (bytes == 0) return POLAR_OK;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return POLAR_EHIP;
+  std::lock_guard<std::mutex> lk(g_mu);
+  SpillBuf& sb = g_spill[dev];
+  if (sb.bytes < bytes) {
+    if (sb.p) {
+      if (hipDeviceSynchronize() != hipSuccess) return POLAR_EHIP;
+      (void)hipFree(sb.p);
+      sb.p = nullptr;
+      sb.bytes = 0;
+    }
+    if (hipMalloc(&sb.p, bytes) != hipSuccess) return POLAR_ENOMEM;
+    sb.bytes = bytes;
+  }
+  w->spill = sb.p;
+  w->spill_bytes = sb.bytes;
+  return POLAR_OK;
+}
+
 // events of the last timed call on this host thread: [0] before the first
 // kernel, [1] after the SC tier, [2] after list tier A, [3] after list tier B
 // (plain schedule: [0] and [3] bracket the one kernel); [4], [5] bracket the
@@ -263,6 +291,32 @@ Work work_view(uint32_t* base, size_t cap) {
   w.tier_heads = base + cap;
   w.heads = base + cap + 2;
   return w;
+}
+
+// Depth-1 spill of the batch: bytes per workgroup (0: no plan spills) and the
+// smallest LDS footprint of a spilled layout, which bounds the workgroups per
+// CU of any launch that can run one.
+static void spill_geometry(const Batch& b, uint64_t* stride, uint32_t* lds_min) {
+  *stride = 0;
+  *lds_min = kLdsLimit;
+  for (polar_plan p : b.plans) {
+    const DevPlan& h = p->hp.hdr;
+    const uint32_t E = elem_bytes(h.quant);
+    const LdsLayout lay = lds_layout(h.N, h.n, E, h.max_list, key_bytes(h.quant));
+    if (!lay.spill1) continue;
+    const uint64_t sb = spill1_bytes(h.N, E, h.max_list);
+    *stride = sb > *stride ? sb : *stride;
+    *lds_min = lay.total < *lds_min ? lay.total : *lds_min;
+  }
+}
+
+uint64_t spill_need(const Batch& b, int cus) {
+  uint64_t stride;
+  uint32_t lds_min;
+  spill_geometry(b, &stride, &lds_min);
+  if (!stride) return 0;
+  const uint32_t per_cu = kLdsLimit / lds_min > 0 ? kLdsLimit / lds_min : 1;
+  return stride * (uint64_t)cus * per_cu;
 }
 
 }  // namespace polar
@@ -459,15 +513,30 @@ int run_classes(const Batch& b, const Work& w, hipStream_t st, bool autotune, hi
 namespace polar {
 
 // Launch one decode of a prepared batch on `st` with work area `w`.
-int launch_batch(const Batch& b, uint32_t schedule, const Work& w, hipStream_t st, bool timed,
+int launch_batch(const Batch& b_in, uint32_t schedule, const Work& w, hipStream_t st, bool timed,
                  bool autotune) {
-  const polar::KArgs& A = b.A;
+  Batch b = b_in;
+  polar::KArgs& A = b.A;
   const uint32_t n_frames = A.n_frames;
   hipEvent_t* ev = timed ? timing_events() : nullptr;
   if (timed && !ev) return POLAR_EHIP;
   int rc = POLAR_OK;
+  int dev0 = 0, cus0 = 1;
+  if (hipGetDevice(&dev0) != hipSuccess) return POLAR_EHIP;
+  rc = device_cus(dev0, &cus0);
+  if (rc) return rc;
+  // spilled layouts: one slot set per workgroup, the grids stay within them
+  uint64_t spill_stride;
+  uint32_t spill_lds;
+  polar::spill_geometry(b, &spill_stride, &spill_lds);
+  if (spill_stride) {
+    if (!w.spill || w.spill_bytes < polar::spill_need(b, cus0)) return POLAR_EINVAL;
+    A.spill = w.spill;
+    A.spill_stride = spill_stride;
+  }
   if (schedule == 1) {
-    const uint32_t grid = n_frames < 0x7FFFFFFFu ? n_frames : 0x7FFFFFFFu;
+    uint32_t grid = n_frames < 0x7FFFFFFFu ? n_frames : 0x7FFFFFFFu;
+    if (spill_stride) grid = persistent_grid(cus0, b.lds, polar::kLdsLimit, n_frames);
     if (ev) (void)hipEventRecord(ev[0], st);
     rc = polar::launch_decode_plain(b.quant, A, b.lds, grid, st);
     if (ev) {
@@ -567,6 +636,12 @@ int polar_scl_decode_batch(const polar_plan* plans, uint32_t n_plans, const pola
     rc = device_scratch(n_frames, &w);
     if (rc) return rc;
   }
+  int dev = 0, cus = 1;
+  if (hipGetDevice(&dev) != hipSuccess) return POLAR_EHIP;
+  rc = device_cus(dev, &cus);
+  if (rc) return rc;
+  rc = device_spill(polar::spill_need(b, cus), &w);
+  if (rc) return rc;
   const uint32_t flags = opts ? opts->flags : 0;
   return launch_batch(b, schedule, w, static_cast<hipStream_t>(stream),
                       (flags & POLAR_OPT_TIER_TIMING) != 0, (flags & POLAR_OPT_AUTOTUNE) != 0);
@@ -636,6 +711,7 @@ struct polar_graph_s {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   uint32_t* work = nullptr;
+  char* spill = nullptr;
 };
 
 extern "C" {
@@ -646,6 +722,7 @@ int polar_graph_destroy(polar_graph g) {
   if (g->exec && hipGraphExecDestroy(g->exec) != hipSuccess) rc = POLAR_EHIP;
   if (g->graph && hipGraphDestroy(g->graph) != hipSuccess) rc = POLAR_EHIP;
   if (g->work && hipFree(g->work) != hipSuccess) rc = POLAR_EHIP;
+  if (g->spill && hipFree(g->spill) != hipSuccess) rc = POLAR_EHIP;
   delete g;
   return rc;
 }
@@ -670,7 +747,21 @@ int polar_graph_create(const polar_plan* plans, uint32_t n_plans, const polar_fr
     delete g;
     return POLAR_ENOMEM;
   }
-  const Work w = work_view(g->work, n_frames);
+  Work w = work_view(g->work, n_frames);
+  int dev = 0, cus = 1;
+  if (hipGetDevice(&dev) != hipSuccess || device_cus(dev, &cus) != POLAR_OK) {
+    (void)polar_graph_destroy(g);
+    return POLAR_EHIP;
+  }
+  const uint64_t sp = polar::spill_need(b, cus);
+  if (sp) {
+    if (hipMalloc(&g->spill, sp) != hipSuccess) {
+      (void)polar_graph_destroy(g);
+      return POLAR_ENOMEM;
+    }
+    w.spill = g->spill;
+    w.spill_bytes = sp;
+  }
   hipStream_t s = nullptr;
   if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
     (void)polar_graph_destroy(g);

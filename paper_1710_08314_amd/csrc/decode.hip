@@ -41,6 +41,7 @@ struct Ctx {
   const uint32_t* prog;
   uint32_t N, n, bw, L;  // L: list size of this stage
   LdsLayout lay;
+  char* gsp;  // this workgroup's depth-1 slots in global memory (spilled layouts)
 };
 
 __device__ __forceinline__ uint32_t* bits_of(const Ctx& c, uint32_t r) {
@@ -52,15 +53,23 @@ __device__ __forceinline__ uint8_t* ptr_tab(const Ctx& c) {
 __device__ __forceinline__ uint32_t* tabs(const Ctx& c) {
   return reinterpret_cast<uint32_t*>(c.smem + c.lay.tabs);
 }
-// Address of element 0 of the depth-d LLRs of the path of rank r.
+// Address of element 0 of the depth-d LLRs of the path of rank r.  With G,
+// the depth-1 slots of a spilled layout (global memory).
+template <bool G = false>
 __device__ __forceinline__ char* node_llr(const Ctx& c, uint32_t d, uint32_t r) {
-  if (d == 0) return c.smem + c.lay.root;
-  const uint32_t* t = tabs(c);
-  return c.smem + t[d] + (uint32_t)ptr_tab(c)[d * 32 + r] * t[12 + d];
+  if constexpr (G) {
+    return c.gsp + (uint32_t)ptr_tab(c)[32 + r] * tabs(c)[13];
+  } else {
+    if (d == 0) return c.smem + c.lay.root;
+    const uint32_t* t = tabs(c);
+    return c.smem + t[d] + (uint32_t)ptr_tab(c)[d * 32 + r] * t[12 + d];
+  }
 }
 
 // ------------------------------------------------------------ F, G and H
-template <typename T, int V, int NT>
+// SG / DG: the source (depth d) / destination (depth d + 1) slots are the
+// spilled depth-1 slots in global memory.
+template <typename T, int V, int NT, bool SG = false, bool DG = false>
 __device__ void run_fg(const Ctx& c, uint32_t d, uint32_t o, uint32_t a, bool is_g) {
   constexpr uint32_t E = VT<T>::E;
   constexpr int NB = V * E;
@@ -71,7 +80,7 @@ __device__ void run_fg(const Ctx& c, uint32_t d, uint32_t o, uint32_t a, bool is
   const uint32_t dbase = t[d + 1], dstride = t[12 + d + 1];
   for (uint32_t it = threadIdx.x; it < total; it += NT) {
     const uint32_t r = it >> lc, j = it & (cpp - 1);
-    const char* src = node_llr(c, d, r) + j * NB;
+    const char* src = node_llr<SG>(c, d, r) + j * NB;
     uint32_t wa[4], wb[4], wo[4] = {0u, 0u, 0u, 0u};
     lds_ld<NB>(src, wa);
     lds_ld<NB>(src + h * E, wb);
@@ -82,15 +91,29 @@ __device__ void run_fg(const Ctx& c, uint32_t d, uint32_t o, uint32_t a, bool is
     } else {
       f_chunk<T, V>(wa, wb, wo);
     }
-    lds_st<NB>(c.smem + dbase + r * dstride + j * NB, wo);
+    if constexpr (DG)
+      lds_st<NB>(c.gsp + r * dstride + j * NB, wo);
+    else
+      lds_st<NB>(c.smem + dbase + r * dstride + j * NB, wo);
   }
   if (threadIdx.x < a) ptr_tab(c)[(d + 1) * 32 + threadIdx.x] = (uint8_t)threadIdx.x;
 }
 
-template <typename T, int NT>
+// SP: this kernel may run spilled layouts (largest list 32).
+template <typename T, int NT, bool SP>
 __device__ void op_fg(const Ctx& c, uint32_t d, uint32_t o, uint32_t a, bool is_g) {
   const uint32_t h = (c.N >> d) >> 1;
   constexpr uint32_t VM = VT<T>::VMAX;
+  if constexpr (SP) {
+    // spilled layouts exist only for N = 2048, where h >= VM at depths 0 and 1
+    if (c.lay.spill1 && d <= 1) {
+      if (d == 0)
+        run_fg<T, VM, NT, false, true>(c, d, o, a, is_g);
+      else
+        run_fg<T, VM, NT, true, false>(c, d, o, a, is_g);
+      return;
+    }
+  }
   if (h >= VM)
     run_fg<T, VM, NT>(c, d, o, a, is_g);
   else if (VM >= 8 && h == 8)
@@ -339,7 +362,7 @@ __device__ __forceinline__ void node_candidate(uint32_t opc, uint32_t q, uint32_
 // j, j + G, ...).  Writes the candidate keys (or, for single-candidate nodes,
 // the updated metric and zero decisions) and, for R1 / SPC, the hard
 // decisions into the parent's own partial-sum region [o, o + m).
-template <typename T, int NT>
+template <typename T, int NT, bool GSP>
 __device__ void node_stats_int(const Ctx& c, uint32_t opc, uint32_t d, uint32_t o, uint32_t a,
                                uint32_t C) {
   using Key = typename VT<T>::Key;
@@ -357,7 +380,7 @@ __device__ void node_stats_int(const Ctx& c, uint32_t opc, uint32_t d, uint32_t 
   for (uint32_t base = 0; base < a; base += ppr) {
     const uint32_t r = base + (tid >> lgG);
     const bool valid = r < a;
-    const T* al = reinterpret_cast<const T*>(node_llr(c, d, valid ? r : 0));
+    const T* al = reinterpret_cast<const T*>(node_llr<GSP>(c, d, valid ? r : 0));
     int p0 = 0, p1 = 0;
     uint32_t par = 0;
     Key top[4] = {~0u, ~0u, ~0u, ~0u};
@@ -421,7 +444,7 @@ __device__ void node_stats_int(const Ctx& c, uint32_t opc, uint32_t d, uint32_t 
     const uint32_t nw = m >= 32 ? (m >> 5) : 1u, lnw = lg2(nw), nb = m >= 32 ? 32u : m;
     for (uint32_t it = tid; it < (a << lnw); it += NT) {
       const uint32_t r = it >> lnw, w = it & (nw - 1u);
-      const T* al = reinterpret_cast<const T*>(node_llr(c, d, r)) + (w << 5);
+      const T* al = reinterpret_cast<const T*>(node_llr<GSP>(c, d, r)) + (w << 5);
       uint32_t hv = 0;
       for (uint32_t b = 0; b < nb; ++b) hv |= (al[b] < (T)0 ? 1u : 0u) << b;
       uint32_t* B = bits_of(c, r);
@@ -439,7 +462,7 @@ __device__ void node_stats_int(const Ctx& c, uint32_t opc, uint32_t d, uint32_t 
 // G = min(64, m) lanes; lane j holds elements j, j + G, j + 2G, ...  The
 // segment sums of the penalties follow the stride-halving order exactly:
 // in-lane halving of the element list, then butterflies over the lanes.
-template <typename T, int NT>
+template <typename T, int NT, bool GSP>
 __device__ void node_stats_float(const Ctx& c, uint32_t opc, uint32_t d, uint32_t o, uint32_t a,
                                  uint32_t C) {
   using Acc = typename VT<T>::Acc;
@@ -456,7 +479,7 @@ __device__ void node_stats_float(const Ctx& c, uint32_t opc, uint32_t d, uint32_
   for (uint32_t base = 0; base < a; base += ppr) {
     const uint32_t r = base + (tid >> lgG);
     const bool valid = r < a;
-    const T* al = reinterpret_cast<const T*>(node_llr(c, d, valid ? r : 0));
+    const T* al = reinterpret_cast<const T*>(node_llr<GSP>(c, d, valid ? r : 0));
     if (opc == OP_R0 || opc == OP_LF || opc == OP_REP || opc == OP_LI) {
       // penalties of the all-0 (v = 0) and all-1 (v = 1) decisions
       Acc x0[kEPL], x1[kEPL];
@@ -575,10 +598,18 @@ __device__ void op_node(const Ctx& c, uint32_t opc, uint32_t d, uint32_t o, uint
   uint16_t* cpos = reinterpret_cast<uint16_t*>(c.smem + c.lay.cpos);
   const bool single = (opc == OP_R0 || opc == OP_LF);
   const uint32_t C = single ? 1u : (opc == OP_R1 ? 4u : (opc == OP_SPC ? 8u : 2u));
-  if constexpr (VT<T>::INT)
-    node_stats_int<T, NT>(c, opc, d, o, a, C);
-  else
-    node_stats_float<T, NT>(c, opc, d, o, a, C);
+  constexpr bool SP = LMAX >= (int)kMaxL;
+  if constexpr (VT<T>::INT) {
+    if (SP && c.lay.spill1 && d == 1)
+      node_stats_int<T, NT, SP>(c, opc, d, o, a, C);
+    else
+      node_stats_int<T, NT, false>(c, opc, d, o, a, C);
+  } else {
+    if (SP && c.lay.spill1 && d == 1)
+      node_stats_float<T, NT, SP>(c, opc, d, o, a, C);
+    else
+      node_stats_float<T, NT, false>(c, opc, d, o, a, C);
+  }
   __syncthreads();
 
   if (single) {
@@ -704,11 +735,11 @@ __device__ void run_program(const Ctx& c, uint32_t& a) {
     const uint32_t opc = op_code(w), d = op_depth(w), o = op_off(w);
     switch (opc) {
       case OP_F:
-        op_fg<T, NT>(c, d, o, a, false);
+        op_fg<T, NT, (LMAX >= (int)kMaxL)>(c, d, o, a, false);
         __syncthreads();
         break;
       case OP_G:
-        op_fg<T, NT>(c, d, o, a, true);
+        op_fg<T, NT, (LMAX >= (int)kMaxL)>(c, d, o, a, true);
         __syncthreads();
         break;
       case OP_H:
@@ -806,8 +837,12 @@ __device__ void setup_stage(Ctx& c, uint32_t L) {
     t[0] = c.lay.root;
     t[12] = 0;
     for (uint32_t d = 1; d <= c.n; ++d) {
-      t[d] = cur;
       t[12 + d] = slot_bytes(c.N, d, VT<T>::E);
+      if (d == 1 && c.lay.spill1) {
+        t[d] = 0;  // in global memory (c.gsp)
+        continue;
+      }
+      t[d] = cur;
       cur += L * t[12 + d];
     }
     pm_tab<T>(c)[0] = (typename VT<T>::Acc)0;
@@ -836,6 +871,7 @@ __device__ bool decode_frame(char* smem, const KArgs& A, uint32_t f, const DevPl
   c.n = uni(P->n);
   c.bw = uni(P->bw);
   c.L = 1;
+  c.gsp = A.spill ? uni_ptr(A.spill + (size_t)blockIdx.x * A.spill_stride) : nullptr;
   c.lay = lds_layout(c.N, c.n, VT<T>::E, 1, (uint32_t)sizeof(typename VT<T>::Key));
   load_root<T, NT>(c, llr);
   uint32_t L = L_first, chosen = 0, a = 1;

@@ -22,6 +22,8 @@ struct KArgs {
   uint32_t* pm_lists;   // nullable
   uint32_t pm_stride;   // entries per frame in pm_lists
   uint64_t* times;      // nullable: realtime stamps, start and end per frame
+  char* spill;          // nullable: depth-1 LLR slots of spilled layouts, spill_stride
+  uint64_t spill_stride;  // bytes per workgroup, indexed by blockIdx.x
 };
 
 // One generic launch: each workgroup decodes whole frames (every stage of

@@ -219,7 +219,7 @@ int make_plan(const polar_plan_desc& d, HostPlan& hp) {
   // ---- header + blob
   const uint32_t E = elem_bytes(d.quant), KB = key_bytes(d.quant);
   const LdsLayout lay = lds_layout(N, n, E, maxl, KB);
-  if (lay.total > kLdsLimit - 1024) return POLAR_EUNSUP;  // headroom for static LDS
+  if (lay.total > kLdsBudget) return POLAR_EUNSUP;  // lds_layout spills what it can
 
   DevPlan h{};
   h.N = N;

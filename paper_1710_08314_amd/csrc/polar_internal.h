@@ -94,7 +94,12 @@ POLAR_HD inline const uint32_t* plan_tab(const DevPlan* p, uint32_t off) {
 // ---------------------------------------------------------------------------
 struct LdsLayout {
   uint32_t root, stages, bits, ptr, pm, cand, sel, cpos, tabs, syn, ord, out, misc, total;
+  uint32_t spill1;  // 1: the depth-1 slots live in global memory (spill1_bytes per workgroup)
 };
+
+// LDS a decoder workgroup may use for its frame (the CU's LDS less room for
+// the kernels' static variables).
+constexpr uint32_t kLdsBudget = kLdsLimit - 1024;
 
 POLAR_HD inline uint32_t ru16(uint32_t x) { return (x + 15u) & ~15u; }
 POLAR_HD inline uint32_t ru4(uint32_t x) { return (x + 3u) & ~3u; }
@@ -105,13 +110,20 @@ POLAR_HD inline uint32_t slot_bytes(uint32_t N, uint32_t d, uint32_t E) {
   return ru4(m * E);
 }
 
-POLAR_HD inline LdsLayout lds_layout(uint32_t N, uint32_t n, uint32_t E, uint32_t L, uint32_t KB) {
+// Bytes of the depth-1 slots of L paths (the largest stage).
+POLAR_HD inline uint32_t spill1_bytes(uint32_t N, uint32_t E, uint32_t L) {
+  return L * slot_bytes(N, 1, E);
+}
+
+POLAR_HD inline LdsLayout lds_layout_s(uint32_t N, uint32_t n, uint32_t E, uint32_t L, uint32_t KB,
+                                       uint32_t spill1) {
   LdsLayout l{};
+  l.spill1 = spill1;
   uint32_t cur = 0;
   l.root = cur;
   cur += ru16(N * E);
   l.stages = cur;
-  for (uint32_t d = 1; d <= n; ++d) cur += L * slot_bytes(N, d, E);
+  for (uint32_t d = spill1 ? 2u : 1u; d <= n; ++d) cur += L * slot_bytes(N, d, E);
   cur = ru16(cur);
   const uint32_t bw = N >= 32 ? N / 32 : 1;
   l.bits = cur;
@@ -138,6 +150,15 @@ POLAR_HD inline LdsLayout lds_layout(uint32_t N, uint32_t n, uint32_t E, uint32_
   cur += 16 * 4;
   l.total = ru16(cur);
   return l;
+}
+
+// The layout of one frame at list size L: everything in LDS when it fits the
+// budget, else with the depth-1 slots (half of all LLR storage) in global
+// memory -- the float32 decoder at N = 2048, L = 32 (272 KB otherwise).
+POLAR_HD inline LdsLayout lds_layout(uint32_t N, uint32_t n, uint32_t E, uint32_t L, uint32_t KB) {
+  const LdsLayout l = lds_layout_s(N, n, E, L, KB, 0);
+  if (l.total <= kLdsBudget || n < 2) return l;
+  return lds_layout_s(N, n, E, L, KB, 1);
 }
 
 // LDS layout of the L = 1 tier for one frame: root N LLRs, the LLRs of the

@@ -17,6 +17,8 @@ struct polar_server_s {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
     uint32_t* work = nullptr;
+    char* spill = nullptr;  // depth-1 slots of spilled layouts, grown on demand
+    uint64_t spill_bytes = 0;
     bool busy = false;
     uint32_t frames = 0;
     uint64_t tag = 0;
@@ -33,6 +35,7 @@ void release(polar_server s) {
     if (sl.done) (void)hipEventDestroy(sl.done);
     if (sl.stream) (void)hipStreamDestroy(sl.stream);
     if (sl.work) (void)hipFree(sl.work);
+    if (sl.spill) (void)hipFree(sl.spill);
   }
   delete s;
 }
@@ -79,8 +82,22 @@ int polar_server_submit(polar_server s, const polar_plan* plans, uint32_t n_plan
                           d_status ? d_status + first : nullptr, nullptr, nullptr, &b);
   if (rc) return rc;
   auto& sl = s->slots[i];
-  rc = polar::launch_batch(b, 0, polar::work_view(sl.work, s->cfg.max_batch), sl.stream, false,
-                           false);
+  int dev = 0, cus = 1;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return POLAR_EHIP;
+  const uint64_t sp = polar::spill_need(b, cus);
+  if (sp > sl.spill_bytes) {  // the slot is idle: nothing of it is in flight
+    if (sl.spill) (void)hipFree(sl.spill);
+    sl.spill = nullptr;
+    sl.spill_bytes = 0;
+    if (hipMalloc(&sl.spill, sp) != hipSuccess) return POLAR_ENOMEM;
+    sl.spill_bytes = sp;
+  }
+  polar::Work w = polar::work_view(sl.work, s->cfg.max_batch);
+  w.spill = sl.spill;
+  w.spill_bytes = sl.spill_bytes;
+  rc = polar::launch_batch(b, 0, w, sl.stream, false, false);
   if (rc) return rc;
   if (hipEventRecord(sl.done, sl.stream) != hipSuccess) return POLAR_EHIP;
   sl.busy = true;

@@ -90,7 +90,6 @@ def test_explicit_frozen_mask_roundtrip():
     (dict(N=64, K=10, algo=P.CA_SCL, L=3), -1), (dict(N=64, K=10, algo=P.CA_SCL, L=64), -2),
     (dict(N=64, K=10, algo=P.FA_SCL, L_max=8), -1),  # FA without a CRC
     (dict(N=64, K=10, quant=7), -1),
-    (dict(N=2048, K=1000, crc_len=11, algo=P.CA_SCL, L=32, quant=P.F32), -2),  # LDS
     (dict(N=64, K=10, n_puncture=64), -1), (dict(N=64, K=10, n_shorten=20, n_puncture=44), -1),
     (dict(N=64, K=30, n_shorten=20, n_puncture=20), -1),  # K > N - S - P
 ])
@@ -144,3 +143,17 @@ def test_punctured_frozen_set_matches_oracle(N, K, c, design, S, Pn):
     bad[j], bad[Pn - 1] = 1, 0  # an information bit inside the punctured head
     with pytest.raises(P.PolarError):
         P.plan_query(N, K, c, 0x621, frozen=bad, n_shorten=S, n_puncture=Pn)
+
+
+def test_float32_list32_n2048_spills_depth1():
+    """float32 at N = 2048, L = 32 needs 272 KB of LDS: the plan accepts it with
+    the depth-1 slots (32 x 1024 floats) moved to global memory and the rest
+    within one CU's LDS; smaller lists and int16 stay entirely in LDS."""
+    info, _ = P.plan_query(2048, 1000, 11, 0x621, design_ebn0_db=2.5, algo=P.CA_SCL, L=32,
+                           quant=P.F32)
+    assert info.lds_bytes <= 160 * 1024 - 1024
+    full = 4 * (2048 + 32 * 2047)
+    assert info.lds_bytes < full - 32 * 1024 * 4 + 16 * 1024
+    i16, _ = P.plan_query(2048, 1000, 11, 0x621, design_ebn0_db=2.5, algo=P.CA_SCL, L=32,
+                          quant=P.I16)
+    assert i16.lds_bytes >= 2 * (2048 + 32 * 2047)

@@ -67,10 +67,20 @@ def test_fa_n2048_k1723_i8(ebn0):
 
 @pytest.mark.parametrize("quant", ["f32", "i16"])
 def test_fa_n2048_k1723_other_quants(quant):
-    code = _code(2048, 1723, 32, 0x04C11DB7, 4.5, quant=quant, algo="fa",
-                 L_max=16 if quant == "f32" else 32)
+    code = _code(2048, 1723, 32, 0x04C11DB7, 4.5, quant=quant, algo="fa", L_max=32)
     _, llr = make_inputs(code, 60, 2100, 3.5)
     compare(code, llr)
+
+
+@pytest.mark.parametrize("schedule", [0, 1])
+def test_float32_list32_n2048(schedule):
+    """float32 at N = 2048 with L = 32: the depth-1 slots (128 KB per frame)
+    live in global memory; CA-SCL through the tiered and the plain schedule,
+    at an Eb/N0 where L = 32 matters."""
+    code = _code(2048, 1723, 32, 0x04C11DB7, 4.5, quant="f32", algo="ca", L=32)
+    _, llr = make_inputs(code, 48, 2200, 3.25)
+    rep = compare(code, llr, schedule=schedule)
+    print("f32 L32", schedule, rep)
 
 
 @pytest.mark.parametrize("algo,L,Lmax", [("fa", 1, 8), ("pa", 1, 8), ("sc", 1, 1)])
@@ -262,3 +272,34 @@ def test_generator_is_counter_based():
     sig = synth.sigma_for(2.5, 120, 256)
     z = (l1 / 4) * s
     assert abs(z.mean() - 2 / sig ** 2) < 0.05 * 2 / sig ** 2
+
+
+def test_class_schedule_with_spilled_float_plan():
+    """A batch of fixed-list float32 plans (class schedule) that includes the
+    spilled layout (N = 2048, L = 32) beside small ones: every frame equals
+    its own oracle decode."""
+    import torch
+    from paper_1710_08314_amd import polar as P
+    from tests.gpu_util import pack_inputs
+
+    specs = [(2048, 1100, 32), (256, 128, 4), (1024, 500, 8), (512, 200, 32)]
+    codes = [_code(N, K, 11, 0x621, 2.5, quant="f32", algo="ca", L=L) for N, K, L in specs]
+    rng = np.random.default_rng(9)
+    plan_of = rng.integers(0, len(specs), 96)
+    ebn0 = rng.uniform(1.5, 3.0, 96)
+    inp = pack_inputs(codes, plan_of, ebn0, 9)
+    plans = [gpu_plan(c) for c in codes]
+    llr = torch.from_numpy(inp["raw"]).cuda()
+    fr = torch.from_numpy(inp["desc"].view(np.int32)).cuda()
+    info, status, _ = P.decode_batch(plans, llr, frames=fr)
+    torch.cuda.synchronize()
+    info = info.cpu().numpy().view(np.uint32)
+    st = P.status_fields(status.cpu().numpy())
+    for f in range(96):
+        cd = codes[plan_of[f]]
+        one = inp["raw"][inp["desc"][f, 0]:inp["desc"][f, 0] + cd.n_tx * 4].view(np.float32)
+        ref = O.decode(cd, one[None].copy())
+        o = inp["out_off"][f]
+        bits = P.unpack_bits(info[o:o + (cd.k_data + 31) // 32], cd.k_data)
+        assert np.array_equal(bits, ref.info[0]) or ref.near_tie[0] == 1, f
+        assert st["L_used"][f] == ref.L_used[0], f
