@@ -68,7 +68,8 @@ __device__ __forceinline__ char* node_llr(const Ctx& c, uint32_t d, uint32_t r) 
 
 // ------------------------------------------------------------ F, G and H
 // SG / DG: the source (depth d) / destination (depth d + 1) slots are the
-// spilled depth-1 slots in global memory.
+// spilled depth-1 slots in global memory.  V elements per item; the slot
+// bases and strides are read once per op.
 template <typename T, int V, int NT, bool SG = false, bool DG = false>
 __device__ void run_fg(const Ctx& c, uint32_t d, uint32_t o, uint32_t a, bool is_g) {
   constexpr uint32_t E = VT<T>::E;
@@ -77,10 +78,17 @@ __device__ void run_fg(const Ctx& c, uint32_t d, uint32_t o, uint32_t a, bool is
   const uint32_t cpp = h / V, lc = lg2(cpp);
   const uint32_t total = a << lc;
   const uint32_t* t = tabs(c);
+  const uint8_t* pt = ptr_tab(c);
   const uint32_t dbase = t[d + 1], dstride = t[12 + d + 1];
+  const uint32_t sbase = d ? t[d] : c.lay.root, sstride = d ? t[12 + d] : 0u;
   for (uint32_t it = threadIdx.x; it < total; it += NT) {
     const uint32_t r = it >> lc, j = it & (cpp - 1);
-    const char* src = node_llr<SG>(c, d, r) + j * NB;
+    const uint32_t slot = d ? (uint32_t)pt[d * 32 + r] : 0u;
+    const char* src;
+    if constexpr (SG)
+      src = c.gsp + slot * t[13] + j * NB;
+    else
+      src = c.smem + sbase + slot * sstride + j * NB;
     uint32_t wa[4], wb[4], wo[4] = {0u, 0u, 0u, 0u};
     lds_ld<NB>(src, wa);
     lds_ld<NB>(src + h * E, wb);
@@ -99,7 +107,10 @@ __device__ void run_fg(const Ctx& c, uint32_t d, uint32_t o, uint32_t a, bool is
   if (threadIdx.x < a) ptr_tab(c)[(d + 1) * 32 + threadIdx.x] = (uint8_t)threadIdx.x;
 }
 
-// SP: this kernel may run spilled layouts (largest list 32).
+// Elements per item: as many as keep every thread of the workgroup busy
+// (a h / NT), at most VMAX and at most h, a power of two.  Small nodes thus
+// spread over many lanes instead of running their elements one after the
+// other on a few.  SP: this kernel may run spilled layouts (largest list 32).
 template <typename T, int NT, bool SP>
 __device__ void op_fg(const Ctx& c, uint32_t d, uint32_t o, uint32_t a, bool is_g) {
   const uint32_t h = (c.N >> d) >> 1;
@@ -114,13 +125,15 @@ __device__ void op_fg(const Ctx& c, uint32_t d, uint32_t o, uint32_t a, bool is_
       return;
     }
   }
-  if (h >= VM)
+  const uint32_t per = (a * h) / (uint32_t)NT;
+  const uint32_t v = per < h ? per : h;
+  if (v >= VM)
     run_fg<T, VM, NT>(c, d, o, a, is_g);
-  else if (VM >= 8 && h == 8)
-    run_fg<T, (VM >= 8 ? 8 : 1), NT>(c, d, o, a, is_g);
-  else if (VM >= 4 && h == 4)
-    run_fg<T, (VM >= 4 ? 4 : 1), NT>(c, d, o, a, is_g);
-  else if (h == 2)
+  else if (VM > 8 && v >= 8)
+    run_fg<T, (VM > 8 ? 8 : 1), NT>(c, d, o, a, is_g);
+  else if (VM > 4 && v >= 4)
+    run_fg<T, (VM > 4 ? 4 : 1), NT>(c, d, o, a, is_g);
+  else if (v >= 2)
     run_fg<T, 2, NT>(c, d, o, a, is_g);
   else
     run_fg<T, 1, NT>(c, d, o, a, is_g);
@@ -328,15 +341,46 @@ __device__ __forceinline__ void top_insert(K (&s)[NK], K x) {
   }
 }
 
+// Merge two ascending lists of NK distinct keys into the NK smallest of
+// both, ascending (for NK = 4: the elementwise minimum of one list and the
+// other reversed is bitonic, then two compare-exchange rounds).
+template <typename K, int NK>
+__device__ __forceinline__ void top_merge(K (&s)[NK], const K (&x)[NK]) {
+  if constexpr (NK == 1) {
+    s[0] = s[0] < x[0] ? s[0] : x[0];
+  } else if constexpr (NK == 2) {
+    const K lo = s[0] < x[0] ? s[0] : x[0], hi = s[0] < x[0] ? x[0] : s[0];
+    const K nx = s[1] < x[1] ? s[1] : x[1];
+    s[0] = lo;
+    s[1] = hi < nx ? hi : nx;
+  } else {
+    static_assert(NK == 4, "lists of 1, 2 or 4 keys");
+    K m[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) m[i] = s[i] < x[3 - i] ? s[i] : x[3 - i];
+    auto ce = [](K& u, K& v) {
+      const K lo = u < v ? u : v, hi = u < v ? v : u;
+      u = lo;
+      v = hi;
+    };
+    ce(m[0], m[2]);
+    ce(m[1], m[3]);
+    ce(m[0], m[1]);
+    ce(m[2], m[3]);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) s[i] = m[i];
+  }
+}
+
 // ------------------------------------------------------------ node ops
 constexpr uint32_t kEPL = 32;  // max elements per lane in a node (N/64)
 
 // Candidate q of a path: the local index (R1: the Chase-2 mask q; SPC: the
 // q-th mask, ascending, over the 4 least reliable positions whose weight has
 // the parity of the hard decision) and its penalty.
-template <typename T>
+template <typename T, int NK>
 __device__ __forceinline__ void node_candidate(uint32_t opc, uint32_t q, uint32_t par,
-                                               const typename VT<T>::Key (&top)[4],
+                                               const typename VT<T>::Key (&top)[NK],
                                                uint32_t* mask_out,
                                                typename VT<T>::Acc* pen_out) {
   using Acc = typename VT<T>::Acc;
@@ -349,7 +393,7 @@ __device__ __forceinline__ void node_candidate(uint32_t opc, uint32_t q, uint32_
   }
   Acc pen = (Acc)0;
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < NK; ++i)
     if ((mask >> i) & 1u) pen = pen + rel_mag<T>(top[i]);
   *mask_out = mask;
   *pen_out = pen;
@@ -359,103 +403,120 @@ __device__ __forceinline__ void node_candidate(uint32_t opc, uint32_t q, uint32_
 // Integer penalty sums are exact, so any lane assignment gives the same
 // result: each path gets a segment of G lanes with G as large as possible
 // while every active path fits one round (lane j of a segment holds elements
-// j, j + G, ...).  Writes the candidate keys (or, for single-candidate nodes,
-// the updated metric and zero decisions) and, for R1 / SPC, the hard
-// decisions into the parent's own partial-sum region [o, o + m).
-template <typename T, int NT, bool GSP>
-__device__ void node_stats_int(const Ctx& c, uint32_t opc, uint32_t d, uint32_t o, uint32_t a,
-                               uint32_t C) {
+// j, j + G, ...).  NK = 0: single-candidate nodes (the metric update and zero
+// decisions) and REP / information leaves (two candidate keys).  NK = 2 / 4:
+// R1 / SPC -- the NK least reliable positions of each path, its candidate
+// keys, and its hard decisions, written into the parent's own partial-sum
+// region [o, o + m) straight from the wave's sign ballots (G consecutive
+// elements of a path per ballot).
+template <typename T, int NT, bool GSP, int NK>
+__device__ void node_stats_int_k(const Ctx& c, uint32_t opc, uint32_t d, uint32_t o, uint32_t a,
+                                 uint32_t C) {
   using Key = typename VT<T>::Key;
   const uint32_t m = c.N >> d;
   uint32_t G = 64;
   while (G > 1 && G * a > (uint32_t)NT) G >>= 1;
   if (G > m) G = m;
   const uint32_t lgG = lg2(G), epl = m >> lgG, ppr = NT >> lgG;
-  const uint32_t tid = threadIdx.x, j = tid & (G - 1);
+  const uint32_t tid = threadIdx.x, j = tid & (G - 1), lane = tid & 63u;
+  const uint32_t seg0 = lane & ~(G - 1);
   int* pm = pm_tab<T>(c);
   Key* cand = reinterpret_cast<Key*>(c.smem + c.lay.cand);
   uint16_t* cpos = reinterpret_cast<uint16_t*>(c.smem + c.lay.cpos);
   const bool single = (opc == OP_R0 || opc == OP_LF);
-  const bool chase = (opc == OP_R1 || opc == OP_SPC);
+  const uint64_t gmask = G >= 64 ? ~0ull : ((1ull << G) - 1ull);
   for (uint32_t base = 0; base < a; base += ppr) {
     const uint32_t r = base + (tid >> lgG);
     const bool valid = r < a;
     const T* al = reinterpret_cast<const T*>(node_llr<GSP>(c, d, valid ? r : 0));
+    uint32_t* B = bits_of(c, valid ? r : 0) + (o >> 5);
     int p0 = 0, p1 = 0;
-    uint32_t par = 0;
-    Key top[4] = {~0u, ~0u, ~0u, ~0u};
+    uint32_t par = 0, hw = 0;
+    Key top[NK > 0 ? NK : 1];
+#pragma unroll
+    for (int i = 0; i < (NK > 0 ? NK : 1); ++i) top[i] = ~(Key)0;
     for (uint32_t t = 0; t < epl; ++t) {
       const uint32_t k = j + (t << lgG);
       const int v = al[k];
       const int mg = abs(v);
-      if (v < 0) {
-        p0 += mg;
-        par ^= 1u;
+      if constexpr (NK == 0) {
+        if (v < 0)
+          p0 += mg;
+        else
+          p1 += mg;
       } else {
-        p1 += mg;
+        top_insert<Key, NK>(top, ((uint32_t)mg << 16) | k);
+        const uint64_t bal = (uint64_t)__ballot(v < 0);
+        par ^= (uint32_t)__popcll((bal >> seg0) & gmask) & 1u;
+        if (G >= 32) {
+          // lanes 32q .. 32q + 31 of the wave hold 32 consecutive elements
+          if (valid && (j & 31u) == 0) B[((t << lgG) + j) >> 5] = (uint32_t)(bal >> (lane & 32u));
+        } else {
+          hw |= (uint32_t)((bal >> seg0) & gmask) << ((t << lgG) & 31u);
+          if (m >= 32 && (((t + 1) << lgG) & 31u) == 0) {
+            if (valid && j == 0) B[(t << lgG) >> 5] = hw;
+            hw = 0;
+          }
+        }
       }
-      if (chase) top_insert<Key, 4>(top, ((uint32_t)mg << 16) | k);
+    }
+    if constexpr (NK > 0) {
+      if (m < 32 && valid && j == 0) {
+        const uint32_t msk = ((1u << m) - 1u) << (o & 31);
+        B[0] = (B[0] & ~msk) | (hw << (o & 31));
+      }
     }
     for (uint32_t s = G >> 1; s >= 1; s >>= 1) {
-      p0 += __shfl_xor(p0, (int)s, 64);
-      p1 += __shfl_xor(p1, (int)s, 64);
-      if (chase) {
-        Key other[4];
+      if constexpr (NK == 0) {
+        p0 += __shfl_xor(p0, (int)s, 64);
+        p1 += __shfl_xor(p1, (int)s, 64);
+      } else {
+        Key other[NK];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) other[i] = __shfl_xor(top[i], (int)s, 64);
-#pragma unroll
-        for (int i = 0; i < 4; ++i) top_insert<Key, 4>(top, other[i]);
-        par ^= __shfl_xor(par, (int)s, 64);
+        for (int i = 0; i < NK; ++i) other[i] = __shfl_xor(top[i], (int)s, 64);
+        top_merge<Key, NK>(top, other);
       }
     }
     if (!valid) continue;
-    if (single) {
-      if (j == 0) pm[r] = pm_add<T>(pm[r], p0);
-      uint32_t* B = bits_of(c, r);
-      if (m >= 32) {
-        for (uint32_t w = j; w < (m >> 5); w += G) B[(o >> 5) + w] = 0u;
+    if constexpr (NK == 0) {
+      if (single) {
+        if (j == 0) pm[r] = pm_add<T>(pm[r], p0);
+        if (m >= 32) {
+          for (uint32_t w = j; w < (m >> 5); w += G) B[w] = 0u;
+        } else if (j == 0) {
+          B[0] &= ~(((1u << m) - 1u) << (o & 31));
+        }
       } else if (j == 0) {
-        B[o >> 5] &= ~(((1u << m) - 1u) << (o & 31));
-      }
-    } else if (!chase) {
-      if (j == 0) {
         cand[r * 2 + 0] = make_key<T>(pm_add<T>(pm[r], p0), r, 0);
         cand[r * 2 + 1] = make_key<T>(pm_add<T>(pm[r], p1), r, 1);
       }
     } else {
-      const uint32_t npos = opc == OP_R1 ? 2u : 4u;
       for (uint32_t q = j; q < C; q += G) {
         uint32_t mask;
         int pen;
-        node_candidate<T>(opc, q, par, top, &mask, &pen);
+        node_candidate<T, NK>(opc, q, par, top, &mask, &pen);
         cand[r * C + q] = make_key<T>(pm_add<T>(pm[r], pen), r, mask);
-        if (q < npos) {
+        if (q < (uint32_t)NK) {
           Key tq = top[0];
 #pragma unroll
-          for (int i = 1; i < 4; ++i)
+          for (int i = 1; i < NK; ++i)
             if ((uint32_t)i == q) tq = top[i];
           cpos[r * 4 + q] = (uint16_t)(tq & 0xFFFFu);
         }
       }
     }
   }
-  if (chase) {
-    // hard decisions, one 32-bit word (or the m < 32 bits) per item
-    const uint32_t nw = m >= 32 ? (m >> 5) : 1u, lnw = lg2(nw), nb = m >= 32 ? 32u : m;
-    for (uint32_t it = tid; it < (a << lnw); it += NT) {
-      const uint32_t r = it >> lnw, w = it & (nw - 1u);
-      const T* al = reinterpret_cast<const T*>(node_llr<GSP>(c, d, r)) + (w << 5);
-      uint32_t hv = 0;
-      for (uint32_t b = 0; b < nb; ++b) hv |= (al[b] < (T)0 ? 1u : 0u) << b;
-      uint32_t* B = bits_of(c, r);
-      if (m >= 32) {
-        B[(o >> 5) + w] = hv;
-      } else {
-        const uint32_t msk = ((1u << m) - 1u) << (o & 31);
-        B[o >> 5] = (B[o >> 5] & ~msk) | (hv << (o & 31));
-      }
-    }
-  }
+}
+
+template <typename T, int NT, bool GSP>
+__device__ void node_stats_int(const Ctx& c, uint32_t opc, uint32_t d, uint32_t o, uint32_t a,
+                               uint32_t C) {
+  if (opc == OP_R1)
+    node_stats_int_k<T, NT, GSP, 2>(c, opc, d, o, a, C);
+  else if (opc == OP_SPC)
+    node_stats_int_k<T, NT, GSP, 4>(c, opc, d, o, a, C);
+  else
+    node_stats_int_k<T, NT, GSP, 0>(c, opc, d, o, a, C);
 }
 
 // Per-path node work (float32).  Each path is handled by a segment of
@@ -570,7 +631,7 @@ __device__ void node_stats_float(const Ctx& c, uint32_t opc, uint32_t d, uint32_
       for (uint32_t q = j; valid && q < C; q += G) {
         uint32_t mask;
         Acc pen;
-        node_candidate<T>(opc, q, par, top, &mask, &pen);
+        node_candidate<T, 4>(opc, q, par, top, &mask, &pen);
         cand[r * C + q] = make_key<T>(pm_add<T>(pm[r], pen), r, mask);
         if (q < npos) {
           Key tq = top[0];
