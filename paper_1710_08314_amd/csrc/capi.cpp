@@ -293,7 +293,7 @@ Work work_view(uint32_t* base, size_t cap) {
   return w;
 }
 
-// Depth-1 spill of the batch: bytes per workgroup (0: no plan spills) and the
+// Spill of the batch: global bytes per workgroup (0: no plan spills) and the
 // smallest LDS footprint of a spilled layout, which bounds the workgroups per
 // CU of any launch that can run one.
 static void spill_geometry(const Batch& b, uint64_t* stride, uint32_t* lds_min) {
@@ -303,8 +303,8 @@ static void spill_geometry(const Batch& b, uint64_t* stride, uint32_t* lds_min) 
     const DevPlan& h = p->hp.hdr;
     const uint32_t E = elem_bytes(h.quant);
     const LdsLayout lay = lds_layout(h.N, h.n, E, h.max_list, key_bytes(h.quant));
-    if (!lay.spill1) continue;
-    const uint64_t sb = spill1_bytes(h.N, E, h.max_list);
+    if (!lay.spill) continue;
+    const uint64_t sb = spill_bytes(h.N, E, h.max_list, lay.spill);
     *stride = sb > *stride ? sb : *stride;
     *lds_min = lay.total < *lds_min ? lay.total : *lds_min;
   }
@@ -589,7 +589,7 @@ int launch_batch(const Batch& b_in, uint32_t schedule, const Work& w, hipStream_
   tp.lds_a = lds_a;
   tp.grid_a = persistent_grid(cus, lds_a, 16, n_frames);
   tp.lds_b = b.lds;
-  tp.grid_b = persistent_grid(cus, b.lds, 4, n_frames);
+  tp.grid_b = persistent_grid(cus, b.lds, 8, n_frames);
   // frames claimed at a time: about n / (32 workgroups' worth), so that the
   // frames a tier has to decode spread evenly over its workgroups; at most 64
   // (one wave's worth of state words), at least 1

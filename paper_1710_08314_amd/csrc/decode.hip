@@ -54,11 +54,12 @@ __device__ __forceinline__ uint32_t* tabs(const Ctx& c) {
   return reinterpret_cast<uint32_t*>(c.smem + c.lay.tabs);
 }
 // Address of element 0 of the depth-d LLRs of the path of rank r.  With G,
-// the depth-1 slots of a spilled layout (global memory).
+// a spilled depth (1 <= d <= lay.spill) in global memory.
 template <bool G = false>
 __device__ __forceinline__ char* node_llr(const Ctx& c, uint32_t d, uint32_t r) {
   if constexpr (G) {
-    return c.gsp + (uint32_t)ptr_tab(c)[32 + r] * tabs(c)[13];
+    const uint32_t* t = tabs(c);
+    return c.gsp + t[d] + (uint32_t)ptr_tab(c)[d * 32 + r] * t[12 + d];
   } else {
     if (d == 0) return c.smem + c.lay.root;
     const uint32_t* t = tabs(c);
@@ -67,9 +68,9 @@ __device__ __forceinline__ char* node_llr(const Ctx& c, uint32_t d, uint32_t r) 
 }
 
 // ------------------------------------------------------------ F, G and H
-// SG / DG: the source (depth d) / destination (depth d + 1) slots are the
-// spilled depth-1 slots in global memory.  V elements per item; the slot
-// bases and strides are read once per op.
+// SG / DG: the source (depth d) / destination (depth d + 1) slots are
+// spilled ones in global memory.  V elements per item; the slot bases and
+// strides are read once per op.
 template <typename T, int V, int NT, bool SG = false, bool DG = false>
 __device__ void run_fg(const Ctx& c, uint32_t d, uint32_t o, uint32_t a, bool is_g) {
   constexpr uint32_t E = VT<T>::E;
@@ -86,7 +87,7 @@ __device__ void run_fg(const Ctx& c, uint32_t d, uint32_t o, uint32_t a, bool is
     const uint32_t slot = d ? (uint32_t)pt[d * 32 + r] : 0u;
     const char* src;
     if constexpr (SG)
-      src = c.gsp + slot * t[13] + j * NB;
+      src = c.gsp + sbase + slot * sstride + j * NB;
     else
       src = c.smem + sbase + slot * sstride + j * NB;
     uint32_t wa[4], wb[4], wo[4] = {0u, 0u, 0u, 0u};
@@ -100,7 +101,7 @@ __device__ void run_fg(const Ctx& c, uint32_t d, uint32_t o, uint32_t a, bool is
       f_chunk<T, V>(wa, wb, wo);
     }
     if constexpr (DG)
-      lds_st<NB>(c.gsp + r * dstride + j * NB, wo);
+      lds_st<NB>(c.gsp + dbase + r * dstride + j * NB, wo);
     else
       lds_st<NB>(c.smem + dbase + r * dstride + j * NB, wo);
   }
@@ -116,10 +117,13 @@ __device__ void op_fg(const Ctx& c, uint32_t d, uint32_t o, uint32_t a, bool is_
   const uint32_t h = (c.N >> d) >> 1;
   constexpr uint32_t VM = VT<T>::VMAX;
   if constexpr (SP) {
-    // spilled layouts exist only for N = 2048, where h >= VM at depths 0 and 1
-    if (c.lay.spill1 && d <= 1) {
+    // spilled layouts have N >= 512, so h >= 64 >= VM at the depths < S + 1
+    const uint32_t S = c.lay.spill;
+    if (d <= S && S) {
       if (d == 0)
         run_fg<T, VM, NT, false, true>(c, d, o, a, is_g);
+      else if (d < S)
+        run_fg<T, VM, NT, true, true>(c, d, o, a, is_g);
       else
         run_fg<T, VM, NT, true, false>(c, d, o, a, is_g);
       return;
@@ -247,18 +251,20 @@ __device__ void sort_keys(const K* src, uint32_t cnt, K* dst, uint32_t keep) {
     sort_keys_kpl<K, 4>(src, cnt, dst, keep);
 }
 
-// Selection by rank counting (more than 64 candidates): every thread takes a
-// candidate, counts the smaller keys (keys are unique), and a candidate of
-// rank < keep lands at sel[rank].  The candidate count is then a multiple of
-// 4 (four or eight candidates per path), so keys are read 16 bytes at a time.
+// Selection by rank counting: every thread takes a candidate, counts the
+// smaller keys (keys are unique), and a candidate of rank < keep lands at
+// sel[rank].  Keys are read 16 bytes at a time (broadcast reads), the tail
+// one at a time.  Unlike a sorting network this has no chain of lane
+// exchanges: two dependent LDS round trips whatever the candidate count.
 template <typename K, int NT>
 __device__ void rank_select(const K* cand, uint32_t total, K* sel, uint32_t keep) {
   constexpr uint32_t PER = 16 / sizeof(K);
   const uint4* c4 = reinterpret_cast<const uint4*>(cand);
+  const uint32_t nv = total / PER;
   for (uint32_t i = threadIdx.x; i < total; i += NT) {
     const K k = cand[i];
     uint32_t rank = 0;
-    for (uint32_t q = 0; q < total / PER; ++q) {
+    for (uint32_t q = 0; q < nv; ++q) {
       const uint4 v = c4[q];
       if constexpr (sizeof(K) == 4) {
         rank += (v.x < k) + (v.y < k) + (v.z < k) + (v.w < k);
@@ -267,6 +273,7 @@ __device__ void rank_select(const K* cand, uint32_t total, K* sel, uint32_t keep
         rank += (a < k) + (b < k);
       }
     }
+    for (uint32_t q = nv * PER; q < total; ++q) rank += cand[q] < k;
     if (rank < keep) sel[rank] = k;
   }
 }
@@ -661,12 +668,12 @@ __device__ void op_node(const Ctx& c, uint32_t opc, uint32_t d, uint32_t o, uint
   const uint32_t C = single ? 1u : (opc == OP_R1 ? 4u : (opc == OP_SPC ? 8u : 2u));
   constexpr bool SP = LMAX >= (int)kMaxL;
   if constexpr (VT<T>::INT) {
-    if (SP && c.lay.spill1 && d == 1)
+    if (SP && d >= 1 && d <= c.lay.spill)
       node_stats_int<T, NT, SP>(c, opc, d, o, a, C);
     else
       node_stats_int<T, NT, false>(c, opc, d, o, a, C);
   } else {
-    if (SP && c.lay.spill1 && d == 1)
+    if (SP && d >= 1 && d <= c.lay.spill)
       node_stats_float<T, NT, SP>(c, opc, d, o, a, C);
     else
       node_stats_float<T, NT, false>(c, opc, d, o, a, C);
@@ -691,16 +698,13 @@ __device__ void op_node(const Ctx& c, uint32_t opc, uint32_t d, uint32_t o, uint
   Key* sel = reinterpret_cast<Key*>(c.smem + c.lay.sel);
   const uint32_t total = a * C;
   const uint32_t keep = total < c.L ? total : c.L;
-  if (total <= 64) {
-    if (tid < 64) sort_keys_small<Key>(cand, total, sel, keep);
-  } else {
-    rank_select<Key, NT>(cand, total, sel, keep);
-  }
+  rank_select<Key, NT>(cand, total, sel, keep);
   __syncthreads();
 
   // ---- path copy: partial-sum words [0, nwc) and slot pointers of depths
   // 1..d from each survivor's parent (register staged: all reads, barrier,
-  // all writes, so a parent can be overwritten by its own child)
+  // all writes, so a parent can be overwritten by its own child).  A
+  // survivor whose parent has its own rank already holds that state.
   uint8_t* pt = ptr_tab(c);
   if (c.L > 1) {
     uint32_t nwc = (o + m + 31u) >> 5;
@@ -715,7 +719,8 @@ __device__ void op_node(const Ctx& c, uint32_t opc, uint32_t d, uint32_t o, uint
       reg[q] = 0;
       if (it < items) {
         const uint32_t i = it >> lw, w = it & ((1u << lw) - 1u);
-        if (w < nwc) reg[q] = bits_of(c, key_parent<T>(sel[i]))[w];
+        const uint32_t p = key_parent<T>(sel[i]);
+        if (w < nwc && p != i) reg[q] = bits_of(c, p)[w];
       }
     }
     constexpr int PMAX = (int)((kMaxLogN * LMAX + NT - 1) / NT);
@@ -736,7 +741,7 @@ __device__ void op_node(const Ctx& c, uint32_t opc, uint32_t d, uint32_t o, uint
       const uint32_t it = tid + q * NT;
       if (it < items) {
         const uint32_t i = it >> lw, w = it & ((1u << lw) - 1u);
-        if (w < nwc) bits_of(c, i)[w] = reg[q];
+        if (w < nwc && key_parent<T>(sel[i]) != i) bits_of(c, i)[w] = reg[q];
       }
     }
 #pragma unroll
@@ -744,7 +749,7 @@ __device__ void op_node(const Ctx& c, uint32_t opc, uint32_t d, uint32_t o, uint
       const uint32_t it = tid + q * NT;
       if (it < pitems) {
         const uint32_t i = it / d, dd = 1 + it % d;
-        pt[dd * 32 + i] = preg[q];
+        if (key_parent<T>(sel[i]) != i) pt[dd * 32 + i] = preg[q];
       }
     }
     __syncthreads();
@@ -894,13 +899,14 @@ __device__ void setup_stage(Ctx& c, uint32_t L) {
   c.lay = lds_layout(c.N, c.n, VT<T>::E, L, (uint32_t)sizeof(typename VT<T>::Key));
   uint32_t* t = tabs(c);
   if (threadIdx.x == 0) {
-    uint32_t cur = c.lay.stages;
+    uint32_t cur = c.lay.stages, gcur = 0;
     t[0] = c.lay.root;
     t[12] = 0;
     for (uint32_t d = 1; d <= c.n; ++d) {
       t[12 + d] = slot_bytes(c.N, d, VT<T>::E);
-      if (d == 1 && c.lay.spill1) {
-        t[d] = 0;  // in global memory (c.gsp)
+      if (d <= c.lay.spill) {
+        t[d] = gcur;  // offset in global memory (c.gsp)
+        gcur += L * t[12 + d];
         continue;
       }
       t[d] = cur;

@@ -94,7 +94,8 @@ POLAR_HD inline const uint32_t* plan_tab(const DevPlan* p, uint32_t off) {
 // ---------------------------------------------------------------------------
 struct LdsLayout {
   uint32_t root, stages, bits, ptr, pm, cand, sel, cpos, tabs, syn, ord, out, misc, total;
-  uint32_t spill1;  // 1: the depth-1 slots live in global memory (spill1_bytes per workgroup)
+  uint32_t spill;  // S: the slots of depths 1..S live in global memory (spill_bytes per
+                   // workgroup, depth 1 first)
 };
 
 // LDS a decoder workgroup may use for its frame (the CU's LDS less room for
@@ -110,20 +111,22 @@ POLAR_HD inline uint32_t slot_bytes(uint32_t N, uint32_t d, uint32_t E) {
   return ru4(m * E);
 }
 
-// Bytes of the depth-1 slots of L paths (the largest stage).
-POLAR_HD inline uint32_t spill1_bytes(uint32_t N, uint32_t E, uint32_t L) {
-  return L * slot_bytes(N, 1, E);
+// Bytes of the slots of depths 1..S of L paths (per workgroup, global memory).
+POLAR_HD inline uint32_t spill_bytes(uint32_t N, uint32_t E, uint32_t L, uint32_t S) {
+  uint32_t b = 0;
+  for (uint32_t d = 1; d <= S; ++d) b += L * slot_bytes(N, d, E);
+  return b;
 }
 
 POLAR_HD inline LdsLayout lds_layout_s(uint32_t N, uint32_t n, uint32_t E, uint32_t L, uint32_t KB,
-                                       uint32_t spill1) {
+                                       uint32_t spill) {
   LdsLayout l{};
-  l.spill1 = spill1;
+  l.spill = spill;
   uint32_t cur = 0;
   l.root = cur;
   cur += ru16(N * E);
   l.stages = cur;
-  for (uint32_t d = spill1 ? 2u : 1u; d <= n; ++d) cur += L * slot_bytes(N, d, E);
+  for (uint32_t d = spill + 1; d <= n; ++d) cur += L * slot_bytes(N, d, E);
   cur = ru16(cur);
   const uint32_t bw = N >= 32 ? N / 32 : 1;
   l.bits = cur;
@@ -152,13 +155,26 @@ POLAR_HD inline LdsLayout lds_layout_s(uint32_t N, uint32_t n, uint32_t E, uint3
   return l;
 }
 
-// The layout of one frame at list size L: everything in LDS when it fits the
-// budget, else with the depth-1 slots (half of all LLR storage) in global
-// memory -- the float32 decoder at N = 2048, L = 32 (272 KB otherwise).
+// Spill policy.  A frame at a large list keeps the LLR slots of its top
+// depths (the largest ones) in global memory: always when its state would
+// not fit a CU's LDS (float32 at N = 2048, L = 32 needs 272 KB), and at
+// L >= kSpillMinL whenever it exceeds kLdsTarget, so that several
+// workgroups share a CU.  At most kMaxSpill depths, only for N >= 512 (the
+// spilled depths then hold nodes of at least 128 elements).  Only kernels
+// that run lists of kMaxL take such layouts.
+constexpr uint32_t kLdsTarget = 32 * 1024;
+constexpr uint32_t kSpillMinL = 16;
+constexpr uint32_t kMaxSpill = 2;
+
 POLAR_HD inline LdsLayout lds_layout(uint32_t N, uint32_t n, uint32_t E, uint32_t L, uint32_t KB) {
-  const LdsLayout l = lds_layout_s(N, n, E, L, KB, 0);
-  if (l.total <= kLdsBudget || n < 2) return l;
-  return lds_layout_s(N, n, E, L, KB, 1);
+  LdsLayout l = lds_layout_s(N, n, E, L, KB, 0);
+  uint32_t s = 0;
+  while (s < kMaxSpill && N >= 512 &&
+         (l.total > kLdsBudget || (L >= kSpillMinL && l.total > kLdsTarget))) {
+    ++s;
+    l = lds_layout_s(N, n, E, L, KB, s);
+  }
+  return l;
 }
 
 // LDS layout of the L = 1 tier for one frame: root N LLRs, the LLRs of the

@@ -145,15 +145,24 @@ def test_punctured_frozen_set_matches_oracle(N, K, c, design, S, Pn):
         P.plan_query(N, K, c, 0x621, frozen=bad, n_shorten=S, n_puncture=Pn)
 
 
-def test_float32_list32_n2048_spills_depth1():
-    """float32 at N = 2048, L = 32 needs 272 KB of LDS: the plan accepts it with
-    the depth-1 slots (32 x 1024 floats) moved to global memory and the rest
-    within one CU's LDS; smaller lists and int16 stay entirely in LDS."""
-    info, _ = P.plan_query(2048, 1000, 11, 0x621, design_ebn0_db=2.5, algo=P.CA_SCL, L=32,
-                           quant=P.F32)
-    assert info.lds_bytes <= 160 * 1024 - 1024
-    full = 4 * (2048 + 32 * 2047)
-    assert info.lds_bytes < full - 32 * 1024 * 4 + 16 * 1024
-    i16, _ = P.plan_query(2048, 1000, 11, 0x621, design_ebn0_db=2.5, algo=P.CA_SCL, L=32,
-                          quant=P.I16)
-    assert i16.lds_bytes >= 2 * (2048 + 32 * 2047)
+def test_large_lists_spill_top_depths():
+    """At N = 2048 the LLR slots of depths 1 and 2 (L x (1024 + 512) elements)
+    of a list of 16 or more move to global memory: float32 at L = 32 (272 KB
+    otherwise) then fits one CU's LDS, int8 at L = 32 fits 32 KB so that
+    several workgroups share a CU.  Lists of at most 8 (the kernels without
+    spill support) keep every slot in LDS."""
+    E = {P.F32: 4, P.I16: 2, P.I8: 1}
+    for q in (P.F32, P.I16, P.I8):
+        for L in (1, 2, 4, 8, 16, 32):
+            info, _ = P.plan_query(2048, 1000, 11, 0x621, design_ebn0_db=2.5, algo=P.CA_SCL,
+                                   L=L, quant=q)
+            full = E[q] * (2048 + L * 2047)  # root + the slots of depths 1..11
+            assert info.lds_bytes <= 160 * 1024 - 1024
+            if L <= 8:
+                assert info.lds_bytes >= full
+            else:
+                spilled = full - E[q] * L * (1024 + 512)
+                assert spilled <= info.lds_bytes < spilled + 16 * 1024, (q, L)
+    i8, _ = P.plan_query(2048, 1000, 11, 0x621, design_ebn0_db=2.5, algo=P.CA_SCL, L=32,
+                         quant=P.I8)
+    assert i8.lds_bytes <= 32 * 1024
