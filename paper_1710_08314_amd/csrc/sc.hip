@@ -7,11 +7,12 @@
 // path copies and no slot indirection.  Its layout follows the shape of the
 // tree instead:
 //   * nodes of size >= 128 keep their LLRs in LDS and use all 64 lanes;
-//   * every subtree of size <= 64 runs in registers: x[k] holds the LLRs of
-//     the current node of size 2^k, one per lane, f and g read the sibling
-//     half through a lane shuffle, and partial sums are 64-bit uniform masks
-//     (beta[k]: the last finished node of size 2^k; left[k]: the left child
-//     of the node of size 2^k being decoded), so h is scalar bit arithmetic;
+//   * every subtree of size <= 64 runs in registers: the nodes of size
+//     2^k <= 32 on the current path share one register, level k in lanes
+//     [2^k, 2^(k+1)), the node of size 64 has a register of its own, and
+//     partial sums are one bit per lane in the same places; an op at any
+//     register level is one code path (operands move between levels by lane
+//     permutation), so the op word is dispatched on its opcode alone;
 //   * a dedicated node decides with a ballot (Rate-1: hard decision; SPC:
 //     hard decision with the least reliable position flipped on odd parity)
 //     or a lane reduction (REP: the two disagreement penalties).
@@ -75,7 +76,6 @@ __device__ __forceinline__ uint64_t rfl64(uint64_t v) {
   return ((uint64_t)rfl((uint32_t)(v >> 32)) << 32) | rfl((uint32_t)v);
 }
 
-constexpr uint64_t mask64(uint32_t w) { return w >= 64 ? ~0ull : ((1ull << w) - 1ull); }
 
 // Decision of a REP node at L = 1: the all-one candidate wins only when its
 // metric is strictly smaller.  Returns v and updates the (float) metric.
@@ -102,124 +102,152 @@ __device__ __forceinline__ A lanes_sum(A v, uint32_t w) {
 }
 
 // ------------------------------------------------------- register levels
+// The nodes of size 2^k <= 32 on the current root-to-leaf path keep their
+// LLRs in one register, xs, in lanes [2^k, 2^(k+1)) (level k; levels 0..5
+// fill lanes 1..63), the node of size 64 in x6 (lane i = element i).
+// Partial sums are one bit per lane in the same places: bs (levels 0..5)
+// and b6 hold the last finished node of each size, ls (lanes [2^(k-1), 2^k))
+// the left child of the level-k node being decoded, l7 the left child (size
+// 64) of the size-128 node.  An op at any register level is one code path
+// with the level k as a run-time value; operands move between levels by
+// lane permutation.
 template <typename T>
 struct Regs {
-  typename Lane<T>::V x[7];
-  uint64_t beta[7];
-  uint64_t left[8];
+  typename Lane<T>::V xs, x6;
+  uint32_t bs, b6, ls, l7;
 };
 
-// Pseudo-ops of codes with N <= 64 (the whole tree in registers), routed
-// through the same compile-time level dispatch so that the register arrays
-// are never indexed at run time (which would place them in scratch memory).
-constexpr uint32_t OPX_LOAD_ROOT = 14;   // x[n] <- the channel LLRs
-constexpr uint32_t OPX_STORE_ROOT = 15;  // LDS codeword bits <- beta[n]
+// Pseudo-ops of codes with N <= 64 (the whole tree in registers).
+constexpr uint32_t OPX_LOAD_ROOT = 14;   // level n <- the channel LLRs
+constexpr uint32_t OPX_STORE_ROOT = 15;  // LDS codeword bits <- level n partial sums
 
-template <typename T, int K>
-__device__ __forceinline__ void reg_op(uint32_t opc, Regs<T>& R, typename VT<T>::Acc& pm,
-                                       uint32_t lane, char* smem) {
+// Sum over the segment of M lanes holding v (aligned to M), stride-halving
+// order; every lane of the segment ends with the total.
+template <typename A>
+__device__ __forceinline__ A seg_sum(A v, uint32_t M) {
+  for (uint32_t s = M >> 1; s >= 1; s >>= 1) v = v + __shfl_xor(v, (int)s, 64);
+  return v;
+}
+__device__ __forceinline__ float lane_f(float v, uint32_t l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), (int)l));
+}
+__device__ __forceinline__ int lane_i(int v, uint32_t l) { return __builtin_amdgcn_readlane(v, (int)l); }
+
+template <typename T>
+__device__ __forceinline__ void reg_op(uint32_t opc, uint32_t K, Regs<T>& R,
+                                       typename VT<T>::Acc& pm, uint32_t lane, char* smem) {
   using V = typename Lane<T>::V;
   using Acc = typename VT<T>::Acc;
-  constexpr uint32_t M = 1u << K;
+  const uint32_t M = 1u << K;
+  const bool top = K == 6;
+  const uint32_t base = top ? 0u : M;  // first lane of level K
+  const uint32_t j = lane - base;      // index in the node (valid if < M)
+  const bool in = j < M;
   if (opc == OPX_LOAD_ROOT) {
-    R.x[K] = lane < M ? (V)reinterpret_cast<const T*>(smem)[lane] : (V)0;
+    const V v = in ? (V)reinterpret_cast<const T*>(smem)[j] : (V)0;
+    if (top)
+      R.x6 = v;
+    else if (in)
+      R.xs = v;
     return;
   }
   if (opc == OPX_STORE_ROOT) {
+    const uint64_t b = (uint64_t)__ballot((top ? R.b6 : R.bs) & 1u);
+    const uint64_t beta = top ? b : ((b >> M) & ((1ull << M) - 1ull));
     uint32_t* bits = reinterpret_cast<uint32_t*>(smem + sc_bits_off(M, VT<T>::E));
-    if (lane < 2) bits[lane] = lane ? (uint32_t)(R.beta[K] >> 32) : (uint32_t)R.beta[K];
+    if (lane < 2) bits[lane] = lane ? (uint32_t)(beta >> 32) : (uint32_t)beta;
     return;
   }
-  if constexpr (K >= 1) {
-    constexpr uint32_t HF = M / 2;
+  const V x = top ? R.x6 : R.xs;
+  if (opc == OP_F || opc == OP_G) {
+    // child (level K - 1) in lanes [h, 2h); element i from the node's i, i + h
+    const uint32_t h = M >> 1, i = (lane - h) & (h - 1);
+    const V a = __shfl(x, (int)(base + i), 64);
+    const V b = __shfl(x, (int)(base + h + i), 64);
+    const bool child = lane - h < h;
     if (opc == OP_F) {
-      const V y = __shfl_down(R.x[K], HF, 64);
-      R.x[K - 1] = fv<T>(R.x[K], y);
-      return;
+      const V y = fv<T>(a, b);
+      if (child) R.xs = y;
+    } else {
+      // the left child's partial sums sit in the same lanes (level K - 1)
+      const V y = gv<T>(a, b, R.bs & 1u);
+      if (child) {
+        R.xs = y;
+        R.ls = R.bs;
+      }
     }
-    if (opc == OP_G) {
-      const V y = __shfl_down(R.x[K], HF, 64);
-      R.left[K] = R.beta[K - 1];
-      const uint32_t s = (uint32_t)(R.beta[K - 1] >> lane) & 1u;
-      R.x[K - 1] = gv<T>(R.x[K], y, s);
-      return;
-    }
-    if (opc == OP_H) {
-      R.beta[K] = ((R.left[K] ^ R.beta[K - 1]) & mask64(HF)) | (R.beta[K - 1] << HF);
-      return;
-    }
+    return;
   }
-  const V v = R.x[K];
-  const bool neg = v < (V)0;
-  const Acc mg = magv<T>(v);
-  const bool in = lane < M;
+  if (opc == OP_H) {
+    // beta_K[i] = left[i] ^ beta_{K-1}[i], beta_K[i + h] = beta_{K-1}[i]
+    const uint32_t h = M >> 1;
+    const uint32_t pk = (R.bs & 1u) | (((R.ls ^ R.bs) & 1u) << 1);
+    const uint32_t g = __shfl(pk, (int)(h + (j & (h - 1))), 64);
+    const uint32_t v = j < h ? (g >> 1) : (g & 1u);
+    if (top)
+      R.b6 = v;
+    else if (in)
+      R.bs = v;
+    return;
+  }
+  const bool neg = x < (V)0;
+  const Acc mg = magv<T>(x);
+  uint32_t bit;
   switch (opc) {
     case OP_LF:
     case OP_R0: {
-      R.beta[K] = 0;
+      bit = 0;
       if constexpr (!VT<T>::INT) {
-        const float pen = rflf(lanes_sum<float>(in && neg ? mg : 0.f, M));
+        const float pen = lane_f(seg_sum<float>(in && neg ? mg : 0.f, M), base);
         pm = pm + pen;
       }
-      return;
+      break;
     }
     case OP_LI:
-    case OP_R1: {
-      R.beta[K] = (uint64_t)__ballot(in && neg) & mask64(M);
-      return;
-    }
+    case OP_R1:
+      bit = neg ? 1u : 0u;
+      break;
     case OP_REP: {
-      Acc p0 = lanes_sum<Acc>(in && neg ? mg : (Acc)0, M);
-      Acc p1 = lanes_sum<Acc>(in && !neg ? mg : (Acc)0, M);
+      Acc p0 = seg_sum<Acc>(in && neg ? mg : (Acc)0, M);
+      Acc p1 = seg_sum<Acc>(in && !neg ? mg : (Acc)0, M);
       if constexpr (VT<T>::INT) {
-        p0 = rfli(p0);
-        p1 = rfli(p1);
+        p0 = lane_i(p0, base);
+        p1 = lane_i(p1, base);
       } else {
-        p0 = rflf(p0);
-        p1 = rflf(p1);
+        p0 = lane_f(p0, base);
+        p1 = lane_f(p1, base);
       }
-      const uint32_t bit = rep_decide<T>(p0, p1, pm);
-      R.beta[K] = bit ? mask64(M) : 0ull;
-      return;
+      bit = rep_decide<T>(p0, p1, pm);
+      break;
     }
     default: {  // OP_SPC
-      uint64_t hd = (uint64_t)__ballot(in && neg) & mask64(M);
+      bit = neg ? 1u : 0u;
+      const uint64_t hd = (uint64_t)__ballot(in && neg);
       if (__popcll(hd) & 1) {
         // least reliable position (smallest |alpha|, then smallest index)
         uint64_t key;
         if constexpr (VT<T>::INT)
-          key = in ? (((uint64_t)(uint32_t)mg << 6) | lane) : ~0ull;
+          key = in ? (((uint64_t)(uint32_t)mg << 6) | j) : ~0ull;
         else
-          key = in ? (((uint64_t)__float_as_uint(mg) << 6) | lane) : ~0ull;
+          key = in ? (((uint64_t)__float_as_uint(mg) << 6) | j) : ~0ull;
         for (uint32_t s = M >> 1; s >= 1; s >>= 1) {
           const uint64_t o = shfl_xor_k(key, (int)s);
           key = o < key ? o : key;
         }
-        key = rfl64(key);
-        const uint32_t idx = (uint32_t)key & 63u;
-        hd ^= 1ull << idx;
-        if constexpr (!VT<T>::INT) pm = pm + __uint_as_float((uint32_t)(key >> 6));
+        const uint64_t kmin = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(key >> 32), (int)base) << 32) |
+                              (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)key, (int)base);
+        if (j == ((uint32_t)kmin & 63u)) bit ^= 1u;
+        if constexpr (!VT<T>::INT) pm = pm + __uint_as_float((uint32_t)(kmin >> 6));
       } else if constexpr (!VT<T>::INT) {
         pm = pm + 0.f;
       }
-      R.beta[K] = hd;
-      return;
+      break;
     }
   }
-}
-
-template <typename T>
-__device__ __forceinline__ void reg_dispatch(uint32_t k, uint32_t opc, Regs<T>& R,
-                                             typename VT<T>::Acc& pm, uint32_t lane, char* smem) {
-  switch (k) {
-    case 0: reg_op<T, 0>(opc, R, pm, lane, smem); break;
-    case 1: reg_op<T, 1>(opc, R, pm, lane, smem); break;
-    case 2: reg_op<T, 2>(opc, R, pm, lane, smem); break;
-    case 3: reg_op<T, 3>(opc, R, pm, lane, smem); break;
-    case 4: reg_op<T, 4>(opc, R, pm, lane, smem); break;
-    case 5: reg_op<T, 5>(opc, R, pm, lane, smem); break;
-    default: reg_op<T, 6>(opc, R, pm, lane, smem); break;
-  }
+  if (top)
+    R.b6 = bit;
+  else if (in)
+    R.bs = bit;
 }
 
 // ------------------------------------------------------------ LDS levels
@@ -244,10 +272,10 @@ __device__ __forceinline__ void lds_op(char* smem, uint32_t N, uint32_t opc, uin
       // the child (size 64) goes to registers: lane i holds element i
       const V a = (V)src[lane], b = (V)src[lane + 64];
       if (opc == OP_F) {
-        R.x[6] = fv<T>(a, b);
+        R.x6 = fv<T>(a, b);
       } else {
-        R.left[7] = R.beta[6];
-        R.x[6] = gv<T>(a, b, (uint32_t)(R.beta[6] >> lane) & 1u);
+        R.l7 = R.b6;
+        R.x6 = gv<T>(a, b, R.b6 & 1u);
       }
       return;
     }
@@ -270,7 +298,8 @@ __device__ __forceinline__ void lds_op(char* smem, uint32_t N, uint32_t opc, uin
   }
   if (opc == OP_H) {
     if (k == 7) {
-      const uint64_t lo = R.left[7] ^ R.beta[6], hi = R.beta[6];
+      const uint64_t lo = (uint64_t)__ballot((R.l7 ^ R.b6) & 1u),
+                     hi = (uint64_t)__ballot(R.b6 & 1u);
       const uint32_t w0 = o >> 5;
       if (lane < 4) {
         const uint64_t v = lane < 2 ? lo : hi;
@@ -421,8 +450,10 @@ __global__ __launch_bounds__(64) void k_sc(KArgs A, uint32_t* state, ClassSel se
       continue;  // a list tier starts it (state[f] already holds its first stage)
     }
     if (A.times && lane == 0) A.times[2 * (size_t)f] = wall_clock64();
-    const uint32_t N = P->N, n = P->n, ntx = P->n_tx, n_ops = P->n_ops, np = P->n_punct;
-    const uint32_t* prog = plan_tab(P, P->off_prog);
+    P = uni_ptr(P);
+    const uint32_t N = uni(P->N), n = uni(P->n), ntx = uni(P->n_tx), n_ops = uni(P->n_ops),
+                   np = uni(P->n_punct);
+    const uint32_t* prog = uni_ptr(plan_tab(P, uni(P->off_prog)));
     // ---- channel LLRs -> root: punctured head [0, P) received nothing (0),
     // sent positions [P, P + n_tx), shortened tail a zero known for certain
     T* root = reinterpret_cast<T*>(smem);
@@ -441,26 +472,24 @@ __global__ __launch_bounds__(64) void k_sc(KArgs A, uint32_t* state, ClassSel se
     __syncthreads();
 
     Regs<T> R;
-#pragma unroll
-    for (int k = 0; k < 7; ++k) {
-      R.x[k] = (V)0;
-      R.beta[k] = 0;
-    }
-#pragma unroll
-    for (int k = 0; k < 8; ++k) R.left[k] = 0;
+    R.xs = (V)0;
+    R.x6 = (V)0;
+    R.bs = R.b6 = R.ls = R.l7 = 0u;
     Acc pm = (Acc)0;
-    if (N <= 64) reg_dispatch<T>(n, OPX_LOAD_ROOT, R, pm, lane, smem);  // whole code in registers
+    if (N <= 64) reg_op<T>(OPX_LOAD_ROOT, n, R, pm, lane, smem);  // whole code in registers
+    uint32_t w_next = n_ops ? prog[0] : 0u;
     for (uint32_t pc = 0; pc < n_ops; ++pc) {
-      const uint32_t w = prog[pc];
+      const uint32_t w = uni(w_next);
+      if (pc + 1 < n_ops) w_next = prog[pc + 1];
       const uint32_t opc = op_code(w), d = op_depth(w), k = n - d;
       if (k >= 7)
         lds_op<T>(smem, N, opc, d, k, op_off(w), R, pm, lane);
       else
-        reg_dispatch<T>(k, opc, R, pm, lane, smem);
+        reg_op<T>(opc, k, R, pm, lane, smem);
     }
     // ---- codeword estimate in LDS bits (small codes: from the root mask)
     uint32_t* bits = reinterpret_cast<uint32_t*>(smem + sc_bits_off(N, E));
-    if (N <= 64) reg_dispatch<T>(n, OPX_STORE_ROOT, R, pm, lane, smem);
+    if (N <= 64) reg_op<T>(OPX_STORE_ROOT, n, R, pm, lane, smem);
     __syncthreads();
     // ---- CRC syndrome through the nibble table
     const uint32_t bw = P->bw;
