@@ -44,10 +44,11 @@ __device__ __forceinline__ float f_op(float a, float b) {
   return ((a < 0.f) != (b < 0.f)) ? -m : m;
 }
 __device__ __forceinline__ float g_op(float a, float b, uint32_t s) { return s ? (b - a) : (b + a); }
-__device__ __forceinline__ int f_opi(int a, int b) {
-  const int m = min(abs(a), abs(b));
-  return ((a ^ b) < 0) ? -m : m;
-}
+// Integer f in branch-free form: max(min(a, b), -max(a, b)) equals
+// sign(a) sign(b) min(|a|, |b|) for all integers (both >= 0: min(a, b);
+// both <= 0: -max(a, b) = min(|a|, |b|); mixed signs: the negative operand
+// or the negated positive one, whichever is closer to zero).
+__device__ __forceinline__ int f_opi(int a, int b) { return max(min(a, b), -max(a, b)); }
 template <int Q>
 __device__ __forceinline__ int g_opi(int a, int b, uint32_t s) {
   const int v = s ? (b - a) : (b + a);
@@ -158,6 +159,14 @@ __device__ __forceinline__ Q* uni_ptr(Q* p) {
 }
 
 // ------------------------------------------------------- wave primitives
+// v of lane src (0..63) of the wave, without the width arithmetic of
+// __shfl (ds_bpermute takes a byte address).
+template <typename V>
+__device__ __forceinline__ V bperm(V v, uint32_t src) {
+  static_assert(sizeof(V) == 4, "32-bit values");
+  return __builtin_bit_cast(V, __builtin_amdgcn_ds_bpermute((int)(src << 2), __builtin_bit_cast(int, v)));
+}
+
 template <typename K>
 __device__ __forceinline__ K shfl_xor_k(K v, int m) {
   if constexpr (sizeof(K) == 8) {

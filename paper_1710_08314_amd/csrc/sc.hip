@@ -117,15 +117,11 @@ struct Regs {
   uint32_t bs, b6, ls, l7;
 };
 
-// Pseudo-ops of codes with N <= 64 (the whole tree in registers).
-constexpr uint32_t OPX_LOAD_ROOT = 14;   // level n <- the channel LLRs
-constexpr uint32_t OPX_STORE_ROOT = 15;  // LDS codeword bits <- level n partial sums
-
 // Sum over the segment of M lanes holding v (aligned to M), stride-halving
 // order; every lane of the segment ends with the total.
 template <typename A>
-__device__ __forceinline__ A seg_sum(A v, uint32_t M) {
-  for (uint32_t s = M >> 1; s >= 1; s >>= 1) v = v + __shfl_xor(v, (int)s, 64);
+__device__ __forceinline__ A seg_sum(A v, uint32_t M, uint32_t lane) {
+  for (uint32_t s = M >> 1; s >= 1; s >>= 1) v = v + bperm(v, lane ^ s);
   return v;
 }
 __device__ __forceinline__ float lane_f(float v, uint32_t l) {
@@ -133,118 +129,133 @@ __device__ __forceinline__ float lane_f(float v, uint32_t l) {
 }
 __device__ __forceinline__ int lane_i(int v, uint32_t l) { return __builtin_amdgcn_readlane(v, (int)l); }
 
+// Level K of the register levels: its first lane, and this lane's index in
+// the node (valid below 2^K).
+struct RegLevel {
+  uint32_t M, base, j;
+  bool top, in;
+  __device__ __forceinline__ RegLevel(uint32_t K, uint32_t lane) {
+    M = 1u << K;
+    top = K == 6;
+    base = top ? 0u : M;
+    j = lane - base;
+    in = j < M;
+  }
+};
+
 template <typename T>
-__device__ __forceinline__ void reg_op(uint32_t opc, uint32_t K, Regs<T>& R,
-                                       typename VT<T>::Acc& pm, uint32_t lane, char* smem) {
+__device__ __forceinline__ void reg_load_root(uint32_t K, Regs<T>& R, uint32_t lane, char* smem) {
+  using V = typename Lane<T>::V;
+  const RegLevel lv(K, lane);
+  const V v = lv.in ? (V)reinterpret_cast<const T*>(smem)[lv.j] : (V)0;
+  if (lv.top)
+    R.x6 = v;
+  else if (lv.in)
+    R.xs = v;
+}
+
+template <typename T>
+__device__ __forceinline__ void reg_store_root(uint32_t K, Regs<T>& R, uint32_t lane, char* smem) {
+  const RegLevel lv(K, lane);
+  const uint64_t b = (uint64_t)__ballot((lv.top ? R.b6 : R.bs) & 1u);
+  const uint64_t beta = lv.top ? b : ((b >> lv.M) & ((1ull << lv.M) - 1ull));
+  uint32_t* bits = reinterpret_cast<uint32_t*>(smem + sc_bits_off(lv.M, VT<T>::E));
+  if (lane < 2) bits[lane] = lane ? (uint32_t)(beta >> 32) : (uint32_t)beta;
+}
+
+// f (G = false) or g (G = true) at level K: the child (level K - 1, lanes
+// [h, 2h)) gets element i from the node's elements i and i + h.
+template <typename T, bool G>
+__device__ __forceinline__ void reg_fg(uint32_t K, Regs<T>& R, uint32_t lane) {
+  using V = typename Lane<T>::V;
+  const RegLevel lv(K, lane);
+  const V x = lv.top ? R.x6 : R.xs;
+  const uint32_t h = lv.M >> 1, i = (lane - h) & (h - 1);
+  const V a = bperm(x, lv.base + i);
+  const V b = bperm(x, lv.base + h + i);
+  const bool child = lane - h < h;
+  if constexpr (!G) {
+    const V y = fv<T>(a, b);
+    if (child) R.xs = y;
+  } else {
+    // the left child's partial sums sit in the same lanes (level K - 1)
+    const V y = gv<T>(a, b, R.bs & 1u);
+    if (child) {
+      R.xs = y;
+      R.ls = R.bs;
+    }
+  }
+}
+
+// h at level K: beta_K[i] = left[i] ^ beta_{K-1}[i], beta_K[i + h] = beta_{K-1}[i]
+template <typename T>
+__device__ __forceinline__ void reg_h(uint32_t K, Regs<T>& R, uint32_t lane) {
+  const RegLevel lv(K, lane);
+  const uint32_t h = lv.M >> 1;
+  const uint32_t pk = (R.bs & 1u) | (((R.ls ^ R.bs) & 1u) << 1);
+  const uint32_t g = bperm(pk, h + (lv.j & (h - 1)));
+  const uint32_t v = lv.j < h ? (g >> 1) : (g & 1u);
+  if (lv.top)
+    R.b6 = v;
+  else if (lv.in)
+    R.bs = v;
+}
+
+// A dedicated node or leaf at level K.
+template <typename T>
+__device__ __forceinline__ void reg_node(uint32_t opc, uint32_t K, Regs<T>& R,
+                                         typename VT<T>::Acc& pm, uint32_t lane) {
   using V = typename Lane<T>::V;
   using Acc = typename VT<T>::Acc;
-  const uint32_t M = 1u << K;
-  const bool top = K == 6;
-  const uint32_t base = top ? 0u : M;  // first lane of level K
-  const uint32_t j = lane - base;      // index in the node (valid if < M)
-  const bool in = j < M;
-  if (opc == OPX_LOAD_ROOT) {
-    const V v = in ? (V)reinterpret_cast<const T*>(smem)[j] : (V)0;
-    if (top)
-      R.x6 = v;
-    else if (in)
-      R.xs = v;
-    return;
-  }
-  if (opc == OPX_STORE_ROOT) {
-    const uint64_t b = (uint64_t)__ballot((top ? R.b6 : R.bs) & 1u);
-    const uint64_t beta = top ? b : ((b >> M) & ((1ull << M) - 1ull));
-    uint32_t* bits = reinterpret_cast<uint32_t*>(smem + sc_bits_off(M, VT<T>::E));
-    if (lane < 2) bits[lane] = lane ? (uint32_t)(beta >> 32) : (uint32_t)beta;
-    return;
-  }
-  const V x = top ? R.x6 : R.xs;
-  if (opc == OP_F || opc == OP_G) {
-    // child (level K - 1) in lanes [h, 2h); element i from the node's i, i + h
-    const uint32_t h = M >> 1, i = (lane - h) & (h - 1);
-    const V a = __shfl(x, (int)(base + i), 64);
-    const V b = __shfl(x, (int)(base + h + i), 64);
-    const bool child = lane - h < h;
-    if (opc == OP_F) {
-      const V y = fv<T>(a, b);
-      if (child) R.xs = y;
-    } else {
-      // the left child's partial sums sit in the same lanes (level K - 1)
-      const V y = gv<T>(a, b, R.bs & 1u);
-      if (child) {
-        R.xs = y;
-        R.ls = R.bs;
-      }
-    }
-    return;
-  }
-  if (opc == OP_H) {
-    // beta_K[i] = left[i] ^ beta_{K-1}[i], beta_K[i + h] = beta_{K-1}[i]
-    const uint32_t h = M >> 1;
-    const uint32_t pk = (R.bs & 1u) | (((R.ls ^ R.bs) & 1u) << 1);
-    const uint32_t g = __shfl(pk, (int)(h + (j & (h - 1))), 64);
-    const uint32_t v = j < h ? (g >> 1) : (g & 1u);
-    if (top)
-      R.b6 = v;
-    else if (in)
-      R.bs = v;
-    return;
-  }
+  const RegLevel lv(K, lane);
+  const uint32_t M = lv.M, base = lv.base, j = lv.j;
+  const bool in = lv.in;
+  const V x = lv.top ? R.x6 : R.xs;
   const bool neg = x < (V)0;
   const Acc mg = magv<T>(x);
-  uint32_t bit;
-  switch (opc) {
-    case OP_LF:
-    case OP_R0: {
-      bit = 0;
-      if constexpr (!VT<T>::INT) {
-        const float pen = lane_f(seg_sum<float>(in && neg ? mg : 0.f, M), base);
-        pm = pm + pen;
+  uint32_t bit = neg ? 1u : 0u;  // Rate-1 / information leaf: the hard decision
+  if (opc == OP_SPC) {
+    const uint64_t hd = (uint64_t)__ballot(in && neg);
+    if (__popcll(hd) & 1) {
+      // least reliable position (smallest |alpha|, then smallest index)
+      uint64_t key;
+      if constexpr (VT<T>::INT)
+        key = in ? (((uint64_t)(uint32_t)mg << 6) | j) : ~0ull;
+      else
+        key = in ? (((uint64_t)__float_as_uint(mg) << 6) | j) : ~0ull;
+      for (uint32_t s = M >> 1; s >= 1; s >>= 1) {
+        const uint32_t src = lane ^ s;
+        const uint64_t o = ((uint64_t)bperm((uint32_t)(key >> 32), src) << 32) |
+                           bperm((uint32_t)key, src);
+        key = o < key ? o : key;
       }
-      break;
+      const uint64_t kmin =
+          ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(key >> 32), (int)base) << 32) |
+          (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)key, (int)base);
+      if (j == ((uint32_t)kmin & 63u)) bit ^= 1u;
+      if constexpr (!VT<T>::INT) pm = pm + __uint_as_float((uint32_t)(kmin >> 6));
+    } else if constexpr (!VT<T>::INT) {
+      pm = pm + 0.f;
     }
-    case OP_LI:
-    case OP_R1:
-      bit = neg ? 1u : 0u;
-      break;
-    case OP_REP: {
-      Acc p0 = seg_sum<Acc>(in && neg ? mg : (Acc)0, M);
-      Acc p1 = seg_sum<Acc>(in && !neg ? mg : (Acc)0, M);
-      if constexpr (VT<T>::INT) {
-        p0 = lane_i(p0, base);
-        p1 = lane_i(p1, base);
-      } else {
-        p0 = lane_f(p0, base);
-        p1 = lane_f(p1, base);
-      }
-      bit = rep_decide<T>(p0, p1, pm);
-      break;
+  } else if (opc == OP_REP) {
+    Acc p0 = seg_sum<Acc>(in && neg ? mg : (Acc)0, M, lane);
+    Acc p1 = seg_sum<Acc>(in && !neg ? mg : (Acc)0, M, lane);
+    if constexpr (VT<T>::INT) {
+      p0 = lane_i(p0, base);
+      p1 = lane_i(p1, base);
+    } else {
+      p0 = lane_f(p0, base);
+      p1 = lane_f(p1, base);
     }
-    default: {  // OP_SPC
-      bit = neg ? 1u : 0u;
-      const uint64_t hd = (uint64_t)__ballot(in && neg);
-      if (__popcll(hd) & 1) {
-        // least reliable position (smallest |alpha|, then smallest index)
-        uint64_t key;
-        if constexpr (VT<T>::INT)
-          key = in ? (((uint64_t)(uint32_t)mg << 6) | j) : ~0ull;
-        else
-          key = in ? (((uint64_t)__float_as_uint(mg) << 6) | j) : ~0ull;
-        for (uint32_t s = M >> 1; s >= 1; s >>= 1) {
-          const uint64_t o = shfl_xor_k(key, (int)s);
-          key = o < key ? o : key;
-        }
-        const uint64_t kmin = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(key >> 32), (int)base) << 32) |
-                              (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)key, (int)base);
-        if (j == ((uint32_t)kmin & 63u)) bit ^= 1u;
-        if constexpr (!VT<T>::INT) pm = pm + __uint_as_float((uint32_t)(kmin >> 6));
-      } else if constexpr (!VT<T>::INT) {
-        pm = pm + 0.f;
-      }
-      break;
+    bit = rep_decide<T>(p0, p1, pm);
+  } else if (opc == OP_R0 || opc == OP_LF) {
+    bit = 0;
+    if constexpr (!VT<T>::INT) {
+      const float pen = lane_f(seg_sum<float>(in && neg ? mg : 0.f, M, lane), base);
+      pm = pm + pen;
     }
   }
-  if (top)
+  if (lv.top)
     R.b6 = bit;
   else if (in)
     R.bs = bit;
@@ -476,20 +487,28 @@ __global__ __launch_bounds__(64) void k_sc(KArgs A, uint32_t* state, ClassSel se
     R.x6 = (V)0;
     R.bs = R.b6 = R.ls = R.l7 = 0u;
     Acc pm = (Acc)0;
-    if (N <= 64) reg_op<T>(OPX_LOAD_ROOT, n, R, pm, lane, smem);  // whole code in registers
+    if (N <= 64) reg_load_root<T>(n, R, lane, smem);  // whole code in registers
     uint32_t w_next = n_ops ? prog[0] : 0u;
     for (uint32_t pc = 0; pc < n_ops; ++pc) {
       const uint32_t w = uni(w_next);
       if (pc + 1 < n_ops) w_next = prog[pc + 1];
       const uint32_t opc = op_code(w), d = op_depth(w), k = n - d;
+      // an if-chain in op frequency order (f, g, h, nodes) keeps the uniform
+      // control flow free of the structurizer's flag variables
       if (k >= 7)
         lds_op<T>(smem, N, opc, d, k, op_off(w), R, pm, lane);
+      else if (opc == OP_F)
+        reg_fg<T, false>(k, R, lane);
+      else if (opc == OP_G)
+        reg_fg<T, true>(k, R, lane);
+      else if (opc == OP_H)
+        reg_h<T>(k, R, lane);
       else
-        reg_op<T>(opc, k, R, pm, lane, smem);
+        reg_node<T>(opc, k, R, pm, lane);
     }
     // ---- codeword estimate in LDS bits (small codes: from the root mask)
     uint32_t* bits = reinterpret_cast<uint32_t*>(smem + sc_bits_off(N, E));
-    if (N <= 64) reg_op<T>(OPX_STORE_ROOT, n, R, pm, lane, smem);
+    if (N <= 64) reg_store_root<T>(n, R, lane, smem);
     __syncthreads();
     // ---- CRC syndrome through the nibble table
     const uint32_t bw = P->bw;
