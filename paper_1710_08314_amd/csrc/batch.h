@@ -21,7 +21,7 @@ struct Work {
   uint32_t* state = nullptr;
   uint32_t* tier_heads = nullptr;
   uint32_t* heads = nullptr;  // class schedule
-  char* spill = nullptr;      // depth-1 slots of spilled layouts (spill_need bytes)
+  char* spill = nullptr;      // LLR buffers of spilled layouts (spill_need bytes)
   uint64_t spill_bytes = 0;
 };
 size_t work_words(size_t cap);                // words of a work area for `cap` frames
@@ -41,8 +41,17 @@ int prepare(const polar_plan* plans, uint32_t n_plans, const polar_frame* d_fram
             uint32_t n_frames, const void* d_llr, uint32_t* d_info, polar_status* d_status,
             uint32_t* d_pm_lists, const polar_decode_opts* opts, Batch* b);
 
+// Largest LDS footprint and spill region per workgroup among the list
+// layouts of the batch's stages with list size in [lo, hi].
+struct StageSpan {
+  uint32_t lds;
+  uint64_t spill;
+};
+StageSpan stage_span(const Batch& b, uint32_t lo, uint32_t hi);
+
 // Global memory the batch's spilled layouts need in a work area (0: none):
-// the depth-1 slots of one frame per workgroup that may hold such a frame.
+// the largest, over every launch any schedule may make for the batch, of
+// its grid times its spill bytes per workgroup.
 uint64_t spill_need(const Batch& b, int cus);
 
 // Enqueue one decode of `b` on `st` using work area `w` (schedule 0 automatic,

@@ -293,30 +293,23 @@ Work work_view(uint32_t* base, size_t cap) {
   return w;
 }
 
-// Spill of the batch: global bytes per workgroup (0: no plan spills) and the
-// smallest LDS footprint of a spilled layout, which bounds the workgroups per
-// CU of any launch that can run one.
-static void spill_geometry(const Batch& b, uint64_t* stride, uint32_t* lds_min) {
-  *stride = 0;
-  *lds_min = kLdsLimit;
+// The list layouts of a batch's stages with list size in [lo, hi] (every
+// stage of every plan's schedule in that range): the largest LDS footprint
+// and the largest spill region per workgroup.
+StageSpan stage_span(const Batch& b, uint32_t lo, uint32_t hi) {
+  StageSpan r{0, 0};
   for (polar_plan p : b.plans) {
     const DevPlan& h = p->hp.hdr;
-    const uint32_t E = elem_bytes(h.quant);
-    const LdsLayout lay = lds_layout(h.N, h.n, E, h.max_list, key_bytes(h.quant));
-    if (!lay.spill) continue;
-    const uint64_t sb = spill_bytes(h.N, E, h.max_list, lay.spill);
-    *stride = sb > *stride ? sb : *stride;
-    *lds_min = lay.total < *lds_min ? lay.total : *lds_min;
+    for (uint32_t L = h.first_stage;; L = stage_after(h.algo == POLAR_PA_SCL, h.L_max, L)) {
+      if (L >= lo && L <= hi) {
+        const LdsLayout lay = lds_layout(h.N, h.n, elem_bytes(h.quant), L, key_bytes(h.quant));
+        r.lds = lay.total > r.lds ? lay.total : r.lds;
+        r.spill = lay.gbytes > r.spill ? lay.gbytes : r.spill;
+      }
+      if (L >= h.L_max) break;
+    }
   }
-}
-
-uint64_t spill_need(const Batch& b, int cus) {
-  uint64_t stride;
-  uint32_t lds_min;
-  spill_geometry(b, &stride, &lds_min);
-  if (!stride) return 0;
-  const uint32_t per_cu = kLdsLimit / lds_min > 0 ? kLdsLimit / lds_min : 1;
-  return stride * (uint64_t)cus * per_cu;
+  return r;
 }
 
 }  // namespace polar
@@ -394,18 +387,28 @@ int build_classes(const Batch& b, const ClassConfig& cfg, int cus,
     if (L <= 8) return cfg.l8_kernel;
     return polar::CK_W4_L32;
   };
-  // [kernel][n class] -> lds
+  // [kernel][n class] -> lds, spill bytes per workgroup
   uint32_t lds[4][4] = {};
+  uint64_t spill[4][4] = {};
   bool used[4][4] = {};
   for (polar_plan p : b.plans) {
     const polar::DevPlan& h = p->hp.hdr;
     const uint32_t k = kernel_of(h.first_stage);
     uint32_t c = 0;
     while (c + 1 < n_nc && h.N > nb[c + 1]) ++c;
-    const uint32_t need = k == polar::CK_SC ? polar::sc_lds_bytes(h.N, polar::elem_bytes(h.quant))
-                                            : polar::plan_lds_bytes(h, h.first_stage);
+    uint32_t need;
+    uint64_t gb = 0;
+    if (k == polar::CK_SC) {
+      need = polar::sc_lds_bytes(h.N, polar::elem_bytes(h.quant));
+    } else {
+      const polar::LdsLayout lay = polar::lds_layout(h.N, h.n, polar::elem_bytes(h.quant),
+                                                     h.first_stage, polar::key_bytes(h.quant));
+      need = lay.total;
+      gb = lay.gbytes;
+    }
     used[k][c] = true;
     lds[k][c] = need > lds[k][c] ? need : lds[k][c];
+    spill[k][c] = gb > spill[k][c] ? gb : spill[k][c];
   }
   out->clear();
   const uint32_t n_frames = b.A.n_frames;
@@ -430,14 +433,70 @@ int build_classes(const Batch& b, const ClassConfig& cfg, int cus,
         cl.sel.lmax = polar::kMaxL;
       }
       cl.lds = lds[k][c];
+      cl.spill = spill[k][c];
       if (k == polar::CK_SC)
         cl.grid = n_frames;  // one wave per frame, frames outside the class exit at once
       else
-        cl.grid = persistent_grid(cus, cl.lds, k == polar::CK_W1_L4 ? 16 : (k == polar::CK_W2_L8 ? 8 : 4),
+        cl.grid = persistent_grid(cus, cl.lds, k == polar::CK_W1_L4 ? 32 : (k == polar::CK_W2_L8 ? 8 : 4),
                                   (n_frames + 63) / 64 * 64);
       out->push_back(cl);
     }
   return out->size() <= polar::kMaxClasses ? POLAR_OK : POLAR_EUNSUP;
+}
+
+// Tiered schedule: SC tier if any plan starts at L = 1; list tier A if any
+// plan has a stage of list size 2..4; list tier B if any plan has a stage
+// above 4 (the stages of a plan: SC {1}, CA {L}, PA {1, L_max}, FA {1, 2, 4,
+// ..., L_max}).
+int plan_tiers(const Batch& b, polar::TierPlan* out) {
+  const uint32_t n_frames = b.A.n_frames;
+  polar::TierPlan tp{};
+  uint32_t lds_sc = 0;
+  for (polar_plan p : b.plans) {
+    const polar::DevPlan& h = p->hp.hdr;
+    if (h.first_stage == 1) tp.run_sc = true;
+    const bool fa = h.algo == POLAR_FA_SCL;
+    const bool has_a = (h.first_stage > 1 && h.first_stage <= polar::kTierALmax) ||
+                       (h.first_stage == 1 && h.max_list > 1 &&
+                        (fa || h.max_list <= polar::kTierALmax));
+    if (has_a) tp.run_a = true;
+    if (h.max_list > polar::kTierALmax) tp.run_b = true;
+    const uint32_t l1 = polar::sc_lds_bytes(h.N, polar::elem_bytes(h.quant));
+    lds_sc = l1 > lds_sc ? l1 : lds_sc;
+  }
+  int dev = 0, cus = 1;
+  if (hipGetDevice(&dev) != hipSuccess) return POLAR_EHIP;
+  const int rc = device_cus(dev, &cus);
+  if (rc) return rc;
+  const polar::StageSpan sa = polar::stage_span(b, 2, polar::kTierALmax);
+  const polar::StageSpan sb =
+      polar::stage_span(b, tp.run_a ? polar::kTierALmax + 1 : 2, polar::kMaxL);
+  tp.lds_sc = lds_sc;
+  tp.grid_sc = n_frames < 0x7FFFFFFFu ? n_frames : 0x7FFFFFFFu;
+  tp.lds_a = sa.lds;
+  tp.spill_a = sa.spill;
+  tp.grid_a = persistent_grid(cus, sa.lds, 32, n_frames);
+  tp.lds_b = b.lds;
+  tp.spill_b = sb.spill;
+  tp.grid_b = persistent_grid(cus, b.lds, 8, n_frames);
+  // frames claimed at a time: about n / (32 workgroups' worth), so that the
+  // frames a tier has to decode spread evenly over its workgroups; at most 64
+  // (one wave's worth of state words), at least 1
+  auto chunk_of = [&](uint32_t grid) {
+    const uint64_t c = n_frames / ((uint64_t)(grid ? grid : 1) * 32);
+    return (uint32_t)(c < 1 ? 1 : (c > 64 ? 64 : c));
+  };
+  tp.chunk_a = chunk_of(tp.grid_a);
+  tp.chunk_b = chunk_of(tp.grid_b);
+  *out = tp;
+  return POLAR_OK;
+}
+
+// Grid of the plain schedule: one workgroup per frame, or a persistent grid
+// (one spill region per workgroup) when a stage spills.
+uint32_t plain_grid(const Batch& b, int cus, uint64_t spill) {
+  const uint32_t n = b.A.n_frames;
+  return spill ? persistent_grid(cus, b.lds, polar::kLdsLimit, n) : (n < 0x7FFFFFFFu ? n : 0x7FFFFFFFu);
 }
 
 const char* kernel_name(uint32_t k) {
@@ -512,6 +571,32 @@ int run_classes(const Batch& b, const Work& w, hipStream_t st, bool autotune, hi
 
 namespace polar {
 
+uint64_t spill_need(const Batch& b, int cus) {
+  uint64_t need = 0;
+  auto upd = [&](uint64_t grid, uint64_t stride) {
+    if (grid * stride > need) need = grid * stride;
+  };
+  TierPlan tp{};
+  if (plan_tiers(b, &tp) == POLAR_OK) {
+    if (tp.run_a) upd(tp.grid_a, tp.spill_a);
+    if (tp.run_b) upd(tp.grid_b, tp.spill_b);
+  }
+  const uint64_t sp = stage_span(b, 1, kMaxL).spill;
+  upd(plain_grid(b, cus, sp), sp);
+  if (uses_classes(b, 0)) {
+    static const ClassConfig cfgs[4] = {{CK_W2_L8, 1, true},
+                                        {CK_W4_L32, 1, true},
+                                        {CK_W2_L8, 0, true},
+                                        {CK_W4_L32, 0, true}};
+    std::vector<ClassLaunch> cls;
+    for (const ClassConfig& cfg : cfgs) {
+      if (build_classes(b, cfg, cus, &cls) != POLAR_OK) continue;
+      for (const ClassLaunch& cl : cls) upd(cl.grid, cl.spill);
+    }
+  }
+  return need;
+}
+
 // Launch one decode of a prepared batch on `st` with work area `w`.
 int launch_batch(const Batch& b_in, uint32_t schedule, const Work& w, hipStream_t st, bool timed,
                  bool autotune) {
@@ -525,18 +610,16 @@ int launch_batch(const Batch& b_in, uint32_t schedule, const Work& w, hipStream_
   if (hipGetDevice(&dev0) != hipSuccess) return POLAR_EHIP;
   rc = device_cus(dev0, &cus0);
   if (rc) return rc;
-  // spilled layouts: one slot set per workgroup, the grids stay within them
-  uint64_t spill_stride;
-  uint32_t spill_lds;
-  polar::spill_geometry(b, &spill_stride, &spill_lds);
-  if (spill_stride) {
-    if (!w.spill || w.spill_bytes < polar::spill_need(b, cus0)) return POLAR_EINVAL;
+  // spilled layouts: one region per workgroup of each launch (each launch
+  // sets its own stride); every launch's grid times stride fits the area
+  const uint64_t need = polar::spill_need(b, cus0);
+  if (need) {
+    if (!w.spill || w.spill_bytes < need) return POLAR_EINVAL;
     A.spill = w.spill;
-    A.spill_stride = spill_stride;
   }
   if (schedule == 1) {
-    uint32_t grid = n_frames < 0x7FFFFFFFu ? n_frames : 0x7FFFFFFFu;
-    if (spill_stride) grid = persistent_grid(cus0, b.lds, polar::kLdsLimit, n_frames);
+    A.spill_stride = polar::stage_span(b, 1, polar::kMaxL).spill;
+    const uint32_t grid = plain_grid(b, cus0, A.spill_stride);
     if (ev) (void)hipEventRecord(ev[0], st);
     rc = polar::launch_decode_plain(b.quant, A, b.lds, grid, st);
     if (ev) {
@@ -557,48 +640,9 @@ int launch_batch(const Batch& b_in, uint32_t schedule, const Work& w, hipStream_
     }
     return rc;
   }
-  // tiered schedule: SC tier if any plan starts at L = 1; list tier A if any
-  // plan has a stage of list size 2..4; list tier B if any plan has a stage
-  // above 4 (the stages of a plan: SC {1}, CA {L}, PA {1, L_max}, FA {1, 2,
-  // 4, ..., L_max})
   polar::TierPlan tp{};
-  uint32_t lds_sc = 0, lds_a = 0;
-  for (polar_plan p : b.plans) {
-    const polar::DevPlan& h = p->hp.hdr;
-    if (h.first_stage == 1) tp.run_sc = true;
-    const bool fa = h.algo == POLAR_FA_SCL;
-    const bool has_a = (h.first_stage > 1 && h.first_stage <= polar::kTierALmax) ||
-                       (h.first_stage == 1 && h.max_list > 1 &&
-                        (fa || h.max_list <= polar::kTierALmax));
-    if (has_a) {
-      tp.run_a = true;
-      const uint32_t la = h.max_list < polar::kTierALmax ? h.max_list : polar::kTierALmax;
-      const uint32_t lb = polar::plan_lds_bytes(h, la);
-      lds_a = lb > lds_a ? lb : lds_a;
-    }
-    if (h.max_list > polar::kTierALmax) tp.run_b = true;
-    const uint32_t l1 = polar::sc_lds_bytes(h.N, polar::elem_bytes(h.quant));
-    lds_sc = l1 > lds_sc ? l1 : lds_sc;
-  }
-  int dev = 0, cus = 1;
-  if (hipGetDevice(&dev) != hipSuccess) return POLAR_EHIP;
-  rc = device_cus(dev, &cus);
+  rc = plan_tiers(b, &tp);
   if (rc) return rc;
-  tp.lds_sc = lds_sc;
-  tp.grid_sc = n_frames < 0x7FFFFFFFu ? n_frames : 0x7FFFFFFFu;
-  tp.lds_a = lds_a;
-  tp.grid_a = persistent_grid(cus, lds_a, 16, n_frames);
-  tp.lds_b = b.lds;
-  tp.grid_b = persistent_grid(cus, b.lds, 8, n_frames);
-  // frames claimed at a time: about n / (32 workgroups' worth), so that the
-  // frames a tier has to decode spread evenly over its workgroups; at most 64
-  // (one wave's worth of state words), at least 1
-  auto chunk_of = [&](uint32_t grid) {
-    const uint64_t c = n_frames / ((uint64_t)(grid ? grid : 1) * 32);
-    return (uint32_t)(c < 1 ? 1 : (c > 64 ? 64 : c));
-  };
-  tp.chunk_a = chunk_of(tp.grid_a);
-  tp.chunk_b = chunk_of(tp.grid_b);
   rc = polar::launch_decode_tiered(b.quant, A, tp, w.state, w.tier_heads, st, ev);
   if (ev) {
     g_timing.ran[0] = tp.run_sc;

@@ -58,6 +58,7 @@ __device__ __forceinline__ uint32_t* tabs(const Ctx& c) {
 template <bool G = false>
 __device__ __forceinline__ char* node_llr(const Ctx& c, uint32_t d, uint32_t r) {
   if constexpr (G) {
+    // spilled depth, or the root (d = 0, slot stride 0) of a groot layout
     const uint32_t* t = tabs(c);
     return c.gsp + t[d] + (uint32_t)ptr_tab(c)[d * 32 + r] * t[12 + d];
   } else {
@@ -81,7 +82,7 @@ __device__ void run_fg(const Ctx& c, uint32_t d, uint32_t o, uint32_t a, bool is
   const uint32_t* t = tabs(c);
   const uint8_t* pt = ptr_tab(c);
   const uint32_t dbase = t[d + 1], dstride = t[12 + d + 1];
-  const uint32_t sbase = d ? t[d] : c.lay.root, sstride = d ? t[12 + d] : 0u;
+  const uint32_t sbase = t[d], sstride = t[12 + d];  // the root: t[0], stride t[12] = 0
   for (uint32_t it = threadIdx.x; it < total; it += NT) {
     const uint32_t r = it >> lc, j = it & (cpp - 1);
     const uint32_t slot = d ? (uint32_t)pt[d * 32 + r] : 0u;
@@ -117,15 +118,18 @@ __device__ void op_fg(const Ctx& c, uint32_t d, uint32_t o, uint32_t a, bool is_
   const uint32_t h = (c.N >> d) >> 1;
   constexpr uint32_t VM = VT<T>::VMAX;
   if constexpr (SP) {
-    // spilled layouts have N >= 512, so h >= 64 >= VM at the depths < S + 1
+    // spilled buffers belong to codes with N >= 512 and depths <= 2, so
+    // h >= 64 >= VM wherever one is read or written
     const uint32_t S = c.lay.spill;
-    if (d <= S && S) {
-      if (d == 0)
-        run_fg<T, VM, NT, false, true>(c, d, o, a, is_g);
-      else if (d < S)
+    const bool sg = d == 0 ? c.lay.groot != 0 : d <= S;
+    const bool dg = d + 1 <= S;
+    if (sg || dg) {
+      if (sg && dg)
         run_fg<T, VM, NT, true, true>(c, d, o, a, is_g);
-      else
+      else if (sg)
         run_fg<T, VM, NT, true, false>(c, d, o, a, is_g);
+      else
+        run_fg<T, VM, NT, false, true>(c, d, o, a, is_g);
       return;
     }
   }
@@ -666,15 +670,15 @@ __device__ void op_node(const Ctx& c, uint32_t opc, uint32_t d, uint32_t o, uint
   uint16_t* cpos = reinterpret_cast<uint16_t*>(c.smem + c.lay.cpos);
   const bool single = (opc == OP_R0 || opc == OP_LF);
   const uint32_t C = single ? 1u : (opc == OP_R1 ? 4u : (opc == OP_SPC ? 8u : 2u));
-  constexpr bool SP = LMAX >= (int)kMaxL;
+  const bool gsp = d == 0 ? c.lay.groot != 0 : d <= c.lay.spill;
   if constexpr (VT<T>::INT) {
-    if (SP && d >= 1 && d <= c.lay.spill)
-      node_stats_int<T, NT, SP>(c, opc, d, o, a, C);
+    if (gsp)
+      node_stats_int<T, NT, true>(c, opc, d, o, a, C);
     else
       node_stats_int<T, NT, false>(c, opc, d, o, a, C);
   } else {
-    if (SP && d >= 1 && d <= c.lay.spill)
-      node_stats_float<T, NT, SP>(c, opc, d, o, a, C);
+    if (gsp)
+      node_stats_float<T, NT, true>(c, opc, d, o, a, C);
     else
       node_stats_float<T, NT, false>(c, opc, d, o, a, C);
   }
@@ -801,11 +805,11 @@ __device__ void run_program(const Ctx& c, uint32_t& a) {
     const uint32_t opc = op_code(w), d = op_depth(w), o = op_off(w);
     switch (opc) {
       case OP_F:
-        op_fg<T, NT, (LMAX >= (int)kMaxL)>(c, d, o, a, false);
+        op_fg<T, NT, true>(c, d, o, a, false);
         __syncthreads();
         break;
       case OP_G:
-        op_fg<T, NT, (LMAX >= (int)kMaxL)>(c, d, o, a, true);
+        op_fg<T, NT, true>(c, d, o, a, true);
         __syncthreads();
         break;
       case OP_H:
@@ -877,7 +881,7 @@ __device__ uint32_t end_of_stage(const Ctx& c, uint32_t a, bool* ok) {
 template <typename T, int NT>
 __device__ void load_root(const Ctx& c, const char* llr) {
   constexpr uint32_t E = VT<T>::E;
-  T* root = reinterpret_cast<T*>(c.smem + c.lay.root);
+  T* root = reinterpret_cast<T*>(c.lay.groot ? c.gsp : c.smem + c.lay.root);
   const uint32_t ntx = uni(c.P->n_tx), np = uni(c.P->n_punct);
   const uint32_t nbytes = ntx * E;
   if ((((uintptr_t)llr) & 15u) == 0 && (nbytes & 15u) == 0 && ((np * E) & 15u) == 0) {
@@ -893,14 +897,17 @@ __device__ void load_root(const Ctx& c, const char* llr) {
   for (uint32_t i = np + ntx + threadIdx.x; i < c.N; i += NT) root[i] = known;
 }
 
+// A stage's layout, its tables, and the root (its place depends on the
+// layout, so it is loaded per stage).
 template <typename T, int NT>
-__device__ void setup_stage(Ctx& c, uint32_t L) {
+__device__ void setup_stage(Ctx& c, uint32_t L, const char* llr) {
   c.L = L;
   c.lay = lds_layout(c.N, c.n, VT<T>::E, L, (uint32_t)sizeof(typename VT<T>::Key));
+  load_root<T, NT>(c, llr);
   uint32_t* t = tabs(c);
   if (threadIdx.x == 0) {
-    uint32_t cur = c.lay.stages, gcur = 0;
-    t[0] = c.lay.root;
+    uint32_t cur = c.lay.stages, gcur = c.lay.groot ? ru16(c.N * VT<T>::E) : 0u;
+    t[0] = c.lay.groot ? 0u : c.lay.root;
     t[12] = 0;
     for (uint32_t d = 1; d <= c.n; ++d) {
       t[12 + d] = slot_bytes(c.N, d, VT<T>::E);
@@ -939,13 +946,11 @@ __device__ bool decode_frame(char* smem, const KArgs& A, uint32_t f, const DevPl
   c.bw = uni(P->bw);
   c.L = 1;
   c.gsp = A.spill ? uni_ptr(A.spill + (size_t)blockIdx.x * A.spill_stride) : nullptr;
-  c.lay = lds_layout(c.N, c.n, VT<T>::E, 1, (uint32_t)sizeof(typename VT<T>::Key));
-  load_root<T, NT>(c, llr);
   uint32_t L = L_first, chosen = 0, a = 1;
   const uint32_t L_max = uni(P->L_max), algo = uni(P->algo);
   bool ok = false;
   for (;;) {
-    setup_stage<T, NT>(c, L);
+    setup_stage<T, NT>(c, L, llr);
     a = 1;
     run_program<T, NT, LMAX>(c, a);
     chosen = end_of_stage<T, NT>(c, a, &ok);
@@ -1195,6 +1200,8 @@ static int launch_classes_t(const KArgs& A, const ClassLaunch* cls, uint32_t n_c
   const uint32_t quant = VT<T>::INT ? (sizeof(T) == 2 ? POLAR_I16 : POLAR_I8) : POLAR_F32;
   for (uint32_t i = 0; i < n_cls; ++i) {
     const ClassLaunch& c = cls[i];
+    KArgs Ac = A;
+    Ac.spill_stride = c.spill;
     switch (c.kernel) {
       case CK_SC: {
         const int rc = launch_decode_sc(quant, A, c.lds, c.grid, heads, c.sel, s);
@@ -1202,16 +1209,16 @@ static int launch_classes_t(const KArgs& A, const ClassLaunch* cls, uint32_t n_c
         break;
       }
       case CK_W1_L4:
-        hipLaunchKernelGGL((k_decode_class<T, 1, 4>), dim3(c.grid), dim3(64), c.lds, s, A,
+        hipLaunchKernelGGL((k_decode_class<T, 1, 4>), dim3(c.grid), dim3(64), c.lds, s, Ac,
                            heads + i, c.sel);
         break;
       case CK_W2_L8:
-        hipLaunchKernelGGL((k_decode_class<T, 2, 8>), dim3(c.grid), dim3(128), c.lds, s, A,
+        hipLaunchKernelGGL((k_decode_class<T, 2, 8>), dim3(c.grid), dim3(128), c.lds, s, Ac,
                            heads + i, c.sel);
         break;
       default:
         hipLaunchKernelGGL((k_decode_class<T, 4, (int)kMaxL>), dim3(c.grid), dim3(256), c.lds, s,
-                           A, heads + i, c.sel);
+                           Ac, heads + i, c.sel);
         break;
     }
   }
@@ -1260,13 +1267,16 @@ static int launch_tiered_t(const KArgs& A, const TierPlan& tp, uint32_t* state, 
     if (rc) return rc;
   }
   if (ev) (void)hipEventRecord(ev[1], s);
+  KArgs Aa = A, Ab = A;
+  Aa.spill_stride = tp.spill_a;
+  Ab.spill_stride = tp.spill_b;
   if (tp.run_a)
     hipLaunchKernelGGL((k_decode_list<T, 1, (int)kTierALmax>), dim3(tp.grid_a), dim3(64), tp.lds_a,
-                       s, A, state, heads, 2u, kTierALmax, tp.chunk_a);
+                       s, Aa, state, heads, 2u, kTierALmax, tp.chunk_a);
   if (ev) (void)hipEventRecord(ev[2], s);
   if (tp.run_b)
     hipLaunchKernelGGL((k_decode_list<T, kListWaves, (int)kMaxL>), dim3(tp.grid_b),
-                       dim3(kListWaves * 64), tp.lds_b, s, A, state, heads + 1,
+                       dim3(kListWaves * 64), tp.lds_b, s, Ab, state, heads + 1,
                        tp.run_a ? kTierALmax + 1 : 2u, kMaxL, tp.chunk_b);
   if (ev) (void)hipEventRecord(ev[3], s);
   return hipGetLastError() == hipSuccess ? POLAR_OK : POLAR_EHIP;

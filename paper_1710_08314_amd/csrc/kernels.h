@@ -22,8 +22,8 @@ struct KArgs {
   uint32_t* pm_lists;   // nullable
   uint32_t pm_stride;   // entries per frame in pm_lists
   uint64_t* times;      // nullable: realtime stamps, start and end per frame
-  char* spill;          // nullable: depth-1 LLR slots of spilled layouts, spill_stride
-  uint64_t spill_stride;  // bytes per workgroup, indexed by blockIdx.x
+  char* spill;          // nullable: LLR buffers of spilled layouts (lds_layout), one region
+  uint64_t spill_stride;  // of spill_stride bytes per workgroup, indexed by blockIdx.x
 };
 
 // One generic launch: each workgroup decodes whole frames (every stage of
@@ -49,6 +49,7 @@ struct TierPlan {
   bool run_sc, run_a, run_b;
   uint32_t lds_sc, lds_a, lds_b, grid_sc, grid_a, grid_b;
   uint32_t chunk_a, chunk_b;  // frames a list-tier workgroup claims at a time (1..64)
+  uint64_t spill_a, spill_b;  // spill bytes per workgroup of the list tiers
 };
 // state: n_frames words; heads: 2 claim counters (tiers A and B).
 // ev (nullable): 4 events recorded before the first tier and after the SC
@@ -94,6 +95,7 @@ struct ClassLaunch {
   uint32_t kernel;  // ClassKernel
   ClassSel sel;
   uint32_t lds, grid;
+  uint64_t spill;  // spill bytes per workgroup
 };
 constexpr uint32_t kMaxClasses = 16;
 // heads: one counter per class, cleared by the first kernel of the launch.

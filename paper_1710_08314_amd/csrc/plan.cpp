@@ -218,7 +218,14 @@ int make_plan(const polar_plan_desc& d, HostPlan& hp) {
 
   // ---- header + blob
   const uint32_t E = elem_bytes(d.quant), KB = key_bytes(d.quant);
-  const LdsLayout lay = lds_layout(N, n, E, maxl, KB);
+  // the largest layout among the schedule's stages (layouts are not monotone
+  // in L: small lists keep their top buffers in global memory)
+  LdsLayout lay = lds_layout(N, n, E, first, KB);
+  for (uint32_t L = first; L < maxl;) {
+    L = stage_after(d.algo == POLAR_PA_SCL, maxl, L);
+    const LdsLayout l2 = lds_layout(N, n, E, L, KB);
+    if (l2.total > lay.total) lay = l2;
+  }
   if (lay.total > kLdsBudget) return POLAR_EUNSUP;  // lds_layout spills what it can
 
   DevPlan h{};

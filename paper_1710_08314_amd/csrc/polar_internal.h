@@ -94,8 +94,11 @@ POLAR_HD inline const uint32_t* plan_tab(const DevPlan* p, uint32_t off) {
 // ---------------------------------------------------------------------------
 struct LdsLayout {
   uint32_t root, stages, bits, ptr, pm, cand, sel, cpos, tabs, syn, ord, out, misc, total;
-  uint32_t spill;  // S: the slots of depths 1..S live in global memory (spill_bytes per
-                   // workgroup, depth 1 first)
+  uint32_t spill;  // S: the slots of depths 1..S live in global memory
+  uint32_t groot;  // 1: the root (channel LLRs) lives in global memory too
+  // global bytes per workgroup: root (if groot, 16-byte padded), then the
+  // slots of depths 1..S
+  uint32_t gbytes;
 };
 
 // LDS a decoder workgroup may use for its frame (the CU's LDS less room for
@@ -111,20 +114,16 @@ POLAR_HD inline uint32_t slot_bytes(uint32_t N, uint32_t d, uint32_t E) {
   return ru4(m * E);
 }
 
-// Bytes of the slots of depths 1..S of L paths (per workgroup, global memory).
-POLAR_HD inline uint32_t spill_bytes(uint32_t N, uint32_t E, uint32_t L, uint32_t S) {
-  uint32_t b = 0;
-  for (uint32_t d = 1; d <= S; ++d) b += L * slot_bytes(N, d, E);
-  return b;
-}
-
 POLAR_HD inline LdsLayout lds_layout_s(uint32_t N, uint32_t n, uint32_t E, uint32_t L, uint32_t KB,
-                                       uint32_t spill) {
+                                       uint32_t spill, uint32_t groot = 0) {
   LdsLayout l{};
   l.spill = spill;
+  l.groot = groot;
+  l.gbytes = groot ? ru16(N * E) : 0u;
+  for (uint32_t d = 1; d <= spill; ++d) l.gbytes += L * slot_bytes(N, d, E);
   uint32_t cur = 0;
   l.root = cur;
-  cur += ru16(N * E);
+  if (!groot) cur += ru16(N * E);
   l.stages = cur;
   for (uint32_t d = spill + 1; d <= n; ++d) cur += L * slot_bytes(N, d, E);
   cur = ru16(cur);
@@ -155,18 +154,25 @@ POLAR_HD inline LdsLayout lds_layout_s(uint32_t N, uint32_t n, uint32_t E, uint3
   return l;
 }
 
-// Spill policy.  A frame at a large list keeps the LLR slots of its top
-// depths (the largest ones) in global memory: always when its state would
-// not fit a CU's LDS (float32 at N = 2048, L = 32 needs 272 KB), and at
-// L >= kSpillMinL whenever it exceeds kLdsTarget, so that several
-// workgroups share a CU.  At most kMaxSpill depths, only for N >= 512 (the
-// spilled depths then hold nodes of at least 128 elements).  Only kernels
-// that run lists of kMaxL take such layouts.
+// Spill policy: which LLR buffers of a frame live in a per-workgroup region
+// of global memory instead of LDS.  Only a handful of ops (f and g at the
+// top depths, a node as large as the code) touch them; moving them out
+// multiplies the workgroups a CU holds, which hides the LDS latency chains
+// of the list decoder.
+//   * Small lists (L <= kSmallListMax) of codes with N >= 1024: the root and
+//     the depth-1 slots.
+//   * Large lists: the slots of the top depths, at most kMaxSpill of them
+//     (N >= 512), always when the state would not fit a CU's LDS (float32
+//     at N = 2048, L = 32 needs 272 KB) and at L >= kSpillMinL whenever it
+//     exceeds kLdsTarget.
+// Spilled depths hold nodes of at least 128 elements.
+constexpr uint32_t kSmallListMax = 4;
 constexpr uint32_t kLdsTarget = 32 * 1024;
 constexpr uint32_t kSpillMinL = 16;
 constexpr uint32_t kMaxSpill = 2;
 
 POLAR_HD inline LdsLayout lds_layout(uint32_t N, uint32_t n, uint32_t E, uint32_t L, uint32_t KB) {
+  if (L <= kSmallListMax && N >= 1024) return lds_layout_s(N, n, E, L, KB, 1, 1);
   LdsLayout l = lds_layout_s(N, n, E, L, KB, 0);
   uint32_t s = 0;
   while (s < kMaxSpill && N >= 512 &&
@@ -191,6 +197,13 @@ POLAR_HD inline uint32_t sc_out_off(uint32_t N, uint32_t E) {
   return sc_bits_off(N, E) + ru16((N >= 64 ? N / 8 : 8));
 }
 POLAR_HD inline uint32_t sc_lds_bytes(uint32_t N, uint32_t E) { return sc_out_off(N, E) + 64 * 4; }
+
+// List size of the stage after stage L of a schedule (Sec. II-B5): the
+// first stage, then L_max (partially adaptive) or 2 L (fully adaptive); the
+// last stage is the first with L >= L_max.
+POLAR_HD inline uint32_t stage_after(uint32_t algo_pa, uint32_t L_max, uint32_t L) {
+  return algo_pa ? L_max : 2 * L;
+}
 
 POLAR_HD inline uint32_t elem_bytes(uint32_t quant) { return quant == 0 ? 4u : (quant == 1 ? 2u : 1u); }
 POLAR_HD inline uint32_t key_bytes(uint32_t quant) { return quant == 0 ? 8u : 4u; }

@@ -145,12 +145,13 @@ def test_punctured_frozen_set_matches_oracle(N, K, c, design, S, Pn):
         P.plan_query(N, K, c, 0x621, frozen=bad, n_shorten=S, n_puncture=Pn)
 
 
-def test_large_lists_spill_top_depths():
-    """At N = 2048 the LLR slots of depths 1 and 2 (L x (1024 + 512) elements)
-    of a list of 16 or more move to global memory: float32 at L = 32 (272 KB
-    otherwise) then fits one CU's LDS, int8 at L = 32 fits 32 KB so that
-    several workgroups share a CU.  Lists of at most 8 (the kernels without
-    spill support) keep every slot in LDS."""
+def test_spilled_layouts_of_n2048():
+    """Which LLR buffers of an N = 2048 frame live in global memory instead of
+    LDS: for lists of at most 4 the root (N elements) and the depth-1 slots
+    (L x 1024); for L = 8 none; for L >= 16 the slots of depths 1 and 2
+    (L x (1024 + 512)) at most, so that float32 at L = 32 (272 KB otherwise)
+    fits one CU's LDS and int8 at L = 32 fits 32 KB.  The LDS figure of a
+    plan is that of its largest stage."""
     E = {P.F32: 4, P.I16: 2, P.I8: 1}
     for q in (P.F32, P.I16, P.I8):
         for L in (1, 2, 4, 8, 16, 32):
@@ -158,7 +159,10 @@ def test_large_lists_spill_top_depths():
                                    L=L, quant=q)
             full = E[q] * (2048 + L * 2047)  # root + the slots of depths 1..11
             assert info.lds_bytes <= 160 * 1024 - 1024
-            if L <= 8:
+            if L <= 4:
+                small = full - E[q] * (2048 + L * 1024)
+                assert small <= info.lds_bytes < small + 8 * 1024, (q, L)
+            elif L == 8:
                 assert info.lds_bytes >= full
             else:
                 spilled = full - E[q] * L * (1024 + 512)
@@ -166,3 +170,11 @@ def test_large_lists_spill_top_depths():
     i8, _ = P.plan_query(2048, 1000, 11, 0x621, design_ebn0_db=2.5, algo=P.CA_SCL, L=32,
                          quant=P.I8)
     assert i8.lds_bytes <= 32 * 1024
+    # a fully adaptive plan reports its largest stage (L = 8 here, all in LDS)
+    fa, _ = P.plan_query(2048, 1000, 11, 0x621, design_ebn0_db=2.5, algo=P.FA_SCL, L_max=8,
+                         quant=P.I8)
+    assert fa.lds_bytes >= 2048 + 8 * 2047
+    # codes shorter than 1024 keep everything in LDS at small lists
+    sm, _ = P.plan_query(512, 256, 11, 0x621, design_ebn0_db=2.5, algo=P.CA_SCL, L=4,
+                         quant=P.I8)
+    assert sm.lds_bytes >= 512 + 4 * 511
