@@ -194,6 +194,31 @@ int make_plan(const polar_plan_desc& d, HostPlan& hp) {
   };
   Emit::go(hp, d, frozen, 0, N, 0, fits, nfrozen);
 
+  // ---- the same walk with fused steps for the single-path tier: f followed
+  // by its left child, or g followed by its right child and the parent's h,
+  // when that child is a dedicated node or leaf of at most 64 positions
+  hp.sc_prog.clear();
+  for (size_t i = 0; i < hp.prog.size(); ++i) {
+    const uint32_t w = hp.prog[i], op = op_code(w), dep = op_depth(w);
+    if ((op == OP_F || op == OP_G) && i + 1 < hp.prog.size() && (N >> (dep + 1)) <= 64) {
+      const uint32_t nx = hp.prog[i + 1], nop = op_code(nx);
+      if (nop >= OP_R0 && nop <= OP_LI && op_depth(nx) == dep + 1) {
+        if (op == OP_F) {
+          hp.sc_prog.push_back(op_make(OP_FN, dep, op_off(w)) | (nop << 24));
+          i += 1;
+          continue;
+        }
+        if (i + 2 < hp.prog.size() && op_code(hp.prog[i + 2]) == OP_H &&
+            op_depth(hp.prog[i + 2]) == dep) {
+          hp.sc_prog.push_back(op_make(OP_GNH, dep, op_off(w)) | (nop << 24));
+          i += 2;
+          continue;
+        }
+      }
+    }
+    hp.sc_prog.push_back(w);
+  }
+
   // ---- CRC syndrome columns.  CRC(data) is the remainder of data(x) x^c
   // by g(x) (MSB first, init 0, no final xor), linear in the data bits: data
   // bit t contributes x^(k_data - 1 - t + c) mod g; a CRC bit contributes its
@@ -250,6 +275,9 @@ int make_plan(const polar_plan_desc& d, HostPlan& hp) {
   uint32_t off = sizeof(DevPlan) / 4;
   h.off_prog = off;
   off += h.n_ops;
+  h.n_sc_ops = uint32_t(hp.sc_prog.size());
+  h.off_sc_prog = off;
+  off += h.n_sc_ops;
   h.off_infomask = off;
   off += bw;
   h.off_datamask = off;
@@ -266,6 +294,7 @@ int make_plan(const polar_plan_desc& d, HostPlan& hp) {
   hp.blob.assign(off, 0);
   std::copy_n(reinterpret_cast<const uint32_t*>(&h), sizeof(DevPlan) / 4, hp.blob.begin());
   std::copy(hp.prog.begin(), hp.prog.end(), hp.blob.begin() + h.off_prog);
+  std::copy(hp.sc_prog.begin(), hp.sc_prog.end(), hp.blob.begin() + h.off_sc_prog);
   std::copy(info.begin(), info.end(), hp.blob.begin() + h.off_infomask);
   std::copy(datamask.begin(), datamask.end(), hp.blob.begin() + h.off_datamask);
   std::copy(prefix.begin(), prefix.end(), hp.blob.begin() + h.off_dataprefix);

@@ -39,6 +39,10 @@ enum Op : uint32_t {
   OP_SPC = 6,
   OP_LF = 7,  // frozen leaf
   OP_LI = 8,  // information leaf
+  // Fused steps of the L = 1 program (a node program of its own, decoded
+  // by the single-path tier): the node's opcode in bits 24..27.
+  OP_FN = 9,    // f at depth d, then the left child: a node (size <= 64)
+  OP_GNH = 10,  // g at depth d, the right child: a node (size <= 64), then h at d
 };
 
 POLAR_HD inline uint32_t op_make(uint32_t op, uint32_t d, uint32_t o) {
@@ -47,6 +51,7 @@ POLAR_HD inline uint32_t op_make(uint32_t op, uint32_t d, uint32_t o) {
 POLAR_HD inline uint32_t op_code(uint32_t w) { return w & 15u; }
 POLAR_HD inline uint32_t op_depth(uint32_t w) { return (w >> 4) & 15u; }
 POLAR_HD inline uint32_t op_off(uint32_t w) { return (w >> 8) & 0xFFFFu; }
+POLAR_HD inline uint32_t op_sub(uint32_t w) { return (w >> 24) & 15u; }
 
 // ---------------------------------------------------------------------------
 // Device plan blob: a header followed by tables, all 32-bit words, offsets
@@ -68,7 +73,9 @@ struct DevPlan {
                           // 4-bit pattern at each nibble position of the codeword
   uint32_t n_punct;       // P: codeword positions [0, P) not sent (LLR 0); the sent
                           // positions are [P, P + n_tx)
-  uint32_t pad[7];
+  uint32_t off_sc_prog;   // n_sc_ops words: the program with fused steps (OP_FN,
+  uint32_t n_sc_ops;      // OP_GNH) for the single-path tier
+  uint32_t pad[5];
 };
 static_assert(sizeof(DevPlan) == 32 * 4, "DevPlan header is 32 words");
 

@@ -462,9 +462,9 @@ __global__ __launch_bounds__(64) void k_sc(KArgs A, uint32_t* state, ClassSel se
     }
     if (A.times && lane == 0) A.times[2 * (size_t)f] = wall_clock64();
     P = uni_ptr(P);
-    const uint32_t N = uni(P->N), n = uni(P->n), ntx = uni(P->n_tx), n_ops = uni(P->n_ops),
+    const uint32_t N = uni(P->N), n = uni(P->n), ntx = uni(P->n_tx), n_ops = uni(P->n_sc_ops),
                    np = uni(P->n_punct);
-    const uint32_t* prog = uni_ptr(plan_tab(P, uni(P->off_prog)));
+    const uint32_t* prog = uni_ptr(plan_tab(P, uni(P->off_sc_prog)));
     // ---- channel LLRs -> root: punctured head [0, P) received nothing (0),
     // sent positions [P, P + n_tx), shortened tail a zero known for certain
     T* root = reinterpret_cast<T*>(smem);
@@ -493,9 +493,27 @@ __global__ __launch_bounds__(64) void k_sc(KArgs A, uint32_t* state, ClassSel se
       const uint32_t w = uni(w_next);
       if (pc + 1 < n_ops) w_next = prog[pc + 1];
       const uint32_t opc = op_code(w), d = op_depth(w), k = n - d;
-      // an if-chain in op frequency order (f, g, h, nodes) keeps the uniform
-      // control flow free of the structurizer's flag variables
-      if (k >= 7)
+      // an if-chain in op frequency order (fused steps, f, g, h, nodes) keeps
+      // the uniform control flow free of the structurizer's flag variables
+      if (opc == OP_GNH) {
+        // g, the right child (a node at level k - 1 <= 6), h
+        if (k >= 7)
+          lds_op<T>(smem, N, OP_G, d, k, op_off(w), R, pm, lane);
+        else
+          reg_fg<T, true>(k, R, lane);
+        reg_node<T>(op_sub(w), k - 1, R, pm, lane);
+        if (k >= 7)
+          lds_op<T>(smem, N, OP_H, d, k, op_off(w), R, pm, lane);
+        else
+          reg_h<T>(k, R, lane);
+      } else if (opc == OP_FN) {
+        // f, the left child (a node at level k - 1 <= 6)
+        if (k >= 7)
+          lds_op<T>(smem, N, OP_F, d, k, op_off(w), R, pm, lane);
+        else
+          reg_fg<T, false>(k, R, lane);
+        reg_node<T>(op_sub(w), k - 1, R, pm, lane);
+      } else if (k >= 7)
         lds_op<T>(smem, N, opc, d, k, op_off(w), R, pm, lane);
       else if (opc == OP_F)
         reg_fg<T, false>(k, R, lane);
