@@ -471,6 +471,19 @@ int plan_tiers(const Batch& b, polar::TierPlan* out) {
   const polar::StageSpan sa = polar::stage_span(b, 2, polar::kTierALmax);
   const polar::StageSpan sb =
       polar::stage_span(b, tp.run_a ? polar::kTierALmax + 1 : 2, polar::kMaxL);
+  // the SC tier reads the channel LLRs in place (no root in LDS) for a
+  // uniform batch of a code that sends all N >= 256 positions, starts with f
+  // and has 4-byte aligned frames
+  if (!b.A.frames && b.plans.size() == 1) {
+    const polar::HostPlan& hp = b.plans[0]->hp;
+    const polar::DevPlan& h = hp.hdr;
+    if (h.n_punct == 0 && h.n_tx == h.N && h.N >= 256 && !hp.prog.empty() &&
+        polar::op_code(hp.prog[0]) == polar::OP_F && (((uintptr_t)b.A.llr) & 3u) == 0 &&
+        (b.A.llr_bytes & 3u) == 0) {
+      tp.sc_groot = 1;
+      lds_sc = polar::sc_lds_bytes(h.N, polar::elem_bytes(h.quant), 1);
+    }
+  }
   tp.lds_sc = lds_sc;
   tp.grid_sc = n_frames < 0x7FFFFFFFu ? n_frames : 0x7FFFFFFFu;
   tp.lds_a = sa.lds;

@@ -1262,8 +1262,10 @@ static int launch_tiered_t(const KArgs& A, const TierPlan& tp, uint32_t* state, 
   hipLaunchKernelGGL(k_state_init, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, s, A, state, heads);
   if (ev) (void)hipEventRecord(ev[0], s);
   if (tp.run_sc) {
+    KArgs As = A;
+    As.sc_groot = tp.sc_groot;
     const int rc = launch_decode_sc(VT<T>::INT ? (sizeof(T) == 2 ? POLAR_I16 : POLAR_I8) : POLAR_F32,
-                                    A, tp.lds_sc, tp.grid_sc, state, ClassSel{}, s);
+                                    As, tp.lds_sc, tp.grid_sc, state, ClassSel{}, s);
     if (rc) return rc;
   }
   if (ev) (void)hipEventRecord(ev[1], s);

@@ -24,6 +24,8 @@ struct KArgs {
   uint64_t* times;      // nullable: realtime stamps, start and end per frame
   char* spill;          // nullable: LLR buffers of spilled layouts (lds_layout), one region
   uint64_t spill_stride;  // of spill_stride bytes per workgroup, indexed by blockIdx.x
+  uint32_t sc_groot;      // 1: the SC tier reads the channel LLRs from global memory (every
+                          // plan sends all N positions, frames 4-byte aligned; no root in LDS)
 };
 
 // One generic launch: each workgroup decodes whole frames (every stage of
@@ -50,6 +52,7 @@ struct TierPlan {
   uint32_t lds_sc, lds_a, lds_b, grid_sc, grid_a, grid_b;
   uint32_t chunk_a, chunk_b;  // frames a list-tier workgroup claims at a time (1..64)
   uint64_t spill_a, spill_b;  // spill bytes per workgroup of the list tiers
+  uint32_t sc_groot;          // the SC tier reads the channel LLRs from global memory
 };
 // state: n_frames words; heads: 2 claim counters (tiers A and B).
 // ev (nullable): 4 events recorded before the first tier and after the SC

@@ -190,20 +190,25 @@ POLAR_HD inline LdsLayout lds_layout(uint32_t N, uint32_t n, uint32_t E, uint32_
   return l;
 }
 
-// LDS layout of the L = 1 tier for one frame: root N LLRs, the LLRs of the
-// nodes of size >= 128 at depths 1, 2, ... (depth d at root_bytes +
+// LDS layout of the L = 1 tier for one frame: root N LLRs (absent with gr:
+// the channel LLRs are then read from global memory), the LLRs of the nodes
+// of size >= 128 at depths 1, 2, ... (depth d at root_bytes +
 // E (N - N / 2^(d-1))), partial sums (N bits), output staging.
-POLAR_HD inline uint32_t sc_root_bytes(uint32_t N, uint32_t E) { return ru16(N * E); }
-POLAR_HD inline uint32_t sc_stage_base(uint32_t N, uint32_t d, uint32_t E) {
-  return sc_root_bytes(N, E) + E * (N - (N >> (d - 1)));
+POLAR_HD inline uint32_t sc_root_bytes(uint32_t N, uint32_t E, uint32_t gr = 0) {
+  return gr ? 0u : ru16(N * E);
 }
-POLAR_HD inline uint32_t sc_bits_off(uint32_t N, uint32_t E) {
-  return ru16(sc_root_bytes(N, E) + E * N);
+POLAR_HD inline uint32_t sc_stage_base(uint32_t N, uint32_t d, uint32_t E, uint32_t gr = 0) {
+  return sc_root_bytes(N, E, gr) + E * (N - (N >> (d - 1)));
 }
-POLAR_HD inline uint32_t sc_out_off(uint32_t N, uint32_t E) {
-  return sc_bits_off(N, E) + ru16((N >= 64 ? N / 8 : 8));
+POLAR_HD inline uint32_t sc_bits_off(uint32_t N, uint32_t E, uint32_t gr = 0) {
+  return ru16(sc_root_bytes(N, E, gr) + E * N);
 }
-POLAR_HD inline uint32_t sc_lds_bytes(uint32_t N, uint32_t E) { return sc_out_off(N, E) + 64 * 4; }
+POLAR_HD inline uint32_t sc_out_off(uint32_t N, uint32_t E, uint32_t gr = 0) {
+  return sc_bits_off(N, E, gr) + ru16((N >= 64 ? N / 8 : 8));
+}
+POLAR_HD inline uint32_t sc_lds_bytes(uint32_t N, uint32_t E, uint32_t gr = 0) {
+  return sc_out_off(N, E, gr) + 64 * 4;
+}
 
 // List size of the stage after stage L of a schedule (Sec. II-B5): the
 // first stage, then L_max (partially adaptive) or 2 L (fully adaptive); the

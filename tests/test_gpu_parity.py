@@ -303,3 +303,53 @@ def test_class_schedule_with_spilled_float_plan():
         bits = P.unpack_bits(info[o:o + (cd.k_data + 31) // 32], cd.k_data)
         assert np.array_equal(bits, ref.info[0]) or ref.near_tie[0] == 1, f
         assert st["L_used"][f] == ref.L_used[0], f
+
+
+@pytest.mark.parametrize("quant", ["i8", "f32"])
+def test_sc_tier_frame_pairs(quant):
+    """The L = 1 tier decodes two frames per wave.  Every frame of an odd-sized
+    uniform batch (channel LLRs read in place), of a shortened code (LLRs
+    staged in LDS), and of a batch whose neighbouring frames belong to
+    different plans (each frame of a pair decoded alone) equals its oracle
+    decode -- even and odd frames alike."""
+    import torch
+    from paper_1710_08314_amd import polar as P
+
+    # odd uniform batch, all N positions sent: in-place path
+    code = _code(1024, 512, 16, 0x1021, 2.0, quant=quant, algo="sc")
+    _, llr = make_inputs(code, 1001, 71, 1.5)
+    compare(code, llr)  # asserts parity (float32: metrics within tolerance, near-ties aside)
+    # shortened code: the root is staged in LDS
+    code_s = _code(1024, 400, 16, 0x1021, 2.0, S=100, quant=quant, algo="fa", L_max=4)
+    _, llr_s = make_inputs(code_s, 333, 72, 2.0)
+    compare(code_s, llr_s)
+    # neighbouring frames of two plans
+    codes = [code, _code(256, 128, 8, 0x07, 2.0, quant=quant, algo="sc")]
+    plans = [gpu_plan(c) for c in codes]
+    llrs = [make_inputs(c, 9, 80 + i, 1.5)[1] for i, c in enumerate(codes)]
+    refs = [O.decode(c, x) for c, x in zip(codes, llrs)]
+    order = [(k % 2, k // 2) for k in range(17)]  # plan 0, 1, 0, 1, ... (odd count)
+    buf, desc, off, out = [], [], 0, 0
+    for i, f in order:
+        b = llrs[i][f].tobytes()
+        pad = (-off) % 16
+        buf.append(b"\0" * pad)
+        off += pad
+        desc.append((off, out, i))
+        buf.append(b)
+        off += len(b)
+        out += plans[i].info.info_words
+    raw = np.frombuffer(b"".join(buf), dtype=np.uint8)
+    fr32 = np.zeros((len(desc), 4), dtype=np.uint32)
+    for k, (lo, oo, pi) in enumerate(desc):
+        fr32[k] = (lo & 0xFFFFFFFF, lo >> 32, oo, pi)
+    info, status, _ = P.decode_batch(plans, torch.from_numpy(raw.copy()).cuda(),
+                                     frames=torch.from_numpy(fr32.view(np.int32)).cuda())
+    torch.cuda.synchronize()
+    info = info.cpu().numpy().view(np.uint32)
+    st = P.status_fields(status.cpu().numpy())
+    for k, (i, f) in enumerate(order):
+        w = info[desc[k][1]:desc[k][1] + plans[i].info.info_words]
+        same = np.array_equal(P.unpack_bits(w, codes[i].k_data), refs[i].info[f])
+        assert same or (quant == "f32" and refs[i].near_tie[f] == 1), (k, i, f)
+        assert st["crc_ok"][k] == refs[i].crc_ok[f]
