@@ -118,8 +118,8 @@ __device__ void op_fg(const Ctx& c, uint32_t d, uint32_t o, uint32_t a, bool is_
   const uint32_t h = (c.N >> d) >> 1;
   constexpr uint32_t VM = VT<T>::VMAX;
   if constexpr (SP) {
-    // spilled buffers belong to codes with N >= 512 and depths <= 2, so
-    // h >= 64 >= VM wherever one is read or written
+    // spilled buffers belong to codes with N >= 512 and depths <= 3, so
+    // h >= 32 >= VM wherever one is read or written
     const uint32_t S = c.lay.spill;
     const bool sg = d == 0 ? c.lay.groot != 0 : d <= S;
     const bool dg = d + 1 <= S;
@@ -1036,6 +1036,15 @@ __device__ __forceinline__ void frame_of(const KArgs& A, uint32_t f, const DevPl
   }
 }
 
+// Occupancy of the list kernels: the integer variants are held to 64 VGPRs
+// (one-wave workgroups, 8 waves per SIMD) or 72 (wider workgroups, 7), so
+// that registers, like the spilled LDS layouts, leave room for more
+// workgroups per CU; float32 keeps its registers.
+template <typename T, int NW>
+constexpr int list_waves_per_eu() {
+  return VT<T>::INT ? (NW == 1 ? 8 : 7) : 1;
+}
+
 // Plain schedule: each workgroup runs whole frames, every stage in place,
 // with LDS sized for the largest list.
 template <typename T, int NW>
@@ -1073,7 +1082,8 @@ __global__ void k_state_init(KArgs A, uint32_t* state, uint32_t* heads) {
 // indices come only from the claim counter, never from memory the device
 // wrote.
 template <typename T, int NW, int LMAX>
-__global__ __launch_bounds__(NW * 64) void k_decode_list(KArgs A, uint32_t* state, uint32_t* head,
+__global__ __launch_bounds__(NW * 64, (list_waves_per_eu<T, NW>())) void k_decode_list(
+    KArgs A, uint32_t* state, uint32_t* head,
                                                          uint32_t L_lo, uint32_t L_hi,
                                                          uint32_t chunk) {
   extern __shared__ __attribute__((aligned(16))) char smem[];
@@ -1124,7 +1134,8 @@ __device__ __forceinline__ bool in_class(const DevPlan* P, const ClassSel& sel) 
 }
 
 template <typename T, int NW, int LMAX>
-__global__ __launch_bounds__(NW * 64) void k_decode_class(KArgs A, uint32_t* head, ClassSel sel) {
+__global__ __launch_bounds__(NW * 64, (list_waves_per_eu<T, NW>())) void k_decode_class(
+    KArgs A, uint32_t* head, ClassSel sel) {
   extern __shared__ __attribute__((aligned(16))) char smem[];
   __shared__ uint32_t s_base;
   __shared__ unsigned long long s_mask;

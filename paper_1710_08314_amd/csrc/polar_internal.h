@@ -167,19 +167,19 @@ POLAR_HD inline LdsLayout lds_layout_s(uint32_t N, uint32_t n, uint32_t E, uint3
 // multiplies the workgroups a CU holds, which hides the LDS latency chains
 // of the list decoder.
 //   * Small lists (L <= kSmallListMax) of codes with N >= 1024: the root and
-//     the depth-1 slots.
+//     the slots of depths 1 and 2.
 //   * Large lists: the slots of the top depths, at most kMaxSpill of them
 //     (N >= 512), always when the state would not fit a CU's LDS (float32
 //     at N = 2048, L = 32 needs 272 KB) and at L >= kSpillMinL whenever it
 //     exceeds kLdsTarget.
-// Spilled depths hold nodes of at least 128 elements.
+// Spilled depths hold nodes of at least 64 elements.
 constexpr uint32_t kSmallListMax = 4;
 constexpr uint32_t kLdsTarget = 32 * 1024;
 constexpr uint32_t kSpillMinL = 16;
-constexpr uint32_t kMaxSpill = 2;
+constexpr uint32_t kMaxSpill = 3;
 
 POLAR_HD inline LdsLayout lds_layout(uint32_t N, uint32_t n, uint32_t E, uint32_t L, uint32_t KB) {
-  if (L <= kSmallListMax && N >= 1024) return lds_layout_s(N, n, E, L, KB, 1, 1);
+  if (L <= kSmallListMax && N >= 1024) return lds_layout_s(N, n, E, L, KB, 2, 1);
   LdsLayout l = lds_layout_s(N, n, E, L, KB, 0);
   uint32_t s = 0;
   while (s < kMaxSpill && N >= 512 &&

@@ -676,8 +676,12 @@ __device__ void decode_pair(const KArgs& A, uint32_t* state, const ClassSel& sel
 // Class schedule (sel on): only the frames of the class, no state.  Two
 // frames of one plan share a pass; otherwise each gets a pass of its own
 // with the other half idle.
+// Occupancy: the integer kernels are held to 64 VGPRs (8 waves per SIMD; a
+// few values spill, which costs less than the latency it hides); float32
+// keeps its registers.
 template <typename T>
-__global__ __launch_bounds__(64) void k_sc(KArgs A, uint32_t* state, ClassSel sel) {
+__global__ __launch_bounds__(64, (VT<T>::INT ? 8 : 1)) void k_sc(KArgs A, uint32_t* state,
+                                                               ClassSel sel) {
   extern __shared__ __attribute__((aligned(16))) char smem[];
   const uint32_t lane = threadIdx.x, half = lane >> 5;
   const uint32_t n_pairs = (A.n_frames + 1) / 2;
