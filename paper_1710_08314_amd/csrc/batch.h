@@ -14,8 +14,8 @@
 namespace polar {
 
 // Work area of one decode: the per-frame state words of the tiered schedule
-// (cap words), its two list-tier claim counters and the per-class claim
-// counters of the class schedule.  Decodes that may run at the same time need
+// (cap words), its list-tier claim counters (kClaimSegs per tier) and the
+// per-class claim counters of the class schedule.  Decodes that may run at the same time need
 // work areas of their own.
 struct Work {
   uint32_t* state = nullptr;

@@ -283,13 +283,13 @@ int polar_plan_get_frozen(polar_plan p, uint32_t* fw) {
 
 namespace polar {
 
-size_t work_words(size_t cap) { return cap + 2 + kMaxClasses; }
+size_t work_words(size_t cap) { return cap + 2 * kClaimSegs + kMaxClasses; }
 
 Work work_view(uint32_t* base, size_t cap) {
   Work w;
   w.state = base;
   w.tier_heads = base + cap;
-  w.heads = base + cap + 2;
+  w.heads = base + cap + 2 * kClaimSegs;
   return w;
 }
 

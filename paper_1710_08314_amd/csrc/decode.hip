@@ -1062,11 +1062,9 @@ __global__ __launch_bounds__(NW * 64) void k_decode_plain(KArgs A) {
 
 // Per-frame state of the tiered schedule (device scratch): state[f] = the
 // list size of frame f's next stage (a finished frame holds 0 or 1, which no
-// list tier takes).  Every frame starts at its plan's first stage; the two
-// list-tier claim counters start at zero.
-__global__ void k_state_init(KArgs A, uint32_t* state, uint32_t* heads) {
+// list tier takes).  Every frame starts at its plan's first stage.
+__global__ void k_state_init(KArgs A, uint32_t* state) {
   const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t < 2) heads[t] = 0;
   for (uint32_t f = t; f < A.n_frames; f += gridDim.x * blockDim.x) {
     const DevPlan* P = A.frames ? A.plans[A.frames[f].plan_idx] : A.plans[0];
     state[f] = P->first_stage;
@@ -1074,7 +1072,11 @@ __global__ void k_state_init(KArgs A, uint32_t* state, uint32_t* heads) {
 }
 
 // List tier: persistent workgroups claim the frames `chunk` (1..64) at a
-// time; wave 0 reads their state words and picks the frames whose next stage lies in
+// time.  The frames are split into S = min(kClaimSegs, grid) contiguous
+// segments, each with a claim counter of its own that the workgroups
+// b = s (mod S) share, so claims stay fine-grained without every workgroup
+// contending for one address.  Wave 0 reads the claimed frames' state
+// words and picks the frames whose next stage lies in
 // [L_lo, L_hi] (a ballot, shared through LDS with the other waves, so every
 // wave of the workgroup works on the same frames).  For each picked frame the
 // stages of its schedule up to L_hi run in place; its state becomes 0 when
@@ -1090,14 +1092,19 @@ __global__ __launch_bounds__(NW * 64, (list_waves_per_eu<T, NW>())) void k_decod
   __shared__ uint32_t s_base;
   __shared__ unsigned long long s_mask;
   __shared__ uint32_t s_L0[64];
+  const uint32_t n_seg = gridDim.x < kClaimSegs ? gridDim.x : kClaimSegs;
+  const uint32_t seg = blockIdx.x % n_seg;
+  const uint32_t seg_len = (A.n_frames + n_seg - 1) / n_seg;
+  const uint32_t seg_lo = seg * seg_len;
+  const uint32_t seg_hi = seg_lo + seg_len < A.n_frames ? seg_lo + seg_len : A.n_frames;
   for (;;) {
-    if (threadIdx.x == 0) s_base = atomicAdd(head, chunk);
+    if (threadIdx.x == 0) s_base = seg_lo + atomicAdd(&head[seg], chunk);
     __syncthreads();
     const uint32_t base = uni(s_base);
-    if (base >= A.n_frames) break;
+    if (base >= seg_hi) break;
     if (threadIdx.x < 64) {
       const uint32_t f = base + threadIdx.x;
-      const uint32_t L0 = (threadIdx.x < chunk && f < A.n_frames) ? state[f] : 0u;
+      const uint32_t L0 = (threadIdx.x < chunk && f < seg_hi) ? state[f] : 0u;
       s_L0[threadIdx.x] = L0;
       const unsigned long long b = __ballot(L0 >= L_lo && L0 <= L_hi);
       if (threadIdx.x == 0) s_mask = b;
@@ -1270,7 +1277,8 @@ template <typename T>
 static int launch_tiered_t(const KArgs& A, const TierPlan& tp, uint32_t* state, uint32_t* heads,
                            hipStream_t s, hipEvent_t* ev) {
   const uint32_t blocks = (A.n_frames + 255) / 256 < 2048 ? (A.n_frames + 255) / 256 : 2048;
-  hipLaunchKernelGGL(k_state_init, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, s, A, state, heads);
+  hipLaunchKernelGGL(k_heads_reset, dim3(1), dim3(64), 0, s, heads, 2 * kClaimSegs);
+  hipLaunchKernelGGL(k_state_init, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, s, A, state);
   if (ev) (void)hipEventRecord(ev[0], s);
   if (tp.run_sc) {
     KArgs As = A;
@@ -1289,7 +1297,7 @@ static int launch_tiered_t(const KArgs& A, const TierPlan& tp, uint32_t* state, 
   if (ev) (void)hipEventRecord(ev[2], s);
   if (tp.run_b)
     hipLaunchKernelGGL((k_decode_list<T, kListWaves, (int)kMaxL>), dim3(tp.grid_b),
-                       dim3(kListWaves * 64), tp.lds_b, s, Ab, state, heads + 1,
+                       dim3(kListWaves * 64), tp.lds_b, s, Ab, state, heads + kClaimSegs,
                        tp.run_a ? kTierALmax + 1 : 2u, kMaxL, tp.chunk_b);
   if (ev) (void)hipEventRecord(ev[3], s);
   return hipGetLastError() == hipSuccess ? POLAR_OK : POLAR_EHIP;

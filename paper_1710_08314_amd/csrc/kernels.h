@@ -54,7 +54,9 @@ struct TierPlan {
   uint64_t spill_a, spill_b;  // spill bytes per workgroup of the list tiers
   uint32_t sc_groot;          // the SC tier reads the channel LLRs from global memory
 };
-// state: n_frames words; heads: 2 claim counters (tiers A and B).
+// state: n_frames words; heads: 2 x kClaimSegs claim counters (tier A, then
+// tier B), cleared by a kernel launched before the state init.
+constexpr uint32_t kClaimSegs = 32;  // claim counters per list tier
 // ev (nullable): 4 events recorded before the first tier and after the SC
 // tier, list tier A and list tier B.
 int launch_decode_tiered(uint32_t quant, const KArgs& A, const TierPlan& tp, uint32_t* state,
