@@ -2,7 +2,8 @@
 
 hipcc cross-compiles for gfx950 without a GPU.  Device code is built without
 packed-FP32 instructions and without floating-point contraction (the float32
-decoder must round every f/g and penalty exactly as written).
+decoder must round every f/g and penalty exactly as written), and with uniform
+control-flow regions left unstructured (scalar branches).
 """
 from __future__ import annotations
 
@@ -22,8 +23,12 @@ CPP_SOURCES = ["plan.cpp", "capi.cpp", "server.cpp"]
 ARCH = os.environ.get("POLAR_OFFLOAD_ARCH", "gfx950")
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-fno-strict-aliasing", "-Wall",
           "-Wno-unused-function"]
+# The decoder's op dispatch is uniform control flow (every lane of a wave runs
+# the same node program); leaving uniform regions to scalar branches instead
+# of the structurizer's flag variables saves scalar and vector instructions.
 DEVICE = ["-x", "hip", f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang",
-          "-packed-fp32-ops", "-fno-gpu-flush-denormals-to-zero", "-munsafe-fp-atomics"]
+          "-packed-fp32-ops", "-fno-gpu-flush-denormals-to-zero", "-munsafe-fp-atomics",
+          "-mllvm", "-structurizecfg-skip-uniform-regions"]
 
 
 def _hipcc() -> str:
