@@ -30,8 +30,9 @@ sys.path.insert(0, ROOT)
 
 WORKLOAD = dict(name="fa_sscl_n2048_k1723_crc32_lmax32_i8", N=2048, K=1723, crc_len=32,
                 crc_poly=0x04C11DB7, design=4.5, L_max=32, frac=2)
-# MI355X: 256 CUs x 64 vector lanes per clock x 2.4 GHz (no FMA, no packing)
-VALU_PEAK_OPS = 256 * 64 * 2.4e9
+# MI355X: 256 CUs x 128 vector lanes per clock x 2.4 GHz, the lane rate of the published fp32
+# vector peak (157.3 TFLOP/s counting an FMA as two), with no FMA credit
+VALU_PEAK_OPS = 256 * 128 * 2.4e9
 PAPER_CONTEXT_MBPS = {3.5: 24.4, 4.0: 227.3, 4.5: 425.9}  # one i5-6600K core, 8-bit FA
 # counter summaries (HBM bytes per launch) and the sources each kernel is built from
 TRAFFIC_FILES = {"k_sc<int8>": "hbm_traffic_k_sc_fa2048_i8.md",
