@@ -35,10 +35,10 @@ WORKLOAD = dict(name="fa_sscl_n2048_k1723_crc32_lmax32_i8", N=2048, K=1723, crc_
 VALU_PEAK_OPS = 256 * 128 * 2.4e9
 PAPER_CONTEXT_MBPS = {3.5: 24.4, 4.0: 227.3, 4.5: 425.9}  # one i5-6600K core, 8-bit FA
 # counter summaries (HBM bytes per launch) and the sources each kernel is built from
-TRAFFIC_FILES = {"k_sc<int8>": "hbm_traffic_k_sc_fa2048_i8.md",
+TRAFFIC_FILES = {"k_scx": "hbm_traffic_k_scx_fa2048_i8.md",
                  "k_decode_list<int8,1,4>": "hbm_traffic_list_a_fa2048_i8.md",
                  "k_decode_list<int8,4,32>": "hbm_traffic_list_b_fa2048_i8.md"}
-KERNEL_SOURCES = {"k_sc<int8>": ["sc.hip", "device_common.h", "kernels.h", "polar_internal.h"],
+KERNEL_SOURCES = {"k_scx": ["scx.hip", "device_common.h", "kernels.h", "polar_internal.h"],
                   "k_decode_list<int8,1,4>": ["decode.hip", "device_common.h", "kernels.h",
                                               "polar_internal.h"],
                   "k_decode_list<int8,4,32>": ["decode.hip", "device_common.h", "kernels.h",
@@ -603,7 +603,7 @@ def main():
 
     total_bits = args.steps * len(points) * F * kd
     value = total_bits / elapsed / 1e6
-    kernel_names = {"sc": "k_sc<int8>", "list_a": "k_decode_list<int8,1,4>",
+    kernel_names = {"sc": "k_scx", "list_a": "k_decode_list<int8,1,4>",
                     "list_b": "k_decode_list<int8,4,32>"}
     tiers = {}
     for t in tier_ms:

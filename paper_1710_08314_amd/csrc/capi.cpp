@@ -482,6 +482,17 @@ int plan_tiers(const Batch& b, polar::TierPlan* out) {
         (b.A.llr_bytes & 3u) == 0) {
       tp.sc_groot = 1;
       lds_sc = polar::sc_lds_bytes(h.N, polar::elem_bytes(h.quant), 1);
+      // int8 with 16-byte aligned frames: one frame per lane, a persistent
+      // grid of up to 16 waves per CU, each with its own region
+      if (h.quant == POLAR_I8 && (((uintptr_t)b.A.llr) & 15u) == 0 &&
+          (b.A.llr_bytes & 15u) == 0 && b.A.llr_bytes >= h.N) {
+        const uint32_t groups = (n_frames + 63) / 64;
+        const uint32_t cap = 16u * (uint32_t)cus;
+        const uint32_t rounds = groups > cap ? (groups + cap - 1) / cap : 1u;
+        tp.sc_x = 1;
+        tp.grid_scx = groups ? (groups + rounds - 1) / rounds : 1u;
+        tp.spill_sc = polar::scx_region_bytes(h.N);
+      }
     }
   }
   tp.lds_sc = lds_sc;
@@ -591,6 +602,7 @@ uint64_t spill_need(const Batch& b, int cus) {
   };
   TierPlan tp{};
   if (plan_tiers(b, &tp) == POLAR_OK) {
+    if (tp.run_sc && tp.sc_x) upd(tp.grid_scx, tp.spill_sc);
     if (tp.run_a) upd(tp.grid_a, tp.spill_a);
     if (tp.run_b) upd(tp.grid_b, tp.spill_b);
   }

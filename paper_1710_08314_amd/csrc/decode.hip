@@ -1280,7 +1280,12 @@ static int launch_tiered_t(const KArgs& A, const TierPlan& tp, uint32_t* state, 
   hipLaunchKernelGGL(k_heads_reset, dim3(1), dim3(64), 0, s, heads, 2 * kClaimSegs);
   hipLaunchKernelGGL(k_state_init, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, s, A, state);
   if (ev) (void)hipEventRecord(ev[0], s);
-  if (tp.run_sc) {
+  if (tp.run_sc && tp.sc_x) {
+    KArgs As = A;
+    As.spill_stride = tp.spill_sc;
+    const int rc = launch_decode_scx(As, tp.grid_scx, state, s);
+    if (rc) return rc;
+  } else if (tp.run_sc) {
     KArgs As = A;
     As.sc_groot = tp.sc_groot;
     const int rc = launch_decode_sc(VT<T>::INT ? (sizeof(T) == 2 ? POLAR_I16 : POLAR_I8) : POLAR_F32,

@@ -36,12 +36,12 @@ int launch_decode_plain(uint32_t quant, const KArgs& A, uint32_t lds, uint32_t g
 // Tiered schedule.  A per-frame state word holds the list size of each
 // frame's next stage, initialised to its plan's first stage; a finished
 // frame's word is 0 (list tiers) or stays 1 (SC tier), which no list tier
-// takes.  SC tier: one wave per frame with the L = 1 footprint,
-// decodes the frames whose plan starts at L = 1.  List tier A: one wave per
-// frame with the L = 4 footprint, the frames whose next stage is 2..4, up to
-// L = 4.  List tier B: several waves per frame with the largest footprint,
-// the frames whose next stage is above A's range, to the end.  The list
-// tiers are persistent kernels that scan the state words 64 frames at a
+// takes.  SC tier: two frames per wave (k_sc), or one frame per lane for a
+// uniform int8 batch (k_scx), decodes the frames whose plan starts at L = 1.
+// List tier A: one wave per frame with the L = 4 footprint, the frames whose
+// next stage is 2..4, up to L = 4.  List tier B: several waves per frame
+// with the largest footprint, the frames whose next stage is above A's
+// range, to the end.  The list tiers are persistent kernels that scan the state words 64 frames at a
 // time; a frame that leaves a tier unfinished carries its next stage in its
 // state word, so escalation needs no host round trip and no frame list.
 constexpr int kListWaves = 4;       // waves per frame in list tier B
@@ -53,6 +53,9 @@ struct TierPlan {
   uint32_t chunk_a, chunk_b;  // frames a list-tier workgroup claims at a time (1..64)
   uint64_t spill_a, spill_b;  // spill bytes per workgroup of the list tiers
   uint32_t sc_groot;          // the SC tier reads the channel LLRs from global memory
+  uint32_t sc_x;              // the SC tier runs one frame per lane (k_scx)
+  uint32_t grid_scx;          // its persistent grid (waves)
+  uint64_t spill_sc;          // its region bytes per wave (scx_region_bytes)
 };
 // state: n_frames words; heads: 2 x kClaimSegs claim counters (tier A, then
 // tier B), cleared by a kernel launched before the state init.
@@ -84,6 +87,14 @@ struct ClassSel {
 };
 int launch_decode_sc(uint32_t quant, const KArgs& A, uint32_t lds, uint32_t grid, uint32_t* state,
                      const ClassSel& sel, hipStream_t s);
+
+// The L = 1 tier with one frame per lane (scx.hip), for a uniform int8
+// batch of a code with N >= 256 that sends every position, whose program
+// starts with f and whose frames are 16-byte aligned: a persistent grid of
+// `grid` waves, each with a region of scx_region_bytes(N) at
+// A.spill + blockIdx.x * A.spill_stride.
+uint64_t scx_region_bytes(uint32_t N);
+int launch_decode_scx(const KArgs& A, uint32_t grid, uint32_t* state, hipStream_t s);
 
 // Class schedule of a batch of fixed-list plans (no escalation): the frames
 // are split into classes by list size and code length, and each class is

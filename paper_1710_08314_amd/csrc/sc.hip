@@ -1,7 +1,8 @@
 // L = 1 tier of the decoder on gfx950: successive cancellation over the
 // pruned tree (Sec. II-B1, II-B3) for every frame, with the CRC check of the
 // fully / partially adaptive schedules (Sec. II-B5) and a per-frame state
-// word for the frames that need a list.
+// word for the frames that need a list.  (Uniform int8 batches of codes
+// that send every position run one frame per lane instead: scx.hip.)
 //
 // A list of one path never forks, so this tier keeps no candidate lists, no
 // path copies and no slot indirection.  One wave decodes two frames of the

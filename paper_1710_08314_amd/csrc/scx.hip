@@ -1,0 +1,483 @@
+// L = 1 tier of the decoder for uniform int8 batches on gfx950: successive
+// cancellation over the pruned tree (Sec. II-B1, II-B3), with the CRC check
+// of the adaptive schedules (Sec. II-B5), one frame per lane.
+//
+// Every frame of a uniform batch runs the same node program, and a list of
+// one path takes the same steps whatever the LLRs are, so a wave decodes 64
+// frames in lockstep: the program walk, its dispatch and every loop bound
+// are scalar, and every lane of every vector instruction does a frame's
+// arithmetic (the inter-frame form of Sec. III-A's SIMD discussion).  The
+// frame-per-half tier (sc.hip) decodes everything else.
+//
+// Per lane (frame):
+//   * the LLRs of the current node at each level k <= 5 (at most 32 of
+//     them) live in registers, packed four int8 per 32-bit word;
+//   * the LLRs of the current node at each level 6 <= k < n live in a
+//     per-wave region of global memory, 16-byte chunks interleaved over the
+//     64 lanes (chunk c of lane l at 16 (64 c + l)), so every access of the
+//     wave is one contiguous kilobyte;
+//   * the root is the channel LLR buffer itself (frame-major);
+//   * partial sums of levels >= 6 are N bits per frame in the same region,
+//     word w of lane l at 4 (64 w + l); those of a node of level <= 5 stay in
+//     a register until its parent consumes them.
+// The decisions are those of the frame-per-half tier and of a list of one
+// under the list decoder's selection rule: the hard decision wins a tie, the
+// all-zero REP candidate wins a tie, SPC flips the first least reliable
+// position; integer metrics stay 0 at L = 1, so only the REP decision needs
+// its (saturated) penalties.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "../../include/polar_scl.h"
+#include "device_common.h"
+#include "kernels.h"
+#include "polar_internal.h"
+
+namespace polar {
+
+namespace {
+
+constexpr int kQ = VT<int8_t>::Q;  // saturation of the int8 LLRs
+
+// -------------------------------------------- packed int8 element arithmetic
+__device__ __forceinline__ int sx8(uint32_t w, int i) { return (int)(int8_t)(w >> (8 * i)); }
+
+// f of four packed elements
+__device__ __forceinline__ uint32_t f4(uint32_t a, uint32_t b) {
+  uint32_t r = 0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) r |= (uint32_t)(uint8_t)f_opi(sx8(a, i), sx8(b, i)) << (8 * i);
+  return r;
+}
+// g of four packed elements; bit i of s is the left partial sum of element i
+__device__ __forceinline__ uint32_t g4(uint32_t a, uint32_t b, uint32_t s) {
+  uint32_t r = 0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+    r |= (uint32_t)(uint8_t)g_opi<kQ>(sx8(a, i), sx8(b, i), (s >> i) & 1u) << (8 * i);
+  return r;
+}
+// hard decisions (sign bits) of four packed elements, element i at bit i:
+// the sign bits 7, 15, 23, 31 are gathered into bits 28..31 by one product
+// whose partial terms never overlap
+__device__ __forceinline__ uint32_t hd4(uint32_t w) {
+  return ((w & 0x80808080u) * 0x00204081u) >> 28;
+}
+
+struct Chunk {
+  uint32_t w[4];  // 16 packed LLRs
+};
+__device__ __forceinline__ Chunk ldc(const char* p) {
+  const uint4 v = *reinterpret_cast<const uint4*>(p);
+  return Chunk{{v.x, v.y, v.z, v.w}};
+}
+__device__ __forceinline__ void stc(char* p, const Chunk& c) {
+  *reinterpret_cast<uint4*>(p) = make_uint4(c.w[0], c.w[1], c.w[2], c.w[3]);
+}
+__device__ __forceinline__ uint32_t hd16(const Chunk& c) {
+  return hd4(c.w[0]) | (hd4(c.w[1]) << 4) | (hd4(c.w[2]) << 8) | (hd4(c.w[3]) << 12);
+}
+
+// --------------------------------------------------------- register levels
+struct XR {
+  uint32_t x5[8], x4[4], x3[2], x2, x1, x0;  // LLRs of the current nodes of levels 5..0
+  uint32_t b;    // partial sums of the last finished node of level <= 5 (2^k bits)
+  uint32_t lft;  // left-child partial sums of the split nodes of levels 1..5: those of
+                 // level K (2^(K-1) bits) at bit 2^(K-1) - 1
+  uint32_t l6;   // left-child partial sums of the split node of level 6
+};
+
+// words of level K (K <= 5): element i in word i / 4, byte i % 4
+template <int K>
+__device__ __forceinline__ uint32_t& xw(XR& R, int j) {
+  if constexpr (K == 5) return R.x5[j];
+  else if constexpr (K == 4) return R.x4[j];
+  else if constexpr (K == 3) return R.x3[j];
+  else if constexpr (K == 2) return R.x2;
+  else if constexpr (K == 1) return R.x1;
+  else return R.x0;
+}
+
+// f (G = false) or g (G = true) of a split node of level K in 1..5: the
+// child (level K - 1) gets element i from elements i and i + 2^(K-1)
+template <int K, bool G>
+__device__ __forceinline__ void reg_fg(XR& R) {
+  constexpr uint32_t h = 1u << (K - 1);
+  if constexpr (G) {
+    const uint32_t hm = (1u << h) - 1u;
+    R.lft = (R.lft & ~(hm << (h - 1))) | ((R.b & hm) << (h - 1));
+  }
+  if constexpr (K >= 3) {
+    constexpr int W = (int)h / 4;  // words of the child
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+      const uint32_t a = xw<K>(R, j), c = xw<K>(R, j + W);
+      xw<K - 1>(R, j) = G ? g4(a, c, (R.b >> (4 * j)) & 15u) : f4(a, c);
+    }
+  } else {
+    // K = 2: bytes 0, 1 against 2, 3; K = 1: byte 0 against byte 1
+    const uint32_t a = xw<K>(R, 0), c = a >> (8 * h);
+    const uint32_t keep = (1u << (8 * h)) - 1u;
+    xw<K - 1>(R, 0) = (G ? g4(a, c, R.b & ((1u << h) - 1u)) : f4(a, c)) & keep;
+  }
+}
+
+// h of a split node of level K in 1..5: beta = [left ^ right, right]
+template <int K>
+__device__ __forceinline__ void reg_h(XR& R) {
+  constexpr uint32_t h = 1u << (K - 1);
+  const uint32_t left = (R.lft >> (h - 1)) & ((1u << h) - 1u);
+  R.b = (left ^ R.b) | (R.b << h);
+}
+
+// a dedicated node or leaf of level K <= 5
+template <int K>
+__device__ __forceinline__ void reg_node(XR& R, uint32_t opc) {
+  constexpr uint32_t M = 1u << K;
+  constexpr int W = M >= 4 ? (int)M / 4 : 1;
+  constexpr uint32_t full = M == 32 ? 0xFFFFFFFFu : ((1u << M) - 1u);
+  if (opc == OP_R0 || opc == OP_LF) {
+    R.b = 0u;
+    return;
+  }
+  uint32_t hd = 0;
+#pragma unroll
+  for (int j = 0; j < W; ++j) hd |= hd4(xw<K>(R, j)) << (4 * j);
+  hd &= full;
+  if (opc == OP_R1 || opc == OP_LI) {
+    R.b = hd;
+    return;
+  }
+  if (opc == OP_REP) {
+    int p0 = 0, p1 = 0;
+#pragma unroll
+    for (int j = 0; j < W; ++j)
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        if (4 * j + i < (int)M) {
+          const int v = sx8(xw<K>(R, j), i);
+          if (v < 0)
+            p0 -= v;
+          else
+            p1 += v;
+        }
+    R.b = min(p1, kQ) < min(p0, kQ) ? full : 0u;
+    return;
+  }
+  // SPC: odd parity flips the least reliable position (smallest index on ties)
+  if (__popc(hd) & 1u) {
+    uint32_t key = 0xFFFFFFFFu;
+#pragma unroll
+    for (int j = 0; j < W; ++j)
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        if (4 * j + i < (int)M) {
+          const uint32_t kk = ((uint32_t)abs(sx8(xw<K>(R, j), i)) << 6) | (uint32_t)(4 * j + i);
+          key = min(key, kk);
+        }
+    hd ^= 1u << (key & 63u);
+  }
+  R.b = hd;
+}
+
+// ---------------------------------------------------------- memory levels
+// The current node of level k >= 6: its LLRs are the channel LLRs (k = n:
+// lane base llr + N f, chunk stride 16) or level k's buffer (lane base
+// buf_k + 16 l, chunk stride 1024).
+struct Src {
+  const char* p;
+  uint32_t cs;
+};
+
+struct Ctx {
+  char* region;       // this wave's region
+  const char* root;   // this lane's channel LLRs
+  uint32_t n, lane;
+  uint32_t* bits;     // partial-sum words of this lane: word w at bits[64 w]
+};
+
+__device__ __forceinline__ char* level_buf(const Ctx& C, uint32_t k) {
+  // levels 6 .. n-1, level k at 64 (2^k - 64) bytes
+  return C.region + (size_t)64u * ((1u << k) - 64u);
+}
+__device__ __forceinline__ Src src_of(const Ctx& C, uint32_t k) {
+  if (k == C.n) return Src{C.root, 16u};
+  return Src{level_buf(C, k) + 16u * C.lane, 1024u};
+}
+
+// f / g of a split node of level k >= 7 (child level k - 1 >= 6 in memory)
+template <bool G>
+__device__ __forceinline__ void mem_fg(const Ctx& C, uint32_t k, uint32_t o) {
+  const Src s = src_of(C, k);
+  const uint32_t nc = 1u << (k - 5);  // chunks of the child (h / 16)
+  const char* pa = s.p;
+  const char* pb = s.p + (size_t)nc * s.cs;
+  char* dst = level_buf(C, k - 1) + 16u * C.lane;
+  const uint32_t* lb = C.bits + (size_t)64u * (o >> 5);
+  for (uint32_t c = 0; c < nc; c += 2) {
+    const Chunk a0 = ldc(pa + (size_t)c * s.cs), b0 = ldc(pb + (size_t)c * s.cs);
+    const Chunk a1 = ldc(pa + (size_t)(c + 1) * s.cs), b1 = ldc(pb + (size_t)(c + 1) * s.cs);
+    Chunk r0, r1;
+    if constexpr (G) {
+      const uint32_t sw = lb[64u * (c >> 1)];  // left partial sums of elements 16c .. 16c+31
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        r0.w[j] = g4(a0.w[j], b0.w[j], (sw >> (4 * j)) & 15u);
+        r1.w[j] = g4(a1.w[j], b1.w[j], (sw >> (16 + 4 * j)) & 15u);
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        r0.w[j] = f4(a0.w[j], b0.w[j]);
+        r1.w[j] = f4(a1.w[j], b1.w[j]);
+      }
+    }
+    stc(dst + (size_t)c * 1024u, r0);
+    stc(dst + (size_t)(c + 1) * 1024u, r1);
+  }
+}
+
+// f / g of a split node of level 6: the child (level 5) goes to registers
+template <bool G>
+__device__ __forceinline__ void mem_fg6(const Ctx& C, XR& R) {
+  const Src s = src_of(C, 6);
+  const Chunk a0 = ldc(s.p), a1 = ldc(s.p + s.cs), b0 = ldc(s.p + 2 * s.cs), b1 = ldc(s.p + 3 * s.cs);
+  if constexpr (G) R.l6 = R.b;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    if constexpr (G) {
+      R.x5[j] = g4(a0.w[j], b0.w[j], (R.b >> (4 * j)) & 15u);
+      R.x5[j + 4] = g4(a1.w[j], b1.w[j], (R.b >> (16 + 4 * j)) & 15u);
+    } else {
+      R.x5[j] = f4(a0.w[j], b0.w[j]);
+      R.x5[j + 4] = f4(a1.w[j], b1.w[j]);
+    }
+  }
+}
+
+// h of a split node of level k >= 6 at leaf offset o
+__device__ __forceinline__ void mem_h(const Ctx& C, XR& R, uint32_t k, uint32_t o) {
+  uint32_t* w = C.bits + (size_t)64u * (o >> 5);
+  if (k == 6) {
+    w[0] = R.l6 ^ R.b;
+    w[64] = R.b;
+    return;
+  }
+  const uint32_t nw = 1u << (k - 6);  // words of each half
+  uint32_t* r = w + (size_t)64u * nw;
+  for (uint32_t q = 0; q < nw; ++q) w[64u * q] ^= r[64u * q];
+}
+
+// a dedicated node of level k >= 6 at leaf offset o
+__device__ __forceinline__ void mem_node(const Ctx& C, uint32_t opc, uint32_t k, uint32_t o) {
+  uint32_t* w = C.bits + (size_t)64u * (o >> 5);
+  const uint32_t nw = 1u << (k - 5);  // 32-bit words of partial sums
+  if (opc == OP_R0) {
+    for (uint32_t q = 0; q < nw; ++q) w[64u * q] = 0u;
+    return;
+  }
+  const Src s = src_of(C, k);
+  if (opc == OP_REP) {
+    int p0 = 0, p1 = 0;
+    for (uint32_t c = 0; c < 2 * nw; ++c) {
+      const Chunk x = ldc(s.p + (size_t)c * s.cs);
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int v = sx8(x.w[j], i);
+          if (v < 0)
+            p0 -= v;
+          else
+            p1 += v;
+        }
+    }
+    const uint32_t v = min(p1, kQ) < min(p0, kQ) ? 0xFFFFFFFFu : 0u;
+    for (uint32_t q = 0; q < nw; ++q) w[64u * q] = v;
+    return;
+  }
+  // R1 / SPC: hard decisions, word q from chunks 2q, 2q + 1
+  uint32_t par = 0, key = 0xFFFFFFFFu;
+  for (uint32_t q = 0; q < nw; ++q) {
+    const Chunk x0 = ldc(s.p + (size_t)(2 * q) * s.cs), x1 = ldc(s.p + (size_t)(2 * q + 1) * s.cs);
+    const uint32_t hw = hd16(x0) | (hd16(x1) << 16);
+    w[64u * q] = hw;
+    if (opc == OP_SPC) {
+      par ^= hw;
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const uint32_t e = 32u * q + 4u * j + i;
+          key = min(key, ((uint32_t)abs(sx8(x0.w[j], i)) << 12) | e);
+          key = min(key, ((uint32_t)abs(sx8(x1.w[j], i)) << 12) | (e + 16u));
+        }
+    }
+  }
+  if (opc == OP_SPC && (__popc(par) & 1u)) {
+    const uint32_t e = key & 0xFFFu;
+    w[64u * (e >> 5)] ^= 1u << (e & 31u);
+  }
+}
+
+// ------------------------------------------------------- the op dispatch
+__device__ __forceinline__ void reg_op(XR& R, uint32_t opc, uint32_t k) {
+  // split-node steps of levels 1..5 and nodes of levels 0..5
+  if (opc == OP_F || opc == OP_G || opc == OP_H) {
+    const bool g = opc == OP_G;
+    if (opc == OP_H) {
+      switch (k) {
+        case 5: reg_h<5>(R); break;
+        case 4: reg_h<4>(R); break;
+        case 3: reg_h<3>(R); break;
+        case 2: reg_h<2>(R); break;
+        default: reg_h<1>(R); break;
+      }
+      return;
+    }
+    switch (k) {
+      case 5: g ? reg_fg<5, true>(R) : reg_fg<5, false>(R); break;
+      case 4: g ? reg_fg<4, true>(R) : reg_fg<4, false>(R); break;
+      case 3: g ? reg_fg<3, true>(R) : reg_fg<3, false>(R); break;
+      case 2: g ? reg_fg<2, true>(R) : reg_fg<2, false>(R); break;
+      default: g ? reg_fg<1, true>(R) : reg_fg<1, false>(R); break;
+    }
+    return;
+  }
+  switch (k) {
+    case 5: reg_node<5>(R, opc); break;
+    case 4: reg_node<4>(R, opc); break;
+    case 3: reg_node<3>(R, opc); break;
+    case 2: reg_node<2>(R, opc); break;
+    case 1: reg_node<1>(R, opc); break;
+    default: reg_node<0>(R, opc); break;
+  }
+}
+
+}  // namespace
+
+// A persistent grid: wave g decodes the groups of 64 frames g, g + G, ...
+// (frame 64 q + lane; lanes past the batch decode its last frame and drop
+// the result).  Every frame of the batch starts at L = 1 (the caller checks
+// the plan); a frame whose CRC fails gets its next list size in state[f],
+// the others are finished here.
+__global__ __launch_bounds__(64) void k_scx(KArgs A, uint32_t* state) {
+  const uint32_t lane = threadIdx.x;
+  const DevPlan* P = uni_ptr(A.plans[0]);
+  const uint32_t N = uni(P->N), n = uni(P->n), n_ops = uni(P->n_ops), bw = uni(P->bw);
+  const uint32_t iw = uni(A.info_words), L_max = uni(P->L_max), c_len = uni(P->c);
+  const uint32_t* prog = uni_ptr(plan_tab(P, uni(P->off_prog)));
+  const uint32_t* imask = uni_ptr(plan_tab(P, uni(P->off_infomask)));
+  const uint32_t* nib = uni_ptr(plan_tab(P, uni(P->off_crcnib)));
+  const uint32_t* dmask = uni_ptr(plan_tab(P, uni(P->off_datamask)));
+  char* region = A.spill + (size_t)blockIdx.x * A.spill_stride;
+  const uint32_t n_groups = (A.n_frames + 63u) / 64u;
+  for (uint32_t q = blockIdx.x; q < n_groups; q += gridDim.x) {
+    const uint32_t f = 64u * q + lane;
+    const bool valid = f < A.n_frames;
+    const uint32_t fi = valid ? f : A.n_frames - 1u;
+    if (valid && A.times) A.times[2 * (size_t)f] = wall_clock64();
+    Ctx C;
+    C.region = region;
+    C.root = A.llr + (size_t)fi * A.llr_bytes;
+    C.n = n;
+    C.lane = lane;
+    C.bits = reinterpret_cast<uint32_t*>(region + (size_t)64u * (N - 64u)) + lane;
+    XR R;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) R.x5[j] = 0u;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) R.x4[j] = 0u;
+    R.x3[0] = R.x3[1] = R.x2 = R.x1 = R.x0 = 0u;
+    R.b = R.lft = R.l6 = 0u;
+    uint32_t w_next = prog[0];
+    for (uint32_t pc = 0; pc < n_ops; ++pc) {
+      const uint32_t w = uni(w_next);
+      if (pc + 1 < n_ops) w_next = prog[pc + 1];
+      const uint32_t opc = op_code(w), k = n - op_depth(w), o = op_off(w);
+      if (k <= 5) {
+        reg_op(R, opc, k);
+      } else if (opc == OP_F) {
+        if (k == 6)
+          mem_fg6<false>(C, R);
+        else
+          mem_fg<false>(C, k, o);
+      } else if (opc == OP_G) {
+        if (k == 6)
+          mem_fg6<true>(C, R);
+        else
+          mem_fg<true>(C, k, o);
+      } else if (opc == OP_H) {
+        mem_h(C, R, k, o);
+      } else {
+        mem_node(C, opc, k, o);
+      }
+    }
+    // ---- CRC syndrome of the codeword estimate through the nibble table
+    uint32_t syn = 0;
+    if (c_len > 0) {
+      for (uint32_t wd = 0; wd < bw; ++wd) {
+        const uint32_t im = imask[wd];
+        if (!im) continue;
+        const uint32_t v = C.bits[64u * wd] & im;
+        for (uint32_t t = 0; t < 8; ++t)
+          if ((im >> (4 * t)) & 15u) syn ^= nib[((wd * 8 + t) << 4) + ((v >> (4 * t)) & 15u)];
+      }
+    }
+    const bool ok = syn == 0u;
+    const bool esc = valid && !ok && L_max > 1;
+    if (esc) state[f] = next_stage(P, 1);
+    const bool fin = valid && !esc;
+    // ---- information bits: the data positions of A in ascending order
+    uint32_t* out = A.info + (size_t)fi * iw;
+    uint32_t cur = 0, pos = 0, ow = 0;
+    for (uint32_t wd = 0; wd < bw; ++wd) {
+      uint32_t dm = dmask[wd];
+      if (!dm) continue;
+      const uint32_t x = C.bits[64u * wd];
+      uint32_t v = 0, cnt = 0;
+      while (dm) {
+        const uint32_t b = __ffs(dm) - 1;
+        v |= ((x >> b) & 1u) << cnt;
+        ++cnt;
+        dm &= dm - 1u;
+      }
+      cur |= v << pos;
+      if (pos + cnt >= 32) {
+        if (fin) out[ow] = cur;
+        ++ow;
+        cur = pos ? v >> (32 - pos) : 0u;
+      }
+      pos = (pos + cnt) & 31u;
+    }
+    if (pos && fin) out[ow] = cur;
+    if (fin) {
+      polar_status st;
+      st.crc_ok = ok ? 1 : 0;
+      st.L_used = 1;
+      st.n_paths = 1;
+      st.flags = 0;
+      st.pm = 0u;
+      A.status[f] = st;
+      if (A.pm_lists)
+        for (uint32_t t = 0; t < A.pm_stride; ++t)
+          A.pm_lists[(size_t)f * A.pm_stride + t] = t == 0 ? 0u : 0xFFFFFFFFu;
+      if (A.times) A.times[2 * (size_t)f + 1] = wall_clock64();
+    }
+  }
+}
+
+// Bytes of one wave's region for a code of length N (levels 6 .. n-1, then
+// the partial sums), 256-byte aligned.
+uint64_t scx_region_bytes(uint32_t N) {
+  const uint64_t b = 64ull * (N - 64u) + 8ull * N;
+  return (b + 255u) & ~255ull;
+}
+
+int launch_decode_scx(const KArgs& A, uint32_t grid, uint32_t* state, hipStream_t s) {
+  hipLaunchKernelGGL(k_scx, dim3(grid > 0 ? grid : 1), dim3(64), 0, s, A, state);
+  return hipGetLastError() == hipSuccess ? POLAR_OK : POLAR_EHIP;
+}
+
+}  // namespace polar

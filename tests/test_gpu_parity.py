@@ -305,6 +305,31 @@ def test_class_schedule_with_spilled_float_plan():
         assert st["L_used"][f] == ref.L_used[0], f
 
 
+SCX_CASES = [
+    # (N, K, c, poly, design dB, algo, L_max, node options, Eb/N0)
+    (256, 200, 11, 0x621, 3.0, "fa", 4, dict(rep_max=0, spc_max=0), 2.5),
+    (512, 300, 11, 0x621, 2.5, "fa", 8, dict(node_enable=0), 2.0),
+    (1024, 700, 24, 0x1864CFB, 3.0, "fa", 2, dict(rep_max=0, spc_max=0, r1_max=64), 2.5),
+    (1024, 512, 11, 0x621, 2.0, "pa", 4, dict(), 1.5),
+    (2048, 1723, 32, 0x04C11DB7, 4.5, "fa", 32, dict(), 3.5),
+]
+
+
+@pytest.mark.parametrize("case", range(len(SCX_CASES)))
+def test_sc_tier_frame_per_lane(case):
+    """Uniform int8 batches of codes that send every position: the L = 1
+    tier runs one frame per lane, 64 frames per wave.  Batches of 1, 65 and
+    200 frames (a lone frame, a ragged last group, several groups), with the
+    nodes of every size in registers and in memory (REP / SPC of any size,
+    no dedicated nodes, a Rate-1 size cap), equal the oracle bit for bit,
+    escalated frames included."""
+    N, K, c, poly, design, algo, Lm, kw, eb = SCX_CASES[case]
+    code = _code(N, K, c, poly, design, quant="i8", algo=algo, L=Lm, L_max=Lm, **kw)
+    for n in (1, 65, 200):
+        _, llr = make_inputs(code, n, 900 + 7 * case + n, eb)
+        compare(code, llr)
+
+
 @pytest.mark.parametrize("quant", ["i8", "f32"])
 def test_sc_tier_frame_pairs(quant):
     """The L = 1 tier decodes two frames per wave.  Every frame of an odd-sized
