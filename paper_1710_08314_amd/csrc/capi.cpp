@@ -483,11 +483,13 @@ int plan_tiers(const Batch& b, polar::TierPlan* out) {
       tp.sc_groot = 1;
       lds_sc = polar::sc_lds_bytes(h.N, polar::elem_bytes(h.quant), 1);
       // int8 with 16-byte aligned frames: one frame per lane, a persistent
-      // grid of up to 16 waves per CU, each with its own region
+      // grid of as many waves as a CU holds (at most 16: its registers; its
+      // LDS), each with its own region
       if (h.quant == POLAR_I8 && (((uintptr_t)b.A.llr) & 15u) == 0 &&
           (b.A.llr_bytes & 15u) == 0 && b.A.llr_bytes >= h.N) {
         const uint32_t groups = (n_frames + 63) / 64;
-        const uint32_t cap = 16u * (uint32_t)cus;
+        const uint32_t per_cu = polar::kLdsLimit / polar::kScxLds;
+        const uint32_t cap = (per_cu < 16u ? per_cu : 16u) * (uint32_t)cus;
         const uint32_t rounds = groups > cap ? (groups + cap - 1) / cap : 1u;
         tp.sc_x = 1;
         tp.grid_scx = groups ? (groups + rounds - 1) / rounds : 1u;

@@ -94,6 +94,7 @@ int launch_decode_sc(uint32_t quant, const KArgs& A, uint32_t lds, uint32_t grid
 // `grid` waves, each with a region of scx_region_bytes(N) at
 // A.spill + blockIdx.x * A.spill_stride.
 uint64_t scx_region_bytes(uint32_t N);
+constexpr uint32_t kScxLds = 4 * 1024;  // its LDS per wave (level 6)
 int launch_decode_scx(const KArgs& A, uint32_t grid, uint32_t* state, hipStream_t s);
 
 // Class schedule of a batch of fixed-list plans (no escalation): the frames

@@ -12,10 +12,11 @@
 // Per lane (frame):
 //   * the LLRs of the current node at each level k <= 5 (at most 32 of
 //     them) live in registers, packed four int8 per 32-bit word;
-//   * the LLRs of the current node at each level 6 <= k < n live in a
-//     per-wave region of global memory, 16-byte chunks interleaved over the
-//     64 lanes (chunk c of lane l at 16 (64 c + l)), so every access of the
-//     wave is one contiguous kilobyte;
+//   * the LLRs of the current node of level 6 live in LDS, those of each
+//     level 7 <= k < n in a per-wave region of global memory; both hold
+//     16-byte chunks interleaved over the 64 lanes (chunk c of lane l at
+//     16 (64 c + l)), so every access of the wave is one contiguous
+//     kilobyte (conflict-free in LDS);
 //   * the root is the channel LLR buffer itself (frame-major);
 //   * partial sums of levels >= 6 are N bits per frame in the same region,
 //     word w of lane l at 4 (64 w + l); those of a node of level <= 5 stay in
@@ -182,7 +183,7 @@ __device__ __forceinline__ void reg_node(XR& R, uint32_t opc) {
 }
 
 // ---------------------------------------------------------- memory levels
-// The current node of level k >= 6: its LLRs are the channel LLRs (k = n:
+// The current node of level k >= 7: its LLRs are the channel LLRs (k = n:
 // lane base llr + N f, chunk stride 16) or level k's buffer (lane base
 // buf_k + 16 l, chunk stride 1024).
 struct Src {
@@ -195,25 +196,31 @@ struct Ctx {
   const char* root;   // this lane's channel LLRs
   uint32_t n, lane;
   uint32_t* bits;     // partial-sum words of this lane: word w at bits[64 w]
+  uint4* l6;          // this lane's level-6 chunks in LDS: chunk c at l6[64 c]
 };
 
 __device__ __forceinline__ char* level_buf(const Ctx& C, uint32_t k) {
-  // levels 6 .. n-1, level k at 64 (2^k - 64) bytes
-  return C.region + (size_t)64u * ((1u << k) - 64u);
+  // levels 7 .. n-1, level k at 64 (2^k - 128) bytes
+  return C.region + (size_t)64u * ((1u << k) - 128u);
+}
+__device__ __forceinline__ Chunk ld6(const Ctx& C, uint32_t c) {
+  const uint4 v = C.l6[64u * c];
+  return Chunk{{v.x, v.y, v.z, v.w}};
 }
 __device__ __forceinline__ Src src_of(const Ctx& C, uint32_t k) {
   if (k == C.n) return Src{C.root, 16u};
   return Src{level_buf(C, k) + 16u * C.lane, 1024u};
 }
 
-// f / g of a split node of level k >= 7 (child level k - 1 >= 6 in memory)
-template <bool G>
+// f / g of a split node of level k >= 7 (child level k - 1 >= 6: LDS for
+// k = 7 (L6), global memory above)
+template <bool G, bool L6>
 __device__ __forceinline__ void mem_fg(const Ctx& C, uint32_t k, uint32_t o) {
   const Src s = src_of(C, k);
   const uint32_t nc = 1u << (k - 5);  // chunks of the child (h / 16)
   const char* pa = s.p;
   const char* pb = s.p + (size_t)nc * s.cs;
-  char* dst = level_buf(C, k - 1) + 16u * C.lane;
+  char* dst = L6 ? nullptr : level_buf(C, k - 1) + 16u * C.lane;
   const uint32_t* lb = C.bits + (size_t)64u * (o >> 5);
   for (uint32_t c = 0; c < nc; c += 2) {
     const Chunk a0 = ldc(pa + (size_t)c * s.cs), b0 = ldc(pb + (size_t)c * s.cs);
@@ -233,16 +240,20 @@ __device__ __forceinline__ void mem_fg(const Ctx& C, uint32_t k, uint32_t o) {
         r1.w[j] = f4(a1.w[j], b1.w[j]);
       }
     }
-    stc(dst + (size_t)c * 1024u, r0);
-    stc(dst + (size_t)(c + 1) * 1024u, r1);
+    if constexpr (L6) {
+      C.l6[64u * c] = make_uint4(r0.w[0], r0.w[1], r0.w[2], r0.w[3]);
+      C.l6[64u * (c + 1)] = make_uint4(r1.w[0], r1.w[1], r1.w[2], r1.w[3]);
+    } else {
+      stc(dst + (size_t)c * 1024u, r0);
+      stc(dst + (size_t)(c + 1) * 1024u, r1);
+    }
   }
 }
 
 // f / g of a split node of level 6: the child (level 5) goes to registers
 template <bool G>
 __device__ __forceinline__ void mem_fg6(const Ctx& C, XR& R) {
-  const Src s = src_of(C, 6);
-  const Chunk a0 = ldc(s.p), a1 = ldc(s.p + s.cs), b0 = ldc(s.p + 2 * s.cs), b1 = ldc(s.p + 3 * s.cs);
+  const Chunk a0 = ld6(C, 0), a1 = ld6(C, 1), b0 = ld6(C, 2), b1 = ld6(C, 3);
   if constexpr (G) R.l6 = R.b;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
@@ -269,19 +280,21 @@ __device__ __forceinline__ void mem_h(const Ctx& C, XR& R, uint32_t k, uint32_t 
   for (uint32_t q = 0; q < nw; ++q) w[64u * q] ^= r[64u * q];
 }
 
-// a dedicated node of level k >= 6 at leaf offset o
-__device__ __forceinline__ void mem_node(const Ctx& C, uint32_t opc, uint32_t k, uint32_t o) {
+// a dedicated node of level k >= 6 at leaf offset o; rd(c) reads chunk c of
+// its LLRs
+template <class RD>
+__device__ __forceinline__ void mem_node_t(const Ctx& C, uint32_t opc, uint32_t k, uint32_t o,
+                                           const RD& rd) {
   uint32_t* w = C.bits + (size_t)64u * (o >> 5);
   const uint32_t nw = 1u << (k - 5);  // 32-bit words of partial sums
   if (opc == OP_R0) {
     for (uint32_t q = 0; q < nw; ++q) w[64u * q] = 0u;
     return;
   }
-  const Src s = src_of(C, k);
   if (opc == OP_REP) {
     int p0 = 0, p1 = 0;
     for (uint32_t c = 0; c < 2 * nw; ++c) {
-      const Chunk x = ldc(s.p + (size_t)c * s.cs);
+      const Chunk x = rd(c);
 #pragma unroll
       for (int j = 0; j < 4; ++j)
 #pragma unroll
@@ -300,7 +313,7 @@ __device__ __forceinline__ void mem_node(const Ctx& C, uint32_t opc, uint32_t k,
   // R1 / SPC: hard decisions, word q from chunks 2q, 2q + 1
   uint32_t par = 0, key = 0xFFFFFFFFu;
   for (uint32_t q = 0; q < nw; ++q) {
-    const Chunk x0 = ldc(s.p + (size_t)(2 * q) * s.cs), x1 = ldc(s.p + (size_t)(2 * q + 1) * s.cs);
+    const Chunk x0 = rd(2 * q), x1 = rd(2 * q + 1);
     const uint32_t hw = hd16(x0) | (hd16(x1) << 16);
     w[64u * q] = hw;
     if (opc == OP_SPC) {
@@ -318,6 +331,14 @@ __device__ __forceinline__ void mem_node(const Ctx& C, uint32_t opc, uint32_t k,
   if (opc == OP_SPC && (__popc(par) & 1u)) {
     const uint32_t e = key & 0xFFFu;
     w[64u * (e >> 5)] ^= 1u << (e & 31u);
+  }
+}
+__device__ __forceinline__ void mem_node(const Ctx& C, uint32_t opc, uint32_t k, uint32_t o) {
+  if (k == 6) {
+    mem_node_t(C, opc, k, o, [&](uint32_t c) { return ld6(C, c); });
+  } else {
+    const Src s = src_of(C, k);
+    mem_node_t(C, opc, k, o, [&](uint32_t c) { return ldc(s.p + (size_t)c * s.cs); });
   }
 }
 
@@ -363,6 +384,8 @@ __device__ __forceinline__ void reg_op(XR& R, uint32_t opc, uint32_t k) {
 // the plan); a frame whose CRC fails gets its next list size in state[f],
 // the others are finished here.
 __global__ __launch_bounds__(64) void k_scx(KArgs A, uint32_t* state) {
+  __shared__ uint4 lds6[4 * 64];  // level 6: 4 chunks per lane
+  static_assert(sizeof(lds6) == kScxLds, "LDS per wave");
   const uint32_t lane = threadIdx.x;
   const DevPlan* P = uni_ptr(A.plans[0]);
   const uint32_t N = uni(P->N), n = uni(P->n), n_ops = uni(P->n_ops), bw = uni(P->bw);
@@ -383,7 +406,8 @@ __global__ __launch_bounds__(64) void k_scx(KArgs A, uint32_t* state) {
     C.root = A.llr + (size_t)fi * A.llr_bytes;
     C.n = n;
     C.lane = lane;
-    C.bits = reinterpret_cast<uint32_t*>(region + (size_t)64u * (N - 64u)) + lane;
+    C.bits = reinterpret_cast<uint32_t*>(region + (size_t)64u * (N - 128u)) + lane;
+    C.l6 = lds6 + lane;
     XR R;
 #pragma unroll
     for (int j = 0; j < 8; ++j) R.x5[j] = 0u;
@@ -401,13 +425,17 @@ __global__ __launch_bounds__(64) void k_scx(KArgs A, uint32_t* state) {
       } else if (opc == OP_F) {
         if (k == 6)
           mem_fg6<false>(C, R);
+        else if (k == 7)
+          mem_fg<false, true>(C, k, o);
         else
-          mem_fg<false>(C, k, o);
+          mem_fg<false, false>(C, k, o);
       } else if (opc == OP_G) {
         if (k == 6)
           mem_fg6<true>(C, R);
+        else if (k == 7)
+          mem_fg<true, true>(C, k, o);
         else
-          mem_fg<true>(C, k, o);
+          mem_fg<true, false>(C, k, o);
       } else if (opc == OP_H) {
         mem_h(C, R, k, o);
       } else {
@@ -468,10 +496,10 @@ __global__ __launch_bounds__(64) void k_scx(KArgs A, uint32_t* state) {
   }
 }
 
-// Bytes of one wave's region for a code of length N (levels 6 .. n-1, then
+// Bytes of one wave's region for a code of length N (levels 7 .. n-1, then
 // the partial sums), 256-byte aligned.
 uint64_t scx_region_bytes(uint32_t N) {
-  const uint64_t b = 64ull * (N - 64u) + 8ull * N;
+  const uint64_t b = 64ull * (N - 128u) + 8ull * N;
   return (b + 255u) & ~255ull;
 }
 
