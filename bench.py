@@ -33,6 +33,7 @@ WORKLOAD = dict(name="fa_sscl_n2048_k1723_crc32_lmax32_i8", N=2048, K=1723, crc_
 # MI355X: 256 CUs x 128 vector lanes per clock x 2.4 GHz, the lane rate of the published fp32
 # vector peak (157.3 TFLOP/s counting an FMA as two), with no FMA credit
 VALU_PEAK_OPS = 256 * 128 * 2.4e9
+HBM_PEAK_BYTES = 8.0e12  # MI355X HBM3E
 PAPER_CONTEXT_MBPS = {3.5: 24.4, 4.0: 227.3, 4.5: 425.9}  # one i5-6600K core, 8-bit FA
 # counter summaries (HBM bytes per launch) and the sources each kernel is built from
 TRAFFIC_FILES = {"k_scx": "hbm_traffic_k_scx_fa2048_i8.md",
@@ -612,6 +613,12 @@ def main():
             tiers[t] = {"kernel": kernel_names[t], "launch_ms": round(tier_ms[t] / len(points), 3),
                         "work_per_launch_ops": int(tier_work[t] / len(points)),
                         "achieved": round(ach / 1e12, 5), "frac": round(ach / VALU_PEAK_OPS, 6)}
+            # measured HBM bytes per launch (counter summary), against the 8 TB/s peak
+            tb = measured_traffic(kernel_names[t])
+            if tb:
+                rate = tb / (tier_ms[t] / len(points) / 1e3)
+                tiers[t].update({"traffic": tb, "hbm_tbs": round(rate / 1e12, 3),
+                                 "hbm_frac": round(rate / HBM_PEAK_BYTES, 4)})
     dom = max(tiers, key=lambda t: tiers[t]["launch_ms"])
     roofline = {"bound": "alu", "achieved": tiers[dom]["achieved"],
                 "peak": round(VALU_PEAK_OPS / 1e12, 2), "unit": "Tops/s",

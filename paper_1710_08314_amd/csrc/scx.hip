@@ -6,7 +6,8 @@
 // one path takes the same steps whatever the LLRs are, so a wave decodes 64
 // frames in lockstep: the program walk, its dispatch and every loop bound
 // are scalar, and every lane of every vector instruction does a frame's
-// arithmetic (the inter-frame form of Sec. III-A's SIMD discussion).  The
+// arithmetic: the inter-frame use of SIMD that Sec. IV-A sets against the
+// intra-frame one, which leaves most lanes idle near the leaves.  The
 // frame-per-half tier (sc.hip) decodes everything else.
 //
 // Per lane (frame):
