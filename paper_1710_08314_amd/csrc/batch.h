@@ -21,6 +21,7 @@ struct Work {
   uint32_t* state = nullptr;
   uint32_t* tier_heads = nullptr;
   uint32_t* heads = nullptr;  // class schedule
+  uint32_t* xlist = nullptr;  // count + frame indices of the frame-per-lane L = 2 stage
   char* spill = nullptr;      // LLR buffers of spilled layouts (spill_need bytes)
   uint64_t spill_bytes = 0;
 };

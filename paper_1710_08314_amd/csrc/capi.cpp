@@ -283,13 +283,14 @@ int polar_plan_get_frozen(polar_plan p, uint32_t* fw) {
 
 namespace polar {
 
-size_t work_words(size_t cap) { return cap + 2 * kClaimSegs + kMaxClasses; }
+size_t work_words(size_t cap) { return 2 * cap + 1 + 2 * kClaimSegs + kMaxClasses; }
 
 Work work_view(uint32_t* base, size_t cap) {
   Work w;
   w.state = base;
   w.tier_heads = base + cap;
   w.heads = base + cap + 2 * kClaimSegs;
+  w.xlist = w.heads + kMaxClasses;
   return w;
 }
 
@@ -494,6 +495,23 @@ int plan_tiers(const Batch& b, polar::TierPlan* out) {
         tp.sc_x = 1;
         tp.grid_scx = groups ? (groups + rounds - 1) / rounds : 1u;
         tp.spill_sc = polar::scx_region_bytes(h.N);
+        // the L = 2 stage the same way, when the schedule has one and every
+        // REP / SPC node fits the register levels (<= 32 positions)
+        const bool stage2 = h.first_stage == 2 ||
+                            (h.first_stage == 1 && h.max_list >= 2 &&
+                             (h.algo == POLAR_FA_SCL || h.max_list == 2));
+        bool small = true;
+        for (uint32_t w : hp.prog) {
+          const uint32_t op = polar::op_code(w);
+          if ((op == polar::OP_REP || op == polar::OP_SPC) && (h.N >> polar::op_depth(w)) > 32)
+            small = false;
+        }
+        if (stage2 && small) {
+          const uint32_t cap2 = 12u * (uint32_t)cus;  // its registers: 3 waves per SIMD
+          tp.run_x2 = 1;
+          tp.grid_x2 = groups < cap2 ? (groups ? groups : 1u) : cap2;
+          tp.spill_x2 = polar::listx2_region_bytes(h.N);
+        }
       }
     }
   }
@@ -605,6 +623,7 @@ uint64_t spill_need(const Batch& b, int cus) {
   TierPlan tp{};
   if (plan_tiers(b, &tp) == POLAR_OK) {
     if (tp.run_sc && tp.sc_x) upd(tp.grid_scx, tp.spill_sc);
+    if (tp.run_x2) upd(tp.grid_x2, tp.spill_x2);
     if (tp.run_a) upd(tp.grid_a, tp.spill_a);
     if (tp.run_b) upd(tp.grid_b, tp.spill_b);
   }
@@ -670,7 +689,7 @@ int launch_batch(const Batch& b_in, uint32_t schedule, const Work& w, hipStream_
   polar::TierPlan tp{};
   rc = plan_tiers(b, &tp);
   if (rc) return rc;
-  rc = polar::launch_decode_tiered(b.quant, A, tp, w.state, w.tier_heads, st, ev);
+  rc = polar::launch_decode_tiered(b.quant, A, tp, w.state, w.tier_heads, w.xlist, st, ev);
   if (ev) {
     g_timing.ran[0] = tp.run_sc;
     g_timing.ran[1] = tp.run_a;

@@ -1275,9 +1275,10 @@ int launch_decode_plain(uint32_t quant, const KArgs& A, uint32_t lds, uint32_t g
 
 template <typename T>
 static int launch_tiered_t(const KArgs& A, const TierPlan& tp, uint32_t* state, uint32_t* heads,
-                           hipStream_t s, hipEvent_t* ev) {
+                           uint32_t* xl, hipStream_t s, hipEvent_t* ev) {
   const uint32_t blocks = (A.n_frames + 255) / 256 < 2048 ? (A.n_frames + 255) / 256 : 2048;
   hipLaunchKernelGGL(k_heads_reset, dim3(1), dim3(64), 0, s, heads, 2 * kClaimSegs);
+  if (tp.run_x2) hipLaunchKernelGGL(k_heads_reset, dim3(1), dim3(64), 0, s, xl, 1u);
   hipLaunchKernelGGL(k_state_init, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, s, A, state);
   if (ev) (void)hipEventRecord(ev[0], s);
   if (tp.run_sc && tp.sc_x) {
@@ -1293,6 +1294,12 @@ static int launch_tiered_t(const KArgs& A, const TierPlan& tp, uint32_t* state, 
     if (rc) return rc;
   }
   if (ev) (void)hipEventRecord(ev[1], s);
+  if (tp.run_x2) {
+    KArgs Ax = A;
+    Ax.spill_stride = tp.spill_x2;
+    const int rc = launch_decode_listx2(Ax, tp.grid_x2, state, xl, s);
+    if (rc) return rc;
+  }
   KArgs Aa = A, Ab = A;
   Aa.spill_stride = tp.spill_a;
   Ab.spill_stride = tp.spill_b;
@@ -1309,11 +1316,11 @@ static int launch_tiered_t(const KArgs& A, const TierPlan& tp, uint32_t* state, 
 }
 
 int launch_decode_tiered(uint32_t quant, const KArgs& A, const TierPlan& tp, uint32_t* state,
-                         uint32_t* heads, hipStream_t s, hipEvent_t* ev) {
+                         uint32_t* heads, uint32_t* xl, hipStream_t s, hipEvent_t* ev) {
   switch (quant) {
-    case POLAR_F32: return launch_tiered_t<float>(A, tp, state, heads, s, ev);
-    case POLAR_I16: return launch_tiered_t<int16_t>(A, tp, state, heads, s, ev);
-    default: return launch_tiered_t<int8_t>(A, tp, state, heads, s, ev);
+    case POLAR_F32: return launch_tiered_t<float>(A, tp, state, heads, xl, s, ev);
+    case POLAR_I16: return launch_tiered_t<int16_t>(A, tp, state, heads, xl, s, ev);
+    default: return launch_tiered_t<int8_t>(A, tp, state, heads, xl, s, ev);
   }
 }
 

@@ -204,10 +204,15 @@ __device__ __forceinline__ char* level_buf(const Ctx& C, uint32_t k) {
   // levels 7 .. n-1, level k at 64 (2^k - 128) bytes
   return C.region + (size_t)64u * ((1u << k) - 128u);
 }
-__device__ __forceinline__ Chunk ld6(const Ctx& C, uint32_t c) {
-  const uint4 v = C.l6[64u * c];
+// chunk c of a lane's LDS buffer whose chunk 0 is at p
+__device__ __forceinline__ Chunk ldl(const uint4* p, uint32_t c) {
+  const uint4 v = p[64u * c];
   return Chunk{{v.x, v.y, v.z, v.w}};
 }
+__device__ __forceinline__ void stl(uint4* p, uint32_t c, const Chunk& x) {
+  p[64u * c] = make_uint4(x.w[0], x.w[1], x.w[2], x.w[3]);
+}
+__device__ __forceinline__ Chunk ld6(const Ctx& C, uint32_t c) { return ldl(C.l6, c); }
 __device__ __forceinline__ Src src_of(const Ctx& C, uint32_t k) {
   if (k == C.n) return Src{C.root, 16u};
   return Src{level_buf(C, k) + 16u * C.lane, 1024u};
@@ -377,6 +382,363 @@ __device__ __forceinline__ void reg_op(XR& R, uint32_t opc, uint32_t k) {
   }
 }
 
+// ===================================================== L = 2, one frame per lane
+// The list stage of size 2 (Algorithm 1 with the dedicated nodes of
+// Sec. II-B3 and the selection of Sec. II-B2) for the frames of a uniform
+// int8 batch whose next stage is L = 2.  Each lane holds its frame's two
+// paths; the number of active paths grows the same way in every frame (one,
+// then two after the first node that forks), so it is scalar.
+//   * Register levels (<= 32 positions) per path, as in the L = 1 kernel.
+//   * Levels >= 6: two slots per level (LDS for level 6, the wave's region
+//     above), the path of rank r reads its node from the slot its slot bit
+//     names and writes its child to slot r (index indirection: a fork copies
+//     no LLRs).
+//   * Partial sums of levels >= 6: one N-bit array per path in the region,
+//     copied from the parent when a selection moves a path.
+// Candidates follow the list decoder: a leaf or REP node offers 0 and 1, a
+// Rate-1 node the Chase-2 flips of its two least reliable positions, an SPC
+// node the flips of its four least reliable positions whose weight has the
+// parity of the hard decisions; a candidate's metric is the parent's plus
+// the flipped magnitudes, saturated at Q; the two smallest keys (metric,
+// parent, local index) survive and metrics are normalised to the best.
+// The caller admits plans whose REP and SPC nodes fit in registers.
+
+struct PS {  // the two paths of a lane
+  XR R[2];
+  int pm[2];
+  uint32_t P[2];  // slot of each level k >= 6 of the path's buffers: bit k - 6
+};
+
+struct Ctx2 {
+  char* region;      // this wave's region
+  const char* root;  // this lane's channel LLRs
+  uint32_t n, lane;
+  uint32_t* bits[2];  // partial-sum words of path r: word w at bits[r][64 w]
+  uint4* l6[2];       // LDS slot s of level 6 for this lane: chunk c at l6[s][64 c]
+};
+
+// level k in 7 .. n-1: two slots of 64 2^k bytes, at 128 (2^k - 128)
+__device__ __forceinline__ char* lbuf2(const Ctx2& C, uint32_t k, uint32_t s) {
+  return C.region + (size_t)128u * ((1u << k) - 128u) + (size_t)s * (64u << k) + 16u * C.lane;
+}
+// the node of level k >= 7 of a path with slot bits Pr
+__device__ __forceinline__ Src src2(const Ctx2& C, uint32_t Pr, uint32_t k) {
+  if (k == C.n) return Src{C.root, 16u};
+  return Src{lbuf2(C, k, (Pr >> (k - 6)) & 1u), 1024u};
+}
+__device__ __forceinline__ const uint4* l6of(const Ctx2& C, uint32_t Pr) {
+  return (Pr & 1u) ? C.l6[1] : C.l6[0];
+}
+__device__ __forceinline__ uint32_t set_slot(uint32_t Pr, uint32_t k, uint32_t r) {
+  return (Pr & ~(1u << (k - 6))) | (r << (k - 6));
+}
+
+// f / g of path r's split node of level k >= 7 into its own slot of level k - 1
+template <bool G, bool DL>
+__device__ __forceinline__ void fg2(const Ctx2& C, uint32_t Pr, uint32_t r, uint32_t k, uint32_t o) {
+  const Src s = src2(C, Pr, k);
+  const uint32_t nc = 1u << (k - 5);
+  const char* pa = s.p;
+  const char* pb = s.p + (size_t)nc * s.cs;
+  char* dst = DL ? nullptr : lbuf2(C, k - 1, r);
+  uint4* dl = C.l6[r];
+  const uint32_t* lb = C.bits[r] + (size_t)64u * (o >> 5);
+  for (uint32_t c = 0; c < nc; c += 2) {
+    const Chunk a0 = ldc(pa + (size_t)c * s.cs), b0 = ldc(pb + (size_t)c * s.cs);
+    const Chunk a1 = ldc(pa + (size_t)(c + 1) * s.cs), b1 = ldc(pb + (size_t)(c + 1) * s.cs);
+    Chunk r0, r1;
+    if constexpr (G) {
+      const uint32_t sw = lb[64u * (c >> 1)];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        r0.w[j] = g4(a0.w[j], b0.w[j], (sw >> (4 * j)) & 15u);
+        r1.w[j] = g4(a1.w[j], b1.w[j], (sw >> (16 + 4 * j)) & 15u);
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        r0.w[j] = f4(a0.w[j], b0.w[j]);
+        r1.w[j] = f4(a1.w[j], b1.w[j]);
+      }
+    }
+    if constexpr (DL) {
+      stl(dl, c, r0);
+      stl(dl, c + 1, r1);
+    } else {
+      stc(dst + (size_t)c * 1024u, r0);
+      stc(dst + (size_t)(c + 1) * 1024u, r1);
+    }
+  }
+}
+
+// f / g of path r's split node of level 6 into its level-5 registers
+template <bool G>
+__device__ __forceinline__ void fg6_2(const Ctx2& C, uint32_t Pr, XR& R) {
+  const uint4* l = l6of(C, Pr);
+  const Chunk a0 = ldl(l, 0), a1 = ldl(l, 1), b0 = ldl(l, 2), b1 = ldl(l, 3);
+  if constexpr (G) R.l6 = R.b;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    if constexpr (G) {
+      R.x5[j] = g4(a0.w[j], b0.w[j], (R.b >> (4 * j)) & 15u);
+      R.x5[j + 4] = g4(a1.w[j], b1.w[j], (R.b >> (16 + 4 * j)) & 15u);
+    } else {
+      R.x5[j] = f4(a0.w[j], b0.w[j]);
+      R.x5[j + 4] = f4(a1.w[j], b1.w[j]);
+    }
+  }
+}
+
+// h of path r's split node of level k >= 6
+__device__ __forceinline__ void h2(const Ctx2& C, uint32_t r, const XR& R, uint32_t k, uint32_t o) {
+  uint32_t* w = C.bits[r] + (size_t)64u * (o >> 5);
+  if (k == 6) {
+    w[0] = R.l6 ^ R.b;
+    w[64] = R.b;
+    return;
+  }
+  const uint32_t nw = 1u << (k - 6);
+  uint32_t* q = w + (size_t)64u * nw;
+  for (uint32_t i = 0; i < nw; ++i) w[64u * i] ^= q[64u * i];
+}
+
+// keep the two smallest keys
+__device__ __forceinline__ void ins2(uint32_t key, uint32_t& k0, uint32_t& k1) {
+  const uint32_t lo = min(key, k0), hi = max(key, k0);
+  k0 = lo;
+  k1 = min(k1, hi);
+}
+__device__ __forceinline__ uint32_t ckey(int pm, uint32_t pen, uint32_t r, uint32_t local) {
+  const int v = min(pm + (int)pen, kQ);
+  return ((uint32_t)v << 8) | (r << 4) | local;
+}
+__device__ __forceinline__ void normalise(PS& S, uint32_t a) {
+  const int mn = a > 1 ? min(S.pm[0], S.pm[1]) : S.pm[0];
+  S.pm[0] -= mn;
+  S.pm[1] -= mn;
+}
+
+// The survivors (keys k0 < k1) replace the paths: registers, metrics and
+// slot bits from their parents, and the partial-sum words [0, W) of levels
+// >= 6 copied where a path's parent is the other rank.
+__device__ __forceinline__ void take(PS& S, const Ctx2& C, uint32_t k0, uint32_t k1, uint32_t W) {
+  const uint32_t p0 = (k0 >> 4) & 1u, p1 = (k1 >> 4) & 1u;
+  const XR r0 = S.R[0], r1 = S.R[1];
+  S.R[0] = p0 ? r1 : r0;
+  S.R[1] = p1 ? r1 : r0;
+  const uint32_t q0 = S.P[0], q1 = S.P[1];
+  S.P[0] = p0 ? q1 : q0;
+  S.P[1] = p1 ? q1 : q0;
+  S.pm[0] = 0;
+  S.pm[1] = (int)(k1 >> 8) - (int)(k0 >> 8);
+  if (p0 != 0u || p1 != 1u) {
+    uint32_t* b0 = C.bits[0];
+    uint32_t* b1 = C.bits[1];
+    for (uint32_t w = 0; w < W; ++w) {
+      const uint32_t x0 = b0[64u * w], x1 = b1[64u * w];
+      b0[64u * w] = p0 ? x1 : x0;
+      b1[64u * w] = p1 ? x1 : x0;
+    }
+  }
+}
+
+// the T = 4 least reliable positions (|alpha|, then index) of a register
+// node, as keys |alpha| << 5 | index in ascending order
+template <int K>
+__device__ __forceinline__ void least4(XR& R, uint32_t s[4]) {
+  constexpr uint32_t M = 1u << K;
+  constexpr int W = M >= 4 ? (int)M / 4 : 1;
+  s[0] = s[1] = s[2] = s[3] = 0xFFFFFFFFu;
+#pragma unroll
+  for (int j = 0; j < W; ++j)
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      if (4 * j + i < (int)M) {
+        uint32_t v = ((uint32_t)abs(sx8(xw<K>(R, j), i)) << 5) | (uint32_t)(4 * j + i);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const uint32_t lo = min(v, s[t]);
+          v = max(v, s[t]);
+          s[t] = lo;
+        }
+      }
+}
+
+// a dedicated node or leaf of level K <= 5 over the a active paths
+template <int K>
+__device__ __forceinline__ void node_reg2(PS& S, const Ctx2& C, uint32_t opc, uint32_t o,
+                                          uint32_t& a) {
+  constexpr uint32_t M = 1u << K;
+  constexpr int W = M >= 4 ? (int)M / 4 : 1;
+  constexpr uint32_t full = M == 32 ? 0xFFFFFFFFu : ((1u << M) - 1u);
+  uint32_t hd[2] = {0u, 0u}, pos[2] = {0u, 0u};
+  uint32_t k0 = 0xFFFFFFFFu, k1 = 0xFFFFFFFFu;
+#pragma unroll
+  for (uint32_t r = 0; r < 2; ++r) {
+    if (r >= a) break;
+    XR& R = S.R[r];
+    int p0 = 0, p1 = 0;  // disagreement with all-0 / all-1
+#pragma unroll
+    for (int j = 0; j < W; ++j)
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        if (4 * j + i < (int)M) {
+          const int v = sx8(xw<K>(R, j), i);
+          if (v < 0)
+            p0 -= v;
+          else
+            p1 += v;
+        }
+    uint32_t h = 0;
+#pragma unroll
+    for (int j = 0; j < W; ++j) h |= hd4(xw<K>(R, j)) << (4 * j);
+    hd[r] = h & full;
+    if (opc == OP_R0 || opc == OP_LF) {
+      S.pm[r] = min(S.pm[r] + p0, kQ);
+      R.b = 0u;
+    } else if (opc == OP_LI || opc == OP_REP) {
+      ins2(ckey(S.pm[r], (uint32_t)p0, r, 0u), k0, k1);
+      ins2(ckey(S.pm[r], (uint32_t)p1, r, 1u), k0, k1);
+    } else {
+      uint32_t s4[4];
+      least4<K>(R, s4);
+      pos[r] = (s4[0] & 31u) | ((s4[1] & 31u) << 5) | ((s4[2] & 31u) << 10) | ((s4[3] & 31u) << 15);
+      const uint32_t m0 = s4[0] >> 5, m1 = s4[1] >> 5, m2 = s4[2] >> 5, m3 = s4[3] >> 5;
+      if (opc == OP_R1) {
+#pragma unroll
+        for (uint32_t mk = 0; mk < 4; ++mk)
+          ins2(ckey(S.pm[r], ((mk & 1u) ? m0 : 0u) + ((mk & 2u) ? m1 : 0u), r, mk), k0, k1);
+      } else {
+        const uint32_t par = __popc(hd[r]) & 1u;
+#pragma unroll
+        for (uint32_t mk = 0; mk < 16; ++mk) {
+          if ((__popc(mk) & 1u) != par) continue;
+          const uint32_t pen = ((mk & 1u) ? m0 : 0u) + ((mk & 2u) ? m1 : 0u) +
+                               ((mk & 4u) ? m2 : 0u) + ((mk & 8u) ? m3 : 0u);
+          ins2(ckey(S.pm[r], pen, r, mk), k0, k1);
+        }
+      }
+    }
+  }
+  if (opc == OP_R0 || opc == OP_LF) {
+    normalise(S, a);
+    return;
+  }
+  const uint32_t W6 = (o >> 6) << 1;  // partial-sum words below the level-6 ancestor
+  const uint32_t pa0 = (k0 >> 4) & 1u, pa1 = (k1 >> 4) & 1u;
+  const uint32_t hd0 = pa0 ? hd[1] : hd[0], hd1 = pa1 ? hd[1] : hd[0];
+  const uint32_t ps0 = pa0 ? pos[1] : pos[0], ps1 = pa1 ? pos[1] : pos[0];
+  take(S, C, k0, k1, W6);
+  a = 2;
+  const uint32_t l0 = k0 & 15u, l1 = k1 & 15u;
+  if (opc == OP_LI || opc == OP_REP) {
+    S.R[0].b = l0 ? full : 0u;
+    S.R[1].b = l1 ? full : 0u;
+    return;
+  }
+  uint32_t f0 = 0, f1 = 0;
+#pragma unroll
+  for (uint32_t t = 0; t < 4; ++t) {
+    f0 |= ((l0 >> t) & 1u) << ((ps0 >> (5 * t)) & 31u);
+    f1 |= ((l1 >> t) & 1u) << ((ps1 >> (5 * t)) & 31u);
+  }
+  S.R[0].b = hd0 ^ f0;
+  S.R[1].b = hd1 ^ f1;
+}
+
+// a Rate-0 or Rate-1 node of level k >= 6 over the a active paths
+__device__ __forceinline__ void node_mem2(PS& S, const Ctx2& C, uint32_t opc, uint32_t k,
+                                          uint32_t o, uint32_t& a) {
+  const uint32_t nw = 1u << (k - 5);
+  uint32_t k0 = 0xFFFFFFFFu, k1 = 0xFFFFFFFFu, pos[2] = {0u, 0u};
+#pragma unroll
+  for (uint32_t r = 0; r < 2; ++r) {
+    if (r >= a) break;
+    const uint32_t Pr = S.P[r];
+    const Src s = k == 6 ? Src{nullptr, 0u} : src2(C, Pr, k);
+    const uint4* l = l6of(C, Pr);
+    uint32_t* w = C.bits[r] + (size_t)64u * (o >> 5);
+    int p0 = 0;
+    uint32_t s0 = 0xFFFFFFFFu, s1 = 0xFFFFFFFFu;
+    for (uint32_t q = 0; q < nw; ++q) {
+      const Chunk x0 = k == 6 ? ldl(l, 2 * q) : ldc(s.p + (size_t)(2 * q) * s.cs);
+      const Chunk x1 = k == 6 ? ldl(l, 2 * q + 1) : ldc(s.p + (size_t)(2 * q + 1) * s.cs);
+      if (opc == OP_R0) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            p0 += max(-sx8(x0.w[j], i), 0);
+            p0 += max(-sx8(x1.w[j], i), 0);
+          }
+        w[64u * q] = 0u;
+      } else {
+        w[64u * q] = hd16(x0) | (hd16(x1) << 16);
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const uint32_t e = 32u * q + 4u * j + i;
+            uint32_t v = ((uint32_t)abs(sx8(x0.w[j], i)) << 12) | e;
+            uint32_t lo = min(v, s0);
+            v = max(v, s0);
+            s0 = lo;
+            s1 = min(v, s1);
+            v = ((uint32_t)abs(sx8(x1.w[j], i)) << 12) | (e + 16u);
+            lo = min(v, s0);
+            v = max(v, s0);
+            s0 = lo;
+            s1 = min(v, s1);
+          }
+      }
+    }
+    if (opc == OP_R0) {
+      S.pm[r] = min(S.pm[r] + p0, kQ);
+    } else {
+      pos[r] = (s0 & 0xFFFu) | ((s1 & 0xFFFu) << 16);
+      const uint32_t m0 = s0 >> 12, m1 = s1 >> 12;
+#pragma unroll
+      for (uint32_t mk = 0; mk < 4; ++mk)
+        ins2(ckey(S.pm[r], ((mk & 1u) ? m0 : 0u) + ((mk & 2u) ? m1 : 0u), r, mk), k0, k1);
+    }
+  }
+  if (opc == OP_R0) {
+    normalise(S, a);
+    return;
+  }
+  const uint32_t pa0 = (k0 >> 4) & 1u, pa1 = (k1 >> 4) & 1u;
+  const uint32_t ps0 = pa0 ? pos[1] : pos[0], ps1 = pa1 ? pos[1] : pos[0];
+  take(S, C, k0, k1, (o >> 5) + nw);
+  a = 2;
+  const uint32_t l[2] = {k0 & 15u, k1 & 15u}, ps[2] = {ps0, ps1};
+#pragma unroll
+  for (uint32_t j = 0; j < 2; ++j)
+#pragma unroll
+    for (uint32_t t = 0; t < 2; ++t)
+      if ((l[j] >> t) & 1u) {
+        const uint32_t e = o + ((ps[j] >> (16 * t)) & 0xFFFu);
+        C.bits[j][64u * (e >> 5)] ^= 1u << (e & 31u);
+      }
+}
+
+__device__ __forceinline__ void reg_fgh2(PS& S, uint32_t opc, uint32_t k, uint32_t a) {
+  reg_op(S.R[0], opc, k);
+  if (a > 1) reg_op(S.R[1], opc, k);
+}
+
+__device__ __forceinline__ void node2(PS& S, const Ctx2& C, uint32_t opc, uint32_t k, uint32_t o,
+                                      uint32_t& a) {
+  switch (k) {
+    case 5: node_reg2<5>(S, C, opc, o, a); break;
+    case 4: node_reg2<4>(S, C, opc, o, a); break;
+    case 3: node_reg2<3>(S, C, opc, o, a); break;
+    case 2: node_reg2<2>(S, C, opc, o, a); break;
+    case 1: node_reg2<1>(S, C, opc, o, a); break;
+    case 0: node_reg2<0>(S, C, opc, o, a); break;
+    default: node_mem2(S, C, opc, k, o, a); break;
+  }
+}
+
 }  // namespace
 
 // A persistent grid: wave g decodes the groups of 64 frames g, g + G, ...
@@ -506,6 +868,186 @@ uint64_t scx_region_bytes(uint32_t N) {
 
 int launch_decode_scx(const KArgs& A, uint32_t grid, uint32_t* state, hipStream_t s) {
   hipLaunchKernelGGL(k_scx, dim3(grid > 0 ? grid : 1), dim3(64), 0, s, A, state);
+  return hipGetLastError() == hipSuccess ? POLAR_OK : POLAR_EHIP;
+}
+
+// Frames whose next stage is L = 2, listed for the frame-per-lane list
+// kernel: xl[0] counts them, xl[1 ..] holds their indices (in no set order).
+__global__ __launch_bounds__(256) void k_gather2(uint32_t n_frames, const uint32_t* state,
+                                                 uint32_t* xl) {
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t w0 = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const uint32_t nw = (gridDim.x * blockDim.x) >> 6;
+  for (uint32_t g = w0; 64u * g < n_frames; g += nw) {
+    const uint32_t f = 64u * g + lane;
+    const bool take = f < n_frames && state[f] == 2u;
+    const uint64_t bal = __ballot(take);
+    uint32_t base = 0;
+    if (lane == 0 && bal) base = atomicAdd(&xl[0], (uint32_t)__popcll(bal));
+    base = __shfl(base, 0, 64);
+    if (take) xl[1 + base + (uint32_t)__popcll(bal & ((1ull << lane) - 1ull))] = f;
+  }
+}
+
+// The L = 2 stage of the listed frames, 64 per wave (persistent grid, wave g
+// takes the groups g, g + G, ...).  A frame whose CRC passes, or whose plan
+// ends at L = 2, is finished (bits, status, metric list, end stamp; state 0);
+// the others get their next stage.
+__global__ __launch_bounds__(64) void k_listx2(KArgs A, uint32_t* state, const uint32_t* xl) {
+  __shared__ uint4 lds6x[2 * 4 * 64];  // level 6: two slots of 4 chunks per lane
+  const uint32_t lane = threadIdx.x;
+  const DevPlan* P = uni_ptr(A.plans[0]);
+  const uint32_t N = uni(P->N), n = uni(P->n), n_ops = uni(P->n_ops), bw = uni(P->bw);
+  const uint32_t iw = uni(A.info_words), L_max = uni(P->L_max), c_len = uni(P->c);
+  const uint32_t* prog = uni_ptr(plan_tab(P, uni(P->off_prog)));
+  const uint32_t* imask = uni_ptr(plan_tab(P, uni(P->off_infomask)));
+  const uint32_t* nib = uni_ptr(plan_tab(P, uni(P->off_crcnib)));
+  const uint32_t* dmask = uni_ptr(plan_tab(P, uni(P->off_datamask)));
+  char* region = A.spill + (size_t)blockIdx.x * A.spill_stride;
+  const uint32_t count = uni(xl[0]);
+  const uint32_t n_groups = (count + 63u) / 64u;
+  for (uint32_t q = blockIdx.x; q < n_groups; q += gridDim.x) {
+    const uint32_t idx = 64u * q + lane;
+    const bool valid = idx < count;
+    const uint32_t f = xl[1 + (valid ? idx : 64u * q)];
+    Ctx2 C;
+    C.region = region;
+    C.root = A.llr + (size_t)f * A.llr_bytes;
+    C.n = n;
+    C.lane = lane;
+    uint32_t* bb = reinterpret_cast<uint32_t*>(region + (size_t)128u * (N - 128u)) + lane;
+    C.bits[0] = bb;
+    C.bits[1] = bb + (size_t)64u * bw;
+    C.l6[0] = lds6x + lane;
+    C.l6[1] = lds6x + 4 * 64 + lane;
+    PS S;
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) S.R[r].x5[j] = 0u;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) S.R[r].x4[j] = 0u;
+      S.R[r].x3[0] = S.R[r].x3[1] = S.R[r].x2 = S.R[r].x1 = S.R[r].x0 = 0u;
+      S.R[r].b = S.R[r].lft = S.R[r].l6 = 0u;
+      S.pm[r] = 0;
+      S.P[r] = 0u;
+    }
+    uint32_t a = 1;
+    uint32_t w_next = prog[0];
+    for (uint32_t pc = 0; pc < n_ops; ++pc) {
+      const uint32_t w = uni(w_next);
+      if (pc + 1 < n_ops) w_next = prog[pc + 1];
+      const uint32_t opc = op_code(w), k = n - op_depth(w), o = op_off(w);
+      if (opc == OP_F || opc == OP_G || opc == OP_H) {
+        if (k <= 5) {
+          reg_fgh2(S, opc, k, a);
+        } else if (opc == OP_H) {
+          h2(C, 0, S.R[0], k, o);
+          if (a > 1) h2(C, 1, S.R[1], k, o);
+        } else if (k == 6) {
+          if (opc == OP_F) {
+            fg6_2<false>(C, S.P[0], S.R[0]);
+            if (a > 1) fg6_2<false>(C, S.P[1], S.R[1]);
+          } else {
+            fg6_2<true>(C, S.P[0], S.R[0]);
+            if (a > 1) fg6_2<true>(C, S.P[1], S.R[1]);
+          }
+        } else {
+          const bool g = opc == OP_G;
+#pragma unroll
+          for (uint32_t r = 0; r < 2; ++r) {
+            if (r >= a) break;
+            if (k == 7)
+              g ? fg2<true, true>(C, S.P[r], r, k, o) : fg2<false, true>(C, S.P[r], r, k, o);
+            else
+              g ? fg2<true, false>(C, S.P[r], r, k, o) : fg2<false, false>(C, S.P[r], r, k, o);
+            S.P[r] = set_slot(S.P[r], k - 1, r);
+          }
+        }
+      } else {
+        node2(S, C, opc, k, o, a);
+      }
+    }
+    // ---- CRC of each path, in metric order (rank breaks ties)
+    uint32_t syn[2] = {0u, 0u};
+    if (c_len > 0) {
+      for (uint32_t wd = 0; wd < bw; ++wd) {
+        const uint32_t im = imask[wd];
+        if (!im) continue;
+        const uint32_t v0 = C.bits[0][64u * wd] & im, v1 = C.bits[1][64u * wd] & im;
+        for (uint32_t t = 0; t < 8; ++t)
+          if ((im >> (4 * t)) & 15u) {
+            const uint32_t base = (wd * 8 + t) << 4;
+            syn[0] ^= nib[base + ((v0 >> (4 * t)) & 15u)];
+            if (a > 1) syn[1] ^= nib[base + ((v1 >> (4 * t)) & 15u)];
+          }
+      }
+    }
+    const uint32_t o0 = (a > 1 && S.pm[1] < S.pm[0]) ? 1u : 0u, o1 = 1u - o0;
+    const bool ok0 = (o0 ? syn[1] : syn[0]) == 0u;
+    const bool ok1 = a > 1 && (o1 ? syn[1] : syn[0]) == 0u;
+    const bool ok = ok0 || ok1;
+    const uint32_t ch = ok0 ? o0 : (ok1 ? o1 : o0);
+    const bool fin = valid && (ok || L_max <= 2);
+    if (valid && !fin) state[f] = next_stage(P, 2);
+    // ---- outputs of a finished frame: the chosen path's data bits
+    uint32_t* out = A.info + (size_t)f * iw;
+    const uint32_t* xb = ch ? C.bits[1] : C.bits[0];
+    uint32_t cur = 0, pos = 0, ow = 0;
+    for (uint32_t wd = 0; wd < bw; ++wd) {
+      uint32_t dm = dmask[wd];
+      if (!dm) continue;
+      const uint32_t x = xb[64u * wd];
+      uint32_t v = 0, cnt = 0;
+      while (dm) {
+        const uint32_t b = __ffs(dm) - 1;
+        v |= ((x >> b) & 1u) << cnt;
+        ++cnt;
+        dm &= dm - 1u;
+      }
+      cur |= v << pos;
+      if (pos + cnt >= 32) {
+        if (fin) out[ow] = cur;
+        ++ow;
+        cur = pos ? v >> (32 - pos) : 0u;
+      }
+      pos = (pos + cnt) & 31u;
+    }
+    if (pos && fin) out[ow] = cur;
+    if (fin) {
+      polar_status st;
+      st.crc_ok = ok ? 1 : 0;
+      st.L_used = 2;
+      st.n_paths = (uint8_t)a;
+      st.flags = 0;
+      st.pm = (uint32_t)(ch ? S.pm[1] : S.pm[0]);
+      A.status[f] = st;
+      if (A.pm_lists)
+        for (uint32_t t = 0; t < A.pm_stride; ++t) {
+          uint32_t v = 0xFFFFFFFFu;
+          if (t < a) v = (uint32_t)((t == 0 ? o0 : o1) ? S.pm[1] : S.pm[0]);
+          A.pm_lists[(size_t)f * A.pm_stride + t] = v;
+        }
+      if (A.times) A.times[2 * (size_t)f + 1] = wall_clock64();
+      state[f] = 0u;
+    }
+  }
+}
+
+// Bytes of one wave's region of the L = 2 kernel for a code of length N
+// (two slots of levels 7 .. n-1, then two partial-sum arrays), 256-aligned.
+uint64_t listx2_region_bytes(uint32_t N) {
+  const uint64_t b = 128ull * (N - 128u) + 16ull * N;
+  return (b + 255u) & ~255ull;
+}
+
+int launch_decode_listx2(const KArgs& A, uint32_t grid, uint32_t* state, uint32_t* xl,
+                         hipStream_t s) {
+  const uint32_t gb = (A.n_frames + 255u) / 256u < 1024u ? (A.n_frames + 255u) / 256u : 1024u;
+  hipLaunchKernelGGL(k_gather2, dim3(gb > 0 ? gb : 1), dim3(256), 0, s, A.n_frames,
+                     (const uint32_t*)state, xl);
+  hipLaunchKernelGGL(k_listx2, dim3(grid > 0 ? grid : 1), dim3(64), 0, s, A, state,
+                     (const uint32_t*)xl);
   return hipGetLastError() == hipSuccess ? POLAR_OK : POLAR_EHIP;
 }
 

@@ -330,6 +330,33 @@ def test_sc_tier_frame_per_lane(case):
         compare(code, llr)
 
 
+X2_CASES = [
+    # (N, K, c, poly, design dB, algo, L_max, node options, Eb/N0)
+    (256, 128, 8, 0x07, 2.0, "ca", 2, dict(), 1.0),
+    (512, 300, 11, 0x621, 2.5, "fa", 2, dict(node_enable=0), 1.5),
+    (1024, 700, 24, 0x1864CFB, 3.0, "pa", 2, dict(r1_max=0), 2.0),
+    (1024, 512, 11, 0x621, 2.0, "fa", 8, dict(spc_max=32, rep_max=32), 1.0),
+    (2048, 1723, 32, 0x04C11DB7, 4.5, "fa", 4, dict(), 3.0),
+    (256, 200, 11, 0x621, 3.0, "fa", 4, dict(node_enable=O.NODE_R0 | O.NODE_R1), 2.0),
+]
+
+
+@pytest.mark.parametrize("case", range(len(X2_CASES)))
+def test_list2_stage_frame_per_lane(case):
+    """Uniform int8 batches whose schedule has an L = 2 stage and whose REP /
+    SPC nodes fit the register levels: that stage runs one frame per lane
+    (two paths per lane) on the frames the gather lists.  A CA L = 2 code
+    (every frame), PA and FA schedules, leaves only, Rate-1 nodes up to the
+    whole code, SPC / REP up to 32 positions, at SNRs where most frames reach
+    L = 2; bits, CRC flags, list sizes, metrics and metric lists equal the
+    oracle for batches of 1, 65 and 200 frames."""
+    N, K, c, poly, design, algo, Lm, kw, eb = X2_CASES[case]
+    code = _code(N, K, c, poly, design, quant="i8", algo=algo, L=Lm, L_max=Lm, **kw)
+    for n in (1, 65, 200):
+        _, llr = make_inputs(code, n, 1300 + 7 * case + n, eb)
+        compare(code, llr)
+
+
 @pytest.mark.parametrize("quant", ["i8", "f32"])
 def test_sc_tier_frame_pairs(quant):
     """The L = 1 tier decodes two frames per wave.  Every frame of an odd-sized
