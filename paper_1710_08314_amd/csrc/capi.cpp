@@ -497,20 +497,23 @@ int plan_tiers(const Batch& b, polar::TierPlan* out) {
         tp.spill_sc = polar::scx_region_bytes(h.N);
         // the L = 2 stage the same way, when the schedule has one and every
         // REP / SPC node fits the register levels (<= 32 positions)
+        const bool fa = h.algo == POLAR_FA_SCL;
         const bool stage2 = h.first_stage == 2 ||
-                            (h.first_stage == 1 && h.max_list >= 2 &&
-                             (h.algo == POLAR_FA_SCL || h.max_list == 2));
+                            (h.first_stage == 1 && h.max_list >= 2 && (fa || h.max_list == 2));
         bool small = true;
         for (uint32_t w : hp.prog) {
           const uint32_t op = polar::op_code(w);
           if ((op == polar::OP_REP || op == polar::OP_SPC) && (h.N >> polar::op_depth(w)) > 32)
             small = false;
         }
+        // (waves per CU that its registers allow: 3 per SIMD).  The L = 4
+        // stage stays with the wave-per-frame list tier: four paths per lane
+        // took longer per group than that tier took per frame.
+        const uint32_t cap2 = 12u * (uint32_t)cus;
         if (stage2 && small) {
-          const uint32_t cap2 = 12u * (uint32_t)cus;  // its registers: 3 waves per SIMD
           tp.run_x2 = 1;
           tp.grid_x2 = groups < cap2 ? (groups ? groups : 1u) : cap2;
-          tp.spill_x2 = polar::listx2_region_bytes(h.N);
+          tp.spill_x2 = polar::listx_region_bytes(h.N, 2);
         }
       }
     }

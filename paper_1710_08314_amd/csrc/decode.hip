@@ -1278,7 +1278,6 @@ static int launch_tiered_t(const KArgs& A, const TierPlan& tp, uint32_t* state, 
                            uint32_t* xl, hipStream_t s, hipEvent_t* ev) {
   const uint32_t blocks = (A.n_frames + 255) / 256 < 2048 ? (A.n_frames + 255) / 256 : 2048;
   hipLaunchKernelGGL(k_heads_reset, dim3(1), dim3(64), 0, s, heads, 2 * kClaimSegs);
-  if (tp.run_x2) hipLaunchKernelGGL(k_heads_reset, dim3(1), dim3(64), 0, s, xl, 1u);
   hipLaunchKernelGGL(k_state_init, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, s, A, state);
   if (ev) (void)hipEventRecord(ev[0], s);
   if (tp.run_sc && tp.sc_x) {
@@ -1297,7 +1296,7 @@ static int launch_tiered_t(const KArgs& A, const TierPlan& tp, uint32_t* state, 
   if (tp.run_x2) {
     KArgs Ax = A;
     Ax.spill_stride = tp.spill_x2;
-    const int rc = launch_decode_listx2(Ax, tp.grid_x2, state, xl, s);
+    const int rc = launch_decode_listx(Ax, tp.grid_x2, state, xl, s);
     if (rc) return rc;
   }
   KArgs Aa = A, Ab = A;

@@ -56,9 +56,9 @@ struct TierPlan {
   uint32_t sc_x;              // the SC tier runs one frame per lane (k_scx)
   uint32_t grid_scx;          // its persistent grid (waves)
   uint64_t spill_sc;          // its region bytes per wave (scx_region_bytes)
-  uint32_t run_x2;            // the L = 2 stage runs one frame per lane first (k_listx2)
+  uint32_t run_x2;            // the L = 2 stage runs one frame per lane first (k_listx<2>)
   uint32_t grid_x2;           // its persistent grid (waves)
-  uint64_t spill_x2;          // its region bytes per wave (listx2_region_bytes)
+  uint64_t spill_x2;          // its region bytes per wave (listx_region_bytes)
 };
 // state: n_frames words; heads: 2 x kClaimSegs claim counters (tier A, then
 // tier B), cleared by a kernel launched before the state init.
@@ -99,15 +99,15 @@ int launch_decode_sc(uint32_t quant, const KArgs& A, uint32_t lds, uint32_t grid
 // A.spill + blockIdx.x * A.spill_stride.
 uint64_t scx_region_bytes(uint32_t N);
 constexpr uint32_t kScxLds = 4 * 1024;  // its LDS per wave (level 6)
-// The L = 2 stage with one frame per lane (scx.hip) for the same batches,
-// when the plan's REP and SPC nodes have at most 32 positions: a gather
-// kernel lists the frames whose next stage is 2 in xl (xl[0] = count, zeroed
-// by the caller), then a persistent grid of `grid` waves decodes them, each
-// wave with a region of listx2_region_bytes(N) at A.spill + blockIdx.x *
+// The stage of size L = 2 with one frame per lane (scx.hip) for the same
+// batches, when the plan's REP and SPC nodes have at most 32 positions:
+// a gather kernel lists the frames whose next stage is L in xl (xl[0] =
+// count), then a persistent grid of `grid` waves decodes them, each wave
+// with a region of listx_region_bytes(N, L) at A.spill + blockIdx.x *
 // A.spill_stride.  Finished frames get state 0, the others their next stage.
-uint64_t listx2_region_bytes(uint32_t N);
-int launch_decode_listx2(const KArgs& A, uint32_t grid, uint32_t* state, uint32_t* xl,
-                         hipStream_t s);
+uint64_t listx_region_bytes(uint32_t N, uint32_t L);
+int launch_decode_listx(const KArgs& A, uint32_t grid, uint32_t* state, uint32_t* xl,
+                        hipStream_t s);
 int launch_decode_scx(const KArgs& A, uint32_t grid, uint32_t* state, hipStream_t s);
 
 // Class schedule of a batch of fixed-list plans (no escalation): the frames

@@ -138,7 +138,7 @@ template <int K>
 __device__ __forceinline__ void reg_node(XR& R, uint32_t opc) {
   constexpr uint32_t M = 1u << K;
   constexpr int W = M >= 4 ? (int)M / 4 : 1;
-  constexpr uint32_t full = M == 32 ? 0xFFFFFFFFu : ((1u << M) - 1u);
+  constexpr uint32_t full = M == 32 ? 0xFFFFFFFFu : ((1u << (M & 31u)) - 1u);
   if (opc == OP_R0 || opc == OP_LF) {
     R.b = 0u;
     return;
@@ -382,15 +382,15 @@ __device__ __forceinline__ void reg_op(XR& R, uint32_t opc, uint32_t k) {
   }
 }
 
-// ===================================================== L = 2, one frame per lane
-// The list stage of size 2 (Algorithm 1 with the dedicated nodes of
-// Sec. II-B3 and the selection of Sec. II-B2) for the frames of a uniform
-// int8 batch whose next stage is L = 2.  Each lane holds its frame's two
-// paths; the number of active paths grows the same way in every frame (one,
-// then two after the first node that forks), so it is scalar.
+// ===================================================== L = 2: one frame per lane
+// A list stage of size L (Algorithm 1 with the dedicated nodes of Sec.
+// II-B3 and the selection of Sec. II-B2) for the frames of a uniform int8
+// batch whose next stage is L; written for L <= 4, launched for L = 2.  Each lane holds its frame's L paths;
+// the number of active paths grows the same way in every frame (a <-
+// min(L, a C) at a node with C candidates per path), so it is scalar.
 //   * Register levels (<= 32 positions) per path, as in the L = 1 kernel.
-//   * Levels >= 6: two slots per level (LDS for level 6, the wave's region
-//     above), the path of rank r reads its node from the slot its slot bit
+//   * Levels >= 6: L slots per level (LDS for level 6, the wave's region
+//     above); the path of rank r reads its node from the slot its slot bit
 //     names and writes its child to slot r (index indirection: a fork copies
 //     no LLRs).
 //   * Partial sums of levels >= 6: one N-bit array per path in the region,
@@ -399,48 +399,59 @@ __device__ __forceinline__ void reg_op(XR& R, uint32_t opc, uint32_t k) {
 // Rate-1 node the Chase-2 flips of its two least reliable positions, an SPC
 // node the flips of its four least reliable positions whose weight has the
 // parity of the hard decisions; a candidate's metric is the parent's plus
-// the flipped magnitudes, saturated at Q; the two smallest keys (metric,
+// the flipped magnitudes, saturated at Q; the L smallest keys (metric,
 // parent, local index) survive and metrics are normalised to the best.
 // The caller admits plans whose REP and SPC nodes fit in registers.
 
-struct PS {  // the two paths of a lane
-  XR R[2];
-  int pm[2];
-  uint32_t P[2];  // slot of each level k >= 6 of the path's buffers: bit k - 6
+template <int L>
+struct PS {  // the paths of a lane
+  XR R[L];
+  int pm[L];
+  uint32_t P[L];  // slot of each level k >= 6 of the path's buffers: 2 bits at 2 (k - 6)
 };
 
-struct Ctx2 {
+template <int L>
+struct CtxL {
   char* region;      // this wave's region
   const char* root;  // this lane's channel LLRs
   uint32_t n, lane;
-  uint32_t* bits[2];  // partial-sum words of path r: word w at bits[r][64 w]
-  uint4* l6[2];       // LDS slot s of level 6 for this lane: chunk c at l6[s][64 c]
+  uint32_t* bits[L];  // partial-sum words of path r: word w at bits[r][64 w]
+  uint4* l6[L];       // LDS slot s of level 6 for this lane: chunk c at l6[s][64 c]
 };
 
-// level k in 7 .. n-1: two slots of 64 2^k bytes, at 128 (2^k - 128)
-__device__ __forceinline__ char* lbuf2(const Ctx2& C, uint32_t k, uint32_t s) {
-  return C.region + (size_t)128u * ((1u << k) - 128u) + (size_t)s * (64u << k) + 16u * C.lane;
+// level k in 7 .. n-1: L slots of 64 2^k bytes, at 64 L (2^k - 128)
+template <int L>
+__device__ __forceinline__ char* lbuf(const CtxL<L>& C, uint32_t k, uint32_t s) {
+  return C.region + (size_t)(64u * L) * ((1u << k) - 128u) + (size_t)s * (64u << k) + 16u * C.lane;
+}
+__device__ __forceinline__ uint32_t slot_of(uint32_t Pr, uint32_t k) { return (Pr >> (2 * (k - 6))) & 3u; }
+__device__ __forceinline__ uint32_t set_slot(uint32_t Pr, uint32_t k, uint32_t r) {
+  return (Pr & ~(3u << (2 * (k - 6)))) | (r << (2 * (k - 6)));
 }
 // the node of level k >= 7 of a path with slot bits Pr
-__device__ __forceinline__ Src src2(const Ctx2& C, uint32_t Pr, uint32_t k) {
+template <int L>
+__device__ __forceinline__ Src srcL(const CtxL<L>& C, uint32_t Pr, uint32_t k) {
   if (k == C.n) return Src{C.root, 16u};
-  return Src{lbuf2(C, k, (Pr >> (k - 6)) & 1u), 1024u};
+  return Src{lbuf<L>(C, k, slot_of(Pr, k)), 1024u};
 }
-__device__ __forceinline__ const uint4* l6of(const Ctx2& C, uint32_t Pr) {
-  return (Pr & 1u) ? C.l6[1] : C.l6[0];
-}
-__device__ __forceinline__ uint32_t set_slot(uint32_t Pr, uint32_t k, uint32_t r) {
-  return (Pr & ~(1u << (k - 6))) | (r << (k - 6));
+template <int L>
+__device__ __forceinline__ const uint4* l6of(const CtxL<L>& C, uint32_t Pr) {
+  const uint32_t s = slot_of(Pr, 6);
+  const uint4* p = C.l6[0];
+#pragma unroll
+  for (int i = 1; i < L; ++i) p = s == (uint32_t)i ? C.l6[i] : p;
+  return p;
 }
 
 // f / g of path r's split node of level k >= 7 into its own slot of level k - 1
-template <bool G, bool DL>
-__device__ __forceinline__ void fg2(const Ctx2& C, uint32_t Pr, uint32_t r, uint32_t k, uint32_t o) {
-  const Src s = src2(C, Pr, k);
+template <int L, bool G, bool DL>
+__device__ __forceinline__ void fgL(const CtxL<L>& C, uint32_t Pr, uint32_t r, uint32_t k,
+                                    uint32_t o) {
+  const Src s = srcL<L>(C, Pr, k);
   const uint32_t nc = 1u << (k - 5);
   const char* pa = s.p;
   const char* pb = s.p + (size_t)nc * s.cs;
-  char* dst = DL ? nullptr : lbuf2(C, k - 1, r);
+  char* dst = DL ? nullptr : lbuf<L>(C, k - 1, r);
   uint4* dl = C.l6[r];
   const uint32_t* lb = C.bits[r] + (size_t)64u * (o >> 5);
   for (uint32_t c = 0; c < nc; c += 2) {
@@ -471,10 +482,10 @@ __device__ __forceinline__ void fg2(const Ctx2& C, uint32_t Pr, uint32_t r, uint
   }
 }
 
-// f / g of path r's split node of level 6 into its level-5 registers
-template <bool G>
-__device__ __forceinline__ void fg6_2(const Ctx2& C, uint32_t Pr, XR& R) {
-  const uint4* l = l6of(C, Pr);
+// f / g of a path's split node of level 6 into its level-5 registers
+template <int L, bool G>
+__device__ __forceinline__ void fg6L(const CtxL<L>& C, uint32_t Pr, XR& R) {
+  const uint4* l = l6of<L>(C, Pr);
   const Chunk a0 = ldl(l, 0), a1 = ldl(l, 1), b0 = ldl(l, 2), b1 = ldl(l, 3);
   if constexpr (G) R.l6 = R.b;
 #pragma unroll
@@ -490,7 +501,9 @@ __device__ __forceinline__ void fg6_2(const Ctx2& C, uint32_t Pr, XR& R) {
 }
 
 // h of path r's split node of level k >= 6
-__device__ __forceinline__ void h2(const Ctx2& C, uint32_t r, const XR& R, uint32_t k, uint32_t o) {
+template <int L>
+__device__ __forceinline__ void hL(const CtxL<L>& C, uint32_t r, const XR& R, uint32_t k,
+                                   uint32_t o) {
   uint32_t* w = C.bits[r] + (size_t)64u * (o >> 5);
   if (k == 6) {
     w[0] = R.l6 ^ R.b;
@@ -502,42 +515,76 @@ __device__ __forceinline__ void h2(const Ctx2& C, uint32_t r, const XR& R, uint3
   for (uint32_t i = 0; i < nw; ++i) w[64u * i] ^= q[64u * i];
 }
 
-// keep the two smallest keys
-__device__ __forceinline__ void ins2(uint32_t key, uint32_t& k0, uint32_t& k1) {
-  const uint32_t lo = min(key, k0), hi = max(key, k0);
-  k0 = lo;
-  k1 = min(k1, hi);
+// keep the L smallest keys, ascending
+template <int L>
+__device__ __forceinline__ void insL(uint32_t key, uint32_t (&kk)[L]) {
+#pragma unroll
+  for (int t = 0; t < L; ++t) {
+    const uint32_t lo = min(key, kk[t]);
+    key = max(key, kk[t]);
+    kk[t] = lo;
+  }
 }
 __device__ __forceinline__ uint32_t ckey(int pm, uint32_t pen, uint32_t r, uint32_t local) {
   const int v = min(pm + (int)pen, kQ);
   return ((uint32_t)v << 8) | (r << 4) | local;
 }
-__device__ __forceinline__ void normalise(PS& S, uint32_t a) {
-  const int mn = a > 1 ? min(S.pm[0], S.pm[1]) : S.pm[0];
-  S.pm[0] -= mn;
-  S.pm[1] -= mn;
+template <int L>
+__device__ __forceinline__ void normalise(PS<L>& S, uint32_t a) {
+  int mn = S.pm[0];
+#pragma unroll
+  for (int r = 1; r < L; ++r)
+    if ((uint32_t)r < a) mn = min(mn, S.pm[r]);
+#pragma unroll
+  for (int r = 0; r < L; ++r) S.pm[r] -= mn;
+}
+// element i of a small per-path array by a lane-varying index
+template <int L, class V>
+__device__ __forceinline__ V pick(const V (&v)[L], uint32_t i) {
+  V x = v[0];
+#pragma unroll
+  for (int t = 1; t < L; ++t) x = i == (uint32_t)t ? v[t] : x;
+  return x;
 }
 
-// The survivors (keys k0 < k1) replace the paths: registers, metrics and
-// slot bits from their parents, and the partial-sum words [0, W) of levels
-// >= 6 copied where a path's parent is the other rank.
-__device__ __forceinline__ void take(PS& S, const Ctx2& C, uint32_t k0, uint32_t k1, uint32_t W) {
-  const uint32_t p0 = (k0 >> 4) & 1u, p1 = (k1 >> 4) & 1u;
-  const XR r0 = S.R[0], r1 = S.R[1];
-  S.R[0] = p0 ? r1 : r0;
-  S.R[1] = p1 ? r1 : r0;
-  const uint32_t q0 = S.P[0], q1 = S.P[1];
-  S.P[0] = p0 ? q1 : q0;
-  S.P[1] = p1 ? q1 : q0;
-  S.pm[0] = 0;
-  S.pm[1] = (int)(k1 >> 8) - (int)(k0 >> 8);
-  if (p0 != 0u || p1 != 1u) {
-    uint32_t* b0 = C.bits[0];
-    uint32_t* b1 = C.bits[1];
+// The survivors (keys kk[0 .. keep)) replace the paths: registers, metrics
+// and slot bits from their parents, and the partial-sum words [0, W) of
+// levels >= 6 copied where a path's parent is another rank.
+template <int L>
+__device__ __forceinline__ void take(PS<L>& S, const CtxL<L>& C, const uint32_t (&kk)[L],
+                                     uint32_t keep, uint32_t W) {
+  uint32_t p[L];
+  bool moved = false;
+#pragma unroll
+  for (int j = 0; j < L; ++j) {
+    p[j] = (uint32_t)j < keep ? (kk[j] >> 4) & 3u : (uint32_t)j;
+    moved = moved || p[j] != (uint32_t)j;
+  }
+  XR old[L];
+  uint32_t oP[L];
+#pragma unroll
+  for (int i = 0; i < L; ++i) {
+    old[i] = S.R[i];
+    oP[i] = S.P[i];
+  }
+#pragma unroll
+  for (int j = 0; j < L; ++j) {
+    XR t = old[0];
+#pragma unroll
+    for (int i = 1; i < L; ++i)
+      if (p[j] == (uint32_t)i) t = old[i];
+    S.R[j] = t;
+    S.P[j] = pick<L>(oP, p[j]);
+    S.pm[j] = (uint32_t)j < keep ? (int)(kk[j] >> 8) - (int)(kk[0] >> 8) : 0;
+  }
+  if (moved) {
     for (uint32_t w = 0; w < W; ++w) {
-      const uint32_t x0 = b0[64u * w], x1 = b1[64u * w];
-      b0[64u * w] = p0 ? x1 : x0;
-      b1[64u * w] = p1 ? x1 : x0;
+      uint32_t x[L];
+#pragma unroll
+      for (int i = 0; i < L; ++i) x[i] = C.bits[i][64u * w];
+#pragma unroll
+      for (int j = 0; j < L; ++j)
+        if (p[j] != (uint32_t)j) C.bits[j][64u * w] = pick<L>(x, p[j]);
     }
   }
 }
@@ -564,17 +611,26 @@ __device__ __forceinline__ void least4(XR& R, uint32_t s[4]) {
       }
 }
 
+// candidates per path of a forking node
+__device__ __forceinline__ uint32_t n_cands(uint32_t opc) {
+  return opc == OP_SPC ? 8u : (opc == OP_R1 ? 4u : 2u);
+}
+
 // a dedicated node or leaf of level K <= 5 over the a active paths
-template <int K>
-__device__ __forceinline__ void node_reg2(PS& S, const Ctx2& C, uint32_t opc, uint32_t o,
+template <int L, int K>
+__device__ __forceinline__ void node_regL(PS<L>& S, const CtxL<L>& C, uint32_t opc, uint32_t o,
                                           uint32_t& a) {
   constexpr uint32_t M = 1u << K;
   constexpr int W = M >= 4 ? (int)M / 4 : 1;
-  constexpr uint32_t full = M == 32 ? 0xFFFFFFFFu : ((1u << M) - 1u);
-  uint32_t hd[2] = {0u, 0u}, pos[2] = {0u, 0u};
-  uint32_t k0 = 0xFFFFFFFFu, k1 = 0xFFFFFFFFu;
+  constexpr uint32_t full = M == 32 ? 0xFFFFFFFFu : ((1u << (M & 31u)) - 1u);
+  uint32_t hd[L], pos[L], kk[L];
 #pragma unroll
-  for (uint32_t r = 0; r < 2; ++r) {
+  for (int r = 0; r < L; ++r) {
+    hd[r] = pos[r] = 0u;
+    kk[r] = 0xFFFFFFFFu;
+  }
+#pragma unroll
+  for (uint32_t r = 0; r < (uint32_t)L; ++r) {
     if (r >= a) break;
     XR& R = S.R[r];
     int p0 = 0, p1 = 0;  // disagreement with all-0 / all-1
@@ -597,8 +653,8 @@ __device__ __forceinline__ void node_reg2(PS& S, const Ctx2& C, uint32_t opc, ui
       S.pm[r] = min(S.pm[r] + p0, kQ);
       R.b = 0u;
     } else if (opc == OP_LI || opc == OP_REP) {
-      ins2(ckey(S.pm[r], (uint32_t)p0, r, 0u), k0, k1);
-      ins2(ckey(S.pm[r], (uint32_t)p1, r, 1u), k0, k1);
+      insL<L>(ckey(S.pm[r], (uint32_t)p0, r, 0u), kk);
+      insL<L>(ckey(S.pm[r], (uint32_t)p1, r, 1u), kk);
     } else {
       uint32_t s4[4];
       least4<K>(R, s4);
@@ -607,7 +663,7 @@ __device__ __forceinline__ void node_reg2(PS& S, const Ctx2& C, uint32_t opc, ui
       if (opc == OP_R1) {
 #pragma unroll
         for (uint32_t mk = 0; mk < 4; ++mk)
-          ins2(ckey(S.pm[r], ((mk & 1u) ? m0 : 0u) + ((mk & 2u) ? m1 : 0u), r, mk), k0, k1);
+          insL<L>(ckey(S.pm[r], ((mk & 1u) ? m0 : 0u) + ((mk & 2u) ? m1 : 0u), r, mk), kk);
       } else {
         const uint32_t par = __popc(hd[r]) & 1u;
 #pragma unroll
@@ -615,48 +671,53 @@ __device__ __forceinline__ void node_reg2(PS& S, const Ctx2& C, uint32_t opc, ui
           if ((__popc(mk) & 1u) != par) continue;
           const uint32_t pen = ((mk & 1u) ? m0 : 0u) + ((mk & 2u) ? m1 : 0u) +
                                ((mk & 4u) ? m2 : 0u) + ((mk & 8u) ? m3 : 0u);
-          ins2(ckey(S.pm[r], pen, r, mk), k0, k1);
+          insL<L>(ckey(S.pm[r], pen, r, mk), kk);
         }
       }
     }
   }
   if (opc == OP_R0 || opc == OP_LF) {
-    normalise(S, a);
+    normalise<L>(S, a);
     return;
   }
-  const uint32_t W6 = (o >> 6) << 1;  // partial-sum words below the level-6 ancestor
-  const uint32_t pa0 = (k0 >> 4) & 1u, pa1 = (k1 >> 4) & 1u;
-  const uint32_t hd0 = pa0 ? hd[1] : hd[0], hd1 = pa1 ? hd[1] : hd[0];
-  const uint32_t ps0 = pa0 ? pos[1] : pos[0], ps1 = pa1 ? pos[1] : pos[0];
-  take(S, C, k0, k1, W6);
-  a = 2;
-  const uint32_t l0 = k0 & 15u, l1 = k1 & 15u;
-  if (opc == OP_LI || opc == OP_REP) {
-    S.R[0].b = l0 ? full : 0u;
-    S.R[1].b = l1 ? full : 0u;
-    return;
-  }
-  uint32_t f0 = 0, f1 = 0;
+  const uint32_t keep = min((uint32_t)L, a * n_cands(opc));
+  uint32_t nb[L];
 #pragma unroll
-  for (uint32_t t = 0; t < 4; ++t) {
-    f0 |= ((l0 >> t) & 1u) << ((ps0 >> (5 * t)) & 31u);
-    f1 |= ((l1 >> t) & 1u) << ((ps1 >> (5 * t)) & 31u);
+  for (int j = 0; j < L; ++j) {
+    const uint32_t pj = (kk[j] >> 4) & 3u, lj = kk[j] & 15u;
+    if (opc == OP_LI || opc == OP_REP) {
+      nb[j] = lj ? full : 0u;
+    } else {
+      const uint32_t ps = pick<L>(pos, pj);
+      uint32_t fl = 0;
+#pragma unroll
+      for (uint32_t t = 0; t < 4; ++t) fl |= ((lj >> t) & 1u) << ((ps >> (5 * t)) & 31u);
+      nb[j] = pick<L>(hd, pj) ^ fl;
+    }
   }
-  S.R[0].b = hd0 ^ f0;
-  S.R[1].b = hd1 ^ f1;
+  take<L>(S, C, kk, keep, (o >> 6) << 1);  // words below the level-6 ancestor
+  a = keep;
+#pragma unroll
+  for (int j = 0; j < L; ++j) S.R[j].b = nb[j];
 }
 
 // a Rate-0 or Rate-1 node of level k >= 6 over the a active paths
-__device__ __forceinline__ void node_mem2(PS& S, const Ctx2& C, uint32_t opc, uint32_t k,
+template <int L>
+__device__ __forceinline__ void node_memL(PS<L>& S, const CtxL<L>& C, uint32_t opc, uint32_t k,
                                           uint32_t o, uint32_t& a) {
   const uint32_t nw = 1u << (k - 5);
-  uint32_t k0 = 0xFFFFFFFFu, k1 = 0xFFFFFFFFu, pos[2] = {0u, 0u};
+  uint32_t kk[L], pos[L];
 #pragma unroll
-  for (uint32_t r = 0; r < 2; ++r) {
+  for (int r = 0; r < L; ++r) {
+    kk[r] = 0xFFFFFFFFu;
+    pos[r] = 0u;
+  }
+#pragma unroll
+  for (uint32_t r = 0; r < (uint32_t)L; ++r) {
     if (r >= a) break;
     const uint32_t Pr = S.P[r];
-    const Src s = k == 6 ? Src{nullptr, 0u} : src2(C, Pr, k);
-    const uint4* l = l6of(C, Pr);
+    const Src s = k == 6 ? Src{nullptr, 0u} : srcL<L>(C, Pr, k);
+    const uint4* l = l6of<L>(C, Pr);
     uint32_t* w = C.bits[r] + (size_t)64u * (o >> 5);
     int p0 = 0;
     uint32_t s0 = 0xFFFFFFFFu, s1 = 0xFFFFFFFFu;
@@ -699,43 +760,45 @@ __device__ __forceinline__ void node_mem2(PS& S, const Ctx2& C, uint32_t opc, ui
       const uint32_t m0 = s0 >> 12, m1 = s1 >> 12;
 #pragma unroll
       for (uint32_t mk = 0; mk < 4; ++mk)
-        ins2(ckey(S.pm[r], ((mk & 1u) ? m0 : 0u) + ((mk & 2u) ? m1 : 0u), r, mk), k0, k1);
+        insL<L>(ckey(S.pm[r], ((mk & 1u) ? m0 : 0u) + ((mk & 2u) ? m1 : 0u), r, mk), kk);
     }
   }
   if (opc == OP_R0) {
-    normalise(S, a);
+    normalise<L>(S, a);
     return;
   }
-  const uint32_t pa0 = (k0 >> 4) & 1u, pa1 = (k1 >> 4) & 1u;
-  const uint32_t ps0 = pa0 ? pos[1] : pos[0], ps1 = pa1 ? pos[1] : pos[0];
-  take(S, C, k0, k1, (o >> 5) + nw);
-  a = 2;
-  const uint32_t l[2] = {k0 & 15u, k1 & 15u}, ps[2] = {ps0, ps1};
+  const uint32_t keep = min((uint32_t)L, a * 4u);
+  uint32_t ps[L], lj[L];
 #pragma unroll
-  for (uint32_t j = 0; j < 2; ++j)
+  for (int j = 0; j < L; ++j) {
+    ps[j] = pick<L>(pos, (kk[j] >> 4) & 3u);
+    lj[j] = kk[j] & 15u;
+  }
+  take<L>(S, C, kk, keep, (o >> 5) + nw);
+  a = keep;
+#pragma unroll
+  for (uint32_t j = 0; j < (uint32_t)L; ++j) {
+    if (j >= keep) break;
 #pragma unroll
     for (uint32_t t = 0; t < 2; ++t)
-      if ((l[j] >> t) & 1u) {
+      if ((lj[j] >> t) & 1u) {
         const uint32_t e = o + ((ps[j] >> (16 * t)) & 0xFFFu);
         C.bits[j][64u * (e >> 5)] ^= 1u << (e & 31u);
       }
+  }
 }
 
-__device__ __forceinline__ void reg_fgh2(PS& S, uint32_t opc, uint32_t k, uint32_t a) {
-  reg_op(S.R[0], opc, k);
-  if (a > 1) reg_op(S.R[1], opc, k);
-}
-
-__device__ __forceinline__ void node2(PS& S, const Ctx2& C, uint32_t opc, uint32_t k, uint32_t o,
-                                      uint32_t& a) {
+template <int L>
+__device__ __forceinline__ void nodeL(PS<L>& S, const CtxL<L>& C, uint32_t opc, uint32_t k,
+                                      uint32_t o, uint32_t& a) {
   switch (k) {
-    case 5: node_reg2<5>(S, C, opc, o, a); break;
-    case 4: node_reg2<4>(S, C, opc, o, a); break;
-    case 3: node_reg2<3>(S, C, opc, o, a); break;
-    case 2: node_reg2<2>(S, C, opc, o, a); break;
-    case 1: node_reg2<1>(S, C, opc, o, a); break;
-    case 0: node_reg2<0>(S, C, opc, o, a); break;
-    default: node_mem2(S, C, opc, k, o, a); break;
+    case 5: node_regL<L, 5>(S, C, opc, o, a); break;
+    case 4: node_regL<L, 4>(S, C, opc, o, a); break;
+    case 3: node_regL<L, 3>(S, C, opc, o, a); break;
+    case 2: node_regL<L, 2>(S, C, opc, o, a); break;
+    case 1: node_regL<L, 1>(S, C, opc, o, a); break;
+    case 0: node_regL<L, 0>(S, C, opc, o, a); break;
+    default: node_memL<L>(S, C, opc, k, o, a); break;
   }
 }
 
@@ -871,16 +934,20 @@ int launch_decode_scx(const KArgs& A, uint32_t grid, uint32_t* state, hipStream_
   return hipGetLastError() == hipSuccess ? POLAR_OK : POLAR_EHIP;
 }
 
-// Frames whose next stage is L = 2, listed for the frame-per-lane list
-// kernel: xl[0] counts them, xl[1 ..] holds their indices (in no set order).
-__global__ __launch_bounds__(256) void k_gather2(uint32_t n_frames, const uint32_t* state,
-                                                 uint32_t* xl) {
+// Frames whose next stage is L, listed for the frame-per-lane list kernel:
+// xl[0] counts them (zeroed by k_xreset first), xl[1 ..] holds their indices
+// (in no set order).
+__global__ void k_xreset(uint32_t* xl) {
+  if (threadIdx.x == 0) xl[0] = 0u;
+}
+__global__ __launch_bounds__(256) void k_gather(uint32_t n_frames, uint32_t L, const uint32_t* state,
+                                                uint32_t* xl) {
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t w0 = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const uint32_t nw = (gridDim.x * blockDim.x) >> 6;
   for (uint32_t g = w0; 64u * g < n_frames; g += nw) {
     const uint32_t f = 64u * g + lane;
-    const bool take = f < n_frames && state[f] == 2u;
+    const bool take = f < n_frames && state[f] == L;
     const uint64_t bal = __ballot(take);
     uint32_t base = 0;
     if (lane == 0 && bal) base = atomicAdd(&xl[0], (uint32_t)__popcll(bal));
@@ -889,12 +956,13 @@ __global__ __launch_bounds__(256) void k_gather2(uint32_t n_frames, const uint32
   }
 }
 
-// The L = 2 stage of the listed frames, 64 per wave (persistent grid, wave g
-// takes the groups g, g + G, ...).  A frame whose CRC passes, or whose plan
-// ends at L = 2, is finished (bits, status, metric list, end stamp; state 0);
-// the others get their next stage.
-__global__ __launch_bounds__(64) void k_listx2(KArgs A, uint32_t* state, const uint32_t* xl) {
-  __shared__ uint4 lds6x[2 * 4 * 64];  // level 6: two slots of 4 chunks per lane
+// The stage of size L of the listed frames, 64 per wave (persistent grid,
+// wave g takes the groups g, g + G, ...).  A frame whose CRC passes, or whose
+// plan ends at L, is finished (bits, status, metric list, end stamp; state
+// 0); the others get their next stage.
+template <int L>
+__global__ __launch_bounds__(64) void k_listx(KArgs A, uint32_t* state, const uint32_t* xl) {
+  __shared__ uint4 lds6x[L * 4 * 64];  // level 6: L slots of 4 chunks per lane
   const uint32_t lane = threadIdx.x;
   const DevPlan* P = uni_ptr(A.plans[0]);
   const uint32_t N = uni(P->N), n = uni(P->n), n_ops = uni(P->n_ops), bw = uni(P->bw);
@@ -910,19 +978,17 @@ __global__ __launch_bounds__(64) void k_listx2(KArgs A, uint32_t* state, const u
     const uint32_t idx = 64u * q + lane;
     const bool valid = idx < count;
     const uint32_t f = xl[1 + (valid ? idx : 64u * q)];
-    Ctx2 C;
+    CtxL<L> C;
     C.region = region;
     C.root = A.llr + (size_t)f * A.llr_bytes;
     C.n = n;
     C.lane = lane;
-    uint32_t* bb = reinterpret_cast<uint32_t*>(region + (size_t)128u * (N - 128u)) + lane;
-    C.bits[0] = bb;
-    C.bits[1] = bb + (size_t)64u * bw;
-    C.l6[0] = lds6x + lane;
-    C.l6[1] = lds6x + 4 * 64 + lane;
-    PS S;
+    uint32_t* bb = reinterpret_cast<uint32_t*>(region + (size_t)(64u * L) * (N - 128u)) + lane;
+    PS<L> S;
 #pragma unroll
-    for (int r = 0; r < 2; ++r) {
+    for (int r = 0; r < L; ++r) {
+      C.bits[r] = bb + (size_t)r * 64u * bw;
+      C.l6[r] = lds6x + r * 4 * 64 + lane;
 #pragma unroll
       for (int j = 0; j < 8; ++j) S.R[r].x5[j] = 0u;
 #pragma unroll
@@ -939,60 +1005,69 @@ __global__ __launch_bounds__(64) void k_listx2(KArgs A, uint32_t* state, const u
       if (pc + 1 < n_ops) w_next = prog[pc + 1];
       const uint32_t opc = op_code(w), k = n - op_depth(w), o = op_off(w);
       if (opc == OP_F || opc == OP_G || opc == OP_H) {
-        if (k <= 5) {
-          reg_fgh2(S, opc, k, a);
-        } else if (opc == OP_H) {
-          h2(C, 0, S.R[0], k, o);
-          if (a > 1) h2(C, 1, S.R[1], k, o);
-        } else if (k == 6) {
-          if (opc == OP_F) {
-            fg6_2<false>(C, S.P[0], S.R[0]);
-            if (a > 1) fg6_2<false>(C, S.P[1], S.R[1]);
-          } else {
-            fg6_2<true>(C, S.P[0], S.R[0]);
-            if (a > 1) fg6_2<true>(C, S.P[1], S.R[1]);
-          }
-        } else {
-          const bool g = opc == OP_G;
+        const bool g = opc == OP_G;
 #pragma unroll
-          for (uint32_t r = 0; r < 2; ++r) {
-            if (r >= a) break;
+        for (uint32_t r = 0; r < (uint32_t)L; ++r) {
+          if (r >= a) break;
+          if (k <= 5) {
+            reg_op(S.R[r], opc, k);
+          } else if (opc == OP_H) {
+            hL<L>(C, r, S.R[r], k, o);
+          } else if (k == 6) {
+            g ? fg6L<L, true>(C, S.P[r], S.R[r]) : fg6L<L, false>(C, S.P[r], S.R[r]);
+          } else {
             if (k == 7)
-              g ? fg2<true, true>(C, S.P[r], r, k, o) : fg2<false, true>(C, S.P[r], r, k, o);
+              g ? fgL<L, true, true>(C, S.P[r], r, k, o) : fgL<L, false, true>(C, S.P[r], r, k, o);
             else
-              g ? fg2<true, false>(C, S.P[r], r, k, o) : fg2<false, false>(C, S.P[r], r, k, o);
+              g ? fgL<L, true, false>(C, S.P[r], r, k, o) : fgL<L, false, false>(C, S.P[r], r, k, o);
             S.P[r] = set_slot(S.P[r], k - 1, r);
           }
         }
       } else {
-        node2(S, C, opc, k, o, a);
+        nodeL<L>(S, C, opc, k, o, a);
       }
     }
     // ---- CRC of each path, in metric order (rank breaks ties)
-    uint32_t syn[2] = {0u, 0u};
+    uint32_t syn[L], ord[L];
+#pragma unroll
+    for (int r = 0; r < L; ++r) {
+      syn[r] = 0u;
+      ord[r] = 0xFFFFFFFFu;
+    }
+#pragma unroll
+    for (uint32_t r = 0; r < (uint32_t)L; ++r)
+      if (r < a) insL<L>(((uint32_t)S.pm[r] << 2) | r, ord);
     if (c_len > 0) {
       for (uint32_t wd = 0; wd < bw; ++wd) {
         const uint32_t im = imask[wd];
         if (!im) continue;
-        const uint32_t v0 = C.bits[0][64u * wd] & im, v1 = C.bits[1][64u * wd] & im;
+        uint32_t v[L];
+#pragma unroll
+        for (int r = 0; r < L; ++r) v[r] = C.bits[r][64u * wd] & im;
         for (uint32_t t = 0; t < 8; ++t)
           if ((im >> (4 * t)) & 15u) {
             const uint32_t base = (wd * 8 + t) << 4;
-            syn[0] ^= nib[base + ((v0 >> (4 * t)) & 15u)];
-            if (a > 1) syn[1] ^= nib[base + ((v1 >> (4 * t)) & 15u)];
+#pragma unroll
+            for (uint32_t r = 0; r < (uint32_t)L; ++r)
+              if (r < a) syn[r] ^= nib[base + ((v[r] >> (4 * t)) & 15u)];
           }
       }
     }
-    const uint32_t o0 = (a > 1 && S.pm[1] < S.pm[0]) ? 1u : 0u, o1 = 1u - o0;
-    const bool ok0 = (o0 ? syn[1] : syn[0]) == 0u;
-    const bool ok1 = a > 1 && (o1 ? syn[1] : syn[0]) == 0u;
-    const bool ok = ok0 || ok1;
-    const uint32_t ch = ok0 ? o0 : (ok1 ? o1 : o0);
-    const bool fin = valid && (ok || L_max <= 2);
-    if (valid && !fin) state[f] = next_stage(P, 2);
+    uint32_t ch = ord[0] & 3u;
+    bool ok = false;
+#pragma unroll
+    for (int t = L - 1; t >= 0; --t) {
+      const uint32_t r = ord[t] & 3u;
+      if ((uint32_t)t < a && pick<L>(syn, r) == 0u) {
+        ch = r;
+        ok = true;
+      }
+    }
+    const bool fin = valid && (ok || L_max <= (uint32_t)L);
+    if (valid && !fin) state[f] = next_stage(P, L);
     // ---- outputs of a finished frame: the chosen path's data bits
     uint32_t* out = A.info + (size_t)f * iw;
-    const uint32_t* xb = ch ? C.bits[1] : C.bits[0];
+    const uint32_t* xb = pick<L>(C.bits, ch);
     uint32_t cur = 0, pos = 0, ow = 0;
     for (uint32_t wd = 0; wd < bw; ++wd) {
       uint32_t dm = dmask[wd];
@@ -1017,15 +1092,15 @@ __global__ __launch_bounds__(64) void k_listx2(KArgs A, uint32_t* state, const u
     if (fin) {
       polar_status st;
       st.crc_ok = ok ? 1 : 0;
-      st.L_used = 2;
+      st.L_used = (uint8_t)L;
       st.n_paths = (uint8_t)a;
       st.flags = 0;
-      st.pm = (uint32_t)(ch ? S.pm[1] : S.pm[0]);
+      st.pm = (uint32_t)pick<L>(S.pm, ch);
       A.status[f] = st;
       if (A.pm_lists)
         for (uint32_t t = 0; t < A.pm_stride; ++t) {
           uint32_t v = 0xFFFFFFFFu;
-          if (t < a) v = (uint32_t)((t == 0 ? o0 : o1) ? S.pm[1] : S.pm[0]);
+          if (t < a) v = pick<L>(ord, t) >> 2;
           A.pm_lists[(size_t)f * A.pm_stride + t] = v;
         }
       if (A.times) A.times[2 * (size_t)f + 1] = wall_clock64();
@@ -1034,19 +1109,21 @@ __global__ __launch_bounds__(64) void k_listx2(KArgs A, uint32_t* state, const u
   }
 }
 
-// Bytes of one wave's region of the L = 2 kernel for a code of length N
-// (two slots of levels 7 .. n-1, then two partial-sum arrays), 256-aligned.
-uint64_t listx2_region_bytes(uint32_t N) {
-  const uint64_t b = 128ull * (N - 128u) + 16ull * N;
+// Bytes of one wave's region of the list kernel of size L for a code of
+// length N (L slots of levels 7 .. n-1, then L partial-sum arrays),
+// 256-byte aligned.
+uint64_t listx_region_bytes(uint32_t N, uint32_t L) {
+  const uint64_t b = 64ull * L * (N - 128u) + 8ull * L * N;
   return (b + 255u) & ~255ull;
 }
 
-int launch_decode_listx2(const KArgs& A, uint32_t grid, uint32_t* state, uint32_t* xl,
-                         hipStream_t s) {
+int launch_decode_listx(const KArgs& A, uint32_t grid, uint32_t* state, uint32_t* xl,
+                        hipStream_t s) {
   const uint32_t gb = (A.n_frames + 255u) / 256u < 1024u ? (A.n_frames + 255u) / 256u : 1024u;
-  hipLaunchKernelGGL(k_gather2, dim3(gb > 0 ? gb : 1), dim3(256), 0, s, A.n_frames,
+  hipLaunchKernelGGL(k_xreset, dim3(1), dim3(64), 0, s, xl);
+  hipLaunchKernelGGL(k_gather, dim3(gb > 0 ? gb : 1), dim3(256), 0, s, A.n_frames, 2u,
                      (const uint32_t*)state, xl);
-  hipLaunchKernelGGL(k_listx2, dim3(grid > 0 ? grid : 1), dim3(64), 0, s, A, state,
+  hipLaunchKernelGGL(k_listx<2>, dim3(grid > 0 ? grid : 1), dim3(64), 0, s, A, state,
                      (const uint32_t*)xl);
   return hipGetLastError() == hipSuccess ? POLAR_OK : POLAR_EHIP;
 }

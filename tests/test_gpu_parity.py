@@ -338,6 +338,8 @@ X2_CASES = [
     (1024, 512, 11, 0x621, 2.0, "fa", 8, dict(spc_max=32, rep_max=32), 1.0),
     (2048, 1723, 32, 0x04C11DB7, 4.5, "fa", 4, dict(), 3.0),
     (256, 200, 11, 0x621, 3.0, "fa", 4, dict(node_enable=O.NODE_R0 | O.NODE_R1), 2.0),
+    (256, 128, 8, 0x07, 2.0, "ca", 4, dict(), 1.0),
+    (512, 256, 11, 0x621, 2.0, "pa", 4, dict(node_enable=0), 1.5),
 ]
 
 
@@ -345,11 +347,13 @@ X2_CASES = [
 def test_list2_stage_frame_per_lane(case):
     """Uniform int8 batches whose schedule has an L = 2 stage and whose REP /
     SPC nodes fit the register levels: that stage runs one frame per lane
-    (two paths per lane) on the frames the gather lists.  A CA L = 2 code
-    (every frame), PA and FA schedules, leaves only, Rate-1 nodes up to the
-    whole code, SPC / REP up to 32 positions, at SNRs where most frames reach
-    L = 2; bits, CRC flags, list sizes, metrics and metric lists equal the
-    oracle for batches of 1, 65 and 200 frames."""
+    (two paths per lane) on the frames the gather lists, the later stages in
+    the list tiers.  A CA L = 2 code (every frame), PA and FA schedules,
+    leaves only, Rate-1 nodes up to the whole code, SPC / REP up to 32
+    positions, at SNRs where most frames reach a list; CA and PA plans with
+    no L = 2 stage stay with the list tiers.  Bits, CRC flags, list sizes,
+    metrics and metric lists equal the oracle for batches of 1, 65 and 200
+    frames."""
     N, K, c, poly, design, algo, Lm, kw, eb = X2_CASES[case]
     code = _code(N, K, c, poly, design, quant="i8", algo=algo, L=Lm, L_max=Lm, **kw)
     for n in (1, 65, 200):
