@@ -37,11 +37,11 @@ HBM_PEAK_BYTES = 8.0e12  # MI355X HBM3E
 PAPER_CONTEXT_MBPS = {3.5: 24.4, 4.0: 227.3, 4.5: 425.9}  # one i5-6600K core, 8-bit FA
 # counter summaries (HBM bytes per launch) and the sources each kernel is built from
 TRAFFIC_FILES = {"k_scx": "hbm_traffic_k_scx_fa2048_i8.md",
-                 "k_listx2": "hbm_traffic_k_listx2_fa2048_i8.md",
+                 "k_listx<2>": "hbm_traffic_k_listx2_fa2048_i8.md",
                  "k_decode_list<int8,1,4>": "hbm_traffic_list_a_fa2048_i8.md",
                  "k_decode_list<int8,4,32>": "hbm_traffic_list_b_fa2048_i8.md"}
 KERNEL_SOURCES = {"k_scx": ["scx.hip", "device_common.h", "kernels.h", "polar_internal.h"],
-                  "k_listx2": ["scx.hip", "device_common.h", "kernels.h", "polar_internal.h"],
+                  "k_listx<2>": ["scx.hip", "device_common.h", "kernels.h", "polar_internal.h"],
                   "k_decode_list<int8,1,4>": ["decode.hip", "device_common.h", "kernels.h",
                                               "polar_internal.h"],
                   "k_decode_list<int8,4,32>": ["decode.hip", "device_common.h", "kernels.h",
@@ -607,7 +607,7 @@ def main():
     total_bits = args.steps * len(points) * F * kd
     value = total_bits / elapsed / 1e6
     # list tier A: the L = 2 stage one frame per lane, then L = 4 one wave per frame
-    kernel_names = {"sc": "k_scx", "list_a": "k_listx2 + k_decode_list<int8,1,4>",
+    kernel_names = {"sc": "k_scx", "list_a": "k_listx<2> + k_decode_list<int8,1,4>",
                     "list_b": "k_decode_list<int8,4,32>"}
     tiers = {}
     for t in tier_ms:
