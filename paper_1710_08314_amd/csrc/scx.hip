@@ -972,7 +972,9 @@ __global__ __launch_bounds__(64) void k_listx(KArgs A, uint32_t* state, const ui
   const uint32_t* nib = uni_ptr(plan_tab(P, uni(P->off_crcnib)));
   const uint32_t* dmask = uni_ptr(plan_tab(P, uni(P->off_datamask)));
   char* region = A.spill + (size_t)blockIdx.x * A.spill_stride;
-  const uint32_t count = uni(xl[0]);
+  // the count through a vector load at device scope, not the scalar cache
+  const uint32_t count =
+      uni(__hip_atomic_load(&xl[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
   const uint32_t n_groups = (count + 63u) / 64u;
   for (uint32_t q = blockIdx.x; q < n_groups; q += gridDim.x) {
     const uint32_t idx = 64u * q + lane;
