@@ -118,8 +118,9 @@ def test_graph_replay_uneven(uneven):
 
 
 def test_graph_replay_adaptive_single_plan():
-    """Graph capture of the tiered schedule (device escalation queues) on the
-    (1024, 488 + CRC-24) code with FA L = 1 -> 8, int8."""
+    """Graph capture of the tiered schedule (per-frame state words, and the
+    frame list of the frame-per-lane L = 2 stage) on the (1024, 488 +
+    CRC-24) code with FA L = 1 -> 8, int8."""
     import torch
 
     import oracle as O
