@@ -515,6 +515,32 @@ int plan_tiers(const Batch& b, polar::TierPlan* out) {
           tp.grid_x2 = groups < cap2 ? (groups ? groups : 1u) : cap2;
           tp.spill_x2 = polar::listx_region_bytes(h.N, 2);
         }
+        // stages above 4: one path per lane when each of them is 8, 16 or 32
+        // (waves per CU that the registers allow: 4 per SIMD at L = 8, 3 above)
+        uint32_t st = h.first_stage, np = 0, pst[3] = {0, 0, 0};
+        bool fits = small;
+        for (int guard = 0; guard < 8; ++guard) {
+          if (st > polar::kTierALmax) {
+            if ((st == 8 || st == 16 || st == 32) && np < 3)
+              pst[np++] = st;
+            else
+              fits = false;
+          }
+          if (st >= h.L_max && st >= h.first_stage) break;
+          st = polar::stage_after(h.algo == POLAR_PA_SCL, h.L_max, st);
+        }
+        if (fits && np > 0) {
+          tp.run_p = 1;
+          tp.n_p = np;
+          tp.spill_p = polar::scx_region_bytes(h.N);
+          for (uint32_t i = 0; i < np; ++i) {
+            const uint32_t fw = 64u / pst[i];
+            const uint32_t need = (n_frames + fw - 1) / fw;
+            const uint32_t capp = (pst[i] == 8 ? 16u : 12u) * (uint32_t)cus;
+            tp.p_stage[i] = pst[i];
+            tp.grid_p[i] = need < capp ? (need ? need : 1u) : capp;
+          }
+        }
       }
     }
   }
@@ -627,6 +653,7 @@ uint64_t spill_need(const Batch& b, int cus) {
   if (plan_tiers(b, &tp) == POLAR_OK) {
     if (tp.run_sc && tp.sc_x) upd(tp.grid_scx, tp.spill_sc);
     if (tp.run_x2) upd(tp.grid_x2, tp.spill_x2);
+    for (uint32_t i = 0; tp.run_p && i < tp.n_p; ++i) upd(tp.grid_p[i], tp.spill_p);
     if (tp.run_a) upd(tp.grid_a, tp.spill_a);
     if (tp.run_b) upd(tp.grid_b, tp.spill_b);
   }

@@ -1306,10 +1306,18 @@ static int launch_tiered_t(const KArgs& A, const TierPlan& tp, uint32_t* state, 
     hipLaunchKernelGGL((k_decode_list<T, 1, (int)kTierALmax>), dim3(tp.grid_a), dim3(64), tp.lds_a,
                        s, Aa, state, heads, 2u, kTierALmax, tp.chunk_a);
   if (ev) (void)hipEventRecord(ev[2], s);
-  if (tp.run_b)
+  if (tp.run_p) {
+    KArgs Ap = A;
+    Ap.spill_stride = tp.spill_p;
+    for (uint32_t i = 0; i < tp.n_p; ++i) {
+      const int rc = launch_decode_listp(tp.p_stage[i], Ap, tp.grid_p[i], state, xl, s);
+      if (rc) return rc;
+    }
+  } else if (tp.run_b) {
     hipLaunchKernelGGL((k_decode_list<T, kListWaves, (int)kMaxL>), dim3(tp.grid_b),
                        dim3(kListWaves * 64), tp.lds_b, s, Ab, state, heads + kClaimSegs,
                        tp.run_a ? kTierALmax + 1 : 2u, kMaxL, tp.chunk_b);
+  }
   if (ev) (void)hipEventRecord(ev[3], s);
   return hipGetLastError() == hipSuccess ? POLAR_OK : POLAR_EHIP;
 }

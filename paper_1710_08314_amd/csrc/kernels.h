@@ -59,6 +59,10 @@ struct TierPlan {
   uint32_t run_x2;            // the L = 2 stage runs one frame per lane first (k_listx<2>)
   uint32_t grid_x2;           // its persistent grid (waves)
   uint64_t spill_x2;          // its region bytes per wave (listx_region_bytes)
+  uint32_t run_p;             // the stages above 4 (8, 16, 32) run one path per lane
+                              // (k_listp) in place of list tier B
+  uint32_t p_stage[3], grid_p[3], n_p;  // those stages in order and their grids (waves)
+  uint64_t spill_p;           // region bytes per wave (scx_region_bytes)
 };
 // state: n_frames words; heads: 2 x kClaimSegs claim counters (tier A, then
 // tier B), cleared by a kernel launched before the state init.
@@ -107,6 +111,12 @@ constexpr uint32_t kScxLds = 4 * 1024;  // its LDS per wave (level 6)
 // A.spill_stride.  Finished frames get state 0, the others their next stage.
 uint64_t listx_region_bytes(uint32_t N, uint32_t L);
 int launch_decode_listx(const KArgs& A, uint32_t grid, uint32_t* state, uint32_t* xl,
+                        hipStream_t s);
+// The stages of size L = 8, 16, 32 with one path per lane (scx.hip), 64 / L
+// frames per wave, for the same batches: the frames whose next stage is L
+// are listed in xl as above, then decoded by a persistent grid of `grid`
+// waves, each with a region of scx_region_bytes(N).
+int launch_decode_listp(uint32_t L, const KArgs& A, uint32_t grid, uint32_t* state, uint32_t* xl,
                         hipStream_t s);
 int launch_decode_scx(const KArgs& A, uint32_t grid, uint32_t* state, hipStream_t s);
 

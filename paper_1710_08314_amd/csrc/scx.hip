@@ -802,6 +802,359 @@ __device__ __forceinline__ void nodeL(PS<L>& S, const CtxL<L>& C, uint32_t opc, 
   }
 }
 
+// ================================================= L = 8..32: one path per lane
+// The list stages of size L >= 8 (Algorithm 1 with the dedicated nodes of
+// Sec. II-B3 and the selection of Sec. II-B2) for the frames of a uniform
+// int8 batch whose next stage is L: 64 / L frames per wave, lane g L + r
+// holding path r of frame g.  Every lane runs its path's steps as in the
+// L = 1 kernel; a lane's buffers of levels >= 6 are the slots of the list:
+// a path reads its node from the lane its slot number names and writes its
+// child to its own lane (index indirection).  At a forking node every path
+// offers its candidates (as in the list decoder), a candidate's rank among
+// the frame's L C keys (metric, parent, local index) is counted across its
+// lanes, the L best are scattered through LDS to their new ranks, and each
+// new path takes its parent's registers and slot numbers by lane
+// permutation and copies its partial sums below the node.
+
+struct PP {  // one path of a lane
+  XR R;
+  int pm;
+  uint32_t P;  // lane holding this path's buffer of level k (6 .. 10): 6 bits at 6 (k - 6)
+};
+
+struct CtxP {
+  char* region;      // this wave's region (as the L = 1 kernel's)
+  const char* root;  // this lane's channel LLRs
+  uint32_t n, lane, bw;
+  uint32_t* bits0;  // partial-sum word w of lane s at bits0[64 w + s]
+  uint4* l60;       // level-6 chunk c of lane s at l60[64 c + s] (LDS)
+  uint32_t* sel;    // LDS: 64 words of selection scratch
+};
+
+__device__ __forceinline__ uint32_t pslot(uint32_t P, uint32_t k) { return (P >> (6 * (k - 6))) & 63u; }
+__device__ __forceinline__ uint32_t pset(uint32_t P, uint32_t k, uint32_t s) {
+  return (P & ~(63u << (6 * (k - 6)))) | (s << (6 * (k - 6)));
+}
+__device__ __forceinline__ char* pbuf(const CtxP& C, uint32_t k, uint32_t s) {
+  return C.region + (size_t)64u * ((1u << k) - 128u) + 16u * s;  // levels 7 .. n-1
+}
+__device__ __forceinline__ Src psrc(const CtxP& C, uint32_t P, uint32_t k) {
+  if (k == C.n) return Src{C.root, 16u};
+  return Src{pbuf(C, k, pslot(P, k)), 1024u};
+}
+__device__ __forceinline__ uint32_t* pcol(const CtxP& C, uint32_t s) { return C.bits0 + s; }
+
+template <bool G, bool DL>
+__device__ __forceinline__ void fgP(const CtxP& C, uint32_t P, uint32_t k, uint32_t o) {
+  const Src s = psrc(C, P, k);
+  const uint32_t nc = 1u << (k - 5);
+  const char* pa = s.p;
+  const char* pb = s.p + (size_t)nc * s.cs;
+  char* dst = DL ? nullptr : pbuf(C, k - 1, C.lane);
+  uint4* dl = C.l60 + C.lane;
+  const uint32_t* lb = pcol(C, C.lane) + (size_t)64u * (o >> 5);
+  for (uint32_t c = 0; c < nc; c += 2) {
+    const Chunk a0 = ldc(pa + (size_t)c * s.cs), b0 = ldc(pb + (size_t)c * s.cs);
+    const Chunk a1 = ldc(pa + (size_t)(c + 1) * s.cs), b1 = ldc(pb + (size_t)(c + 1) * s.cs);
+    Chunk r0, r1;
+    if constexpr (G) {
+      const uint32_t sw = lb[64u * (c >> 1)];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        r0.w[j] = g4(a0.w[j], b0.w[j], (sw >> (4 * j)) & 15u);
+        r1.w[j] = g4(a1.w[j], b1.w[j], (sw >> (16 + 4 * j)) & 15u);
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        r0.w[j] = f4(a0.w[j], b0.w[j]);
+        r1.w[j] = f4(a1.w[j], b1.w[j]);
+      }
+    }
+    if constexpr (DL) {
+      stl(dl, c, r0);
+      stl(dl, c + 1, r1);
+    } else {
+      stc(dst + (size_t)c * 1024u, r0);
+      stc(dst + (size_t)(c + 1) * 1024u, r1);
+    }
+  }
+}
+
+template <bool G>
+__device__ __forceinline__ void fg6P(const CtxP& C, uint32_t P, XR& R) {
+  const uint4* l = C.l60 + pslot(P, 6);
+  const Chunk a0 = ldl(l, 0), a1 = ldl(l, 1), b0 = ldl(l, 2), b1 = ldl(l, 3);
+  if constexpr (G) R.l6 = R.b;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    if constexpr (G) {
+      R.x5[j] = g4(a0.w[j], b0.w[j], (R.b >> (4 * j)) & 15u);
+      R.x5[j + 4] = g4(a1.w[j], b1.w[j], (R.b >> (16 + 4 * j)) & 15u);
+    } else {
+      R.x5[j] = f4(a0.w[j], b0.w[j]);
+      R.x5[j + 4] = f4(a1.w[j], b1.w[j]);
+    }
+  }
+}
+
+__device__ __forceinline__ void hP(const CtxP& C, const XR& R, uint32_t k, uint32_t o) {
+  uint32_t* w = pcol(C, C.lane) + (size_t)64u * (o >> 5);
+  if (k == 6) {
+    w[0] = R.l6 ^ R.b;
+    w[64] = R.b;
+    return;
+  }
+  const uint32_t nw = 1u << (k - 6);
+  uint32_t* q = w + (size_t)64u * nw;
+  for (uint32_t i = 0; i < nw; ++i) w[64u * i] ^= q[64u * i];
+}
+
+__device__ __forceinline__ XR bperm_xr(const XR& R, uint32_t src) {
+  XR o;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) o.x5[j] = bperm(R.x5[j], src);
+#pragma unroll
+  for (int j = 0; j < 4; ++j) o.x4[j] = bperm(R.x4[j], src);
+  o.x3[0] = bperm(R.x3[0], src);
+  o.x3[1] = bperm(R.x3[1], src);
+  o.x2 = bperm(R.x2, src);
+  o.x1 = bperm(R.x1, src);
+  o.x0 = bperm(R.x0, src);
+  o.b = bperm(R.b, src);
+  o.lft = bperm(R.lft, src);
+  o.l6 = bperm(R.l6, src);
+  return o;
+}
+
+// smallest value over the L lanes of the caller's frame
+template <int L>
+__device__ __forceinline__ int group_min(int v, uint32_t lane) {
+#pragma unroll
+  for (uint32_t s = 1; s < (uint32_t)L; s <<= 1) v = min(v, (int)bperm((uint32_t)v, lane ^ s));
+  return v;
+}
+
+// Keys: metric << 9 | parent rank << 4 | local index (unique in a frame).
+__device__ __forceinline__ uint32_t pkey(int pm, uint32_t pen, uint32_t r, uint32_t local) {
+  return ((uint32_t)min(pm + (int)pen, kQ) << 9) | (r << 4) | local;
+}
+
+// The L best of the frame's candidates (kc[0 .. C) per lane, ~0 where
+// absent) become the new paths: returns this lane's new key (~0 when the
+// lane holds no path afterwards) and its parent's lane.
+template <int L, int C>
+__device__ __forceinline__ uint32_t select_p(const CtxP& C_, const uint32_t (&kc)[C], uint32_t keep,
+                                             uint32_t& parent_lane, uint32_t& best) {
+  const uint32_t lane = C_.lane, g0 = lane & ~(uint32_t)(L - 1);
+  uint32_t rk[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) rk[c] = 0;
+  for (uint32_t t = 0; t < (uint32_t)L; ++t) {
+#pragma unroll
+    for (int c2 = 0; c2 < C; ++c2) {
+      const uint32_t o = bperm(kc[c2], g0 + t);
+#pragma unroll
+      for (int c = 0; c < C; ++c) rk[c] += o < kc[c] ? 1u : 0u;
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < C; ++c)
+    if (kc[c] != 0xFFFFFFFFu && rk[c] < keep) C_.sel[g0 + rk[c]] = kc[c];
+  __syncthreads();
+  const uint32_t r = lane - g0;
+  const uint32_t nk = r < keep ? C_.sel[lane] : 0xFFFFFFFFu;
+  best = C_.sel[g0];
+  __syncthreads();
+  // a lane left without a path keeps its own state (and reads only its own column)
+  parent_lane = nk == 0xFFFFFFFFu ? lane : g0 + ((nk >> 4) & 31u);
+  return nk;
+}
+
+// new paths take their parents' state; partial-sum words [0, W) follow the parent
+__device__ __forceinline__ void adopt(PP& S, const CtxP& C, uint32_t nk, uint32_t pl, uint32_t best,
+                                      uint32_t W) {
+  S.R = bperm_xr(S.R, pl);
+  S.P = bperm(S.P, pl);
+  S.pm = nk == 0xFFFFFFFFu ? 0 : (int)(nk >> 9) - (int)(best >> 9);
+  const bool mv = nk != 0xFFFFFFFFu && pl != C.lane;
+  if (__ballot(mv) == 0ull) return;
+  uint32_t* src = pcol(C, pl);
+  uint32_t* dst = pcol(C, C.lane);
+  // every lane reads word w before any lane overwrites it (a parent's column
+  // may be another new path's own)
+  for (uint32_t w = 0; w < W; ++w) {
+    const uint32_t x = src[64u * w];
+    __syncthreads();
+    if (mv) dst[64u * w] = x;
+  }
+}
+
+// a dedicated node or leaf of level K <= 5; r: this lane's path rank, a: active paths
+template <int L, int K>
+__device__ __forceinline__ void node_regP(PP& S, const CtxP& C, uint32_t opc, uint32_t o, uint32_t r,
+                                          uint32_t& a) {
+  constexpr uint32_t M = 1u << K;
+  constexpr int W = M >= 4 ? (int)M / 4 : 1;
+  constexpr uint32_t full = M == 32 ? 0xFFFFFFFFu : ((1u << (M & 31u)) - 1u);
+  const bool act = r < a;
+  XR& R = S.R;
+  int p0 = 0, p1 = 0;
+#pragma unroll
+  for (int j = 0; j < W; ++j)
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      if (4 * j + i < (int)M) {
+        const int v = sx8(xw<K>(R, j), i);
+        if (v < 0)
+          p0 -= v;
+        else
+          p1 += v;
+      }
+  uint32_t hd = 0;
+#pragma unroll
+  for (int j = 0; j < W; ++j) hd |= hd4(xw<K>(R, j)) << (4 * j);
+  hd &= full;
+  if (opc == OP_R0 || opc == OP_LF) {
+    S.pm = min(S.pm + p0, kQ);
+    R.b = 0u;
+    const int mn = group_min<L>(act ? S.pm : 0x7FFFFFFF, C.lane);
+    S.pm -= mn;
+    return;
+  }
+  uint32_t nk, pl, best;
+  uint32_t pos = 0;
+  if (opc == OP_LI || opc == OP_REP) {
+    uint32_t kc[2] = {act ? pkey(S.pm, (uint32_t)p0, r, 0u) : 0xFFFFFFFFu,
+                      act ? pkey(S.pm, (uint32_t)p1, r, 1u) : 0xFFFFFFFFu};
+    nk = select_p<L, 2>(C, kc, min((uint32_t)L, a * 2u), pl, best);
+    a = min((uint32_t)L, a * 2u);
+  } else {
+    uint32_t s4[4];
+    least4<K>(R, s4);
+    pos = (s4[0] & 31u) | ((s4[1] & 31u) << 5) | ((s4[2] & 31u) << 10) | ((s4[3] & 31u) << 15);
+    const uint32_t m0 = s4[0] >> 5, m1 = s4[1] >> 5, m2 = s4[2] >> 5, m3 = s4[3] >> 5;
+    if (opc == OP_R1) {
+      uint32_t kc[4];
+#pragma unroll
+      for (uint32_t mk = 0; mk < 4; ++mk)
+        kc[mk] = act ? pkey(S.pm, ((mk & 1u) ? m0 : 0u) + ((mk & 2u) ? m1 : 0u), r, mk) : 0xFFFFFFFFu;
+      nk = select_p<L, 4>(C, kc, min((uint32_t)L, a * 4u), pl, best);
+      a = min((uint32_t)L, a * 4u);
+    } else {
+      // the eight masks whose weight has the parity of the hard decisions
+      // (nibble i of 0xFCA96530: the even ones, of 0xEDB87421: the odd ones)
+      const uint32_t masks = (__popc(hd) & 1u) ? 0xEDB87421u : 0xFCA96530u;
+      uint32_t kc[8];
+#pragma unroll
+      for (uint32_t i = 0; i < 8; ++i) {
+        const uint32_t mk = (masks >> (4 * i)) & 15u;
+        const uint32_t pen = ((mk & 1u) ? m0 : 0u) + ((mk & 2u) ? m1 : 0u) + ((mk & 4u) ? m2 : 0u) +
+                             ((mk & 8u) ? m3 : 0u);
+        kc[i] = act ? pkey(S.pm, pen, r, mk) : 0xFFFFFFFFu;
+      }
+      nk = select_p<L, 8>(C, kc, min((uint32_t)L, a * 8u), pl, best);
+      a = min((uint32_t)L, a * 8u);
+    }
+  }
+  const uint32_t hdp = bperm(hd, pl), posp = bperm(pos, pl);
+  adopt(S, C, nk, pl, best, (o >> 6) << 1);
+  const uint32_t lj = nk & 15u;
+  if (opc == OP_LI || opc == OP_REP) {
+    S.R.b = lj ? full : 0u;
+  } else {
+    uint32_t fl = 0;
+#pragma unroll
+    for (uint32_t t = 0; t < 4; ++t) fl |= ((lj >> t) & 1u) << ((posp >> (5 * t)) & 31u);
+    S.R.b = hdp ^ fl;
+  }
+}
+
+// a Rate-0 or Rate-1 node of level k >= 6
+template <int L>
+__device__ __forceinline__ void node_memP(PP& S, const CtxP& C, uint32_t opc, uint32_t k, uint32_t o,
+                                          uint32_t r, uint32_t& a) {
+  const uint32_t nw = 1u << (k - 5);
+  const bool act = r < a;
+  const Src s = k == 6 ? Src{nullptr, 0u} : psrc(C, S.P, k);
+  const uint4* l = C.l60 + pslot(S.P, 6);
+  uint32_t* w = pcol(C, C.lane) + (size_t)64u * (o >> 5);
+  int p0 = 0;
+  uint32_t s0 = 0xFFFFFFFFu, s1 = 0xFFFFFFFFu;
+  for (uint32_t q = 0; q < nw; ++q) {
+    const Chunk x0 = k == 6 ? ldl(l, 2 * q) : ldc(s.p + (size_t)(2 * q) * s.cs);
+    const Chunk x1 = k == 6 ? ldl(l, 2 * q + 1) : ldc(s.p + (size_t)(2 * q + 1) * s.cs);
+    if (opc == OP_R0) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          p0 += max(-sx8(x0.w[j], i), 0);
+          p0 += max(-sx8(x1.w[j], i), 0);
+        }
+      w[64u * q] = 0u;
+    } else {
+      w[64u * q] = hd16(x0) | (hd16(x1) << 16);
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const uint32_t e = 32u * q + 4u * j + i;
+          uint32_t v = ((uint32_t)abs(sx8(x0.w[j], i)) << 12) | e;
+          uint32_t lo = min(v, s0);
+          v = max(v, s0);
+          s0 = lo;
+          s1 = min(v, s1);
+          v = ((uint32_t)abs(sx8(x1.w[j], i)) << 12) | (e + 16u);
+          lo = min(v, s0);
+          v = max(v, s0);
+          s0 = lo;
+          s1 = min(v, s1);
+        }
+    }
+  }
+  if (opc == OP_R0) {
+    S.pm = min(S.pm + p0, kQ);
+    const int mn = group_min<L>(act ? S.pm : 0x7FFFFFFF, C.lane);
+    S.pm -= mn;
+    return;
+  }
+  const uint32_t pos = (s0 & 0xFFFu) | ((s1 & 0xFFFu) << 16);
+  const uint32_t m0 = s0 >> 12, m1 = s1 >> 12;
+  uint32_t kc[4];
+#pragma unroll
+  for (uint32_t mk = 0; mk < 4; ++mk)
+    kc[mk] = act ? pkey(S.pm, ((mk & 1u) ? m0 : 0u) + ((mk & 2u) ? m1 : 0u), r, mk) : 0xFFFFFFFFu;
+  uint32_t pl, best;
+  const uint32_t nk = select_p<L, 4>(C, kc, min((uint32_t)L, a * 4u), pl, best);
+  a = min((uint32_t)L, a * 4u);
+  const uint32_t posp = bperm(pos, pl);
+  adopt(S, C, nk, pl, best, (o >> 5) + nw);
+  const uint32_t lj = nk & 15u;
+  if (nk != 0xFFFFFFFFu) {
+#pragma unroll
+    for (uint32_t t = 0; t < 2; ++t)
+      if ((lj >> t) & 1u) {
+        const uint32_t e = o + ((posp >> (16 * t)) & 0xFFFu);
+        pcol(C, C.lane)[64u * (e >> 5)] ^= 1u << (e & 31u);
+      }
+  }
+}
+
+template <int L>
+__device__ __forceinline__ void nodeP(PP& S, const CtxP& C, uint32_t opc, uint32_t k, uint32_t o,
+                                      uint32_t r, uint32_t& a) {
+  switch (k) {
+    case 5: node_regP<L, 5>(S, C, opc, o, r, a); break;
+    case 4: node_regP<L, 4>(S, C, opc, o, r, a); break;
+    case 3: node_regP<L, 3>(S, C, opc, o, r, a); break;
+    case 2: node_regP<L, 2>(S, C, opc, o, r, a); break;
+    case 1: node_regP<L, 1>(S, C, opc, o, r, a); break;
+    case 0: node_regP<L, 0>(S, C, opc, o, r, a); break;
+    default: node_memP<L>(S, C, opc, k, o, r, a); break;
+  }
+}
+
 }  // namespace
 
 // A persistent grid: wave g decodes the groups of 64 frames g, g + G, ...
@@ -1127,6 +1480,159 @@ int launch_decode_listx(const KArgs& A, uint32_t grid, uint32_t* state, uint32_t
                      (const uint32_t*)state, xl);
   hipLaunchKernelGGL(k_listx<2>, dim3(grid > 0 ? grid : 1), dim3(64), 0, s, A, state,
                      (const uint32_t*)xl);
+  return hipGetLastError() == hipSuccess ? POLAR_OK : POLAR_EHIP;
+}
+
+// The stage of size L >= 8 of the listed frames, 64 / L per wave
+// (persistent grid, wave q takes the groups q, q + G, ...).  A frame whose
+// CRC passes, or whose plan ends at L, is finished (bits, status, metric
+// list, end stamp; state 0); the others get their next stage.
+template <int L>
+__global__ __launch_bounds__(64) void k_listp(KArgs A, uint32_t* state, const uint32_t* xl) {
+  __shared__ uint4 lds6p[4 * 64];  // level 6: 4 chunks per lane
+  __shared__ uint32_t selp[64];
+  constexpr uint32_t FW = 64u / L;  // frames per wave
+  const uint32_t lane = threadIdx.x, gi = lane / L, r = lane % L, g0 = lane - r;
+  const DevPlan* P = uni_ptr(A.plans[0]);
+  const uint32_t N = uni(P->N), n = uni(P->n), n_ops = uni(P->n_ops), bw = uni(P->bw);
+  const uint32_t iw = uni(A.info_words), L_max = uni(P->L_max), c_len = uni(P->c);
+  const uint32_t* prog = uni_ptr(plan_tab(P, uni(P->off_prog)));
+  const uint32_t* imask = uni_ptr(plan_tab(P, uni(P->off_infomask)));
+  const uint32_t* nib = uni_ptr(plan_tab(P, uni(P->off_crcnib)));
+  const uint32_t* dmask = uni_ptr(plan_tab(P, uni(P->off_datamask)));
+  char* region = A.spill + (size_t)blockIdx.x * A.spill_stride;
+  // the count through a vector load at device scope, not the scalar cache
+  const uint32_t count =
+      uni(__hip_atomic_load(&xl[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+  const uint32_t n_groups = (count + FW - 1u) / FW;
+  for (uint32_t q = blockIdx.x; q < n_groups; q += gridDim.x) {
+    const uint32_t idx = FW * q + gi;
+    const bool valid = idx < count;
+    const uint32_t f = xl[1 + (valid ? idx : FW * q)];
+    CtxP C;
+    C.region = region;
+    C.root = A.llr + (size_t)f * A.llr_bytes;
+    C.n = n;
+    C.lane = lane;
+    C.bw = bw;
+    C.bits0 = reinterpret_cast<uint32_t*>(region + (size_t)64u * (N - 128u));
+    C.l60 = lds6p;
+    C.sel = selp;
+    PP S;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) S.R.x5[j] = 0u;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) S.R.x4[j] = 0u;
+    S.R.x3[0] = S.R.x3[1] = S.R.x2 = S.R.x1 = S.R.x0 = 0u;
+    S.R.b = S.R.lft = S.R.l6 = 0u;
+    S.pm = 0;
+    S.P = 0u;
+    uint32_t a = 1;
+    uint32_t w_next = prog[0];
+    for (uint32_t pc = 0; pc < n_ops; ++pc) {
+      const uint32_t w = uni(w_next);
+      if (pc + 1 < n_ops) w_next = prog[pc + 1];
+      const uint32_t opc = op_code(w), k = n - op_depth(w), o = op_off(w);
+      if (opc == OP_F || opc == OP_G || opc == OP_H) {
+        const bool g = opc == OP_G;
+        if (k <= 5) {
+          reg_op(S.R, opc, k);
+        } else if (opc == OP_H) {
+          hP(C, S.R, k, o);
+        } else if (k == 6) {
+          g ? fg6P<true>(C, S.P, S.R) : fg6P<false>(C, S.P, S.R);
+        } else {
+          if (k == 7)
+            g ? fgP<true, true>(C, S.P, k, o) : fgP<false, true>(C, S.P, k, o);
+          else
+            g ? fgP<true, false>(C, S.P, k, o) : fgP<false, false>(C, S.P, k, o);
+          S.P = pset(S.P, k - 1, lane);
+        }
+      } else {
+        nodeP<L>(S, C, opc, k, o, r, a);
+      }
+    }
+    // ---- order of the paths (metric, rank), CRC of each, first passing wins
+    const bool act = r < a;
+    const uint32_t okey = act ? (((uint32_t)S.pm << 6) | r) : 0xFFFFFFFFu;
+    uint32_t ordr = 0;
+    for (uint32_t t = 0; t < (uint32_t)L; ++t) ordr += bperm(okey, g0 + t) < okey ? 1u : 0u;
+    uint32_t syn = 0;
+    if (c_len > 0) {
+      const uint32_t* col = pcol(C, lane);
+      for (uint32_t wd = 0; wd < bw; ++wd) {
+        const uint32_t im = imask[wd];
+        if (!im) continue;
+        const uint32_t v = col[64u * wd] & im;
+        for (uint32_t t = 0; t < 8; ++t)
+          if ((im >> (4 * t)) & 15u) syn ^= nib[((wd * 8 + t) << 4) + ((v >> (4 * t)) & 15u)];
+      }
+    }
+    const int first = group_min<L>(act && syn == 0u ? (int)ordr : 255, lane);
+    const bool ok = first < 255;
+    const uint32_t cho = ok ? (uint32_t)first : 0u;
+    const bool ch = act && ordr == cho;
+    const bool fin = valid && (ok || L_max <= (uint32_t)L);
+    if (r == 0 && valid) state[f] = fin ? 0u : next_stage(P, L);
+    // ---- outputs of a finished frame from its chosen path's lane
+    uint32_t* out = A.info + (size_t)f * iw;
+    const uint32_t* xb = pcol(C, lane);
+    const bool wr = fin && ch;
+    uint32_t cur = 0, pos = 0, ow = 0;
+    for (uint32_t wd = 0; wd < bw; ++wd) {
+      uint32_t dm = dmask[wd];
+      if (!dm) continue;
+      const uint32_t x = xb[64u * wd];
+      uint32_t v = 0, cnt = 0;
+      while (dm) {
+        const uint32_t b = __ffs(dm) - 1;
+        v |= ((x >> b) & 1u) << cnt;
+        ++cnt;
+        dm &= dm - 1u;
+      }
+      cur |= v << pos;
+      if (pos + cnt >= 32) {
+        if (wr) out[ow] = cur;
+        ++ow;
+        cur = pos ? v >> (32 - pos) : 0u;
+      }
+      pos = (pos + cnt) & 31u;
+    }
+    if (pos && wr) out[ow] = cur;
+    if (wr) {
+      polar_status st;
+      st.crc_ok = ok ? 1 : 0;
+      st.L_used = (uint8_t)L;
+      st.n_paths = (uint8_t)a;
+      st.flags = 0;
+      st.pm = (uint32_t)S.pm;
+      A.status[f] = st;
+      if (A.times) A.times[2 * (size_t)f + 1] = wall_clock64();
+    }
+    // metric list in order: each path's metric to its order's place
+    if (act) selp[g0 + ordr] = (uint32_t)S.pm;
+    __syncthreads();
+    const uint32_t mine = r < a ? selp[lane] : 0xFFFFFFFFu;
+    __syncthreads();
+    if (fin && A.pm_lists)
+      for (uint32_t t = r; t < A.pm_stride; t += L)
+        A.pm_lists[(size_t)f * A.pm_stride + t] = t == r ? mine : 0xFFFFFFFFu;
+  }
+}
+
+int launch_decode_listp(uint32_t L, const KArgs& A, uint32_t grid, uint32_t* state, uint32_t* xl,
+                        hipStream_t s) {
+  const uint32_t gb = (A.n_frames + 255u) / 256u < 1024u ? (A.n_frames + 255u) / 256u : 1024u;
+  hipLaunchKernelGGL(k_xreset, dim3(1), dim3(64), 0, s, xl);
+  hipLaunchKernelGGL(k_gather, dim3(gb > 0 ? gb : 1), dim3(256), 0, s, A.n_frames, L,
+                     (const uint32_t*)state, xl);
+  const dim3 gr(grid > 0 ? grid : 1);
+  if (L == 8)
+    hipLaunchKernelGGL(k_listp<8>, gr, dim3(64), 0, s, A, state, (const uint32_t*)xl);
+  else if (L == 16)
+    hipLaunchKernelGGL(k_listp<16>, gr, dim3(64), 0, s, A, state, (const uint32_t*)xl);
+  else
+    hipLaunchKernelGGL(k_listp<32>, gr, dim3(64), 0, s, A, state, (const uint32_t*)xl);
   return hipGetLastError() == hipSuccess ? POLAR_OK : POLAR_EHIP;
 }
 

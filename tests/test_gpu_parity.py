@@ -361,6 +361,35 @@ def test_list2_stage_frame_per_lane(case):
         compare(code, llr)
 
 
+P_CASES = [
+    # (N, K, c, poly, design dB, algo, L_max, node options, Eb/N0)
+    (256, 128, 8, 0x07, 2.0, "ca", 8, dict(), 1.0),
+    (512, 300, 11, 0x621, 2.5, "ca", 16, dict(node_enable=0), 1.5),
+    (256, 200, 11, 0x621, 3.0, "pa", 32, dict(), 1.5),
+    (1024, 512, 11, 0x621, 2.0, "fa", 8, dict(spc_max=32, rep_max=32), 1.0),
+    (512, 256, 11, 0x621, 2.0, "fa", 32, dict(node_enable=O.NODE_R0 | O.NODE_R1), 0.5),
+    (2048, 1723, 32, 0x04C11DB7, 4.5, "fa", 32, dict(), 3.0),
+]
+
+
+@pytest.mark.parametrize("case", range(len(P_CASES)))
+def test_list_stages_path_per_lane(case):
+    """Uniform int8 batches whose stages above L = 4 are 8, 16 or 32 and
+    whose REP / SPC nodes fit the register levels: those stages run one path
+    per lane, 64 / L frames per wave (selection across a frame's lanes, path
+    copies by lane permutation).  CA L = 8 and 16 (every frame), PA L = 32,
+    FA to 8 and 32, leaves only, Rate-0 / Rate-1 only, the (2048, 1723) code,
+    at SNRs where many frames reach the large lists and exact metric ties are
+    common; bits, CRC flags, list sizes, metrics and metric lists equal the
+    oracle for batches of 1, 33 and 100 frames (a lone frame, ragged waves,
+    several waves)."""
+    N, K, c, poly, design, algo, Lm, kw, eb = P_CASES[case]
+    code = _code(N, K, c, poly, design, quant="i8", algo=algo, L=Lm, L_max=Lm, **kw)
+    for n in (1, 33, 100):
+        _, llr = make_inputs(code, n, 1700 + 7 * case + n, eb)
+        compare(code, llr)
+
+
 @pytest.mark.parametrize("quant", ["i8", "f32"])
 def test_sc_tier_frame_pairs(quant):
     """The L = 1 tier decodes two frames per wave.  Every frame of an odd-sized
