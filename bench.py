@@ -38,10 +38,15 @@ PAPER_CONTEXT_MBPS = {3.5: 24.4, 4.0: 227.3, 4.5: 425.9}  # one i5-6600K core, 8
 # counter summaries (HBM bytes per launch) and the sources each kernel is built from
 TRAFFIC_FILES = {"k_scx": "hbm_traffic_k_scx_fa2048_i8.md",
                  "k_listx<2>": "hbm_traffic_k_listx2_fa2048_i8.md",
-                 "k_decode_list<int8,1,4>": "hbm_traffic_list_a_fa2048_i8.md",
-                 "k_decode_list<int8,4,32>": "hbm_traffic_list_b_fa2048_i8.md"}
+                 "k_listp<8>": "hbm_traffic_k_listp8_fa2048_i8.md",
+                 "k_listp<16>": "hbm_traffic_k_listp16_fa2048_i8.md",
+                 "k_listp<32>": "hbm_traffic_k_listp32_fa2048_i8.md",
+                 "k_decode_list<int8,1,4>": "hbm_traffic_list_a_fa2048_i8.md"}
 KERNEL_SOURCES = {"k_scx": ["scx.hip", "device_common.h", "kernels.h", "polar_internal.h"],
                   "k_listx<2>": ["scx.hip", "device_common.h", "kernels.h", "polar_internal.h"],
+                  "k_listp<8>": ["scx.hip", "device_common.h", "kernels.h", "polar_internal.h"],
+                  "k_listp<16>": ["scx.hip", "device_common.h", "kernels.h", "polar_internal.h"],
+                  "k_listp<32>": ["scx.hip", "device_common.h", "kernels.h", "polar_internal.h"],
                   "k_decode_list<int8,1,4>": ["decode.hip", "device_common.h", "kernels.h",
                                               "polar_internal.h"],
                   "k_decode_list<int8,4,32>": ["decode.hip", "device_common.h", "kernels.h",
@@ -123,7 +128,11 @@ def kernel_source_hash(files):
 
 def measured_traffic(kernel):
     """HBM bytes per launch of `kernel` from the committed counter summary,
-    or None when there is none or the kernel's sources changed since."""
+    or None when there is none or the kernel's sources changed since.  A
+    tier of several kernels ("a + b") sums theirs."""
+    if " + " in kernel:
+        parts = [measured_traffic(k) for k in kernel.split(" + ")]
+        return None if any(p is None for p in parts) else sum(parts)
     path = os.path.join(ROOT, "profiles", TRAFFIC_FILES.get(kernel, "-"))
     if not os.path.exists(path):
         return None
@@ -608,7 +617,7 @@ def main():
     value = total_bits / elapsed / 1e6
     # list tier A: the L = 2 stage one frame per lane, then L = 4 one wave per frame
     kernel_names = {"sc": "k_scx", "list_a": "k_listx<2> + k_decode_list<int8,1,4>",
-                    "list_b": "k_decode_list<int8,4,32>"}
+                    "list_b": "k_listp<8> + k_listp<16> + k_listp<32>"}
     tiers = {}
     for t in tier_ms:
         if tier_ms[t] > 0:
