@@ -38,12 +38,13 @@ PAPER_CONTEXT_MBPS = {3.5: 24.4, 4.0: 227.3, 4.5: 425.9}  # one i5-6600K core, 8
 # counter summaries (HBM bytes per launch) and the sources each kernel is built from
 TRAFFIC_FILES = {"k_scx": "hbm_traffic_k_scx_fa2048_i8.md",
                  "k_listx<2>": "hbm_traffic_k_listx2_fa2048_i8.md",
+                 "k_listp<4>": "hbm_traffic_k_listp4_fa2048_i8.md",
                  "k_listp<8>": "hbm_traffic_k_listp8_fa2048_i8.md",
                  "k_listp<16>": "hbm_traffic_k_listp16_fa2048_i8.md",
-                 "k_listp<32>": "hbm_traffic_k_listp32_fa2048_i8.md",
-                 "k_decode_list<int8,1,4>": "hbm_traffic_list_a_fa2048_i8.md"}
+                 "k_listp<32>": "hbm_traffic_k_listp32_fa2048_i8.md"}
 KERNEL_SOURCES = {"k_scx": ["scx.hip", "device_common.h", "kernels.h", "polar_internal.h"],
                   "k_listx<2>": ["scx.hip", "device_common.h", "kernels.h", "polar_internal.h"],
+                  "k_listp<4>": ["scx.hip", "device_common.h", "kernels.h", "polar_internal.h"],
                   "k_listp<8>": ["scx.hip", "device_common.h", "kernels.h", "polar_internal.h"],
                   "k_listp<16>": ["scx.hip", "device_common.h", "kernels.h", "polar_internal.h"],
                   "k_listp<32>": ["scx.hip", "device_common.h", "kernels.h", "polar_internal.h"],
@@ -615,9 +616,10 @@ def main():
 
     total_bits = args.steps * len(points) * F * kd
     value = total_bits / elapsed / 1e6
-    # list tier A: the L = 2 stage one frame per lane, then L = 4 one wave per frame
-    kernel_names = {"sc": "k_scx", "list_a": "k_listx<2> + k_decode_list<int8,1,4>",
-                    "list_b": "k_listp<8> + k_listp<16> + k_listp<32>"}
+    # the L = 2 stage one frame per lane (list tier A's interval), the stages
+    # from L = 4 on one path per lane (list tier B's interval)
+    kernel_names = {"sc": "k_scx", "list_a": "k_listx<2>",
+                    "list_b": "k_listp<4> + k_listp<8> + k_listp<16> + k_listp<32>"}
     tiers = {}
     for t in tier_ms:
         if tier_ms[t] > 0:

@@ -515,13 +515,14 @@ int plan_tiers(const Batch& b, polar::TierPlan* out) {
           tp.grid_x2 = groups < cap2 ? (groups ? groups : 1u) : cap2;
           tp.spill_x2 = polar::listx_region_bytes(h.N, 2);
         }
-        // stages above 4: one path per lane when each of them is 8, 16 or 32
-        // (waves per CU that the registers allow: 4 per SIMD at L = 8, 3 above)
-        uint32_t st = h.first_stage, np = 0, pst[3] = {0, 0, 0};
+        // stages from 4 on: one path per lane when each of them is 4, 8, 16
+        // or 32 (waves per CU that the registers allow: 4 per SIMD at L <= 8,
+        // 3 above)
+        uint32_t st = h.first_stage, np = 0, pst[4] = {0, 0, 0, 0};
         bool fits = small;
         for (int guard = 0; guard < 8; ++guard) {
-          if (st > polar::kTierALmax) {
-            if ((st == 8 || st == 16 || st == 32) && np < 3)
+          if (st >= 4) {
+            if ((st == 4 || st == 8 || st == 16 || st == 32) && np < 4)
               pst[np++] = st;
             else
               fits = false;
@@ -536,7 +537,7 @@ int plan_tiers(const Batch& b, polar::TierPlan* out) {
           for (uint32_t i = 0; i < np; ++i) {
             const uint32_t fw = 64u / pst[i];
             const uint32_t need = (n_frames + fw - 1) / fw;
-            const uint32_t capp = (pst[i] == 8 ? 16u : 12u) * (uint32_t)cus;
+            const uint32_t capp = (pst[i] <= 8 ? 16u : 12u) * (uint32_t)cus;
             tp.p_stage[i] = pst[i];
             tp.grid_p[i] = need < capp ? (need ? need : 1u) : capp;
           }

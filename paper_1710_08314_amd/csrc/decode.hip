@@ -1302,7 +1302,9 @@ static int launch_tiered_t(const KArgs& A, const TierPlan& tp, uint32_t* state, 
   KArgs Aa = A, Ab = A;
   Aa.spill_stride = tp.spill_a;
   Ab.spill_stride = tp.spill_b;
-  if (tp.run_a)
+  // with the path-per-lane stages from L = 4 on (and the L = 2 stage one
+  // frame per lane wherever the plan has one), list tier A has no frames
+  if (tp.run_a && !tp.run_p)
     hipLaunchKernelGGL((k_decode_list<T, 1, (int)kTierALmax>), dim3(tp.grid_a), dim3(64), tp.lds_a,
                        s, Aa, state, heads, 2u, kTierALmax, tp.chunk_a);
   if (ev) (void)hipEventRecord(ev[2], s);
