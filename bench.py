@@ -37,13 +37,13 @@ HBM_PEAK_BYTES = 8.0e12  # MI355X HBM3E
 PAPER_CONTEXT_MBPS = {3.5: 24.4, 4.0: 227.3, 4.5: 425.9}  # one i5-6600K core, 8-bit FA
 # counter summaries (HBM bytes per launch) and the sources each kernel is built from
 TRAFFIC_FILES = {"k_scx": "hbm_traffic_k_scx_fa2048_i8.md",
-                 "k_listx<2>": "hbm_traffic_k_listx2_fa2048_i8.md",
+                 "k_listp<2>": "hbm_traffic_k_listp2_fa2048_i8.md",
                  "k_listp<4>": "hbm_traffic_k_listp4_fa2048_i8.md",
                  "k_listp<8>": "hbm_traffic_k_listp8_fa2048_i8.md",
                  "k_listp<16>": "hbm_traffic_k_listp16_fa2048_i8.md",
                  "k_listp<32>": "hbm_traffic_k_listp32_fa2048_i8.md"}
 KERNEL_SOURCES = {"k_scx": ["scx.hip", "device_common.h", "kernels.h", "polar_internal.h"],
-                  "k_listx<2>": ["scx.hip", "device_common.h", "kernels.h", "polar_internal.h"],
+                  "k_listp<2>": ["scx.hip", "device_common.h", "kernels.h", "polar_internal.h"],
                   "k_listp<4>": ["scx.hip", "device_common.h", "kernels.h", "polar_internal.h"],
                   "k_listp<8>": ["scx.hip", "device_common.h", "kernels.h", "polar_internal.h"],
                   "k_listp<16>": ["scx.hip", "device_common.h", "kernels.h", "polar_internal.h"],
@@ -594,7 +594,9 @@ def main():
         per_point[str(eb)]["tier_ms"] = {t: round(ms[t], 3) for t in tier_ms}
         for l in sched:
             reached = int(sum(hist[x] for x in sched if x >= l))
-            tier = "sc" if l == 1 else ("list_a" if l <= 4 else "list_b")
+            # every list stage of this workload runs one path per lane, in the
+            # library's second list interval (the first stays empty)
+            tier = "sc" if l == 1 else "list_b"
             tier_work[tier] += reached * plan.stage_work(l)
 
     # ---- latency: per-frame decode time from device realtime stamps
@@ -616,13 +618,11 @@ def main():
 
     total_bits = args.steps * len(points) * F * kd
     value = total_bits / elapsed / 1e6
-    # the L = 2 stage one frame per lane (list tier A's interval), the stages
-    # from L = 4 on one path per lane (list tier B's interval)
-    kernel_names = {"sc": "k_scx", "list_a": "k_listx<2>",
-                    "list_b": "k_listp<4> + k_listp<8> + k_listp<16> + k_listp<32>"}
+    kernel_names = {"sc": "k_scx", "list_a": "k_decode_list<int8,1,4>",
+                    "list_b": "k_listp<2> + k_listp<4> + k_listp<8> + k_listp<16> + k_listp<32>"}
     tiers = {}
     for t in tier_ms:
-        if tier_ms[t] > 0:
+        if tier_ms[t] > 0 and tier_work[t] > 0:
             ach = tier_work[t] / (tier_ms[t] / 1e3)
             tiers[t] = {"kernel": kernel_names[t], "launch_ms": round(tier_ms[t] / len(points), 3),
                         "work_per_launch_ops": int(tier_work[t] / len(points)),

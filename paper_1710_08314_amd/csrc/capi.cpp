@@ -506,23 +506,23 @@ int plan_tiers(const Batch& b, polar::TierPlan* out) {
           if ((op == polar::OP_REP || op == polar::OP_SPC) && (h.N >> polar::op_depth(w)) > 32)
             small = false;
         }
-        // (waves per CU that its registers allow: 3 per SIMD).  The L = 4
-        // stage stays with the wave-per-frame list tier: four paths per lane
-        // took longer per group than that tier took per frame.
+        // (waves per CU that its registers allow: 3 per SIMD); the
+        // path-per-lane stages below replace it when they cover every list
+        // stage of the plan
         const uint32_t cap2 = 12u * (uint32_t)cus;
         if (stage2 && small) {
           tp.run_x2 = 1;
           tp.grid_x2 = groups < cap2 ? (groups ? groups : 1u) : cap2;
           tp.spill_x2 = polar::listx_region_bytes(h.N, 2);
         }
-        // stages from 4 on: one path per lane when each of them is 4, 8, 16
-        // or 32 (waves per CU that the registers allow: 4 per SIMD at L <= 8,
-        // 3 above)
-        uint32_t st = h.first_stage, np = 0, pst[4] = {0, 0, 0, 0};
+        // list stages: one path per lane when each of them is 2, 4, 8, 16 or
+        // 32 (then also in place of the frame-per-lane L = 2 stage; waves per
+        // CU that the registers allow: 4 per SIMD at L <= 8, 3 above)
+        uint32_t st = h.first_stage, np = 0, pst[5] = {0, 0, 0, 0, 0};
         bool fits = small;
         for (int guard = 0; guard < 8; ++guard) {
-          if (st >= 4) {
-            if ((st == 4 || st == 8 || st == 16 || st == 32) && np < 4)
+          if (st >= 2) {
+            if ((st == 2 || st == 4 || st == 8 || st == 16 || st == 32) && np < 5)
               pst[np++] = st;
             else
               fits = false;
@@ -531,6 +531,7 @@ int plan_tiers(const Batch& b, polar::TierPlan* out) {
           st = polar::stage_after(h.algo == POLAR_PA_SCL, h.L_max, st);
         }
         if (fits && np > 0) {
+          tp.run_x2 = 0;
           tp.run_p = 1;
           tp.n_p = np;
           tp.spill_p = polar::scx_region_bytes(h.N);

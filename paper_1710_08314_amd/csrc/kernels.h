@@ -59,9 +59,9 @@ struct TierPlan {
   uint32_t run_x2;            // the L = 2 stage runs one frame per lane first (k_listx<2>)
   uint32_t grid_x2;           // its persistent grid (waves)
   uint64_t spill_x2;          // its region bytes per wave (listx_region_bytes)
-  uint32_t run_p;             // the stages from 4 on (4, 8, 16, 32) run one path per lane
+  uint32_t run_p;             // the list stages (2, 4, 8, 16, 32) run one path per lane
                               // (k_listp) in place of list tiers A and B
-  uint32_t p_stage[4], grid_p[4], n_p;  // those stages in order and their grids (waves)
+  uint32_t p_stage[5], grid_p[5], n_p;  // those stages in order and their grids (waves)
   uint64_t spill_p;           // region bytes per wave (scx_region_bytes)
 };
 // state: n_frames words; heads: 2 x kClaimSegs claim counters (tier A, then
@@ -112,7 +112,7 @@ constexpr uint32_t kScxLds = 4 * 1024;  // its LDS per wave (level 6)
 uint64_t listx_region_bytes(uint32_t N, uint32_t L);
 int launch_decode_listx(const KArgs& A, uint32_t grid, uint32_t* state, uint32_t* xl,
                         hipStream_t s);
-// The stages of size L = 4, 8, 16, 32 with one path per lane (scx.hip), 64 / L
+// The stages of size L = 2, 4, 8, 16, 32 with one path per lane (scx.hip), 64 / L
 // frames per wave, for the same batches: the frames whose next stage is L
 // are listed in xl as above, then decoded by a persistent grid of `grid`
 // waves, each with a region of scx_region_bytes(N).

@@ -802,8 +802,8 @@ __device__ __forceinline__ void nodeL(PS<L>& S, const CtxL<L>& C, uint32_t opc, 
   }
 }
 
-// ================================================= L = 4..32: one path per lane
-// The list stages of size L >= 4 (Algorithm 1 with the dedicated nodes of
+// ================================================= L = 2..32: one path per lane
+// The list stages of size L >= 2 (Algorithm 1 with the dedicated nodes of
 // Sec. II-B3 and the selection of Sec. II-B2) for the frames of a uniform
 // int8 batch whose next stage is L: 64 / L frames per wave, lane g L + r
 // holding path r of frame g.  Every lane runs its path's steps as in the
@@ -1483,7 +1483,7 @@ int launch_decode_listx(const KArgs& A, uint32_t grid, uint32_t* state, uint32_t
   return hipGetLastError() == hipSuccess ? POLAR_OK : POLAR_EHIP;
 }
 
-// The stage of size L >= 4 of the listed frames, 64 / L per wave
+// The stage of size L >= 2 of the listed frames, 64 / L per wave
 // (persistent grid, wave q takes the groups q, q + G, ...).  A frame whose
 // CRC passes, or whose plan ends at L, is finished (bits, status, metric
 // list, end stamp; state 0); the others get their next stage.
@@ -1627,7 +1627,9 @@ int launch_decode_listp(uint32_t L, const KArgs& A, uint32_t grid, uint32_t* sta
   hipLaunchKernelGGL(k_gather, dim3(gb > 0 ? gb : 1), dim3(256), 0, s, A.n_frames, L,
                      (const uint32_t*)state, xl);
   const dim3 gr(grid > 0 ? grid : 1);
-  if (L == 4)
+  if (L == 2)
+    hipLaunchKernelGGL(k_listp<2>, gr, dim3(64), 0, s, A, state, (const uint32_t*)xl);
+  else if (L == 4)
     hipLaunchKernelGGL(k_listp<4>, gr, dim3(64), 0, s, A, state, (const uint32_t*)xl);
   else if (L == 8)
     hipLaunchKernelGGL(k_listp<8>, gr, dim3(64), 0, s, A, state, (const uint32_t*)xl);
