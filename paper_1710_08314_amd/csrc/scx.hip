@@ -1,6 +1,14 @@
-// L = 1 tier of the decoder for uniform int8 batches on gfx950: successive
-// cancellation over the pruned tree (Sec. II-B1, II-B3), with the CRC check
-// of the adaptive schedules (Sec. II-B5), one frame per lane.
+// The decoder's stages for uniform int8 batches on gfx950, with the lanes of
+// a wave spread over frames (L = 1) or over the paths of a list:
+//   * k_scx: the L = 1 stage, successive cancellation over the pruned tree
+//     (Sec. II-B1, II-B3) with the CRC check of the adaptive schedules
+//     (Sec. II-B5), one frame per lane;
+//   * k_listx<L>: a list stage with a frame's L paths in one lane (kept for
+//     L = 2 where the path-per-lane stages do not apply);
+//   * k_listp<L>: a list stage (L = 2 .. 32) with one path per lane and
+//     64 / L frames per wave;
+//   * k_gather: the list of frames whose next stage is L.
+// This comment describes the L = 1 kernel; each list kernel has its own.
 //
 // Every frame of a uniform batch runs the same node program, and a list of
 // one path takes the same steps whatever the LLRs are, so a wave decodes 64
