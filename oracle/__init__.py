@@ -19,6 +19,9 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.cpp")
 _LIB = os.path.join(_HERE, "liboracle.so")
+# A build of a modified copy of oracle.cpp may be loaded instead, for the
+# mutation check of the pins (tests/oracle_mutations.py); never set otherwise.
+_LIB_OVERRIDE = os.environ.get("POLAR_ORACLE_LIB_OVERRIDE")
 
 F32, I16, I8, F64 = 0, 1, 2, 3
 SC, CA_SCL, PA_SCL, FA_SCL = 0, 1, 2, 3
@@ -62,9 +65,12 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-            build(force=True)
-        L = ctypes.CDLL(_LIB)
+        if _LIB_OVERRIDE:
+            L = ctypes.CDLL(_LIB_OVERRIDE)
+        else:
+            if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+                build(force=True)
+            L = ctypes.CDLL(_LIB)
         vp, i32, u64, dbl = ctypes.c_void_p, ctypes.c_int, ctypes.c_uint64, ctypes.c_double
         L.orc_logz_z0.argtypes = [i32, dbl, vp]
         L.orc_construct.argtypes = [i32, i32, i32, i32, dbl, vp]

@@ -636,7 +636,9 @@ int decode_frame(const orc_cfg& c, const void* llr_in, uint8_t* info_out, uint8_
     Scl<A> dec(c, stages[si]);
     dec.run(chan);
     dec.select(b_hat, x_hat, ok, pm, pm_list);
-    tie = dec.near_tie();
+    // near-tie over every stage run: a tie in a stage that failed its CRC
+    // could have decided that failure, and with it the later stages
+    tie = tie || dec.near_tie();
     used = stages[si];
     alive = dec.alive();
     if (ok) break;
