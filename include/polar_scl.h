@@ -143,9 +143,17 @@ typedef struct {
   uint8_t crc_ok;   /* 1: the output passed the CRC (always 1 without a CRC)     */
   uint8_t L_used;   /* list size of the stage whose output was taken              */
   uint8_t n_paths;  /* paths alive at the end of that stage                       */
-  uint8_t flags;    /* reserved, 0                                                */
+  uint8_t flags;    /* bit 0 (POLAR_STATUS_NEAR_TIE), float32 plans only: some
+                     * decision of the decode -- a selection of the L best
+                     * candidates (Sec. II-B2), or the final CRC choice in
+                     * metric order (Sec. II-B4) -- separated the kept path from
+                     * a rejected or passed-over one by a metric gap of at most
+                     * 1e-4 max(1, |metric|), in any stage run (Sec. II-B5);
+                     * another float rounding could then decide otherwise.
+                     * Always 0 in the integer modes.  Other bits 0.         */
   uint32_t pm;      /* path metric of the output: float32 bits, or int32 value    */
 } polar_status;
+#define POLAR_STATUS_NEAR_TIE 1u
 
 /* opts->flags: record HIP events on `stream` around every kernel launch of
  * the call (see polar_last_tier_ms). */

@@ -260,8 +260,9 @@ __device__ void sort_keys(const K* src, uint32_t cnt, K* dst, uint32_t keep) {
 // sel[rank].  Keys are read 16 bytes at a time (broadcast reads), the tail
 // one at a time.  Unlike a sorting network this has no chain of lane
 // exchanges: two dependent LDS round trips whatever the candidate count.
+// `over` (nullable) receives the key of rank `keep`, the best one rejected.
 template <typename K, int NT>
-__device__ void rank_select(const K* cand, uint32_t total, K* sel, uint32_t keep) {
+__device__ void rank_select(const K* cand, uint32_t total, K* sel, uint32_t keep, K* over) {
   constexpr uint32_t PER = 16 / sizeof(K);
   const uint4* c4 = reinterpret_cast<const uint4*>(cand);
   const uint32_t nv = total / PER;
@@ -279,8 +280,19 @@ __device__ void rank_select(const K* cand, uint32_t total, K* sel, uint32_t keep
     }
     for (uint32_t q = nv * PER; q < total; ++q) rank += cand[q] < k;
     if (rank < keep) sel[rank] = k;
+    if (over && rank == keep) *over = k;
   }
 }
+
+// Near-tie test (float32): the metric lo of the last kept candidate and hi
+// of the best rejected one (lo <= hi) within 1e-4 relative, in double.
+__device__ __forceinline__ bool tie_gap(float lo, float hi) {
+  return (double)hi - (double)lo <= 1e-4 * fmax(1.0, fabs((double)lo));
+}
+// LDS words of a stage's misc area: [0] chosen rank, [1] CRC passed, [2]
+// near-tie seen in this stage (float32), [4..5] the best rejected key of a
+// selection
+constexpr uint32_t kMiscTie = 2, kMiscOver = 4;
 
 // ------------------------------------------------------------ keys
 // Candidate key (metric, parent rank, local index), compared as one unsigned
@@ -702,8 +714,15 @@ __device__ void op_node(const Ctx& c, uint32_t opc, uint32_t d, uint32_t o, uint
   Key* sel = reinterpret_cast<Key*>(c.smem + c.lay.sel);
   const uint32_t total = a * C;
   const uint32_t keep = total < c.L ? total : c.L;
-  rank_select<Key, NT>(cand, total, sel, keep);
+  uint32_t* misc = reinterpret_cast<uint32_t*>(c.smem + c.lay.misc);
+  Key* over = reinterpret_cast<Key*>(misc + kMiscOver);
+  rank_select<Key, NT>(cand, total, sel, keep, VT<T>::INT ? nullptr : over);
   __syncthreads();
+  // float32: the L-th kept key against the best rejected one (R-21 reading)
+  if constexpr (!VT<T>::INT) {
+    if (tid == 0 && total > keep && tie_gap(key_pm<T>(sel[keep - 1]), key_pm<T>(*over)))
+      misc[kMiscTie] = 1u;
+  }
 
   // ---- path copy: partial-sum words [0, nwc) and slot pointers of depths
   // 1..d from each survivor's parent (register staged: all reads, barrier,
@@ -871,6 +890,20 @@ __device__ uint32_t end_of_stage(const Ctx& c, uint32_t a, bool* ok) {
     }
   }
   __syncthreads();
+  // float32 near-tie of the final choice: another path with the chosen
+  // metric within 1e-4 relative that also passes the CRC (any path when
+  // none passes)
+  if constexpr (!VT<T>::INT) {
+    if (tid < a) {
+      const uint32_t ch = misc[0], r = ord[tid];
+      const bool pass = misc[1] != 0;
+      if (r != ch && (!pass || syn[r] == 0u)) {
+        const double d = fabs((double)pm[r] - (double)pm[ch]);
+        if (d <= 1e-4 * fmax(1.0, fabs((double)pm[ch]))) atomicOr(&misc[kMiscTie], 1u);
+      }
+    }
+    __syncthreads();
+  }
   *ok = uni(misc[1]) != 0;
   return uni(misc[0]);
 }
@@ -920,6 +953,7 @@ __device__ void setup_stage(Ctx& c, uint32_t L, const char* llr) {
       cur += L * t[12 + d];
     }
     pm_tab<T>(c)[0] = (typename VT<T>::Acc)0;
+    reinterpret_cast<uint32_t*>(c.smem + c.lay.misc)[kMiscTie] = 0u;
   }
   __syncthreads();
 }
@@ -927,11 +961,14 @@ __device__ void setup_stage(Ctx& c, uint32_t L, const char* llr) {
 // Decode frame f: run the plan's list-size schedule (Sec. II-B5) from
 // `L_first`.  A frame whose stage at list size >= L_stop fails the CRC while
 // a larger stage remains is left for the list tier: returns false and writes
-// nothing.  Otherwise writes bits, status, the metric list and the end stamp.
+// nothing but *L_last and *tie.  Otherwise writes bits, status, the metric
+// list and the end stamp.  tie0: a near-tie already met by an earlier stage
+// (float32; status flag bit 0 covers every stage of the frame).
 template <typename T, int NT, int LMAX>
 __device__ bool decode_frame(char* smem, const KArgs& A, uint32_t f, const DevPlan* P,
                              const char* llr, uint32_t out_off, uint32_t L_first,
-                             uint32_t L_stop, uint32_t* L_last = nullptr) {
+                             uint32_t L_stop, uint32_t* L_last = nullptr, uint32_t tie0 = 0,
+                             uint32_t* tie_out = nullptr) {
   using Acc = typename VT<T>::Acc;
   P = uni_ptr(P);
   llr = uni_ptr(llr);
@@ -949,14 +986,20 @@ __device__ bool decode_frame(char* smem, const KArgs& A, uint32_t f, const DevPl
   uint32_t L = L_first, chosen = 0, a = 1;
   const uint32_t L_max = uni(P->L_max), algo = uni(P->algo);
   bool ok = false;
+  uint32_t tie = uni(tie0);
   for (;;) {
     setup_stage<T, NT>(c, L, llr);
     a = 1;
     run_program<T, NT, LMAX>(c, a);
     chosen = end_of_stage<T, NT>(c, a, &ok);
+    tie |= uni(reinterpret_cast<const uint32_t*>(c.smem + c.lay.misc)[kMiscTie]);
+    // every wave has read the stage's misc words before the next stage's
+    // layout (whose tables may sit there) is written
+    __syncthreads();
     if (ok || L >= L_max) break;
     if (L >= L_stop) {
       if (L_last) *L_last = L;
+      if (tie_out) *tie_out = tie;
       return false;
     }
     L = (algo == POLAR_PA_SCL) ? L_max : 2 * L;
@@ -994,7 +1037,7 @@ __device__ bool decode_frame(char* smem, const KArgs& A, uint32_t f, const DevPl
     st.crc_ok = ok ? 1 : 0;
     st.L_used = (uint8_t)L;
     st.n_paths = (uint8_t)a;
-    st.flags = 0;
+    st.flags = (uint8_t)tie;
     const Acc v = pm[chosen];
     if constexpr (VT<T>::INT)
       st.pm = (uint32_t)v;
@@ -1060,9 +1103,10 @@ __global__ __launch_bounds__(NW * 64) void k_decode_plain(KArgs A) {
   }
 }
 
-// Per-frame state of the tiered schedule (device scratch): state[f] = the
-// list size of frame f's next stage (a finished frame holds 0 or 1, which no
-// list tier takes).  Every frame starts at its plan's first stage.
+// Per-frame state of the tiered schedule (device scratch): bits 0..7 of
+// state[f] = the list size of frame f's next stage (a finished frame holds 0
+// or 1, which no list tier takes), bit 8 = a float32 near-tie met by an
+// earlier stage.  Every frame starts at its plan's first stage.
 __global__ void k_state_init(KArgs A, uint32_t* state) {
   const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
   for (uint32_t f = t; f < A.n_frames; f += gridDim.x * blockDim.x) {
@@ -1104,8 +1148,9 @@ __global__ __launch_bounds__(NW * 64, (list_waves_per_eu<T, NW>())) void k_decod
     if (base >= seg_hi) break;
     if (threadIdx.x < 64) {
       const uint32_t f = base + threadIdx.x;
-      const uint32_t L0 = (threadIdx.x < chunk && f < seg_hi) ? state[f] : 0u;
-      s_L0[threadIdx.x] = L0;
+      const uint32_t w0 = (threadIdx.x < chunk && f < seg_hi) ? state[f] : 0u;
+      s_L0[threadIdx.x] = w0;
+      const uint32_t L0 = w0 & 0xFFu;
       const unsigned long long b = __ballot(L0 >= L_lo && L0 <= L_hi);
       if (threadIdx.x == 0) s_mask = b;
     }
@@ -1115,17 +1160,17 @@ __global__ __launch_bounds__(NW * 64, (list_waves_per_eu<T, NW>())) void k_decod
       const uint32_t j = (uint32_t)(__ffsll((unsigned long long)mask) - 1);
       mask &= mask - 1ull;
       const uint32_t f = base + j;
-      const uint32_t L0 = uni(s_L0[j]);
+      const uint32_t w0 = uni(s_L0[j]), L0 = w0 & 0xFFu;
       const DevPlan* P;
       const char* llr;
       uint32_t out_off;
       frame_of(A, f, P, llr, out_off);
       if (L0 == P->first_stage && A.times && threadIdx.x == 0)
         A.times[2 * (size_t)f] = wall_clock64();
-      uint32_t L_last = L0;
-      const bool done =
-          decode_frame<T, NW * 64, LMAX>(smem, A, f, P, llr, out_off, L0, L_hi, &L_last);
-      if (threadIdx.x == 0) state[f] = done ? 0u : next_stage(P, L_last);
+      uint32_t L_last = L0, tie = 0;
+      const bool done = decode_frame<T, NW * 64, LMAX>(smem, A, f, P, llr, out_off, L0, L_hi,
+                                                       &L_last, (w0 >> 8) & 1u, &tie);
+      if (threadIdx.x == 0) state[f] = done ? 0u : (next_stage(P, L_last) | (tie << 8));
     }
     __syncthreads();
   }

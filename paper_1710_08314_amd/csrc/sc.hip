@@ -25,7 +25,10 @@
 // hard-decision candidate wins a tie, the all-zero REP candidate wins a tie,
 // and float32 metrics are summed in the stride-halving order.  Integer metrics
 // are normalised after every update, so they stay 0 at L = 1; only the REP
-// decision needs its saturated penalties.
+// decision needs its saturated penalties.  In float32 every forking decision
+// also compares the best candidate metric with the runner-up's: a gap
+// within 1e-4 relative flags the frame as a near-tie (bit 0 of its status
+// flags, or bit 8 of its state word when it moves on to a list).
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -71,11 +74,18 @@ __device__ __forceinline__ typename VT<T>::Acc magv(typename Lane<T>::V v) {
     return fabsf(v);
 }
 
+// Near-tie test of a selection (float32): the kept candidate's metric lo and
+// the best rejected one's hi (lo <= hi) within 1e-4 relative, in double.
+__device__ __forceinline__ uint32_t tie_gap(float lo, float hi) {
+  return (double)hi - (double)lo <= 1e-4 * fmax(1.0, fabs((double)lo)) ? 1u : 0u;
+}
+
 // Decision of a REP node at L = 1: the all-one candidate wins only when its
-// metric is strictly smaller.  Returns v and updates the (float) metric.
+// metric is strictly smaller.  Returns v and updates the (float) metric and
+// near-tie flag.
 template <typename T>
 __device__ __forceinline__ uint32_t rep_decide(typename VT<T>::Acc p0, typename VT<T>::Acc p1,
-                                               typename VT<T>::Acc& pm) {
+                                               typename VT<T>::Acc& pm, uint32_t& tie) {
   if constexpr (VT<T>::INT) {
     const int q0 = min(p0, VT<T>::Q), q1 = min(p1, VT<T>::Q);
     return q1 < q0 ? 1u : 0u;
@@ -83,8 +93,20 @@ __device__ __forceinline__ uint32_t rep_decide(typename VT<T>::Acc p0, typename 
     const float a0 = pm + p0, a1 = pm + p1;
     const uint32_t v = a1 < a0 ? 1u : 0u;
     pm = v ? a1 : a0;
+    tie |= v ? tie_gap(a1, a0) : tie_gap(a0, a1);
     return v;
   }
+}
+
+// Float32 near-tie of a Rate-1 node or information leaf at L = 1 (metric pm
+// before the node): the hard decision (penalty 0) against the Chase flip of
+// the least reliable position (penalty mn = its |alpha|).
+__device__ __forceinline__ uint32_t r1_tie(float pm, float mn) { return tie_gap(pm + 0.f, pm + mn); }
+// ... of an SPC node: with even parity the hard decision against the flip of
+// the two least reliable positions (m1 <= m2); with odd parity the flip of the
+// least reliable against that of the second.
+__device__ __forceinline__ uint32_t spc_tie(float pm, uint32_t odd, float m1, float m2) {
+  return odd ? tie_gap(pm + m1, pm + m2) : tie_gap(pm + 0.f, pm + ((0.f + m1) + m2));
 }
 
 // Butterfly reduction over aligned segments of M <= 32 lanes (stride-halving
@@ -104,6 +126,20 @@ __device__ __forceinline__ uint64_t seg_min64(uint64_t v, uint32_t M, uint32_t l
   }
   return v;
 }
+__device__ __forceinline__ float seg_minf(float v, uint32_t M, uint32_t lane) {
+  for (uint32_t s = M >> 1; s >= 1; s >>= 1) v = fminf(v, bperm(v, lane ^ s));
+  return v;
+}
+// The two smallest magnitudes (m1 <= m2) over aligned segments of M lanes,
+// each lane offering the key k = (|alpha| bits << 6) | position (unique per
+// position; ~0 for none): every lane ends with its segment's pair.
+__device__ __forceinline__ void seg_two_smallest(uint64_t k, uint32_t M, uint32_t lane, float& m1,
+                                                 float& m2) {
+  const uint64_t k1 = seg_min64(k, M, lane);
+  const uint64_t k2 = seg_min64(k == k1 ? ~0ull : k, M, lane);
+  m1 = __uint_as_float((uint32_t)(k1 >> 6));
+  m2 = __uint_as_float((uint32_t)(k2 >> 6));
+}
 // bits of the calling lane's half in a wave ballot
 __device__ __forceinline__ uint32_t half_bits(uint64_t bal, uint32_t hb) {
   return (uint32_t)(bal >> hb);
@@ -115,6 +151,7 @@ struct Regs {
   typename Lane<T>::V xs, x5, x6a, x6b;  // LLRs: levels 0..4, 5, 6 (elements l, l + 32)
   uint32_t bs, b5, b6a, b6b;             // partial sums of the last finished nodes
   uint32_t ls, l6, l7a, l7b;             // left children of the nodes being decoded
+  uint32_t tie;                          // float32: a decision of the frame was a near-tie
 };
 
 template <typename T>
@@ -213,12 +250,22 @@ __device__ __forceinline__ void node64(uint32_t opc, Regs<T>& R, typename VT<T>:
   const V xa = R.x6a, xb = R.x6b;
   const bool na = xa < (V)0, nb = xb < (V)0;
   const Acc ma = magv<T>(xa), mb = magv<T>(xb);
+  const Acc pm0 = pm;  // the metric before the node
   uint32_t ba = na ? 1u : 0u, bb = nb ? 1u : 0u;
   if (opc == OP_SPC) {
     const uint64_t pa = __ballot(na), pb = __ballot(nb);
     const uint32_t odd0 = (__popc((uint32_t)pa) + __popc((uint32_t)pb)) & 1u;
     const uint32_t odd1 = (__popc((uint32_t)(pa >> 32)) + __popc((uint32_t)(pb >> 32))) & 1u;
     const uint32_t odd = hb ? odd1 : odd0;
+    if constexpr (!VT<T>::INT) {
+      // the two least reliable of the 64 positions (two per lane)
+      const uint64_t ka = ((uint64_t)__float_as_uint(ma) << 6) | l;
+      const uint64_t kb = ((uint64_t)__float_as_uint(mb) << 6) | (l + 32);
+      const uint64_t k1 = seg_min64(ka < kb ? ka : kb, 32, lane);
+      const uint64_t k2 = seg_min64(ka == k1 ? kb : (kb == k1 ? ka : (ka < kb ? ka : kb)), 32, lane);
+      R.tie |= spc_tie(pm0, odd, __uint_as_float((uint32_t)(k1 >> 6)),
+                       __uint_as_float((uint32_t)(k2 >> 6)));
+    }
     if (odd0 | odd1) {
       uint64_t ka, kb;
       if constexpr (VT<T>::INT) {
@@ -242,13 +289,16 @@ __device__ __forceinline__ void node64(uint32_t opc, Regs<T>& R, typename VT<T>:
     // stride-halving: element i + 32 onto i first, then across the lanes
     const Acc p0 = seg_sum<Acc>((na ? ma : (Acc)0) + (nb ? mb : (Acc)0), 32, lane);
     const Acc p1 = seg_sum<Acc>((na ? (Acc)0 : ma) + (nb ? (Acc)0 : mb), 32, lane);
-    ba = bb = rep_decide<T>(p0, p1, pm);
+    ba = bb = rep_decide<T>(p0, p1, pm, R.tie);
   } else if (opc == OP_R0 || opc == OP_LF) {
     ba = bb = 0;
     if constexpr (!VT<T>::INT) {
       const float pen = seg_sum<float>((na ? ma : 0.f) + (nb ? mb : 0.f), 32, lane);
       pm = pm + pen;
     }
+  } else if constexpr (!VT<T>::INT) {
+    // Rate-1: the hard decision against the flip of the least reliable
+    R.tie |= r1_tie(pm0, seg_minf(fminf(ma, mb), 32, lane));
   }
   R.b6a = ba;
   R.b6b = bb;
@@ -272,11 +322,17 @@ __device__ __forceinline__ void reg_node(uint32_t opc, uint32_t K, Regs<T>& R,
   const V x = K == 5 ? x5v : xsv;
   const bool neg = x < (V)0;
   const Acc mg = magv<T>(x);
+  const Acc pm0 = pm;  // the metric before the node
   uint32_t bit = neg ? 1u : 0u;  // Rate-1 / information leaf: the hard decision
   if (opc == OP_SPC) {
     const uint64_t hd = __ballot(in && neg);
     const uint32_t odd0 = __popc((uint32_t)hd) & 1u, odd1 = __popc((uint32_t)(hd >> 32)) & 1u;
     const uint32_t odd = hb ? odd1 : odd0;
+    if constexpr (!VT<T>::INT) {
+      float m1, m2;
+      seg_two_smallest(in ? (((uint64_t)__float_as_uint(mg) << 6) | j) : ~0ull, M, lane, m1, m2);
+      R.tie |= spc_tie(pm0, odd, bperm(m1, first), bperm(m2, first));
+    }
     if (odd0 | odd1) {
       // least reliable position (smallest |alpha|, then smallest index)
       uint64_t key;
@@ -293,10 +349,14 @@ __device__ __forceinline__ void reg_node(uint32_t opc, uint32_t K, Regs<T>& R,
   } else if (opc == OP_REP) {
     const Acc p0 = bperm(seg_sum<Acc>(in && neg ? mg : (Acc)0, M, lane), first);
     const Acc p1 = bperm(seg_sum<Acc>(in && !neg ? mg : (Acc)0, M, lane), first);
-    bit = rep_decide<T>(p0, p1, pm);
+    bit = rep_decide<T>(p0, p1, pm, R.tie);
   } else if (opc == OP_R0 || opc == OP_LF) {
     bit = 0;
     if constexpr (!VT<T>::INT) pm = pm + bperm(seg_sum<float>(in && neg ? mg : 0.f, M, lane), first);
+  } else if constexpr (!VT<T>::INT) {
+    // Rate-1 or information leaf: the hard decision against the flip of the
+    // least reliable position
+    R.tie |= r1_tie(pm0, bperm(seg_minf(in ? mg : __int_as_float(0x7f800000), M, lane), first));
   }
   R.b5 = K == 5 ? bit : R.b5;
   R.bs = (K != 5 && in) ? bit : R.bs;
@@ -414,7 +474,8 @@ __device__ __forceinline__ void lds_op(char* fs, uint32_t N, uint32_t gr, const 
   }
   if (opc == OP_R1 || opc == OP_SPC) {
     uint32_t par = 0, w_lo = 0, w_hi = 0;
-    uint64_t key = ~0ull;
+    uint64_t key = ~0ull, key2 = ~0ull;  // the lane's two least reliable (float32 near-tie)
+    const Acc pm0 = pm;
     for (uint32_t t = 0; t < epl; ++t) {
       const uint32_t e = l + (t << 5);
       const V v = (V)src[e];
@@ -426,14 +487,22 @@ __device__ __forceinline__ void lds_op(char* fs, uint32_t N, uint32_t gr, const 
         else
           w_hi = w;
       }
-      if (opc == OP_SPC) {
-        uint64_t kk;
-        if constexpr (VT<T>::INT)
-          kk = ((uint64_t)(uint32_t)abs(v) << 16) | e;
-        else
-          kk = ((uint64_t)__float_as_uint(fabsf(v)) << 16) | e;
+      if constexpr (VT<T>::INT) {
+        if (opc == OP_SPC) {
+          const uint64_t kk = ((uint64_t)(uint32_t)abs(v) << 16) | e;
+          key = kk < key ? kk : key;
+        }
+      } else {
+        const uint64_t kk = ((uint64_t)__float_as_uint(fabsf(v)) << 16) | e;
+        key2 = kk < key ? key : (kk < key2 ? kk : key2);
         key = kk < key ? kk : key;
       }
+    }
+    if constexpr (!VT<T>::INT) {
+      const uint64_t k1 = seg_min64(key, 32, lane);
+      const uint64_t k2 = seg_min64(key == k1 ? key2 : key, 32, lane);
+      const float m1 = __uint_as_float((uint32_t)(k1 >> 16)), m2 = __uint_as_float((uint32_t)(k2 >> 16));
+      R.tie |= opc == OP_SPC ? spc_tie(pm0, par, m1, m2) : r1_tie(pm0, m1);
     }
     if (l < epl) nb[l] = w_lo;
     if (l + 32 < epl) nb[l + 32] = w_hi;
@@ -486,7 +555,7 @@ __device__ __forceinline__ void lds_op(char* fs, uint32_t N, uint32_t gr, const 
     p0 = seg_sum<float>(x0[0], 32, lane);
     p1 = seg_sum<float>(x1[0], 32, lane);
   }
-  const uint32_t v = rep_decide<T>(p0, p1, pm);
+  const uint32_t v = rep_decide<T>(p0, p1, pm, R.tie);
   for (uint32_t q = l; q < epl; q += 32) nb[q] = v ? ~0u : 0u;
   __syncthreads();
 }
@@ -553,6 +622,7 @@ __device__ void decode_pair(const KArgs& A, uint32_t* state, const ClassSel& sel
   Regs<T> R;
   R.xs = R.x5 = R.x6a = R.x6b = (V)0;
   R.bs = R.b5 = R.b6a = R.b6b = R.ls = R.l6 = R.l7a = R.l7b = 0u;
+  R.tie = 0u;
   Acc pm = (Acc)0;
   if (N <= 64) reg_load_root<T>(n, R, fs, l);  // whole code in registers
   // the next op word is fetched while the current op runs
@@ -614,7 +684,7 @@ __device__ void decode_pair(const KArgs& A, uint32_t* state, const ClassSel& sel
   // a frame of an adaptive plan whose L = 1 decision fails goes to the list tiers
   const uint32_t L_max = uni(P->L_max);
   const bool esc = on && !ok && L_max > 1 && !sel.on;
-  if (esc && l == 0) state[f] = next_stage(P, 1);
+  if (esc && l == 0) state[f] = next_stage(P, 1) | (R.tie << 8);
   const bool fin = on && !esc;
   // ---- outputs: information bits (data positions of A, ascending)
   uint32_t* out = reinterpret_cast<uint32_t*>(fs + sc_out_off(N, E, gr));
@@ -650,7 +720,7 @@ __device__ void decode_pair(const KArgs& A, uint32_t* state, const ClassSel& sel
       st.crc_ok = ok ? 1 : 0;
       st.L_used = 1;
       st.n_paths = 1;
-      st.flags = 0;
+      st.flags = (uint8_t)R.tie;
       if constexpr (VT<T>::INT)
         st.pm = 0u;
       else

@@ -1308,7 +1308,7 @@ __global__ __launch_bounds__(256) void k_gather(uint32_t n_frames, uint32_t L, c
   const uint32_t nw = (gridDim.x * blockDim.x) >> 6;
   for (uint32_t g = w0; 64u * g < n_frames; g += nw) {
     const uint32_t f = 64u * g + lane;
-    const bool take = f < n_frames && state[f] == L;
+    const bool take = f < n_frames && (state[f] & 0xFFu) == L;
     const uint64_t bal = __ballot(take);
     uint32_t base = 0;
     if (lane == 0 && bal) base = atomicAdd(&xl[0], (uint32_t)__popcll(bal));
@@ -1333,14 +1333,18 @@ __global__ __launch_bounds__(64) void k_listx(KArgs A, uint32_t* state, const ui
   const uint32_t* nib = uni_ptr(plan_tab(P, uni(P->off_crcnib)));
   const uint32_t* dmask = uni_ptr(plan_tab(P, uni(P->off_datamask)));
   char* region = A.spill + (size_t)blockIdx.x * A.spill_stride;
-  // the count through a vector load at device scope, not the scalar cache
-  const uint32_t count =
+  // the count through a vector load at device scope, not the scalar cache;
+  // a list never holds more frames than the batch, and the list's capacity
+  // is the batch size, so a count above it is never trusted
+  const uint32_t count0 =
       uni(__hip_atomic_load(&xl[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+  const uint32_t count = count0 < A.n_frames ? count0 : A.n_frames;
   const uint32_t n_groups = (count + 63u) / 64u;
   for (uint32_t q = blockIdx.x; q < n_groups; q += gridDim.x) {
     const uint32_t idx = 64u * q + lane;
     const bool valid = idx < count;
-    const uint32_t f = xl[1 + (valid ? idx : 64u * q)];
+    const uint32_t f0 = xl[1 + (valid ? idx : 64u * q)];
+    const uint32_t f = f0 < A.n_frames ? f0 : A.n_frames - 1u;
     CtxL<L> C;
     C.region = region;
     C.root = A.llr + (size_t)f * A.llr_bytes;
@@ -1509,14 +1513,18 @@ __global__ __launch_bounds__(64) void k_listp(KArgs A, uint32_t* state, const ui
   const uint32_t* nib = uni_ptr(plan_tab(P, uni(P->off_crcnib)));
   const uint32_t* dmask = uni_ptr(plan_tab(P, uni(P->off_datamask)));
   char* region = A.spill + (size_t)blockIdx.x * A.spill_stride;
-  // the count through a vector load at device scope, not the scalar cache
-  const uint32_t count =
+  // the count through a vector load at device scope, not the scalar cache;
+  // a list never holds more frames than the batch, and the list's capacity
+  // is the batch size, so a count above it is never trusted
+  const uint32_t count0 =
       uni(__hip_atomic_load(&xl[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+  const uint32_t count = count0 < A.n_frames ? count0 : A.n_frames;
   const uint32_t n_groups = (count + FW - 1u) / FW;
   for (uint32_t q = blockIdx.x; q < n_groups; q += gridDim.x) {
     const uint32_t idx = FW * q + gi;
     const bool valid = idx < count;
-    const uint32_t f = xl[1 + (valid ? idx : FW * q)];
+    const uint32_t f0 = xl[1 + (valid ? idx : FW * q)];
+    const uint32_t f = f0 < A.n_frames ? f0 : A.n_frames - 1u;
     CtxP C;
     C.region = region;
     C.root = A.llr + (size_t)f * A.llr_bytes;

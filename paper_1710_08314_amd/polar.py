@@ -458,5 +458,5 @@ def status_fields(status):
     """Split a [F, 8] uint8 status tensor (host numpy) into named arrays."""
     st = np.ascontiguousarray(status)
     return {"crc_ok": st[:, 0].astype(np.int32), "L_used": st[:, 1].astype(np.int32),
-            "n_paths": st[:, 2].astype(np.int32),
+            "n_paths": st[:, 2].astype(np.int32), "near_tie": (st[:, 3] & 1).astype(np.int32),
             "pm_bits": st[:, 4:8].copy().view(np.uint32).reshape(-1)}

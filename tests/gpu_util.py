@@ -87,6 +87,9 @@ def compare(code: O.Code, llr: np.ndarray, ref: O.Result | None = None, schedule
     assert np.array_equal(st["L_used"], ref.L_used), "L_used"
     assert np.array_equal(st["crc_ok"], ref.crc_ok), "crc_ok"
     assert np.array_equal(st["n_paths"], ref.n_pm), "paths alive"
+    # the near-tie flag: computed on both sides in float32, never set in int modes
+    tie_bad = np.nonzero(st["near_tie"] != ref.near_tie)[0]
+    assert len(tie_bad) == 0, f"near-tie flag: {len(tie_bad)} frames, first {tie_bad[:5]}"
     bit_eq = (bits == ref.info).all(axis=1)
     if code.quant == O.F32:
         tol = PM_RTOL * np.maximum(1.0, np.abs(ref.pm))

@@ -438,3 +438,55 @@ def test_sc_tier_frame_pairs(quant):
         same = np.array_equal(P.unpack_bits(w, codes[i].k_data), refs[i].info[f])
         assert same or (quant == "f32" and refs[i].near_tie[f] == 1), (k, i, f)
         assert st["crc_ok"][k] == refs[i].crc_ok[f]
+
+
+# ---------------------------------------------------------------- near ties
+ALL_INFO4 = np.zeros(4, dtype=np.uint8)
+
+
+@pytest.mark.parametrize("case", [
+    # (L, algo, L_max, nodes, crc, llr): the decodes worked out by hand in
+    # tests/test_oracle_hand.py -- a tie at the L-th selection boundary, a
+    # 1e-3 gap, a tie at the final choice, a tie met only by the first of two
+    # FA stages, and L = 1 / int-free variants of the same frames
+    (2, "ca", 2, O.NODE_ALL, (0, 0), [-1.0, 1.0, 1.0, 1.0]),
+    (2, "ca", 2, O.NODE_ALL, (0, 0), [-1.0, 1.001, 1.5, 1.5]),
+    (1, "sc", 1, O.NODE_ALL, (0, 0), [-1.0, 1.001, 1.5, 1.5]),
+    (4, "ca", 4, O.NODE_ALL, (0, 0), [0.0, 1.0, 1.0, 1.0]),
+    (1, "fa", 2, 0, (2, 0b11), [0.0, -2.0, -5.0, -3.0]),
+    (2, "ca", 2, 0, (2, 0b11), [0.0, -2.0, -5.0, -3.0]),
+    (1, "sc", 1, 0, (0, 0), [0.0, -2.0, -5.0, -3.0]),
+])
+@pytest.mark.parametrize("schedule", [0, 1])
+def test_near_tie_hand_cases(case, schedule):
+    L, algo, L_max, nodes, (c, poly), llr = case
+    code = O.Code(4, 4, ALL_INFO4, c, poly, quant=O.F32, algo=AMAP_T[algo], L=L, L_max=L_max,
+                  node_enable=nodes)
+    x = np.array([llr], dtype=np.float32)
+    ref = O.decode(code, x)
+    rep = compare(code, np.repeat(x, 3, axis=0), ref=O.decode(code, np.repeat(x, 3, axis=0)),
+                  schedule=schedule)
+    print(case, "near_tie", int(ref.near_tie[0]), rep)
+
+
+AMAP_T = {"sc": O.SC, "ca": O.CA_SCL, "pa": O.PA_SCL, "fa": O.FA_SCL}
+
+
+@pytest.mark.parametrize("N,K,c,poly,algo,L,Lmax,S", [
+    (64, 32, 8, 0x07, "sc", 1, 1, 0), (256, 128, 8, 0x07, "ca", 4, 4, 0),
+    (256, 128, 8, 0x07, "fa", 1, 32, 0), (1024, 512, 24, 0x1864CFB, "pa", 1, 8, 0),
+    (512, 200, 11, 0x621, "ca", 32, 32, 37), (2048, 1723, 32, 0x04C11DB7, "fa", 1, 32, 0)])
+@pytest.mark.parametrize("schedule", [0, 1])
+def test_near_tie_flag_on_coarse_llrs(N, K, c, poly, algo, L, Lmax, S, schedule):
+    """float32 LLRs on a grid of 0.5: equal metrics are common, so the flag is
+    set at selection boundaries, final choices and L = 1 decisions of every
+    node kind; it must equal the oracle's on every frame, metrics stay within
+    the tolerance, and the bits may differ only on flagged frames."""
+    code = _code(N, K, c, poly, 2.0 if N < 2048 else 4.5, S=S, quant="f32", algo=algo, L=L,
+                 L_max=Lmax)
+    _, llr = make_inputs(code, 160, 7100 + N + L, 1.5 if N < 2048 else 3.5)
+    llr = (np.round(llr.astype(np.float64) * 2.0) / 2.0).astype(np.float32)
+    ref = O.decode(code, llr, threads=8)
+    rep = compare(code, llr, ref=ref, schedule=schedule)
+    print(N, algo, L, Lmax, "flagged", int(ref.near_tie.sum()), "of", len(llr), rep)
+    assert ref.near_tie.sum() > 0

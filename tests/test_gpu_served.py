@@ -5,8 +5,8 @@ loop (continuous batching over several HIP streams with a frame budget).
 
 Each served result must equal the same request decoded in one plain batch of
 all requests, and decoded alone; sampled requests are checked against the
-oracle (int8 bit-exact; float32 within the metric tolerance, bits equal
-except oracle-flagged near-ties)."""
+oracle (int8 bit-exact; float32 metrics within the tolerance, bits equal
+except on near-tie frames, and the near-tie flag equal to the oracle's)."""
 import numpy as np
 import pytest
 
@@ -86,9 +86,10 @@ def _served_case(quant, alone_schedule):
             assert np.array_equal(bits, ref.info[0]), r
             assert g_pm == ref.pm[0], r
         else:
+            # bits may differ only on near-tie frames; metrics always within tolerance
             assert np.array_equal(bits, ref.info[0]) or ref.near_tie[0] == 1, r
-            assert abs(g_pm - ref.pm[0]) <= PM_RTOL * max(1.0, abs(ref.pm[0])) or \
-                ref.near_tie[0] == 1, r
+            assert abs(g_pm - ref.pm[0]) <= PM_RTOL * max(1.0, abs(ref.pm[0])), r
+        assert st["near_tie"][r] == ref.near_tie[0], r
     srv.close()
 
 
@@ -100,8 +101,9 @@ def test_served_equals_alone(quant):
 
 
 @pytest.mark.skip(reason="one-frame batches through the tiered schedule hung once on the GPU "
-                         "(escalation queues, since replaced by per-frame state words); the cause "
-                         "was not shown, so this case stays off the GPU")
+                         "(escalation queues, since replaced by per-frame state words); no cause "
+                         "was found by reading the old or the current code, so this case stays "
+                         "off the GPU")
 @pytest.mark.parametrize("quant", ["i8"])
 def test_served_equals_alone_tiered(quant):
     _served_case(quant, alone_schedule=0)
