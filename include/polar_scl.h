@@ -42,6 +42,8 @@ extern "C" {
 #define POLAR_EHIP (-4)      /* a HIP runtime call failed                        */
 #define POLAR_ENOTSYS (-5)   /* frozen set unusable for systematic encoding      */
 #define POLAR_EAGAIN (-6)    /* serving: no free slot or budget right now; poll  */
+#define POLAR_ESCRATCH (-7)  /* polar_scl_decode_batch_noalloc: the batch needs
+                              * more than its fixed device area                  */
 
 /* ------------------------------------------------------------ enumerations */
 /* LLR / path-metric arithmetic (Sec. III-B3).  Integer modes saturate to
@@ -206,6 +208,28 @@ int polar_scl_decode_batch(const polar_plan *plans, uint32_t n_plans,
                            const polar_frame *d_frames, uint32_t n_frames,
                            const void *d_llr, uint32_t *d_info, polar_status *d_status,
                            uint32_t *d_pm_lists, const polar_decode_opts *opts, void *stream);
+
+/* Allocation-free decode, for callers that cannot allocate device memory:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation.  Same arguments, outputs and kernels as polar_scl_decode_batch
+ * (opts->flags may not contain POLAR_OPT_TIER_TIMING or POLAR_OPT_AUTOTUNE:
+ * both create events; POLAR_EINVAL), but the call allocates nothing: its
+ * plan table, work area and spill regions live in a fixed device area of
+ * 96 MiB that the library holds once per GPU until the process ends (its
+ * address is looked up at the first polar_scl_plan on each device).
+ * Persistent grids are cut so that their spill regions fit the area, so a
+ * large batch may run on fewer workgroups than polar_scl_decode_batch uses.
+ * Limits: n_frames <= 2^21 and n_plans <= 16384, and the batch's largest
+ * spill region must fit; otherwise POLAR_ESCRATCH and nothing is enqueued.
+ * Every call on a GPU uses that GPU's one area and leaves its contents
+ * behind (each call clears what must start at zero with its own kernels):
+ * calls that overlap on one GPU -- on different streams, or from several
+ * host threads -- race and must be serialised by the caller. */
+int polar_scl_decode_batch_noalloc(const polar_plan *plans, uint32_t n_plans,
+                                   const polar_frame *d_frames, uint32_t n_frames,
+                                   const void *d_llr, uint32_t *d_info, polar_status *d_status,
+                                   uint32_t *d_pm_lists, const polar_decode_opts *opts,
+                                   void *stream);
 
 /* ---------------------------------------------------- encoder and channel */
 /* Systematic encoding with CRC attachment (Sec. II-A, Sec. II-B4): per frame,

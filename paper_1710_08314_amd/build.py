@@ -17,7 +17,7 @@ CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libpolar_scl.so")
 BUILD_DIR = os.path.join(PKG, "_build")
 
-HIP_SOURCES = ["decode.hip", "sc.hip", "scx.hip", "gen.hip"]
+HIP_SOURCES = ["decode.hip", "sc.hip", "scx.hip", "gen.hip", "noalloc.hip"]
 CPP_SOURCES = ["plan.cpp", "capi.cpp", "server.cpp"]
 
 ARCH = os.environ.get("POLAR_OFFLOAD_ARCH", "gfx950")

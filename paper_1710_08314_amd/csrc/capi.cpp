@@ -197,7 +197,9 @@ int polar_scl_plan(const polar_plan_desc* desc, polar_plan* out) {
     delete p;
     return rc;
   }
-  if (hipGetDevice(&p->device) != hipSuccess || ensure_attributes(p->device) != POLAR_OK) {
+  char* area = nullptr;  // set-up of the allocation-free entry point on this device
+  if (hipGetDevice(&p->device) != hipSuccess || ensure_attributes(p->device) != POLAR_OK ||
+      polar::noalloc_area(&area) != POLAR_OK) {
     delete p;
     return POLAR_EHIP;
   }
@@ -324,7 +326,7 @@ namespace polar {
 
 int prepare(const polar_plan* plans, uint32_t n_plans, const polar_frame* d_frames,
             uint32_t n_frames, const void* d_llr, uint32_t* d_info, polar_status* d_status,
-            uint32_t* d_pm_lists, const polar_decode_opts* opts, Batch* b) {
+            uint32_t* d_pm_lists, const polar_decode_opts* opts, Batch* b, bool upload_table) {
   if (!plans || n_plans == 0) return POLAR_EINVAL;
   for (uint32_t i = 0; i < n_plans; ++i)
     if (!plans[i]) return POLAR_EINVAL;
@@ -342,8 +344,10 @@ int prepare(const polar_plan* plans, uint32_t n_plans, const polar_frame* d_fram
   b->plans.assign(plans, plans + n_plans);
   int rc = POLAR_OK;
   polar::KArgs& A = b->A;
-  A.plans = plan_table(plans, n_plans, &rc);
-  if (rc) return rc;
+  if (upload_table || n_plans == 1) {
+    A.plans = plan_table(plans, n_plans, &rc);
+    if (rc) return rc;
+  }
   A.frames = d_frames;
   A.n_frames = n_frames;
   A.llr = static_cast<const char*>(d_llr);
@@ -438,8 +442,10 @@ int build_classes(const Batch& b, const ClassConfig& cfg, int cus,
       if (k == polar::CK_SC)
         cl.grid = n_frames;  // one wave per frame, frames outside the class exit at once
       else
-        cl.grid = persistent_grid(cus, cl.lds, k == polar::CK_W1_L4 ? 32 : (k == polar::CK_W2_L8 ? 8 : 4),
-                                  (n_frames + 63) / 64 * 64);
+        cl.grid = polar::cap_grid(
+            persistent_grid(cus, cl.lds, k == polar::CK_W1_L4 ? 32 : (k == polar::CK_W2_L8 ? 8 : 4),
+                            (n_frames + 63) / 64 * 64),
+            cl.spill, b.spill_cap);
       out->push_back(cl);
     }
   return out->size() <= polar::kMaxClasses ? POLAR_OK : POLAR_EUNSUP;
@@ -493,8 +499,9 @@ int plan_tiers(const Batch& b, polar::TierPlan* out) {
         const uint32_t cap = (per_cu < 16u ? per_cu : 16u) * (uint32_t)cus;
         const uint32_t rounds = groups > cap ? (groups + cap - 1) / cap : 1u;
         tp.sc_x = 1;
-        tp.grid_scx = groups ? (groups + rounds - 1) / rounds : 1u;
         tp.spill_sc = polar::scx_region_bytes(h.N);
+        tp.grid_scx = polar::cap_grid(groups ? (groups + rounds - 1) / rounds : 1u, tp.spill_sc,
+                                      b.spill_cap);
         // the L = 2 stage the same way, when the schedule has one and every
         // REP / SPC node fits the register levels (<= 32 positions)
         const bool fa = h.algo == POLAR_FA_SCL;
@@ -512,8 +519,9 @@ int plan_tiers(const Batch& b, polar::TierPlan* out) {
         const uint32_t cap2 = 12u * (uint32_t)cus;
         if (stage2 && small) {
           tp.run_x2 = 1;
-          tp.grid_x2 = groups < cap2 ? (groups ? groups : 1u) : cap2;
           tp.spill_x2 = polar::listx_region_bytes(h.N, 2);
+          tp.grid_x2 = polar::cap_grid(groups < cap2 ? (groups ? groups : 1u) : cap2, tp.spill_x2,
+                                       b.spill_cap);
         }
         // list stages: one path per lane when each of them is 2, 4, 8, 16 or
         // 32 (then also in place of the frame-per-lane L = 2 stage; waves per
@@ -540,7 +548,8 @@ int plan_tiers(const Batch& b, polar::TierPlan* out) {
             const uint32_t need = (n_frames + fw - 1) / fw;
             const uint32_t capp = (pst[i] <= 8 ? 16u : 12u) * (uint32_t)cus;
             tp.p_stage[i] = pst[i];
-            tp.grid_p[i] = need < capp ? (need ? need : 1u) : capp;
+            tp.grid_p[i] = polar::cap_grid(need < capp ? (need ? need : 1u) : capp, tp.spill_p,
+                                           b.spill_cap);
           }
         }
       }
@@ -550,10 +559,10 @@ int plan_tiers(const Batch& b, polar::TierPlan* out) {
   tp.grid_sc = n_frames < 0x7FFFFFFFu ? n_frames : 0x7FFFFFFFu;
   tp.lds_a = sa.lds;
   tp.spill_a = sa.spill;
-  tp.grid_a = persistent_grid(cus, sa.lds, 32, n_frames);
+  tp.grid_a = polar::cap_grid(persistent_grid(cus, sa.lds, 32, n_frames), sa.spill, b.spill_cap);
   tp.lds_b = b.lds;
   tp.spill_b = sb.spill;
-  tp.grid_b = persistent_grid(cus, b.lds, 8, n_frames);
+  tp.grid_b = polar::cap_grid(persistent_grid(cus, b.lds, 8, n_frames), sb.spill, b.spill_cap);
   // frames claimed at a time: about n / (32 workgroups' worth), so that the
   // frames a tier has to decode spread evenly over its workgroups; at most 64
   // (one wave's worth of state words), at least 1
@@ -571,7 +580,8 @@ int plan_tiers(const Batch& b, polar::TierPlan* out) {
 // (one spill region per workgroup) when a stage spills.
 uint32_t plain_grid(const Batch& b, int cus, uint64_t spill) {
   const uint32_t n = b.A.n_frames;
-  return spill ? persistent_grid(cus, b.lds, polar::kLdsLimit, n) : (n < 0x7FFFFFFFu ? n : 0x7FFFFFFFu);
+  return spill ? polar::cap_grid(persistent_grid(cus, b.lds, polar::kLdsLimit, n), spill, b.spill_cap)
+               : (n < 0x7FFFFFFFu ? n : 0x7FFFFFFFu);
 }
 
 const char* kernel_name(uint32_t k) {
@@ -769,6 +779,62 @@ int polar_scl_decode_batch(const polar_plan* plans, uint32_t n_plans, const pola
                       (flags & POLAR_OPT_TIER_TIMING) != 0, (flags & POLAR_OPT_AUTOTUNE) != 0);
 }
 
+int polar_scl_decode_batch_noalloc(const polar_plan* plans, uint32_t n_plans,
+                                   const polar_frame* d_frames, uint32_t n_frames,
+                                   const void* d_llr, uint32_t* d_info, polar_status* d_status,
+                                   uint32_t* d_pm_lists, const polar_decode_opts* opts,
+                                   void* stream) {
+  if (!plans || n_plans == 0) return POLAR_EINVAL;
+  for (uint32_t i = 0; i < n_plans; ++i)
+    if (!plans[i]) return POLAR_EINVAL;
+  const uint32_t flags = opts ? opts->flags : 0;
+  // timing and autotuning create events: not for callers that cannot allocate
+  if (flags & (POLAR_OPT_TIER_TIMING | POLAR_OPT_AUTOTUNE)) return POLAR_EINVAL;
+  const uint32_t schedule = opts ? opts->schedule : 0;
+  if (schedule > 1) return POLAR_EINVAL;
+  if (n_frames == 0) return POLAR_OK;
+  if (n_frames > polar::kNoAllocMaxFrames || n_plans > polar::kNoAllocMaxPlans)
+    return POLAR_ESCRATCH;
+  char* base = nullptr;
+  int rc = polar::noalloc_area(&base);
+  if (rc) return rc;
+  Batch b;
+  rc = prepare(plans, n_plans, d_frames, n_frames, d_llr, d_info, d_status, d_pm_lists, opts, &b,
+               false);
+  if (rc) return rc;
+  // area: [plan table (multi-plan batches)] [work area] [spill regions], each 256-byte aligned
+  auto up256 = [](uint64_t v) { return (v + 255u) & ~(uint64_t)255u; };
+  const uint64_t tab_bytes = n_plans > 1 ? up256((uint64_t)n_plans * sizeof(void*)) : 0;
+  const uint64_t work_bytes = up256(polar::work_words(n_frames) * sizeof(uint32_t));
+  if (tab_bytes + work_bytes >= polar::kNoAllocBytes) return POLAR_ESCRATCH;
+  Work w = work_view(reinterpret_cast<uint32_t*>(base + tab_bytes), n_frames);
+  b.spill_cap = polar::kNoAllocBytes - tab_bytes - work_bytes;
+  int dev = 0, cus = 1;
+  if (hipGetDevice(&dev) != hipSuccess) return POLAR_EHIP;
+  rc = device_cus(dev, &cus);
+  if (rc) return rc;
+  // every grid is cut to the spill room; a single region larger than it fails
+  const uint64_t need = polar::spill_need(b, cus);
+  if (need > b.spill_cap) return POLAR_ESCRATCH;
+  if (need) {
+    w.spill = base + tab_bytes + work_bytes;
+    w.spill_bytes = b.spill_cap;
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (n_plans > 1) {
+    const void* h[256];
+    const polar::DevPlan** tab = reinterpret_cast<const polar::DevPlan**>(base);
+    for (uint32_t i = 0; i < n_plans; i += 256) {
+      const uint32_t m = n_plans - i < 256 ? n_plans - i : 256;
+      for (uint32_t j = 0; j < m; ++j) h[j] = plans[i + j]->d_blob;
+      rc = polar::launch_store_ptrs(reinterpret_cast<const void**>(tab + i), h, m, st);
+      if (rc) return rc;
+    }
+    b.A.plans = tab;
+  }
+  return launch_batch(b, schedule, w, st, false, false);
+}
+
 int polar_last_tier_ms(float ms[5]) {
   if (!ms || !g_timing.valid) return POLAR_EINVAL;
   for (int i = 0; i < 5; ++i) ms[i] = 0.f;
@@ -960,6 +1026,8 @@ const char* polar_strerror(int err) {
     case POLAR_EHIP: return "HIP runtime error";
     case POLAR_ENOTSYS: return "frozen set not usable for systematic encoding";
     case POLAR_EAGAIN: return "no free serving slot or budget; poll and retry";
+    case POLAR_ESCRATCH:
+      return "batch exceeds the fixed device area of the allocation-free entry point";
     default: return "unknown error";
   }
 }

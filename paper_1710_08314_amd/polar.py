@@ -33,7 +33,8 @@ ELEM_BYTES = {F32: 4, I16: 2, I8: 1}
 ERRORS = {0: "success", -1: "invalid argument", -2: "unsupported configuration",
           -3: "out of memory", -4: "HIP runtime error",
           -5: "frozen set not usable for systematic encoding",
-          -6: "no free serving slot or budget"}
+          -6: "no free serving slot or budget",
+          -7: "batch exceeds the fixed device area of the allocation-free entry point"}
 EAGAIN = -6
 
 
@@ -73,7 +74,7 @@ class _ServerCfg(ctypes.Structure):
 
 EXPORTS = ["polar_scl_plan", "polar_plan_destroy", "polar_plan_get_info", "polar_plan_get_frozen",
            "polar_plan_query",
-           "polar_scl_decode_batch", "polar_encode", "polar_gen_data", "polar_channel",
+           "polar_scl_decode_batch", "polar_scl_decode_batch_noalloc", "polar_encode", "polar_gen_data", "polar_channel",
            "polar_plan_stage_work", "polar_device_clock_khz", "polar_last_tier_ms",
            "polar_schedule_describe", "polar_graph_create", "polar_graph_launch",
            "polar_graph_destroy", "polar_server_create", "polar_server_submit",
@@ -93,6 +94,7 @@ def _load():
     L.polar_plan_get_frozen.argtypes = [vp, vp]
     L.polar_plan_query.argtypes = [ctypes.POINTER(_Desc), ctypes.POINTER(_Info), vp]
     L.polar_scl_decode_batch.argtypes = [vp, u32, vp, u32, vp, vp, vp, vp, vp, vp]
+    L.polar_scl_decode_batch_noalloc.argtypes = [vp, u32, vp, u32, vp, vp, vp, vp, vp, vp]
     L.polar_encode.argtypes = [vp, vp, vp, u32, vp]
     L.polar_gen_data.argtypes = [vp, u64, u64, u32, vp, vp]
     L.polar_channel.argtypes = [vp, vp, u32, ctypes.c_float, i32, u64, u64, vp, vp]
@@ -419,6 +421,24 @@ def decode_batch(plans, llr, frames=None, n_frames=None, with_pm_lists=False, sc
                                       ctypes.byref(opts), _stream_ptr(stream)),
            "polar_scl_decode_batch")
     return info, status, pml
+
+
+def decode_batch_noalloc(plans, llr, info, status, pm_lists=None, frames=None, n_frames=None,
+                         schedule=0, stream=None):
+    """polar_scl_decode_batch_noalloc: the decode of decode_batch into output
+    tensors the caller provides (info, status and optional pm_lists, shaped as
+    decode_batch returns them), using the library's fixed device area."""
+    if isinstance(plans, Plan):
+        plans = [plans]
+    if n_frames is None:
+        n_frames = frames.shape[0] if frames is not None else llr.shape[0]
+    arr = (ctypes.c_void_p * len(plans))(*[p.handle.value for p in plans])
+    opts = _Opts(schedule, 0, None)
+    _check(lib.polar_scl_decode_batch_noalloc(arr, len(plans), _dptr(frames), n_frames,
+                                              _dptr(llr), _dptr(info), _dptr(status),
+                                              _dptr(pm_lists), ctypes.byref(opts),
+                                              _stream_ptr(stream)),
+           "polar_scl_decode_batch_noalloc")
 
 
 def encode(plan: Plan, data, stream=None):
