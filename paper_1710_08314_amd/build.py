@@ -17,7 +17,11 @@ CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libpolar_scl.so")
 BUILD_DIR = os.path.join(PKG, "_build")
 
-HIP_SOURCES = ["decode.hip", "sc.hip", "scx.hip", "gen.hip", "noalloc.hip"]
+HIP_SOURCES = ["decode.hip", "sc.hip", "scx.hip", "rq.hip", "gen.hip", "noalloc.hip"]
+# Per-file flags.  rq.hip keeps a path's whole state in registers, reached
+# through a switch over tree levels; merging the cases' common stores would
+# turn those registers into stack memory.
+EXTRA = {"rq.hip": ["-mllvm", "-simplifycfg-sink-common=false"]}
 CPP_SOURCES = ["plan.cpp", "capi.cpp", "server.cpp"]
 
 ARCH = os.environ.get("POLAR_OFFLOAD_ARCH", "gfx950")
@@ -55,7 +59,8 @@ def build(verbose: bool = False) -> str:
     jobs = []
     for src in HIP_SOURCES:
         obj = os.path.join(BUILD_DIR, src + ".o")
-        jobs.append([hipcc, *COMMON, *DEVICE, *inc, "-c", os.path.join(CSRC, src), "-o", obj])
+        jobs.append([hipcc, *COMMON, *DEVICE, *EXTRA.get(src, []), *inc, "-c",
+                     os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
     for src in CPP_SOURCES:
         obj = os.path.join(BUILD_DIR, src + ".o")

@@ -517,6 +517,14 @@ int plan_tiers(const Batch& b, polar::TierPlan* out) {
         // path-per-lane stages below replace it when they cover every list
         // stage of the plan
         const uint32_t cap2 = 12u * (uint32_t)cus;
+        // N = 2048 with REP / SPC nodes in the register levels: four lanes per
+        // frame, the state in registers (2 waves per SIMD: its registers)
+        if (small && h.n == 11) {
+          const uint32_t g16 = (n_frames + 15) / 16, capq = 8u * (uint32_t)cus;
+          tp.sc_q = 1;
+          tp.n_ops = h.n_ops;
+          tp.grid_q = g16 < capq ? (g16 ? g16 : 1u) : capq;
+        }
         if (stage2 && small) {
           tp.run_x2 = 1;
           tp.spill_x2 = polar::listx_region_bytes(h.N, 2);
@@ -550,6 +558,10 @@ int plan_tiers(const Batch& b, polar::TierPlan* out) {
             tp.p_stage[i] = pst[i];
             tp.grid_p[i] = polar::cap_grid(need < capp ? (need ? need : 1u) : capp, tp.spill_p,
                                            b.spill_cap);
+            // four lanes per path: 16 / L frames per wave, 2 waves per SIMD
+            const uint32_t nq = (n_frames + 16u / pst[i] - 1u) / (16u / pst[i] < 1u ? 1u : 16u / pst[i]);
+            const uint32_t capq = 8u * (uint32_t)cus;
+            tp.grid_ql[i] = nq < capq ? (nq ? nq : 1u) : capq;
           }
         }
       }
@@ -663,9 +675,10 @@ uint64_t spill_need(const Batch& b, int cus) {
   };
   TierPlan tp{};
   if (plan_tiers(b, &tp) == POLAR_OK) {
-    if (tp.run_sc && tp.sc_x) upd(tp.grid_scx, tp.spill_sc);
+    if (tp.run_sc && tp.sc_x && !tp.sc_q) upd(tp.grid_scx, tp.spill_sc);
     if (tp.run_x2) upd(tp.grid_x2, tp.spill_x2);
-    for (uint32_t i = 0; tp.run_p && i < tp.n_p; ++i) upd(tp.grid_p[i], tp.spill_p);
+    for (uint32_t i = 0; tp.run_p && i < tp.n_p; ++i)
+      if (!(tp.sc_q && tp.p_stage[i] <= 16)) upd(tp.grid_p[i], tp.spill_p);
     if (tp.run_a) upd(tp.grid_a, tp.spill_a);
     if (tp.run_b) upd(tp.grid_b, tp.spill_b);
   }

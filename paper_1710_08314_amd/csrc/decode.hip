@@ -1325,7 +1325,10 @@ static int launch_tiered_t(const KArgs& A, const TierPlan& tp, uint32_t* state, 
   hipLaunchKernelGGL(k_heads_reset, dim3(1), dim3(64), 0, s, heads, 2 * kClaimSegs);
   hipLaunchKernelGGL(k_state_init, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, s, A, state);
   if (ev) (void)hipEventRecord(ev[0], s);
-  if (tp.run_sc && tp.sc_x) {
+  if (tp.run_sc && tp.sc_q) {
+    const int rc = launch_decode_rq1(A, tp.n_ops, tp.grid_q, state, s);
+    if (rc) return rc;
+  } else if (tp.run_sc && tp.sc_x) {
     KArgs As = A;
     As.spill_stride = tp.spill_sc;
     const int rc = launch_decode_scx(As, tp.grid_scx, state, s);
@@ -1357,7 +1360,9 @@ static int launch_tiered_t(const KArgs& A, const TierPlan& tp, uint32_t* state, 
     KArgs Ap = A;
     Ap.spill_stride = tp.spill_p;
     for (uint32_t i = 0; i < tp.n_p; ++i) {
-      const int rc = launch_decode_listp(tp.p_stage[i], Ap, tp.grid_p[i], state, xl, s);
+      const int rc = tp.sc_q && tp.p_stage[i] <= 16
+                         ? launch_decode_rqL(tp.p_stage[i], A, tp.n_ops, tp.grid_ql[i], state, xl, s)
+                         : launch_decode_listp(tp.p_stage[i], Ap, tp.grid_p[i], state, xl, s);
       if (rc) return rc;
     }
   } else if (tp.run_b) {

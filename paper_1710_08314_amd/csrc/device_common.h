@@ -55,6 +55,33 @@ __device__ __forceinline__ int g_opi(int a, int b, uint32_t s) {
   return max(-Q, min(Q, v));
 }
 
+// ------------------------------------ packed int8 element arithmetic
+// Four int8 LLRs per 32-bit word, element i in byte i.
+__device__ __forceinline__ int sx8(uint32_t w, int i) { return (int)(int8_t)(w >> (8 * i)); }
+
+// f of four packed elements
+__device__ __forceinline__ uint32_t f4(uint32_t a, uint32_t b) {
+  uint32_t r = 0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) r |= (uint32_t)(uint8_t)f_opi(sx8(a, i), sx8(b, i)) << (8 * i);
+  return r;
+}
+// g of four packed elements (saturated at the int8 range); bit i of s is the
+// left partial sum of element i
+__device__ __forceinline__ uint32_t g4(uint32_t a, uint32_t b, uint32_t s) {
+  uint32_t r = 0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+    r |= (uint32_t)(uint8_t)g_opi<VT<int8_t>::Q>(sx8(a, i), sx8(b, i), (s >> i) & 1u) << (8 * i);
+  return r;
+}
+// hard decisions (sign bits) of four packed elements, element i at bit i:
+// the sign bits 7, 15, 23, 31 are gathered into bits 28..31 by one product
+// whose partial terms never overlap
+__device__ __forceinline__ uint32_t hd4(uint32_t w) {
+  return ((w & 0x80808080u) * 0x00204081u) >> 28;
+}
+
 template <typename T>
 __device__ __forceinline__ typename VT<T>::Acc as_acc(T v) {
   return (typename VT<T>::Acc)v;

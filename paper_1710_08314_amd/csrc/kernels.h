@@ -63,6 +63,12 @@ struct TierPlan {
                               // (k_listp) in place of list tiers A and B
   uint32_t p_stage[5], grid_p[5], n_p;  // those stages in order and their grids (waves)
   uint64_t spill_p;           // region bytes per wave (scx_region_bytes)
+  uint32_t sc_q;              // the L = 1 stage runs four lanes per frame, its state in
+                              // registers (k_rq1, N = 2048), in place of k_scx
+  uint32_t grid_q;            // its persistent grid (waves)
+  uint32_t n_ops;             // program words of the batch's plan (uniform batches)
+  uint32_t grid_ql[5];        // with sc_q: grids of the list stages L <= 16, which then run
+                              // four lanes per path (k_rq) in place of k_listp
 };
 // state: n_frames words; heads: 2 x kClaimSegs claim counters (tier A, then
 // tier B), cleared by a kernel launched before the state init.
@@ -119,6 +125,22 @@ int launch_decode_listx(const KArgs& A, uint32_t grid, uint32_t* state, uint32_t
 int launch_decode_listp(uint32_t L, const KArgs& A, uint32_t grid, uint32_t* state, uint32_t* xl,
                         hipStream_t s);
 int launch_decode_scx(const KArgs& A, uint32_t grid, uint32_t* state, hipStream_t s);
+// The L = 1 stage with four lanes per frame and the decoder state in
+// registers (rq.hip), for the batches of k_scx with N = 2048 whose REP and
+// SPC nodes have at most 32 positions: 16 frames per wave, a persistent grid
+// of `grid` waves, no spill region; the plan's program (n_ops words) is
+// staged in LDS.
+int launch_decode_rq1(const KArgs& A, uint32_t n_ops, uint32_t grid, uint32_t* state,
+                      hipStream_t s);
+// The list stage of size L = 2, 4, 8 or 16 the same way (rq.hip), 16 / L
+// frames per wave, for the frames whose next stage is L (listed in xl by
+// launch_gather first).  Finished frames get state 0, the others their next
+// stage.
+int launch_decode_rqL(uint32_t L, const KArgs& A, uint32_t n_ops, uint32_t grid, uint32_t* state,
+                      uint32_t* xl, hipStream_t s);
+// The frames whose next stage is L, listed in xl (xl[0] = count, then their
+// indices in no set order; scx.hip).
+int launch_gather(uint32_t n_frames, uint32_t L, const uint32_t* state, uint32_t* xl, hipStream_t s);
 
 // Class schedule of a batch of fixed-list plans (no escalation): the frames
 // are split into classes by list size and code length, and each class is

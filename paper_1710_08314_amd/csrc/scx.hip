@@ -50,31 +50,6 @@ namespace {
 
 constexpr int kQ = VT<int8_t>::Q;  // saturation of the int8 LLRs
 
-// -------------------------------------------- packed int8 element arithmetic
-__device__ __forceinline__ int sx8(uint32_t w, int i) { return (int)(int8_t)(w >> (8 * i)); }
-
-// f of four packed elements
-__device__ __forceinline__ uint32_t f4(uint32_t a, uint32_t b) {
-  uint32_t r = 0;
-#pragma unroll
-  for (int i = 0; i < 4; ++i) r |= (uint32_t)(uint8_t)f_opi(sx8(a, i), sx8(b, i)) << (8 * i);
-  return r;
-}
-// g of four packed elements; bit i of s is the left partial sum of element i
-__device__ __forceinline__ uint32_t g4(uint32_t a, uint32_t b, uint32_t s) {
-  uint32_t r = 0;
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-    r |= (uint32_t)(uint8_t)g_opi<kQ>(sx8(a, i), sx8(b, i), (s >> i) & 1u) << (8 * i);
-  return r;
-}
-// hard decisions (sign bits) of four packed elements, element i at bit i:
-// the sign bits 7, 15, 23, 31 are gathered into bits 28..31 by one product
-// whose partial terms never overlap
-__device__ __forceinline__ uint32_t hd4(uint32_t w) {
-  return ((w & 0x80808080u) * 0x00204081u) >> 28;
-}
-
 struct Chunk {
   uint32_t w[4];  // 16 packed LLRs
 };
@@ -1634,6 +1609,13 @@ __global__ __launch_bounds__(64) void k_listp(KArgs A, uint32_t* state, const ui
       for (uint32_t t = r; t < A.pm_stride; t += L)
         A.pm_lists[(size_t)f * A.pm_stride + t] = t == r ? mine : 0xFFFFFFFFu;
   }
+}
+
+int launch_gather(uint32_t n_frames, uint32_t L, const uint32_t* state, uint32_t* xl, hipStream_t s) {
+  const uint32_t gb = (n_frames + 255u) / 256u < 1024u ? (n_frames + 255u) / 256u : 1024u;
+  hipLaunchKernelGGL(k_xreset, dim3(1), dim3(64), 0, s, xl);
+  hipLaunchKernelGGL(k_gather, dim3(gb > 0 ? gb : 1), dim3(256), 0, s, n_frames, L, state, xl);
+  return hipGetLastError() == hipSuccess ? POLAR_OK : POLAR_EHIP;
 }
 
 int launch_decode_listp(uint32_t L, const KArgs& A, uint32_t grid, uint32_t* state, uint32_t* xl,
