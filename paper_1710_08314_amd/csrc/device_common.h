@@ -59,27 +59,47 @@ __device__ __forceinline__ int g_opi(int a, int b, uint32_t s) {
 // Four int8 LLRs per 32-bit word, element i in byte i.
 __device__ __forceinline__ int sx8(uint32_t w, int i) { return (int)(int8_t)(w >> (8 * i)); }
 
-// f of four packed elements
+// f and g of four packed elements work on pairs of 16-bit lanes: element i
+// of a word goes to the high byte of a 16-bit lane (v_perm_b32), so that the
+// packed 16-bit min / max / add instructions compute on 256 times the value
+// and the result is the high bytes again.  For values in [-127, 127] this is
+// exactly f_opi / g_opi.
+typedef short s16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ s16x2 as_s16x2(uint32_t v) { return __builtin_bit_cast(s16x2, v); }
+__device__ __forceinline__ uint32_t as_u32(s16x2 v) { return __builtin_bit_cast(uint32_t, v); }
+// f of four packed elements: max(min(a, b), -max(a, b))
 __device__ __forceinline__ uint32_t f4(uint32_t a, uint32_t b) {
-  uint32_t r = 0;
-#pragma unroll
-  for (int i = 0; i < 4; ++i) r |= (uint32_t)(uint8_t)f_opi(sx8(a, i), sx8(b, i)) << (8 * i);
-  return r;
+  const s16x2 z = {0, 0};
+  const s16x2 al = as_s16x2(__builtin_amdgcn_perm(0u, a, 0x010C000Cu));
+  const s16x2 ah = as_s16x2(__builtin_amdgcn_perm(0u, a, 0x030C020Cu));
+  const s16x2 bl = as_s16x2(__builtin_amdgcn_perm(0u, b, 0x010C000Cu));
+  const s16x2 bh = as_s16x2(__builtin_amdgcn_perm(0u, b, 0x030C020Cu));
+  const s16x2 rl = __builtin_elementwise_max(__builtin_elementwise_min(al, bl),
+                                             z - __builtin_elementwise_max(al, bl));
+  const s16x2 rh = __builtin_elementwise_max(__builtin_elementwise_min(ah, bh),
+                                             z - __builtin_elementwise_max(ah, bh));
+  return __builtin_amdgcn_perm(as_u32(rh), as_u32(rl), 0x07050301u);
 }
-// g of four packed elements (saturated at the int8 range); bit i of s is the
-// left partial sum of element i
+// g of four packed elements, saturated at [-127, 127]; bit i of s is the left
+// partial sum of element i.  b's low bytes are 0xFF and a negated operand
+// is its bitwise complement (-256 a - 1), so the 16-bit sum's high byte is
+// b + a or b - a exactly; the clamped add and a max at -127 * 256 saturate.
 __device__ __forceinline__ uint32_t g4(uint32_t a, uint32_t b, uint32_t s) {
-  uint32_t r = 0;
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-    r |= (uint32_t)(uint8_t)g_opi<VT<int8_t>::Q>(sx8(a, i), sx8(b, i), (s >> i) & 1u) << (8 * i);
-  return r;
+  const uint32_t al = __builtin_amdgcn_perm(0u, a, 0x010C000Cu);
+  const uint32_t ah = __builtin_amdgcn_perm(0u, a, 0x030C020Cu);
+  const s16x2 bl = as_s16x2(__builtin_amdgcn_perm(0u, b, 0x010D000Du));
+  const s16x2 bh = as_s16x2(__builtin_amdgcn_perm(0u, b, 0x030D020Du));
+  const uint32_t ml = ((s & 1u) ? 0xFFFFu : 0u) | ((s & 2u) ? 0xFFFF0000u : 0u);
+  const uint32_t mh = ((s & 4u) ? 0xFFFFu : 0u) | ((s & 8u) ? 0xFFFF0000u : 0u);
+  const s16x2 lo = {-127 * 256, -127 * 256};
+  const s16x2 rl = __builtin_elementwise_max(__builtin_elementwise_add_sat(bl, as_s16x2(al ^ ml)), lo);
+  const s16x2 rh = __builtin_elementwise_max(__builtin_elementwise_add_sat(bh, as_s16x2(ah ^ mh)), lo);
+  return __builtin_amdgcn_perm(as_u32(rh), as_u32(rl), 0x07050301u);
 }
 // hard decisions (sign bits) of four packed elements, element i at bit i:
-// the sign bits 7, 15, 23, 31 are gathered into bits 28..31 by one product
-// whose partial terms never overlap
+// a dot product of the sign bits with the weights 1, 2, 4, 8
 __device__ __forceinline__ uint32_t hd4(uint32_t w) {
-  return ((w & 0x80808080u) * 0x00204081u) >> 28;
+  return __builtin_amdgcn_udot4((w >> 7) & 0x01010101u, 0x08040201u, 0u, false);
 }
 
 template <typename T>

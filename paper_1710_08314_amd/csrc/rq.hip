@@ -65,6 +65,12 @@ __device__ __forceinline__ uint32_t q_min(uint32_t v) {
 
 constexpr uint32_t lowmask(int n) { return n >= 32 ? 0xFFFFFFFFu : ((1u << n) - 1u); }
 
+// a load from global memory (plan tables, channel LLRs) through a global
+// rather than a flat pointer
+__device__ __forceinline__ uint32_t gld(const uint32_t* p) {
+  return *(const __attribute__((address_space(1))) uint32_t*)(p);
+}
+
 // ---------------------------------------------------------- path registers
 struct RQ {
   // LLRs of the current node of levels 10 .. 0 (words per lane: 2^(K-4) for
@@ -183,16 +189,12 @@ __device__ __forceinline__ void fg_root(RQ& R, const uint32_t* rw, uint32_t q) {
   constexpr int WC = 1 << (NL - 5);
   constexpr int HALF = 1 << (NL - 3);  // words of half the root
   const uint32_t* rq = rw + q;
-  // eight words at a time: the loads of one group are consumed before the
-  // next group is issued, which bounds the registers in flight
+  // all loads issued together (the child's registers are free to take
+  // them), one memory latency per step
 #pragma unroll
-  for (int j0 = 0; j0 < WC; j0 += 8) {
-#pragma unroll
-    for (int j = j0; j < j0 + 8 && j < WC; ++j) {
-      const uint32_t a = rq[4 * j], c = rq[4 * j + HALF];
-      X<NL - 1>(R, j) = G ? g4(a, c, sgn4<NL>(R, j)) : f4(a, c);
-    }
-    __builtin_amdgcn_sched_barrier(0);
+  for (int j = 0; j < WC; ++j) {
+    const uint32_t a = gld(rq + 4 * j), c = gld(rq + 4 * j + HALF);
+    X<NL - 1>(R, j) = G ? g4(a, c, sgn4<NL>(R, j)) : f4(a, c);
   }
 }
 
@@ -269,7 +271,7 @@ __device__ __forceinline__ void node1(RQ& R, uint32_t opc, uint32_t q) {
     for (int w = 0; w < NW; ++w) R.b[w] = hd[w];
     return;
   }
-  constexpr int WX = K >= 4 ? (1 << (K - 4)) : (K == 3 ? 2 : 1);  // LLR words per lane
+  constexpr int WX = K >= 4 ? (1 << (K >= 4 ? K - 4 : 0)) : (K == 3 ? 2 : 1);  // LLR words per lane
   constexpr int EW = K >= 2 ? 4 : (1 << K);                       // elements per word
   if (opc == OP_REP) {
     int p0 = 0, p1 = 0;
@@ -481,7 +483,7 @@ __device__ __forceinline__ void fork(RQ& R, PL& S, const Geo& G, uint32_t k0, ui
 // (|alpha| << 12) | element
 template <int K, int T>
 __device__ __forceinline__ void least(RQ& R, uint32_t q, uint32_t (&s)[T]) {
-  constexpr int WX = K >= 4 ? (1 << (K - 4)) : (K == 3 ? 2 : 1);
+  constexpr int WX = K >= 4 ? (1 << (K >= 4 ? K - 4 : 0)) : (K == 3 ? 2 : 1);
   constexpr int EW = K >= 2 ? 4 : (1 << K);
 #pragma unroll
   for (int t = 0; t < T; ++t) s[t] = 0xFFFFFFFFu;
@@ -520,7 +522,7 @@ __device__ __forceinline__ void least(RQ& R, uint32_t q, uint32_t (&s)[T]) {
 template <int K, int L>
 __device__ __forceinline__ void nodeL(RQ& R, PL& S, const Geo& G, uint32_t opc, uint32_t& a) {
   constexpr int NW = nwords(K);
-  constexpr int WX = K >= 4 ? (1 << (K - 4)) : (K == 3 ? 2 : 1);
+  constexpr int WX = K >= 4 ? (1 << (K >= 4 ? K - 4 : 0)) : (K == 3 ? 2 : 1);
   constexpr int EW = K >= 2 ? 4 : (1 << K);
   const bool act = G.r < a;
   uint32_t hd[NW];
@@ -713,6 +715,47 @@ __device__ __forceinline__ void node_any(RQ& R, PL& S, const Geo& G, uint32_t op
 #undef POLAR_N
 }
 
+// Fused steps of the node program: f at level K and the left child (a node
+// of level K - 1 <= 6), or g at level K, the right child and h at level K.
+template <int NL, int L, int K, bool GNH>
+__device__ __forceinline__ void fused_step(RQ& R, PL& S, const Geo& G, uint32_t sub,
+                                           const uint32_t* rw, uint32_t& a) {
+  if constexpr (K == NL) {
+    if constexpr (L == 1)
+      fg_root<NL, GNH>(R, rw, G.q);
+    else
+      fg_rootL<NL, GNH>(R, S, rw, G.q, G.Q);
+  } else if constexpr (L == 1) {
+    fg_reg<K, GNH>(R, G.q);
+  } else {
+    fg_regL<K, GNH>(R, S, G.q, G.Q);
+  }
+  if constexpr (L == 1)
+    node1<K - 1>(R, sub, G.q);
+  else
+    nodeL<K - 1, L>(R, S, G, sub, a);
+  if constexpr (GNH && K < NL) {
+    if constexpr (L == 1)
+      h_step<K>(R, G.q);
+    else
+      h_stepL<K>(R, S, G.q);
+  }
+}
+template <int NL, int L, bool GNH>
+__device__ __forceinline__ void fused_any(RQ& R, PL& S, const Geo& G, uint32_t sub, uint32_t k,
+                                          const uint32_t* rw, uint32_t& a) {
+  // the child has at most 64 positions: K <= 7
+  switch (k) {
+    case 7: if constexpr (7 <= NL) fused_step<NL, L, 7, GNH>(R, S, G, sub, rw, a); break;
+    case 6: if constexpr (6 <= NL) fused_step<NL, L, 6, GNH>(R, S, G, sub, rw, a); break;
+    case 5: fused_step<NL, L, 5, GNH>(R, S, G, sub, rw, a); break;
+    case 4: fused_step<NL, L, 4, GNH>(R, S, G, sub, rw, a); break;
+    case 3: fused_step<NL, L, 3, GNH>(R, S, G, sub, rw, a); break;
+    case 2: fused_step<NL, L, 2, GNH>(R, S, G, sub, rw, a); break;
+    default: fused_step<NL, L, 1, GNH>(R, S, G, sub, rw, a); break;
+  }
+}
+
 }  // namespace
 
 // One stage of list size L (1, 2, 4, 8 or 16) of a uniform int8 batch of a
@@ -739,9 +782,10 @@ __global__ __launch_bounds__(64, 2) void k_rq(KArgs A, uint32_t* state, const ui
   G.fl = G.lane & (4u * L - 1u);
   const uint32_t gi = G.Q / L;
   const DevPlan* P = uni_ptr(A.plans[0]);
-  const uint32_t n_ops = uni(P->n_ops);
+  // the program with fused steps (f or g merged with an adjacent child node)
+  const uint32_t n_ops = uni(P->n_sc_ops);
   const uint32_t iw = uni(A.info_words), L_max = uni(P->L_max), c_len = uni(P->c);
-  const uint32_t* prog = uni_ptr(plan_tab(P, uni(P->off_prog)));
+  const uint32_t* prog = uni_ptr(plan_tab(P, uni(P->off_sc_prog)));
   const uint32_t* imask = uni_ptr(plan_tab(P, uni(P->off_infomask)));
   const uint32_t* nib = uni_ptr(plan_tab(P, uni(P->off_crcnib)));
   const uint32_t* dmask = uni_ptr(plan_tab(P, uni(P->off_datamask)));
@@ -790,11 +834,18 @@ __global__ __launch_bounds__(64, 2) void k_rq(KArgs A, uint32_t* state, const ui
       // from it (element indices, addresses) is hoisted out of the walk and
       // held in registers for its whole length
       Geo Go = G;
-      asm volatile("" : "+v"(Go.lane), "+v"(Go.q), "+v"(Go.Q), "+v"(Go.r), "+v"(Go.g0), "+v"(Go.fl));
+      if constexpr (L == 1)
+        asm volatile("" : "+v"(Go.q));
+      else
+        asm volatile("" : "+v"(Go.lane), "+v"(Go.q), "+v"(Go.Q), "+v"(Go.r), "+v"(Go.g0), "+v"(Go.fl));
       if (opc == OP_F || opc == OP_G)
         fg_any<NL, L>(R, S, opc == OP_G, k, rw, Go.q, Go.Q);
       else if (opc == OP_H)
         h_any<NL, L>(R, S, k, Go.q);
+      else if (opc == OP_FN)
+        fused_any<NL, L, false>(R, S, Go, op_sub(w), k, rw, a);
+      else if (opc == OP_GNH)
+        fused_any<NL, L, true>(R, S, Go, op_sub(w), k, rw, a);
       else
         node_any<NL, L>(R, S, Go, opc, k, a);
     }
@@ -816,7 +867,10 @@ __global__ __launch_bounds__(64, 2) void k_rq(KArgs A, uint32_t* state, const ui
     // nibble table (information positions only)
     uint32_t syn = 0;
     if (c_len > 0) {
-      for (uint32_t wd = G.q; wd < (1u << (NL - 5)); wd += 4u) {
+      // unrolled, so that every table lookup of the frame is in flight at once
+#pragma unroll
+      for (int i = 0; i < (1 << (NL - 7)); ++i) {
+        const uint32_t wd = 4u * i + G.q;
         const uint4 lb = *reinterpret_cast<const uint4*>(&cw[G.Q][wd >> 2][0]);
         const uint32_t sh = 8u * (wd & 3u);
         const uint32_t l4[4] = {(lb.x >> sh) & 0xFFu, (lb.y >> sh) & 0xFFu, (lb.z >> sh) & 0xFFu,
@@ -825,11 +879,12 @@ __global__ __launch_bounds__(64, 2) void k_rq(KArgs A, uint32_t* state, const ui
 #pragma unroll
         for (int t = 0; t < 4; ++t)
           x |= ((l4[t] & 15u) << (4 * t)) | ((l4[t] >> 4) << (16 + 4 * t));
-        const uint32_t im = imask[wd], xv = x & im;
+        // every nibble looked up (a nibble with no information position
+        // masks to 0, whose table entry is 0), so the loads go out together
+        const uint32_t xv = x & gld(imask + wd);
         const uint32_t* nw = nib + (wd << 7);
 #pragma unroll
-        for (int t = 0; t < 8; ++t)
-          if ((im >> (4 * t)) & 15u) syn ^= nw[(t << 4) | ((xv >> (4 * t)) & 15u)];
+        for (int t = 0; t < 8; ++t) syn ^= gld(nw + ((t << 4) | ((xv >> (4 * t)) & 15u)));
       }
       syn = q_xor(syn);
     }
@@ -852,8 +907,10 @@ __global__ __launch_bounds__(64, 2) void k_rq(KArgs A, uint32_t* state, const ui
     }
     // ---- data bits of the output path, packed into its quad's output words
     if (win && fin)
-      for (uint32_t wd = G.q; wd < (1u << (NL - 5)); wd += 4u) {
-        uint32_t dm = dmask[wd];
+#pragma unroll
+      for (int i = 0; i < (1 << (NL - 7)); ++i) {
+        const uint32_t wd = 4u * i + G.q;
+        uint32_t dm = gld(dmask + wd);
         if (!dm) continue;
         const uint4 lb = *reinterpret_cast<const uint4*>(&cw[G.Q][wd >> 2][0]);
         const uint32_t sh = 8u * (wd & 3u);
@@ -870,7 +927,7 @@ __global__ __launch_bounds__(64, 2) void k_rq(KArgs A, uint32_t* state, const ui
           ++cnt;
           dm &= dm - 1u;
         }
-        const uint32_t p0 = prefix[wd], o = p0 & 31u;
+        const uint32_t p0 = gld(prefix + wd), o = p0 & 31u;
         atomicOr(&stage[G.Q][p0 >> 5], v << o);
         if (o + cnt > 32u) atomicOr(&stage[G.Q][(p0 >> 5) + 1u], v >> (32u - o));
       }

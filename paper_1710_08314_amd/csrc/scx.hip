@@ -1278,17 +1278,32 @@ __global__ void k_xreset(uint32_t* xl) {
 }
 __global__ __launch_bounds__(256) void k_gather(uint32_t n_frames, uint32_t L, const uint32_t* state,
                                                 uint32_t* xl) {
+  // each wave takes chunks of kGatherGroups groups of 64 frames: it counts
+  // the chunk's frames, reserves their places with one atomic, then writes
+  // them (the chunk's state words are read twice, the second time from cache)
+  constexpr uint32_t kGatherGroups = 16;
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t w0 = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const uint32_t nw = (gridDim.x * blockDim.x) >> 6;
-  for (uint32_t g = w0; 64u * g < n_frames; g += nw) {
-    const uint32_t f = 64u * g + lane;
-    const bool take = f < n_frames && (state[f] & 0xFFu) == L;
-    const uint64_t bal = __ballot(take);
+  const uint32_t n_groups = (n_frames + 63u) / 64u;
+  for (uint32_t c = w0; kGatherGroups * c < n_groups; c += nw) {
+    const uint32_t g_end = min(n_groups, kGatherGroups * (c + 1u));
+    uint32_t tot = 0;
+    for (uint32_t g = kGatherGroups * c; g < g_end; ++g) {
+      const uint32_t f = 64u * g + lane;
+      tot += (uint32_t)__popcll(__ballot(f < n_frames && (state[f] & 0xFFu) == L));
+    }
+    if (!tot) continue;
     uint32_t base = 0;
-    if (lane == 0 && bal) base = atomicAdd(&xl[0], (uint32_t)__popcll(bal));
+    if (lane == 0) base = atomicAdd(&xl[0], tot);
     base = __shfl(base, 0, 64);
-    if (take) xl[1 + base + (uint32_t)__popcll(bal & ((1ull << lane) - 1ull))] = f;
+    for (uint32_t g = kGatherGroups * c; g < g_end; ++g) {
+      const uint32_t f = 64u * g + lane;
+      const bool take = f < n_frames && (state[f] & 0xFFu) == L;
+      const uint64_t bal = __ballot(take);
+      if (take) xl[1 + base + (uint32_t)__popcll(bal & ((1ull << lane) - 1ull))] = f;
+      base += (uint32_t)__popcll(bal);
+    }
   }
 }
 
