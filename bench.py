@@ -357,7 +357,10 @@ def bench_served(args):
         ms_plain = e0.elapsed_time(e1)
         hist = np.bincount(b_st[:, 1].cpu().numpy(), minlength=9)
         per_rate = {}
-        srv = P.Server(n_slots=4, max_batch=16384, max_inflight=65536)
+        # admission by frames and by device bytes (each request charged its
+        # plan's in-flight figure): half of what 65,536 of the largest take
+        budget = 65536 * max(p.frame_bytes() for p in plans) // 2
+        srv = P.Server(n_slots=4, max_batch=16384, max_inflight=65536, budget_bytes=budget)
         for k, rate in enumerate(synth.C4_RATES_MREQ):
             rng = np.random.default_rng(4200 + k)
             gaps = rng.exponential(1.0 / rate, size=n)  # us
@@ -365,7 +368,7 @@ def bench_served(args):
             info = torch.zeros(max(n_words, 1), dtype=torch.int32, device="cuda")
             status = torch.zeros((n, 8), dtype=torch.uint8, device="cuda")
             torch.cuda.synchronize()
-            done_us, stats = srv.replay(plans, d_fr, arrival, d_llr, info, status)
+            done_us, stats = srv.replay(plans, d_fr, arrival, d_llr, info, status, plan_of=plan_of)
             torch.cuda.synchronize()
             same = bool(torch.equal(status, b_st) and torch.equal(info[:n_words], b_info[:n_words]))
             lat = done_us - arrival
@@ -375,7 +378,9 @@ def bench_served(args):
                 "latency_p50_us": round(float(np.percentile(lat, 50)), 1),
                 "latency_p99_us": round(float(np.percentile(lat, 99)), 1),
                 "batches": stats["batches"], "mean_batch": round(stats["mean_batch"], 1),
-                "peak_inflight": stats["peak_inflight"], "results_equal_batch": same}
+                "peak_inflight": stats["peak_inflight"],
+                "peak_inflight_bytes": stats["peak_inflight_bytes"], "budget_bytes": budget,
+                "results_equal_batch": same}
             print(f"served {quant} {rate} Mreq/s: {per_rate[str(rate)]}", file=sys.stderr,
                   flush=True)
         srv.close()

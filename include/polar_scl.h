@@ -255,6 +255,16 @@ int polar_gen_data(polar_plan p, uint64_t seed, uint64_t frame0, uint32_t n_fram
 int polar_channel(polar_plan p, const uint32_t *d_code, uint32_t n_frames, float ebn0_db,
                   int32_t frac_bits, uint64_t seed, uint64_t frame0, void *d_llr, void *stream);
 
+/* The LLR quantiser of the fixed-point decoders (Sec. III-B3): n float32
+ * LLRs (device) to the type of `quant` (polar_quant) in d_out (device, n
+ * elements): q = clamp(rint(llr * 2^frac_bits), -Q, Q) with rounding half
+ * to even, Q = 127 (int8, the paper's 6 integer + 2 fractional bits at
+ * frac_bits = 2) or 32767 (int16); infinities saturate, NaN gives +Q;
+ * POLAR_F32 copies.  Async on `stream`.  POLAR_EINVAL for a bad quant or
+ * frac_bits outside 0..14. */
+int polar_quantize(const float *d_llr, uint32_t n, int32_t quant, int32_t frac_bits, void *d_out,
+                   void *stream);
+
 /* Algorithmic work of one decoding stage of plan p at list size L, counted
  * from the node program and the deterministic growth of the active list
  * (a <- min(L, a * candidates) at every forking node): f and g LLR updates
@@ -299,33 +309,57 @@ int polar_graph_destroy(polar_graph g);
 
 /* -------------------------------------------------------------- serving */
 /* Continuous batching of decode requests on one device.  A server owns
- * `n_slots` HIP streams, each with a work area for up to `max_batch` frames.
- * A submitted batch (a range of a caller's frame descriptors whose LLRs are
- * already in device memory) is admitted when a slot is free and the frames
- * in flight stay within `max_inflight`; it is then enqueued at once on the
- * slot's stream, so batches admitted while others run overlap on the device.
- * All decoding, including the adaptive list escalation (Sec. II-B5), happens
- * on the device without host round trips; the host only admits and polls. */
+ * `n_slots` HIP streams, each with a work area for up to `max_batch` frames
+ * and a fixed spill area, all allocated by polar_server_create.  A submitted
+ * batch (a range of a caller's frame descriptors whose LLRs are already in
+ * device memory) is admitted when a slot is free and the admission budget
+ * holds it; it is then enqueued at once on the slot's stream, so batches
+ * admitted while others run overlap on the device.  All decoding, including
+ * the adaptive list escalation (Sec. II-B5), happens on the device without
+ * host round trips; the host only admits and polls.
+ *
+ * Admission budget: frames in flight stay within `max_inflight`, and, with
+ * budget_bytes > 0, the device bytes of the frames in flight stay within
+ * budget_bytes, a frame being charged polar_plan_frame_bytes of its plan
+ * (its LLRs, outputs, work-area words and the decoder state of its largest
+ * list stage). */
 typedef struct {
   uint32_t n_slots;       /* concurrent batches (HIP streams), 1..64             */
   uint32_t max_batch;     /* frames per batch                                    */
-  uint32_t max_inflight;  /* admission budget: frames admitted, not yet complete */
-  uint32_t reserved;
+  uint32_t max_inflight;  /* frames admitted, not yet complete                   */
+  uint32_t reserved;      /* 0                                                   */
+  uint64_t budget_bytes;  /* 0: no byte budget; else the bytes admitted, not yet
+                           * complete, stay within it                            */
+  uint64_t slot_spill_bytes; /* spill area per slot (0: 64 MiB); persistent grids
+                              * of a batch are cut to fit it, and a batch whose
+                              * largest spill region does not fit is refused
+                              * with POLAR_EUNSUP                                 */
 } polar_server_config;
 
 typedef struct polar_server_s *polar_server;
 
 int polar_server_create(const polar_server_config *cfg, polar_server *out);
 
+/* Device bytes one in-flight frame of plan p is charged by a server's byte
+ * budget: its channel LLRs, information words and status, its work-area
+ * entries, and the decoder state of its largest list stage (the LDS
+ * footprint of that stage's layout, plus any part of it kept in global
+ * memory). */
+int polar_plan_frame_bytes(polar_plan p, uint64_t *bytes);
+
 /* Admit one batch: frames [first, first + count) of d_frames, decoded as by
  * polar_scl_decode_batch with schedule 0 (outputs at the descriptors' out_off
- * in d_info, statuses at d_status[first ..]).  Returns POLAR_OK and *slot, or
- * POLAR_EAGAIN when no slot is free or the budget is full (nothing enqueued),
- * POLAR_EINVAL when count exceeds max_batch.  `tag` is returned by poll. */
+ * in d_info, statuses at d_status[first ..]).  h_plan_idx (nullable) is a
+ * host copy of the batch's plan indices (count entries, those of
+ * d_frames[first ..]) used to charge the byte budget; without it every frame
+ * is charged the most of the plan list.  Returns POLAR_OK and *slot, or
+ * POLAR_EAGAIN when no slot is free or the budget cannot take the batch
+ * (nothing enqueued), POLAR_EINVAL when count exceeds max_batch.  The call
+ * allocates no device memory.  `tag` is returned by poll. */
 int polar_server_submit(polar_server s, const polar_plan *plans, uint32_t n_plans,
                         const polar_frame *d_frames, uint32_t first, uint32_t count,
-                        const void *d_llr, uint32_t *d_info, polar_status *d_status,
-                        uint64_t tag, uint32_t *slot);
+                        const uint32_t *h_plan_idx, const void *d_llr, uint32_t *d_info,
+                        polar_status *d_status, uint64_t tag, uint32_t *slot);
 
 /* Non-blocking: the tags of batches that completed since the last poll
  * (up to max), their slots freed.  *n receives the count. */
@@ -338,16 +372,18 @@ int polar_server_destroy(polar_server s);
 
 /* Serving session over requests pre-staged in device memory: request r is
  * frame r of d_frames and arrives at host time arrival_us[r] (microseconds
- * after the call starts, non-decreasing).  The loop releases requests at
- * their arrival times and, whenever a slot and budget are free, admits every
- * released request not yet admitted (up to max_batch) as one batch; it polls
- * completions and writes, per request, the host-observed completion time
- * (us, same clock) to complete_us.  stats (nullable, 4 values): batches,
- * mean frames per batch, largest frames in flight, session length in us. */
+ * after the call starts, non-decreasing); h_plan_of (nullable) holds their
+ * plan indices on the host, for the byte budget.  The loop releases
+ * requests at their arrival times and, whenever a slot and budget are free,
+ * admits the released requests not yet admitted (up to max_batch, and as
+ * many as the budget takes) as one batch; it polls completions and writes,
+ * per request, the host-observed completion time (us, same clock) to
+ * complete_us.  stats (nullable, 5 values): batches, mean frames per batch,
+ * largest frames in flight, session length in us, largest bytes in flight. */
 int polar_serve_replay(polar_server s, const polar_plan *plans, uint32_t n_plans,
                        const polar_frame *d_frames, uint32_t n_req, const double *arrival_us,
-                       const void *d_llr, uint32_t *d_info, polar_status *d_status,
-                       double *complete_us, double *stats);
+                       const uint32_t *h_plan_of, const void *d_llr, uint32_t *d_info,
+                       polar_status *d_status, double *complete_us, double *stats);
 
 /* --------------------------------------------------------------- misc */
 /* Frequency of the device realtime counter used by d_times, in kHz, for the

@@ -18,6 +18,7 @@
 
 struct polar_plan_s {
   polar::HostPlan hp;
+  uint64_t frame_bytes = 0;  // device bytes an in-flight frame is charged (serving budget)
   int device = 0;
   polar::DevPlan* d_blob = nullptr;
   const polar::DevPlan** d_self = nullptr;  // one-entry device plan table
@@ -203,6 +204,20 @@ int polar_scl_plan(const polar_plan_desc* desc, polar_plan* out) {
     delete p;
     return POLAR_EHIP;
   }
+  {
+    // LLRs, outputs, status, work-area words, and the decoder state of the
+    // largest stage of the schedule (its layout's LDS and global parts)
+    const polar::DevPlan& h = p->hp.hdr;
+    const uint32_t E = polar::elem_bytes(h.quant);
+    uint64_t state = 0;
+    for (uint32_t L = h.first_stage;; L = polar::stage_after(h.algo == POLAR_PA_SCL, h.L_max, L)) {
+      const polar::LdsLayout lay = polar::lds_layout(h.N, h.n, E, L, polar::key_bytes(h.quant));
+      const uint64_t v = (uint64_t)lay.total + lay.gbytes;
+      state = v > state ? v : state;
+      if (L >= h.L_max) break;
+    }
+    p->frame_bytes = (uint64_t)h.n_tx * E + 4ull * h.info_words + sizeof(polar_status) + 8 + state;
+  }
   const size_t bytes = p->hp.blob.size() * 4;
   if (hipMalloc(&p->d_blob, bytes) != hipSuccess) {
     delete p;
@@ -275,6 +290,12 @@ int polar_plan_query(const polar_plan_desc* desc, polar_plan_info* info, uint32_
   return POLAR_OK;
 }
 
+int polar_plan_frame_bytes(polar_plan p, uint64_t* bytes) {
+  if (!p || !bytes) return POLAR_EINVAL;
+  *bytes = p->frame_bytes;
+  return POLAR_OK;
+}
+
 int polar_plan_get_frozen(polar_plan p, uint32_t* fw) {
   if (!p || !fw) return POLAR_EINVAL;
   std::memcpy(fw, p->hp.frozen.data(), p->hp.frozen.size() * 4);
@@ -334,13 +355,19 @@ int prepare(const polar_plan* plans, uint32_t n_plans, const polar_frame* d_fram
   if (!d_frames && n_plans != 1) return POLAR_EINVAL;
   b->quant = plans[0]->hp.hdr.quant;
   uint32_t pm_stride = 0;
+  bool mixed = false;
   for (uint32_t i = 0; i < n_plans; ++i) {
     const polar::DevPlan& h = plans[i]->hp.hdr;
-    if (h.quant != b->quant) return POLAR_EINVAL;
+    mixed = mixed || h.quant != b->quant;
     b->lds = h.lds_max > b->lds ? h.lds_max : b->lds;
     pm_stride = h.max_list > pm_stride ? h.max_list : pm_stride;
     if (h.algo != POLAR_SC && h.algo != POLAR_CA_SCL) b->fixed_list = false;
   }
+  // plans of different LLR types in one decode: the class schedule (fixed
+  // lists, frame descriptors, automatic schedule), whose classes each take
+  // one type
+  if (mixed && (!b->fixed_list || !d_frames || n_plans < 2 || (opts && opts->schedule != 0)))
+    return POLAR_EINVAL;
   b->plans.assign(plans, plans + n_plans);
   int rc = POLAR_OK;
   polar::KArgs& A = b->A;
@@ -392,12 +419,13 @@ int build_classes(const Batch& b, const ClassConfig& cfg, int cus,
     if (L <= 8) return cfg.l8_kernel;
     return polar::CK_W4_L32;
   };
-  // [kernel][n class] -> lds, spill bytes per workgroup
-  uint32_t lds[4][4] = {};
-  uint64_t spill[4][4] = {};
-  bool used[4][4] = {};
+  // [quant][kernel][n class] -> lds, spill bytes per workgroup
+  uint32_t lds[3][4][4] = {};
+  uint64_t spill[3][4][4] = {};
+  bool used[3][4][4] = {};
   for (polar_plan p : b.plans) {
     const polar::DevPlan& h = p->hp.hdr;
+    const uint32_t qt = h.quant;
     const uint32_t k = kernel_of(h.first_stage);
     uint32_t c = 0;
     while (c + 1 < n_nc && h.N > nb[c + 1]) ++c;
@@ -411,18 +439,20 @@ int build_classes(const Batch& b, const ClassConfig& cfg, int cus,
       need = lay.total;
       gb = lay.gbytes;
     }
-    used[k][c] = true;
-    lds[k][c] = need > lds[k][c] ? need : lds[k][c];
-    spill[k][c] = gb > spill[k][c] ? gb : spill[k][c];
+    used[qt][k][c] = true;
+    lds[qt][k][c] = need > lds[qt][k][c] ? need : lds[qt][k][c];
+    spill[qt][k][c] = gb > spill[qt][k][c] ? gb : spill[qt][k][c];
   }
   out->clear();
   const uint32_t n_frames = b.A.n_frames;
+  for (uint32_t qt = 0; qt < 3; ++qt)
   for (uint32_t k = 0; k < 4; ++k)
     for (uint32_t c = 0; c < n_nc; ++c) {
-      if (!used[k][c]) continue;
+      if (!used[qt][k][c]) continue;
       polar::ClassLaunch cl{};
       cl.kernel = k;
       cl.sel.on = 1;
+      cl.sel.quant = qt;
       cl.sel.nmin = nb[c] + 1;
       cl.sel.nmax = nb[c + 1];
       if (k == polar::CK_SC) {
@@ -437,8 +467,8 @@ int build_classes(const Batch& b, const ClassConfig& cfg, int cus,
         cl.sel.lmin = cfg.l8_kernel == polar::CK_W4_L32 ? 5 : 9;
         cl.sel.lmax = polar::kMaxL;
       }
-      cl.lds = lds[k][c];
-      cl.spill = spill[k][c];
+      cl.lds = lds[qt][k][c];
+      cl.spill = spill[qt][k][c];
       if (k == polar::CK_SC)
         cl.grid = n_frames;  // one wave per frame, frames outside the class exit at once
       else
@@ -638,7 +668,7 @@ int run_classes(const Batch& b, const Work& w, hipStream_t st, bool autotune, hi
     for (uint32_t i = 0; i < 4 && rc == POLAR_OK; ++i) {
       rc = build_classes(b, cands[i], cus, &cls);
       if (rc) break;
-      rc = polar::launch_decode_classes(b.quant, b.A, cls.data(), (uint32_t)cls.size(), w.heads,
+      rc = polar::launch_decode_classes(b.A, cls.data(), (uint32_t)cls.size(), w.heads,
                                         st, e[0], e[1]);
       float ms = 0.f;
       if (rc == POLAR_OK && (hipEventSynchronize(e[1]) != hipSuccess ||
@@ -660,7 +690,7 @@ int run_classes(const Batch& b, const Work& w, hipStream_t st, bool autotune, hi
   }
   rc = build_classes(b, cfg, cus, &cls);
   if (rc) return rc;
-  return polar::launch_decode_classes(b.quant, b.A, cls.data(), (uint32_t)cls.size(), w.heads, st,
+  return polar::launch_decode_classes(b.A, cls.data(), (uint32_t)cls.size(), w.heads, st,
                                       ev0, ev1);
 }
 
@@ -898,7 +928,8 @@ int polar_schedule_describe(const polar_plan* plans, uint32_t n_plans, char* buf
                   " l8=" + kernel_name(cfg.l8_kernel) + " split_n=" + std::to_string(cfg.split_n) +
                   " tuned=" + std::to_string(found && cfg.tuned ? 1 : 0);
   for (const auto& c : cls)
-    t += "; " + std::string(kernel_name(c.kernel)) + " L" + std::to_string(c.sel.lmin) + "-" +
+    t += "; " + std::string(kernel_name(c.kernel)) + " q" + std::to_string(c.sel.quant) + " L" +
+         std::to_string(c.sel.lmin) + "-" +
          std::to_string(c.sel.lmax) + " N" + std::to_string(c.sel.nmin) + "-" +
          std::to_string(c.sel.nmax) + " lds=" + std::to_string(c.lds) + " wg=" + std::to_string(c.grid);
   std::snprintf(buf, len, "%s", t.c_str());
@@ -1012,6 +1043,14 @@ int polar_channel(polar_plan p, const uint32_t* d_code, uint32_t n_frames, float
   if (frac_bits < 0 || frac_bits > 14) return POLAR_EINVAL;
   return polar::launch_channel(p->hp.hdr, d_code, n_frames, ebn0_db, frac_bits, seed, frame0,
                                d_llr, static_cast<hipStream_t>(stream));
+}
+
+int polar_quantize(const float* d_llr, uint32_t n, int32_t quant, int32_t frac_bits, void* d_out,
+                   void* stream) {
+  if (n && (!d_llr || !d_out)) return POLAR_EINVAL;
+  if (quant < POLAR_F32 || quant > POLAR_I8 || frac_bits < 0 || frac_bits > 14) return POLAR_EINVAL;
+  return polar::launch_quantize(d_llr, n, (uint32_t)quant, frac_bits, d_out,
+                                static_cast<hipStream_t>(stream));
 }
 
 int polar_plan_stage_work(polar_plan p, uint32_t L, uint64_t* ops) {

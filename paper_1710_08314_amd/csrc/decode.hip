@@ -1182,7 +1182,7 @@ __global__ __launch_bounds__(NW * 64, (list_waves_per_eu<T, NW>())) void k_decod
 // each in its single stage.
 __device__ __forceinline__ bool in_class(const DevPlan* P, const ClassSel& sel) {
   return P->first_stage >= sel.lmin && P->first_stage <= sel.lmax && P->N >= sel.nmin &&
-         P->N <= sel.nmax;
+         P->N <= sel.nmax && P->quant == sel.quant;
 }
 
 template <typename T, int NW, int LMAX>
@@ -1257,47 +1257,43 @@ int init_kernel_attributes() {
 }
 
 template <typename T>
-static int launch_classes_t(const KArgs& A, const ClassLaunch* cls, uint32_t n_cls,
-                            uint32_t* heads, hipStream_t s) {
-  hipLaunchKernelGGL(k_heads_reset, dim3(1), dim3(64), 0, s, heads, n_cls);
+static int launch_class_t(const KArgs& A, const ClassLaunch& c, uint32_t* head, uint32_t* heads,
+                          hipStream_t s) {
   const uint32_t quant = VT<T>::INT ? (sizeof(T) == 2 ? POLAR_I16 : POLAR_I8) : POLAR_F32;
-  for (uint32_t i = 0; i < n_cls; ++i) {
-    const ClassLaunch& c = cls[i];
-    KArgs Ac = A;
-    Ac.spill_stride = c.spill;
-    switch (c.kernel) {
-      case CK_SC: {
-        const int rc = launch_decode_sc(quant, A, c.lds, c.grid, heads, c.sel, s);
-        if (rc) return rc;
-        break;
-      }
-      case CK_W1_L4:
-        hipLaunchKernelGGL((k_decode_class<T, 1, 4>), dim3(c.grid), dim3(64), c.lds, s, Ac,
-                           heads + i, c.sel);
-        break;
-      case CK_W2_L8:
-        hipLaunchKernelGGL((k_decode_class<T, 2, 8>), dim3(c.grid), dim3(128), c.lds, s, Ac,
-                           heads + i, c.sel);
-        break;
-      default:
-        hipLaunchKernelGGL((k_decode_class<T, 4, (int)kMaxL>), dim3(c.grid), dim3(256), c.lds, s,
-                           Ac, heads + i, c.sel);
-        break;
-    }
+  KArgs Ac = A;
+  Ac.spill_stride = c.spill;
+  switch (c.kernel) {
+    case CK_SC:
+      return launch_decode_sc(quant, A, c.lds, c.grid, heads, c.sel, s);
+    case CK_W1_L4:
+      hipLaunchKernelGGL((k_decode_class<T, 1, 4>), dim3(c.grid), dim3(64), c.lds, s, Ac, head,
+                         c.sel);
+      break;
+    case CK_W2_L8:
+      hipLaunchKernelGGL((k_decode_class<T, 2, 8>), dim3(c.grid), dim3(128), c.lds, s, Ac, head,
+                         c.sel);
+      break;
+    default:
+      hipLaunchKernelGGL((k_decode_class<T, 4, (int)kMaxL>), dim3(c.grid), dim3(256), c.lds, s, Ac,
+                         head, c.sel);
+      break;
   }
   return hipGetLastError() == hipSuccess ? POLAR_OK : POLAR_EHIP;
 }
 
-int launch_decode_classes(uint32_t quant, const KArgs& A, const ClassLaunch* cls, uint32_t n_cls,
-                          uint32_t* heads, hipStream_t s, hipEvent_t ev_begin,
-                          hipEvent_t ev_end) {
+int launch_decode_classes(const KArgs& A, const ClassLaunch* cls, uint32_t n_cls, uint32_t* heads,
+                          hipStream_t s, hipEvent_t ev_begin, hipEvent_t ev_end) {
   if (n_cls > kMaxClasses) return POLAR_EINVAL;
   if (ev_begin) (void)hipEventRecord(ev_begin, s);
-  int rc;
-  switch (quant) {
-    case POLAR_F32: rc = launch_classes_t<float>(A, cls, n_cls, heads, s); break;
-    case POLAR_I16: rc = launch_classes_t<int16_t>(A, cls, n_cls, heads, s); break;
-    default: rc = launch_classes_t<int8_t>(A, cls, n_cls, heads, s); break;
+  hipLaunchKernelGGL(k_heads_reset, dim3(1), dim3(64), 0, s, heads, n_cls);
+  int rc = POLAR_OK;
+  for (uint32_t i = 0; i < n_cls && rc == POLAR_OK; ++i) {
+    // each class has one quantisation (its plans' LLR type)
+    switch (cls[i].sel.quant) {
+      case POLAR_F32: rc = launch_class_t<float>(A, cls[i], heads + i, heads, s); break;
+      case POLAR_I16: rc = launch_class_t<int16_t>(A, cls[i], heads + i, heads, s); break;
+      default: rc = launch_class_t<int8_t>(A, cls[i], heads + i, heads, s); break;
+    }
   }
   if (ev_end) (void)hipEventRecord(ev_end, s);
   return rc;

@@ -150,6 +150,34 @@ __global__ void k_channel(const uint32_t* code, uint32_t cw, uint32_t p0, uint32
   }
 }
 
+template <typename T>
+__global__ void k_quantize(const float* in, uint32_t n, float qscale, int Q, T* out) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = quantise<T>(in[i], qscale, Q);
+}
+
+int launch_quantize(const float* d_llr, uint32_t n, uint32_t quant, int32_t frac_bits, void* d_out,
+                    hipStream_t s) {
+  if (n == 0) return POLAR_OK;
+  const float qscale = std::ldexp(1.0f, frac_bits);
+  const uint32_t blocks = (uint32_t)(((uint64_t)n + 255) / 256);
+  switch (quant) {
+    case POLAR_F32:
+      hipLaunchKernelGGL(k_quantize<float>, dim3(blocks), dim3(256), 0, s, d_llr, n, qscale, 0,
+                         (float*)d_out);
+      break;
+    case POLAR_I16:
+      hipLaunchKernelGGL(k_quantize<int16_t>, dim3(blocks), dim3(256), 0, s, d_llr, n, qscale, 32767,
+                         (int16_t*)d_out);
+      break;
+    default:
+      hipLaunchKernelGGL(k_quantize<int8_t>, dim3(blocks), dim3(256), 0, s, d_llr, n, qscale, 127,
+                         (int8_t*)d_out);
+      break;
+  }
+  return hipGetLastError() == hipSuccess ? POLAR_OK : POLAR_EHIP;
+}
+
 int launch_encode(const DevPlan* dplan, const DevPlan& h, const uint32_t* d_data,
                   uint32_t* d_code, uint32_t n_frames, hipStream_t s) {
   if (n_frames == 0) return POLAR_OK;

@@ -98,6 +98,7 @@ struct ClassSel {
   uint32_t on;
   uint32_t lmin, lmax;  // the plan's first stage (list size) in [lmin, lmax]
   uint32_t nmin, nmax;  // the plan's code length in [nmin, nmax]
+  uint32_t quant;       // the plan's LLR type (polar_quant)
 };
 int launch_decode_sc(uint32_t quant, const KArgs& A, uint32_t lds, uint32_t grid, uint32_t* state,
                      const ClassSel& sel, hipStream_t s);
@@ -159,10 +160,12 @@ struct ClassLaunch {
   uint32_t lds, grid;
   uint64_t spill;  // spill bytes per workgroup
 };
-constexpr uint32_t kMaxClasses = 16;
-// heads: one counter per class, cleared by the first kernel of the launch.
-int launch_decode_classes(uint32_t quant, const KArgs& A, const ClassLaunch* cls, uint32_t n_cls,
-                          uint32_t* heads, hipStream_t s, hipEvent_t ev_begin, hipEvent_t ev_end);
+constexpr uint32_t kMaxClasses = 48;  // 3 quantisations x 4 kernels x 4 code lengths
+// heads: one counter per class, cleared by the first kernel of the launch;
+// each class is launched for its own quantisation, so one decode may mix
+// plans of different LLR types.
+int launch_decode_classes(const KArgs& A, const ClassLaunch* cls, uint32_t n_cls, uint32_t* heads,
+                          hipStream_t s, hipEvent_t ev_begin, hipEvent_t ev_end);
 // Allow every decoder kernel the whole LDS of a CU (called once, outside any
 // graph capture); launches then pass their actual footprint.
 int init_kernel_attributes();
@@ -172,6 +175,8 @@ int launch_encode(const DevPlan* dplan, const DevPlan& h, const uint32_t* d_data
                   uint32_t* d_code, uint32_t n_frames, hipStream_t s);
 int launch_gen_data(const DevPlan& h, uint64_t seed, uint64_t frame0, uint32_t n_frames,
                     uint32_t* d_data, hipStream_t s);
+int launch_quantize(const float* d_llr, uint32_t n, uint32_t quant, int32_t frac_bits, void* d_out,
+                    hipStream_t s);
 int launch_channel(const DevPlan& h, const uint32_t* d_code, uint32_t n_frames, float ebn0_db,
                    int32_t frac_bits, uint64_t seed, uint64_t frame0, void* d_llr, hipStream_t s);
 

@@ -580,7 +580,7 @@ __device__ __forceinline__ void frame_at(const KArgs& A, uint32_t f, const DevPl
 __device__ __forceinline__ bool sc_takes(const DevPlan* P, const ClassSel& sel) {
   if (sel.on)
     return P->first_stage >= sel.lmin && P->first_stage <= sel.lmax && P->N >= sel.nmin &&
-           P->N <= sel.nmax;
+           P->N <= sel.nmax && P->quant == sel.quant;
   return P->first_stage == 1;
 }
 

@@ -69,7 +69,8 @@ class _Opts(ctypes.Structure):
 
 class _ServerCfg(ctypes.Structure):
     _fields_ = [("n_slots", ctypes.c_uint32), ("max_batch", ctypes.c_uint32),
-                ("max_inflight", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("max_inflight", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("budget_bytes", ctypes.c_uint64), ("slot_spill_bytes", ctypes.c_uint64)]
 
 
 EXPORTS = ["polar_scl_plan", "polar_plan_destroy", "polar_plan_get_info", "polar_plan_get_frozen",
@@ -79,7 +80,7 @@ EXPORTS = ["polar_scl_plan", "polar_plan_destroy", "polar_plan_get_info", "polar
            "polar_schedule_describe", "polar_graph_create", "polar_graph_launch",
            "polar_graph_destroy", "polar_server_create", "polar_server_submit",
            "polar_server_poll", "polar_server_inflight", "polar_server_destroy",
-           "polar_serve_replay", "polar_strerror",
+           "polar_serve_replay", "polar_plan_frame_bytes", "polar_quantize", "polar_strerror",
            "polar_version"]
 
 
@@ -106,12 +107,14 @@ def _load():
     L.polar_graph_launch.argtypes = [vp, vp]
     L.polar_graph_destroy.argtypes = [vp]
     L.polar_server_create.argtypes = [ctypes.POINTER(_ServerCfg), ctypes.POINTER(vp)]
-    L.polar_server_submit.argtypes = [vp, vp, u32, vp, u32, u32, vp, vp, vp, u64,
+    L.polar_server_submit.argtypes = [vp, vp, u32, vp, u32, u32, vp, vp, vp, vp, u64,
                                       ctypes.POINTER(u32)]
+    L.polar_plan_frame_bytes.argtypes = [vp, ctypes.POINTER(u64)]
+    L.polar_quantize.argtypes = [vp, u32, i32, i32, vp, vp]
     L.polar_server_poll.argtypes = [vp, ctypes.POINTER(u64), u32, ctypes.POINTER(u32)]
     L.polar_server_inflight.argtypes = [vp, ctypes.POINTER(u32)]
     L.polar_server_destroy.argtypes = [vp]
-    L.polar_serve_replay.argtypes = [vp, vp, u32, vp, u32, vp, vp, vp, vp, vp, vp]
+    L.polar_serve_replay.argtypes = [vp, vp, u32, vp, u32, vp, vp, vp, vp, vp, vp, vp]
     L.polar_strerror.argtypes = [ctypes.c_int]
     L.polar_strerror.restype = ctypes.c_char_p
     L.polar_version.restype = ctypes.c_char_p
@@ -239,6 +242,12 @@ class Plan:
     def handle(self):
         return self._h
 
+    def frame_bytes(self) -> int:
+        """polar_plan_frame_bytes: bytes a frame in flight is charged by a server."""
+        v = ctypes.c_uint64()
+        _check(lib.polar_plan_frame_bytes(self._h, ctypes.byref(v)), "polar_plan_frame_bytes")
+        return int(v.value)
+
     def stage_work(self, L: int) -> int:
         """Algorithmic element operations of one stage at list size L."""
         v = ctypes.c_uint64()
@@ -348,17 +357,21 @@ class Graph:
 class Server:
     """polar_server_*: continuous batching over `n_slots` HIP streams."""
 
-    def __init__(self, n_slots=4, max_batch=4096, max_inflight=16384):
-        cfg = _ServerCfg(n_slots, max_batch, max_inflight, 0)
+    def __init__(self, n_slots=4, max_batch=4096, max_inflight=16384, budget_bytes=0,
+                 slot_spill_bytes=0):
+        cfg = _ServerCfg(n_slots, max_batch, max_inflight, 0, budget_bytes, slot_spill_bytes)
         h = ctypes.c_void_p()
         _check(lib.polar_server_create(ctypes.byref(cfg), ctypes.byref(h)), "polar_server_create")
         self._h = h
 
-    def submit(self, plans, frames, first, count, llr, info, status, tag=0):
-        """Admit frames [first, first + count); False when no slot or budget."""
+    def submit(self, plans, frames, first, count, llr, info, status, tag=0, plan_idx=None):
+        """Admit frames [first, first + count); False when no slot or budget.
+        plan_idx: optional host array of the batch's plan indices (byte budget)."""
         arr = (ctypes.c_void_p * len(plans))(*[p.handle.value for p in plans])
         slot = ctypes.c_uint32()
+        pi = np.ascontiguousarray(plan_idx, dtype=np.uint32) if plan_idx is not None else None
         rc = lib.polar_server_submit(self._h, arr, len(plans), _dptr(frames), first, count,
+                                     pi.ctypes.data if pi is not None else None,
                                      _dptr(llr), _dptr(info), _dptr(status), tag,
                                      ctypes.byref(slot))
         if rc == EAGAIN:
@@ -377,18 +390,22 @@ class Server:
         _check(lib.polar_server_inflight(self._h, ctypes.byref(v)), "polar_server_inflight")
         return int(v.value)
 
-    def replay(self, plans, frames, arrival_us, llr, info, status):
-        """polar_serve_replay: returns (completion times in us, stats dict)."""
+    def replay(self, plans, frames, arrival_us, llr, info, status, plan_of=None):
+        """polar_serve_replay: returns (completion times in us, stats dict).
+        plan_of: optional host array of every request's plan index (byte budget)."""
         arr = (ctypes.c_void_p * len(plans))(*[p.handle.value for p in plans])
         arrival = np.ascontiguousarray(arrival_us, dtype=np.float64)
         n = len(arrival)
         done = np.zeros(n, dtype=np.float64)
-        stats = np.zeros(4, dtype=np.float64)
+        stats = np.zeros(5, dtype=np.float64)
+        po = np.ascontiguousarray(plan_of, dtype=np.uint32) if plan_of is not None else None
         _check(lib.polar_serve_replay(self._h, arr, len(plans), _dptr(frames), n,
-                                      arrival.ctypes.data, _dptr(llr), _dptr(info), _dptr(status),
+                                      arrival.ctypes.data, po.ctypes.data if po is not None else None,
+                                      _dptr(llr), _dptr(info), _dptr(status),
                                       done.ctypes.data, stats.ctypes.data), "polar_serve_replay")
         return done, {"batches": int(stats[0]), "mean_batch": float(stats[1]),
-                      "peak_inflight": int(stats[2]), "session_us": float(stats[3])}
+                      "peak_inflight": int(stats[2]), "session_us": float(stats[3]),
+                      "peak_inflight_bytes": int(stats[4])}
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
@@ -472,6 +489,21 @@ def channel(plan: Plan, code, ebn0_db: float, seed: int, frame0: int, frac_bits=
     _check(lib.polar_channel(plan.handle, _dptr(code), F, float(ebn0_db), int(frac_bits), seed,
                              frame0, _dptr(llr), _stream_ptr(stream)), "polar_channel")
     return llr
+
+
+def quantize(llr, quant, frac_bits=None, stream=None):
+    """polar_quantize: float32 device LLRs -> the quant's type (new tensor)."""
+    import torch
+
+    if isinstance(quant, str):
+        quant = QUANT_NAMES[quant]
+    if frac_bits is None:
+        frac_bits = {I8: 2, I16: 3}.get(quant, 0)
+    src = llr.contiguous()
+    out = torch.empty(src.shape, dtype=llr_dtype(quant), device=src.device)
+    _check(lib.polar_quantize(_dptr(src), src.numel(), quant, int(frac_bits), _dptr(out),
+                              _stream_ptr(stream)), "polar_quantize")
+    return out
 
 
 def status_fields(status):

@@ -138,7 +138,7 @@ def pack_inputs(codes, plan_of, ebn0, seed):
     codes[plan_of[f]], Eb/N0 ebn0[f], draws synth.frame_draws(seed, f)),
     packed for a multi-plan decode: each frame's LLRs 16-byte aligned."""
     n = len(plan_of)
-    es = np.dtype(O.DTYPES[codes[0].quant]).itemsize
+    ess = [np.dtype(O.DTYPES[cd.quant]).itemsize for cd in codes]  # per code: plans may mix types
     offs = np.zeros(n, dtype=np.int64)
     out_off = np.zeros(n, dtype=np.int64)
     off = out = 0
@@ -146,7 +146,7 @@ def pack_inputs(codes, plan_of, ebn0, seed):
         cd = codes[plan_of[f]]
         off = (off + 15) // 16 * 16
         offs[f] = off
-        off += cd.n_tx * es
+        off += cd.n_tx * ess[plan_of[f]]
         out_off[f] = out
         out += (cd.k_data + 31) // 32
     raw = np.zeros(off, dtype=np.uint8)
@@ -156,7 +156,7 @@ def pack_inputs(codes, plan_of, ebn0, seed):
         b, z = synth.frame_draws(seed, f, cd.k_data, cd.n_tx)
         sigma = synth.sigma_for(float(ebn0[f]), cd.k_data, cd.n_tx)
         l = O.make_frames(cd, b[None, :], z[None, :], sigma)
-        raw[offs[f]:offs[f] + cd.n_tx * es] = l.view(np.uint8).reshape(-1)
+        raw[offs[f]:offs[f] + cd.n_tx * ess[plan_of[f]]] = l.view(np.uint8).reshape(-1)
         data.append(b)
     desc = np.zeros((n, 4), dtype=np.uint32)
     desc[:, 0] = offs & 0xFFFFFFFF

@@ -155,3 +155,84 @@ def test_graph_replay_adaptive_single_plan():
     assert np.array_equal(P.unpack_bits(g.info.cpu().numpy().view(np.uint32)[:200], code.k_data),
                           ref.info)
     g.close()
+
+
+def test_mixed_quantisations_one_decode():
+    """Plans of float32, int16 and int8 LLRs (CA-SCL, N in {128, 256, 512},
+    L in {2, 8}, CRC-11) in one decode call: the class schedule splits the
+    frames by LLR type too.  Every frame is checked against the oracle
+    (int: bit-exact bits, metric, metric list; float32: metrics within 1e-4,
+    bits equal unless near-tie, flags equal), and against the frames of each
+    type decoded alone."""
+    import torch
+
+    import oracle as O
+    from paper_1710_08314_amd import polar as P
+    from paper_1710_08314_amd import synth
+    from tests.gpu_util import PM_RTOL, QMAP, oracle_code, pack_inputs, pm_values
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c, poly = synth.C3_CRC
+    specs = [(N, K, L, q) for q in ("f32", "i16", "i8") for (N, K) in ((128, 48), (256, 140), (512, 300))
+             for L in (2, 8)]
+    codes = [oracle_code(N, K, c, poly, O.construct(N, K, 0, c, synth.C3_DESIGN_DB), quant=q,
+                         algo="ca", L=L) for (N, K, L, q) in specs]
+    rng = np.random.default_rng(3400)
+    n = 1800
+    plan_of = rng.integers(0, len(specs), n)
+    ebn0 = rng.uniform(1.0, 3.0, n)
+    inp = pack_inputs(codes, plan_of, ebn0, 3401)
+    plans = [gpu_plan(cd) for cd in codes]
+    llr = torch.from_numpy(inp["raw"]).cuda()
+    fr = torch.from_numpy(inp["desc"].view(np.int32)).cuda()
+    info, status, pml = P.decode_batch(plans, llr, frames=fr, with_pm_lists=True)
+    torch.cuda.synchronize()
+    desc = P.schedule_describe(plans)
+    print(desc, flush=True)
+    assert " q0 " in desc and " q1 " in desc and " q2 " in desc
+    info_h = info.cpu().numpy().view(np.uint32)
+    st = P.status_fields(status.cpu().numpy())
+    pml_h = pml.cpu().numpy().view(np.uint32)
+    for pi, cd in enumerate(codes):
+        fs = np.nonzero(plan_of == pi)[0]
+        if not len(fs):
+            continue
+        es = np.dtype(O.DTYPES[cd.quant]).itemsize
+        llrs = np.stack([inp["raw"][inp["desc"][f, 0]:inp["desc"][f, 0] + cd.n_tx * es]
+                         .view(O.DTYPES[cd.quant]) for f in fs])
+        ref = O.decode(cd, llrs, threads=8)
+        iw = (cd.k_data + 31) // 32
+        bits = np.stack([P.unpack_bits(info_h[inp["out_off"][f]:inp["out_off"][f] + iw], cd.k_data)
+                         for f in fs])
+        assert np.array_equal(st["L_used"][fs], ref.L_used), specs[pi]
+        assert np.array_equal(st["crc_ok"][fs], ref.crc_ok), specs[pi]
+        assert np.array_equal(st["n_paths"][fs], ref.n_pm), specs[pi]
+        assert np.array_equal(st["near_tie"][fs], ref.near_tie), specs[pi]
+        g_pm = pm_values(st["pm_bits"][fs], cd.quant)
+        if cd.quant == O.F32:
+            assert (np.abs(g_pm - ref.pm) <= PM_RTOL * np.maximum(1.0, np.abs(ref.pm))).all(), specs[pi]
+            eq = (bits == ref.info).all(axis=1)
+            assert (eq | (ref.near_tie == 1)).all(), specs[pi]
+        else:
+            assert np.array_equal(g_pm, ref.pm), specs[pi]
+            assert np.array_equal(bits, ref.info), specs[pi]
+            for j, f in enumerate(fs):
+                k = int(ref.n_pm[j])
+                assert np.array_equal(pml_h[f, :k].view(np.int32), ref.pm_list[j, :k].astype(np.int32))
+    # each type decoded alone (its own plans only) gives the same outputs
+    for q in ("f32", "i16", "i8"):
+        sub = [i for i, s in enumerate(specs) if s[3] == q]
+        fs = np.nonzero(np.isin(plan_of, sub))[0]
+        remap = {p: j for j, p in enumerate(sub)}
+        d = inp["desc"][fs].copy()
+        d[:, 3] = [remap[int(p)] for p in d[:, 3]]
+        a_info, a_st, _ = P.decode_batch([plans[i] for i in sub], llr,
+                                         frames=torch.from_numpy(d.view(np.int32)).cuda())
+        torch.cuda.synchronize()
+        a_info_h = a_info.cpu().numpy().view(np.uint32)
+        assert np.array_equal(a_st.cpu().numpy(), status.cpu().numpy()[fs]), q
+        for f in fs:
+            o = inp["out_off"][f]
+            iw = (codes[plan_of[f]].k_data + 31) // 32
+            assert np.array_equal(a_info_h[o:o + iw], info_h[o:o + iw]), (q, f)

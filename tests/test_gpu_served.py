@@ -42,10 +42,14 @@ def _served_case(quant, alone_schedule):
     n_words = int(inp["out_off"][-1]) + (codes[plan_of[-1]].k_data + 31) // 32
     info = torch.zeros(n_words, dtype=torch.int32, device="cuda")
     status = torch.zeros((N_REQ, 8), dtype=torch.uint8, device="cuda")
-    srv = P.Server(n_slots=4, max_batch=2048, max_inflight=8192)
-    done_us, stats = srv.replay(plans, fr, arrival, llr, info, status)
+    # admission by frames and by device bytes (each request charged its plan's
+    # figure): the byte budget is a quarter of what 8192 of the largest take
+    budget = 8192 * max(p.frame_bytes() for p in plans) // 4
+    srv = P.Server(n_slots=4, max_batch=2048, max_inflight=8192, budget_bytes=budget)
+    done_us, stats = srv.replay(plans, fr, arrival, llr, info, status, plan_of=plan_of)
     print(quant, stats, flush=True)
     assert stats["batches"] >= 2 and stats["peak_inflight"] <= 8192
+    assert 0 < stats["peak_inflight_bytes"] <= budget
     assert (done_us >= arrival).all()
     lat = done_us - arrival
     print(f"latency p50 {np.percentile(lat, 50):.1f} us p99 {np.percentile(lat, 99):.1f} us",
@@ -90,6 +94,49 @@ def _served_case(quant, alone_schedule):
             assert np.array_equal(bits, ref.info[0]) or ref.near_tie[0] == 1, r
             assert abs(g_pm - ref.pm[0]) <= PM_RTOL * max(1.0, abs(ref.pm[0])), r
         assert st["near_tie"][r] == ref.near_tie[0], r
+    srv.close()
+
+
+def test_byte_budget_refuses_before_frame_budget():
+    """A batch that fits the frame budget and a free slot but not the byte
+    budget is refused (POLAR_EAGAIN, nothing enqueued); a batch of a smaller
+    plan that fits is admitted; once the first batch completes the refused
+    one is admitted.  Every output equals one plain batch of the same frames."""
+    import torch
+    from paper_1710_08314_amd import polar as P
+
+    c, poly = synth.C4_CRC
+    specs = [(64, 24), (1024, 512)]
+    codes = [oracle_code(N, K, c, poly, O.construct(N, K, 0, c, synth.C4_DESIGN_DB), quant="i8",
+                         algo="fa", L_max=synth.C4_L_MAX) for (N, K) in specs]
+    plan_of = np.array([1] * 120 + [0] * 40, dtype=np.int64)
+    inp = pack_inputs(codes, plan_of, np.full(len(plan_of), 1.0), 4100)
+    plans = [gpu_plan(cd) for cd in codes]
+    small, big = plans[0].frame_bytes(), plans[1].frame_bytes()
+    print("bytes per frame", small, big, flush=True)
+    assert big > 4 * small
+    llr = torch.from_numpy(inp["raw"]).cuda()
+    fr = torch.from_numpy(inp["desc"].view(np.int32)).cuda()
+    n_words = int(inp["out_off"][-1]) + (codes[0].k_data + 31) // 32
+    info = torch.zeros(n_words, dtype=torch.int32, device="cuda")
+    status = torch.zeros((len(plan_of), 8), dtype=torch.uint8, device="cuda")
+    srv = P.Server(n_slots=4, max_batch=1024, max_inflight=1000, budget_bytes=100 * big)
+    assert srv.submit(plans, fr, 0, 80, llr, info, status, tag=1, plan_idx=plan_of[:80])
+    # 120 frames in flight would fit the frame budget (1000) and a slot is free
+    assert not srv.submit(plans, fr, 80, 40, llr, info, status, tag=2, plan_idx=plan_of[80:120])
+    assert srv.inflight() == 80
+    assert srv.submit(plans, fr, 120, 40, llr, info, status, tag=3, plan_idx=plan_of[120:])
+    done = set()
+    while 1 not in done:
+        done.update(srv.poll())
+    assert srv.submit(plans, fr, 80, 40, llr, info, status, tag=2, plan_idx=plan_of[80:120])
+    while len(done) < 3:
+        done.update(srv.poll())
+    torch.cuda.synchronize()
+    b_info, b_st, _ = P.decode_batch(plans, llr, frames=fr)
+    torch.cuda.synchronize()
+    assert np.array_equal(b_info.cpu().numpy()[:n_words], info.cpu().numpy())
+    assert np.array_equal(b_st.cpu().numpy(), status.cpu().numpy())
     srv.close()
 
 
