@@ -36,22 +36,17 @@ VALU_PEAK_OPS = 256 * 128 * 2.4e9
 HBM_PEAK_BYTES = 8.0e12  # MI355X HBM3E
 PAPER_CONTEXT_MBPS = {3.5: 24.4, 4.0: 227.3, 4.5: 425.9}  # one i5-6600K core, 8-bit FA
 # counter summaries (HBM bytes per launch) and the sources each kernel is built from
-TRAFFIC_FILES = {"k_scx": "hbm_traffic_k_scx_fa2048_i8.md",
-                 "k_listp<2>": "hbm_traffic_k_listp2_fa2048_i8.md",
-                 "k_listp<4>": "hbm_traffic_k_listp4_fa2048_i8.md",
-                 "k_listp<8>": "hbm_traffic_k_listp8_fa2048_i8.md",
-                 "k_listp<16>": "hbm_traffic_k_listp16_fa2048_i8.md",
+LIST_KERNELS = ["k_rq<11,2>", "k_rq<11,4>", "k_rq<11,8>", "k_rq<11,16>", "k_listp<32>"]
+TRAFFIC_FILES = {"k_rq<11,1>": "hbm_traffic_k_rq1_fa2048_i8.md",
+                 "k_rq<11,2>": "hbm_traffic_k_rq2_fa2048_i8.md",
+                 "k_rq<11,4>": "hbm_traffic_k_rq4_fa2048_i8.md",
+                 "k_rq<11,8>": "hbm_traffic_k_rq8_fa2048_i8.md",
+                 "k_rq<11,16>": "hbm_traffic_k_rq16_fa2048_i8.md",
                  "k_listp<32>": "hbm_traffic_k_listp32_fa2048_i8.md"}
-KERNEL_SOURCES = {"k_scx": ["scx.hip", "device_common.h", "kernels.h", "polar_internal.h"],
-                  "k_listp<2>": ["scx.hip", "device_common.h", "kernels.h", "polar_internal.h"],
-                  "k_listp<4>": ["scx.hip", "device_common.h", "kernels.h", "polar_internal.h"],
-                  "k_listp<8>": ["scx.hip", "device_common.h", "kernels.h", "polar_internal.h"],
-                  "k_listp<16>": ["scx.hip", "device_common.h", "kernels.h", "polar_internal.h"],
-                  "k_listp<32>": ["scx.hip", "device_common.h", "kernels.h", "polar_internal.h"],
-                  "k_decode_list<int8,1,4>": ["decode.hip", "device_common.h", "kernels.h",
-                                              "polar_internal.h"],
-                  "k_decode_list<int8,4,32>": ["decode.hip", "device_common.h", "kernels.h",
-                                               "polar_internal.h"]}
+_RQ_SRC = ["rq.hip", "device_common.h", "kernels.h", "polar_internal.h"]
+KERNEL_SOURCES = {"k_rq<11,1>": _RQ_SRC, "k_rq<11,2>": _RQ_SRC, "k_rq<11,4>": _RQ_SRC,
+                  "k_rq<11,8>": _RQ_SRC, "k_rq<11,16>": _RQ_SRC,
+                  "k_listp<32>": ["scx.hip", "device_common.h", "kernels.h", "polar_internal.h"]}
 
 
 def wilson(k, n, z=1.96):
@@ -61,7 +56,8 @@ def wilson(k, n, z=1.96):
     d = 1 + z * z / n
     c = (p + z * z / (2 * n)) / d
     h = z * math.sqrt(p * (1 - p) / n + z * z / (4 * n * n)) / d
-    return (max(0.0, c - h), min(1.0, c + h))
+    # the interval's ends are exactly 0 and 1 when no frame (every frame) fails
+    return (0.0 if k == 0 else max(0.0, c - h), 1.0 if k == n else min(1.0, c + h))
 
 
 def stage_schedule(L_max):
@@ -73,8 +69,29 @@ def stage_schedule(L_max):
     return s
 
 
-def cpu_baseline(points, frames_per_point, threads):
-    """The CPU oracle as it stands, on a host-made sample of the workload."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def host_cores():
+    """Cores this process may run on (its affinity mask)."""
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
+def cpu_baseline(points, frames_per_point, threads, frames_1core):
+    """The CPU oracle as it stands, on a host-made sample of the workload:
+    frame-parallel over every host core, then on one core (a smaller
+    sample).  Returns the record and the oracle's frame errors per point."""
     import oracle as O
     from paper_1710_08314_amd import synth
 
@@ -82,8 +99,8 @@ def cpu_baseline(points, frames_per_point, threads):
     fz = O.construct(W["N"], W["K"], 0, W["crc_len"], W["design"])
     code = O.Code(W["N"], W["K"], fz, W["crc_len"], W["crc_poly"], quant=O.I8, algo=O.FA_SCL,
                   L_max=W["L_max"], rep_max=8, spc_max=4)
-    bits_total, secs = 0, 0.0
-    per = {}
+    bits_total, secs, bits_1, secs_1 = 0, 0.0, 0, 0.0
+    per, errs = {}, {}
     for i, eb in enumerate(points):
         data, noise = synth.frames(7000 + i, 0, frames_per_point, code.k_data, code.n_tx)
         x = np.zeros((frames_per_point, code.N), np.uint8)
@@ -96,12 +113,22 @@ def cpu_baseline(points, frames_per_point, threads):
         secs += dt
         bits_total += frames_per_point * code.k_data
         per[str(eb)] = round(frames_per_point * code.k_data / dt / 1e6, 3)
-    return {"value": round(bits_total / secs / 1e6, 3), "unit": "Mb/s", "cores": threads,
-            "kind": "oracle",
-            "sample": f"{frames_per_point} host-generated frames per Eb/N0 point "
-                      f"({', '.join(str(p) for p in points)} dB) of the same workload, "
-                      f"frame-parallel over {threads} threads; decode time only",
-            "per_point_mbps": per}
+        errs[eb] = int((r.info != data).any(axis=1).sum())
+        m = min(frames_1core, frames_per_point)
+        t0 = time.perf_counter()
+        O.decode(code, llr[:m], threads=1)
+        secs_1 += time.perf_counter() - t0
+        bits_1 += m * code.k_data
+    rec = {"value": round(bits_total / secs / 1e6, 3), "unit": "Mb/s", "cores": threads,
+           "kind": "oracle", "cpu_model": cpu_model(),
+           "sample": f"{frames_per_point} host-generated frames per Eb/N0 point "
+                     f"({', '.join(str(p) for p in points)} dB) of the same workload, "
+                     f"frame-parallel over {threads} threads (every core the process may use); "
+                     f"decode time only; the one-core rate on the first {frames_1core} frames "
+                     f"of each point",
+           "per_point_mbps": per, "one_core_mbps": round(bits_1 / secs_1 / 1e6, 3),
+           "oracle_frame_errors": {str(k): v for k, v in errs.items()}}
+    return rec, errs
 
 
 def calib_copy(nbytes):
@@ -278,7 +305,7 @@ def bench_uneven(args):
                                "decode_p99_us": round(float(np.percentile(svc, 99)), 1),
                                "per_list_size": per_L}},
     }
-    print(json.dumps(out))
+    return out
 
 
 def bench_served(args):
@@ -403,7 +430,7 @@ def bench_served(args):
         "dtype": "i8", "data": "synthetic",
         "config": {"workload": "served_fa_lmax8_crc11_n32_1024", "per_quant": results},
     }
-    print(json.dumps(out))
+    return out
 
 
 def bench_pruning(args):
@@ -462,41 +489,12 @@ def bench_pruning(args):
            "vs_baseline": None, "dtype": "i8", "data": "synthetic",
            "config": {"workload": "pruning_sweep_fa2048_k1723_i8", "frames_per_point": F,
                       "variants": rows}}
-    print(json.dumps(out))
+    return out
 
 
-def main():
-    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--frames", type=int, default=1_000_000, help="frames per Eb/N0 point")
-    ap.add_argument("--points", default="3.5,4.0,4.5")
-    ap.add_argument("--schedule", type=int, default=0, help="0 automatic, 1 plain")
-    ap.add_argument("--cpu-frames", type=int, default=3000, help="oracle sample per point")
-    ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--compare-plain", type=int, default=1,
-                    help="also time the plain one-launch form once per point")
-    ap.add_argument("--calib-copy", type=int, default=0, metavar="BYTES",
-                    help="only run a plain device copy of BYTES (HBM counter calibration)")
-    ap.add_argument("--workload", default="headline",
-                    choices=["headline", "uneven", "served", "pruning"],
-                    help="uneven: the batched uneven launch (2^20 frames of mixed codes); "
-                         "served: Poisson arrivals of mixed-size requests through the serving loop")
-    args = ap.parse_args()
-    if args.calib_copy:
-        calib_copy(args.calib_copy)
-        return
-    if args.workload in ("uneven", "served", "pruning"):
-        if args.gpus != 1:
-            sys.exit(2)
-        {"uneven": bench_uneven, "served": bench_served, "pruning": bench_pruning}[args.workload](args)
-        return
-    if args.gpus != 1:
-        print("bench.py runs on one GPU: the decoder shards frames across GPUs with no "
-              "collective, so only --gpus 1 is measured", file=sys.stderr)
-        sys.exit(2)
-
+def headline(args):
+    """The headline workload: FA-SSCL on the (2048, 1723) code at three Eb/N0
+    points; returns the JSON record (value, per-point figures, roofline)."""
     import torch
 
     from paper_1710_08314_amd import polar as P
@@ -545,25 +543,36 @@ def main():
 
     # ---- per point: FER, list-size histogram, algorithmic work
     sched = stage_schedule(W["L_max"])
-    cum, acc = {}, 0
-    for l in sched:
-        acc += plan.stage_work(l)
-        cum[l] = acc
-    per_point, work_per_launch = {}, {}
+    per_point = {}
     for (eb, data, llr), (info, status) in zip(batches, outs):
         err = (info != data).any(dim=1)
         n_err = int(err.sum().item())
         lu = status[:, 1].to(torch.int64)
         hist = torch.bincount(lu, minlength=W["L_max"] + 1).cpu().numpy()
-        work = sum(int(hist[l]) * cum[l] for l in sched)
-        work_per_launch[eb] = work
         lo, hi = wilson(n_err, F)
-        per_point[str(eb)] = {"fer": n_err / F, "fer_ci95": [lo, hi],
+        per_point[str(eb)] = {"fer": n_err / F, "fer_ci95": [lo, hi], "frame_errors": n_err,
                               "crc_fail": int((status[:, 0] == 0).sum().item()),
                               "L_used_hist": {str(l): int(hist[l]) for l in sched if hist[l]},
                               "avg_stages": float(sum(hist[l] * (sched.index(l) + 1)
                                                       for l in sched) / F)}
-    # the plain form (one generic launch per configuration), same inputs
+    khz = P.device_clock_khz()
+
+    def latency(llr, schedule, pl=plan):
+        times = torch.zeros((F, 2), dtype=torch.int64, device="cuda")
+        P.decode_batch(pl, llr, schedule=schedule, stream=stream, times=times)
+        torch.cuda.synchronize()
+        t = times.cpu().numpy().astype(np.float64)
+        svc = (t[:, 1] - t[:, 0]) / khz * 1e3  # us
+        done = (t[:, 1] - t[:, 0].min()) / khz * 1e3
+        return {"decode_p50_us": round(float(np.percentile(svc, 50)), 2),
+                "decode_p99_us": round(float(np.percentile(svc, 99)), 2),
+                "decode_mean_us": round(float(svc.mean()), 2),
+                "decode_max_us": round(float(svc.max()), 2),
+                "batch_completion_p50_us": round(float(np.percentile(done, 50)), 1),
+                "batch_completion_p99_us": round(float(np.percentile(done, 99)), 1)}
+
+    # the plain form (one generic launch per configuration), same inputs:
+    # time and per-frame latency
     plain_ms = {}
     if args.schedule == 0 and args.compare_plain:
         for eb, data, llr in batches:
@@ -573,6 +582,7 @@ def main():
             e1.record(stream)
             torch.cuda.synchronize()
             plain_ms[eb] = e0.elapsed_time(e1)
+            per_point[str(eb)]["plain_latency"] = latency(llr, 1)
     kms = {}
     for eb, e0, e1 in events:
         kms.setdefault(eb, []).append(e0.elapsed_time(e1))
@@ -599,32 +609,44 @@ def main():
         per_point[str(eb)]["tier_ms"] = {t: round(ms[t], 3) for t in tier_ms}
         for l in sched:
             reached = int(sum(hist[x] for x in sched if x >= l))
-            # every list stage of this workload runs one path per lane, in the
-            # library's second list interval (the first stays empty)
+            # every list stage of this workload runs in the library's second
+            # list interval (the first stays empty)
             tier = "sc" if l == 1 else "list_b"
             tier_work[tier] += reached * plan.stage_work(l)
 
-    # ---- latency: per-frame decode time from device realtime stamps
-    khz = P.device_clock_khz()
-    lat = {}
+    # ---- latency of the automatic schedule: per-frame decode time from
+    # device realtime stamps
     for eb, data, llr in batches:
-        times = torch.zeros((F, 2), dtype=torch.int64, device="cuda")
-        P.decode_batch(plan, llr, schedule=args.schedule, stream=stream, times=times)
-        torch.cuda.synchronize()
-        t = times.cpu().numpy().astype(np.float64)
-        svc = (t[:, 1] - t[:, 0]) / khz * 1e3  # us
-        done = (t[:, 1] - t[:, 0].min()) / khz * 1e3
-        lat[str(eb)] = {"decode_p50_us": round(float(np.percentile(svc, 50)), 2),
-                        "decode_p99_us": round(float(np.percentile(svc, 99)), 2),
-                        "decode_max_us": round(float(svc.max()), 2),
-                        "batch_completion_p50_us": round(float(np.percentile(done, 50)), 1),
-                        "batch_completion_p99_us": round(float(np.percentile(done, 99)), 1)}
-        per_point[str(eb)]["latency"] = lat[str(eb)]
+        per_point[str(eb)]["latency"] = latency(llr, args.schedule)
+
+    # ---- partially adaptive SSCL (stages 1, L_max) on the same inputs
+    pa = {}
+    if args.pa:
+        pplan = P.Plan(W["N"], W["K"], W["crc_len"], W["crc_poly"], design_ebn0_db=W["design"],
+                       algo=P.PA_SCL, L_max=W["L_max"], quant=P.I8, rep_max=8, spc_max=4)
+        for eb, data, llr in batches:
+            P.decode_batch(pplan, llr, stream=stream)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            info, status, _ = P.decode_batch(pplan, llr, stream=stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1)
+            n_err = int((info != data).any(dim=1).sum().item())
+            lat = latency(llr, 0, pplan)
+            pa[str(eb)] = {"kernel_ms": round(ms, 3), "info_mbps": round(F * kd / (ms / 1e3) / 1e6, 1),
+                           "fer": n_err / F, "fer_ci95": list(wilson(n_err, F)),
+                           "decode_mean_us": lat["decode_mean_us"],
+                           "decode_max_us": lat["decode_max_us"],
+                           "decode_p99_us": lat["decode_p99_us"],
+                           "fa_info_mbps": per_point[str(eb)]["info_mbps"],
+                           "fa_decode_mean_us": per_point[str(eb)]["latency"]["decode_mean_us"],
+                           "fa_decode_max_us": per_point[str(eb)]["latency"]["decode_max_us"]}
 
     total_bits = args.steps * len(points) * F * kd
     value = total_bits / elapsed / 1e6
-    kernel_names = {"sc": "k_scx", "list_a": "k_decode_list<int8,1,4>",
-                    "list_b": "k_listp<2> + k_listp<4> + k_listp<8> + k_listp<16> + k_listp<32>"}
+    kernel_names = {"sc": "k_rq<11,1>", "list_a": "k_decode_list<int8,1,4>",
+                    "list_b": " + ".join(LIST_KERNELS)}
     tiers = {}
     for t in tier_ms:
         if tier_ms[t] > 0 and tier_work[t] > 0:
@@ -638,15 +660,24 @@ def main():
                 rate = tb / (tier_ms[t] / len(points) / 1e3)
                 tiers[t].update({"traffic": tb, "hbm_tbs": round(rate / 1e12, 3),
                                  "hbm_frac": round(rate / HBM_PEAK_BYTES, 4)})
-    dom = max(tiers, key=lambda t: tiers[t]["launch_ms"])
-    roofline = {"bound": "alu", "achieved": tiers[dom]["achieved"],
+            # the bound: the larger of the issue and the memory fractions
+            tiers[t]["bound"] = ("hbm" if tiers[t].get("hbm_frac", 0.0) > tiers[t]["frac"]
+                                 else "alu")
+    # the dominant kernel: the single kernel with the longest average launch
+    # (the L = 1 stage; each list stage runs as a launch of its own, shorter
+    # on average over the points)
+    dom = "sc" if "sc" in tiers else max(tiers, key=lambda t: tiers[t]["launch_ms"])
+    roofline = {"bound": tiers[dom]["bound"], "achieved": tiers[dom]["achieved"],
                 "peak": round(VALU_PEAK_OPS / 1e12, 2), "unit": "Tops/s",
                 "frac": tiers[dom]["frac"], "traffic": measured_traffic(tiers[dom]["kernel"]),
                 "kernel": tiers[dom]["kernel"],
                 "work_per_launch_ops": tiers[dom]["work_per_launch_ops"],
                 "launch_ms": tiers[dom]["launch_ms"], "tiers": tiers}
+    if roofline["bound"] == "hbm":
+        roofline.update({"achieved": tiers[dom]["hbm_tbs"] * 1e3, "peak": HBM_PEAK_BYTES / 1e9,
+                         "unit": "GB/s", "frac": tiers[dom]["hbm_frac"]})
 
-    out = {
+    return {
         "metric": "info Mb/s per MI355X at matched FER + p50/p99 decode latency, batched vs plain",
         "value": round(value, 1), "unit": "Mb/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(elapsed / args.steps * 1e3, 2),
@@ -659,12 +690,85 @@ def main():
                    "coded_mbps": round(value * W["N"] / kd, 1),
                    "plain_mbps": (round(len(points) * F * kd / (sum(plain_ms.values()) / 1e3) / 1e6, 1)
                                   if plain_ms else None),
-                   "per_point": per_point},
+                   "per_point": per_point, "pa_sscl": pa or None},
         "roofline": roofline,
     }
+
+
+def compact_uneven(r):
+    c = r["config"]
+    return {"workload": c["workload"], "frames": c["frames"], "plans": c["plans"], "dtype": r["dtype"],
+            "batched_info_mbps": c["batched_info_mbps"], "batched_kernel_ms": c["batched_kernel_ms"],
+            "graph_info_mbps": c["graph_info_mbps"], "plain_info_mbps": c["plain_info_mbps"],
+            "coded_mbps": c["coded_mbps"], "schedule": c["schedule"].split(";")[0],
+            "latency": {k: v for k, v in c["latency"].items() if k != "per_list_size"}}
+
+
+def compact_served(r):
+    out = {"workload": r["config"]["workload"]}
+    for q, v in r["config"]["per_quant"].items():
+        out[q] = {"requests": v["requests"], "plans": v["plans"],
+                  "batched_info_mbps": v["batched"]["info_mbps"],
+                  "plain_info_mbps": v["plain"]["info_mbps"],
+                  "served": {rate: {k: x[k] for k in ("served_mreq_s", "info_mbps", "latency_p50_us",
+                                                       "latency_p99_us", "results_equal_batch")}
+                             for rate, x in v["served"].items()}}
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--frames", type=int, default=1_000_000, help="frames per Eb/N0 point")
+    ap.add_argument("--points", default="3.5,4.0,4.5")
+    ap.add_argument("--schedule", type=int, default=0, help="0 automatic, 1 plain")
+    ap.add_argument("--cpu-frames", type=int, default=3000, help="oracle sample per point")
+    ap.add_argument("--cpu-frames-1core", type=int, default=500,
+                    help="oracle one-core sample per point")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--compare-plain", type=int, default=1,
+                    help="also time the plain one-launch form once per point")
+    ap.add_argument("--pa", type=int, default=1, help="also run PA-SSCL (stages 1, L_max)")
+    ap.add_argument("--extras", type=int, default=1,
+                    help="also run compact records of the uneven batch and of serving")
+    ap.add_argument("--calib-copy", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device copy of BYTES (HBM counter calibration)")
+    ap.add_argument("--workload", default="headline",
+                    choices=["headline", "uneven", "served", "pruning"],
+                    help="uneven: the batched uneven launch (2^20 frames of mixed codes); "
+                         "served: Poisson arrivals of mixed-size requests through the serving loop")
+    args = ap.parse_args()
+    if args.calib_copy:
+        calib_copy(args.calib_copy)
+        return
+    if args.gpus != 1:
+        print("bench.py runs on one GPU: the decoder shards frames across GPUs with no "
+              "collective, so only --gpus 1 is measured", file=sys.stderr)
+        sys.exit(2)
+    if args.workload in ("uneven", "served", "pruning"):
+        r = {"uneven": bench_uneven, "served": bench_served, "pruning": bench_pruning}[args.workload](args)
+        print(json.dumps(r))
+        return
+
+    out = headline(args)
+    if args.extras:
+        sub = argparse.Namespace(**vars(args))
+        sub.frames = 1_000_000  # each workload's own default size
+        sub.steps, sub.warmup, sub.compare_plain = 3, 1, 1
+        out["config"]["batched_uneven"] = compact_uneven(bench_uneven(sub))
+        out["config"]["served"] = compact_served(bench_served(sub))
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(points, args.cpu_frames,
-                                           min(16, os.cpu_count() or 1))
+        points = out["config"]["ebn0_db"]
+        rec, errs = cpu_baseline(points, args.cpu_frames, host_cores(), args.cpu_frames_1core)
+        out["cpu_baseline"] = rec
+        # matched FER: the GPU's FER lies in the oracle sample's 95% interval
+        for eb in points:
+            pp = out["config"]["per_point"][str(eb)]
+            lo, hi = wilson(errs[eb], args.cpu_frames)
+            pp["oracle_fer_ci95"] = [lo, hi]
+            pp["fer_matched"] = bool(lo <= pp["fer"] <= hi)
     print(json.dumps(out))
 
 

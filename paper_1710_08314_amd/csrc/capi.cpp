@@ -728,6 +728,8 @@ uint64_t spill_need(const Batch& b, int cus) {
   return need;
 }
 
+constexpr uint32_t kTinyAdaptive = 32;
+
 // Launch one decode of a prepared batch on `st` with work area `w`.
 int launch_batch(const Batch& b_in, uint32_t schedule, const Work& w, hipStream_t st, bool timed,
                  bool autotune) {
@@ -748,6 +750,11 @@ int launch_batch(const Batch& b_in, uint32_t schedule, const Work& w, hipStream_
     if (!w.spill || w.spill_bytes < need) return POLAR_EINVAL;
     A.spill = w.spill;
   }
+  // A batch of fewer than kTinyAdaptive frames with an adaptive plan runs
+  // the plain form: one launch instead of the tier chain, whose launches
+  // would each hold a handful of frames (and one-frame batches once hung in
+  // that chain without a cause found).
+  if (schedule == 0 && !b.fixed_list && n_frames < kTinyAdaptive) schedule = 1;
   if (schedule == 1) {
     A.spill_stride = polar::stage_span(b, 1, polar::kMaxL).spill;
     const uint32_t grid = plain_grid(b, cus0, A.spill_stride);

@@ -147,10 +147,10 @@ def test_served_equals_alone(quant):
     _served_case(quant, alone_schedule=1)
 
 
-@pytest.mark.skip(reason="one-frame batches through the tiered schedule hung once on the GPU "
-                         "(escalation queues, since replaced by per-frame state words); no cause "
-                         "was found by reading the old or the current code, so this case stays "
-                         "off the GPU")
 @pytest.mark.parametrize("quant", ["i8"])
-def test_served_equals_alone_tiered(quant):
+def test_served_equals_alone_automatic(quant):
+    """Requests decoded alone with the automatic schedule.  A batch of fewer
+    than 32 frames with an adaptive plan runs the plain one-launch form, so
+    one-frame batches never enter the tier chain (where a one-frame batch
+    once hung with no cause found); this checks that routing."""
     _served_case(quant, alone_schedule=0)
