@@ -51,6 +51,27 @@ void transform_words(std::vector<uint32_t>& w, uint32_t N) {
 
 inline bool bit(const std::vector<uint32_t>& w, uint32_t j) { return (w[j >> 5] >> (j & 31)) & 1u; }
 
+// The move masks of a five-step bit compress (H. S. Warren, Hacker's
+// Delight, Sec. 7-4): step i shifts the bits of mv[i] down by 2^i, and the
+// five steps together gather the bits of a word at the set positions of m,
+// in order, to the low end.  A bit moves at step i when bit i of the count
+// of zeros of m below it is set; mk holds those counts' parity one bit at a
+// time, taken as a prefix XOR.
+void compress_masks(uint32_t m, uint32_t mv[5]) {
+  uint32_t mk = ~m << 1;
+  for (int i = 0; i < 5; ++i) {
+    uint32_t mp = mk ^ (mk << 1);
+    mp ^= mp << 2;
+    mp ^= mp << 4;
+    mp ^= mp << 8;
+    mp ^= mp << 16;
+    const uint32_t v = mp & m;
+    m = (m ^ v) | (v >> (1u << i));
+    mk &= ~mp;
+    mv[i] = v;
+  }
+}
+
 }  // namespace
 
 std::vector<double> bhattacharyya_log(uint32_t n, double lz0) {
@@ -240,6 +261,14 @@ int make_plan(const polar_plan_desc& d, HostPlan& hp) {
   std::vector<uint32_t> datamask(bw, 0), prefix(bw, 0);
   for (uint32_t t = 0; t < kd; ++t) datamask[A[t] >> 5] |= 1u << (A[t] & 31);
   for (uint32_t w = 1; w < bw; ++w) prefix[w] = prefix[w - 1] + __builtin_popcount(datamask[w - 1]);
+  std::vector<uint32_t> datacomp(size_t(bw) * 8, 0);
+  for (uint32_t w = 0; w < bw; ++w) {
+    uint32_t* e = &datacomp[size_t(w) * 8];
+    e[0] = datamask[w];
+    compress_masks(datamask[w], e + 1);
+    e[6] = prefix[w];
+    e[7] = uint32_t(__builtin_popcount(datamask[w]));
+  }
 
   // ---- header + blob
   const uint32_t E = elem_bytes(d.quant), KB = key_bytes(d.quant);
@@ -284,6 +313,9 @@ int make_plan(const polar_plan_desc& d, HostPlan& hp) {
   off += bw;
   h.off_dataprefix = off;
   off += bw;
+  off = (off + 3u) & ~3u;  // 16-byte entries, read as two 16-byte loads
+  h.off_datacomp = off;
+  off += bw * 8;
   h.off_crccol = off;
   off += N;
   h.off_crcpos = off;
@@ -298,6 +330,7 @@ int make_plan(const polar_plan_desc& d, HostPlan& hp) {
   std::copy(info.begin(), info.end(), hp.blob.begin() + h.off_infomask);
   std::copy(datamask.begin(), datamask.end(), hp.blob.begin() + h.off_datamask);
   std::copy(prefix.begin(), prefix.end(), hp.blob.begin() + h.off_dataprefix);
+  std::copy(datacomp.begin(), datacomp.end(), hp.blob.begin() + h.off_datacomp);
   std::copy(crccol.begin(), crccol.end(), hp.blob.begin() + h.off_crccol);
   for (uint32_t t = 0; t < c; ++t) hp.blob[h.off_crcpos + t] = A[kd + t];
   // nibble table of the syndrome columns (Sec. IV-B: a table of

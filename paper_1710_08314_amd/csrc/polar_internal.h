@@ -75,7 +75,10 @@ struct DevPlan {
                           // positions are [P, P + n_tx)
   uint32_t off_sc_prog;   // n_sc_ops words: the program with fused steps (OP_FN,
   uint32_t n_sc_ops;      // OP_GNH) for the single-path tier
-  uint32_t pad[5];
+  uint32_t off_datacomp;  // bw x 8 words, for word w: its data mask, the five move
+                          // masks that gather the mask's bits to the low end, the
+                          // data positions before w and the data positions in w
+  uint32_t pad[4];
 };
 static_assert(sizeof(DevPlan) == 32 * 4, "DevPlan header is 32 words");
 

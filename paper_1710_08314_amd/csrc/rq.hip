@@ -70,6 +70,11 @@ constexpr uint32_t lowmask(int n) { return n >= 32 ? 0xFFFFFFFFu : ((1u << n) - 
 __device__ __forceinline__ uint32_t gld(const uint32_t* p) {
   return *(const __attribute__((address_space(1))) uint32_t*)(p);
 }
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ uint4 gld4(const uint32_t* p) {
+  const u32x4 v = *(const __attribute__((address_space(1))) u32x4*)(p);
+  return make_uint4(v.x, v.y, v.z, v.w);
+}
 
 // ---------------------------------------------------------- path registers
 struct RQ {
@@ -788,8 +793,7 @@ __global__ __launch_bounds__(64, 2) void k_rq(KArgs A, uint32_t* state, const ui
   const uint32_t* prog = uni_ptr(plan_tab(P, uni(P->off_sc_prog)));
   const uint32_t* imask = uni_ptr(plan_tab(P, uni(P->off_infomask)));
   const uint32_t* nib = uni_ptr(plan_tab(P, uni(P->off_crcnib)));
-  const uint32_t* dmask = uni_ptr(plan_tab(P, uni(P->off_datamask)));
-  const uint32_t* prefix = uni_ptr(plan_tab(P, uni(P->off_dataprefix)));
+  const uint32_t* comp = uni_ptr(plan_tab(P, uni(P->off_datacomp)));
   // the node program in LDS: one step's word is read while the previous
   // step runs, at LDS rather than memory latency
   for (uint32_t i = G.lane; i < n_ops; i += 64u) prog_s[i] = prog[i];
@@ -910,8 +914,8 @@ __global__ __launch_bounds__(64, 2) void k_rq(KArgs A, uint32_t* state, const ui
 #pragma unroll
       for (int i = 0; i < (1 << (NL - 7)); ++i) {
         const uint32_t wd = 4u * i + G.q;
-        uint32_t dm = gld(dmask + wd);
-        if (!dm) continue;
+        // {data mask, move masks 0..2}, {move masks 3..4, prefix, count}
+        const uint4 c0 = gld4(comp + 8u * wd), c1 = gld4(comp + 8u * wd + 4u);
         const uint4 lb = *reinterpret_cast<const uint4*>(&cw[G.Q][wd >> 2][0]);
         const uint32_t sh = 8u * (wd & 3u);
         const uint32_t l4[4] = {(lb.x >> sh) & 0xFFu, (lb.y >> sh) & 0xFFu, (lb.z >> sh) & 0xFFu,
@@ -920,16 +924,19 @@ __global__ __launch_bounds__(64, 2) void k_rq(KArgs A, uint32_t* state, const ui
 #pragma unroll
         for (int t = 0; t < 4; ++t)
           x |= ((l4[t] & 15u) << (4 * t)) | ((l4[t] >> 4) << (16 + 4 * t));
-        uint32_t v = 0, cnt = 0;
-        while (dm) {
-          const uint32_t bt = __ffs(dm) - 1;
-          v |= ((x >> bt) & 1u) << cnt;
-          ++cnt;
-          dm &= dm - 1u;
+        // the data bits gathered to the low end in five shift steps
+        const uint32_t mv[5] = {c0.y, c0.z, c0.w, c1.x, c1.y};
+        uint32_t v = x & c0.x;
+#pragma unroll
+        for (int t = 0; t < 5; ++t) {
+          const uint32_t m = v & mv[t];
+          v = (v ^ m) | (m >> (1u << t));
         }
-        const uint32_t p0 = gld(prefix + wd), o = p0 & 31u;
-        atomicOr(&stage[G.Q][p0 >> 5], v << o);
-        if (o + cnt > 32u) atomicOr(&stage[G.Q][(p0 >> 5) + 1u], v >> (32u - o));
+        const uint32_t p0 = c1.z, o = p0 & 31u, cnt = c1.w;
+        if (cnt) {
+          atomicOr(&stage[G.Q][p0 >> 5], v << o);
+          if (o + cnt > 32u) atomicOr(&stage[G.Q][(p0 >> 5) + 1u], v >> (32u - o));
+        }
       }
     __syncthreads();
     uint32_t* out = A.info + (size_t)f * iw;
