@@ -81,19 +81,25 @@ __device__ __forceinline__ uint32_t f4(uint32_t a, uint32_t b) {
   return __builtin_amdgcn_perm(as_u32(rh), as_u32(rl), 0x07050301u);
 }
 // g of four packed elements, saturated at [-127, 127]; bit i of s is the left
-// partial sum of element i.  b's low bytes are 0xFF and a negated operand
-// is its bitwise complement (-256 a - 1), so the 16-bit sum's high byte is
-// b + a or b - a exactly; the clamped add and a max at -127 * 256 saturate.
+// partial sum of element i.  The sum bits become byte masks m (0xFF where
+// the element is negated); a negated operand is its bitwise complement
+// over a low byte of 0xFF (-256 a - 1), a kept one a over a low byte of 0,
+// and b's low bytes are 0xFF, so the 16-bit sum's high byte is b + a or
+// b - a exactly; the clamped add and a max at -127 * 256 saturate.
 __device__ __forceinline__ uint32_t g4(uint32_t a, uint32_t b, uint32_t s) {
-  const uint32_t al = __builtin_amdgcn_perm(0u, a, 0x010C000Cu);
-  const uint32_t ah = __builtin_amdgcn_perm(0u, a, 0x030C020Cu);
+  // bit i of the nibble to bit 8 i (the four shifted copies do not
+  // overlap), then each such bit to a whole byte: 0x80 - x per byte (no
+  // borrow crosses a byte) is 0x80 or 0x7F, flipped at bit 7 to 0 or 0xFF
+  const uint32_t x = ((s & 15u) * 0x00204081u) & 0x01010101u;
+  const uint32_t m = (0x80808080u - x) ^ 0x80808080u;
+  const uint32_t an = a ^ m;
+  const s16x2 al = as_s16x2(__builtin_amdgcn_perm(m, an, 0x01050004u));
+  const s16x2 ah = as_s16x2(__builtin_amdgcn_perm(m, an, 0x03070206u));
   const s16x2 bl = as_s16x2(__builtin_amdgcn_perm(0u, b, 0x010D000Du));
   const s16x2 bh = as_s16x2(__builtin_amdgcn_perm(0u, b, 0x030D020Du));
-  const uint32_t ml = ((s & 1u) ? 0xFFFFu : 0u) | ((s & 2u) ? 0xFFFF0000u : 0u);
-  const uint32_t mh = ((s & 4u) ? 0xFFFFu : 0u) | ((s & 8u) ? 0xFFFF0000u : 0u);
   const s16x2 lo = {-127 * 256, -127 * 256};
-  const s16x2 rl = __builtin_elementwise_max(__builtin_elementwise_add_sat(bl, as_s16x2(al ^ ml)), lo);
-  const s16x2 rh = __builtin_elementwise_max(__builtin_elementwise_add_sat(bh, as_s16x2(ah ^ mh)), lo);
+  const s16x2 rl = __builtin_elementwise_max(__builtin_elementwise_add_sat(bl, al), lo);
+  const s16x2 rh = __builtin_elementwise_max(__builtin_elementwise_add_sat(bh, ah), lo);
   return __builtin_amdgcn_perm(as_u32(rh), as_u32(rl), 0x07050301u);
 }
 // hard decisions (sign bits) of four packed elements, element i at bit i:

@@ -656,10 +656,10 @@ __device__ __forceinline__ void h_stepL(RQ& R, PL& S, uint32_t q) {
 // ------------------------------------------------------------- dispatch
 #define POLAR_LEVELS(M) M(10) M(9) M(8) M(7) M(6) M(5) M(4) M(3) M(2) M(1)
 
-template <int NL, int L>
+template <int NL, int L, int KLO, int KHI>
 __device__ __forceinline__ void fg_any(RQ& R, PL& S, bool g, uint32_t k, const uint32_t* rw,
                                        uint32_t q, uint32_t Q) {
-  if (k == (uint32_t)NL) {
+  if (KHI >= NL && k == (uint32_t)NL) {
     if constexpr (L == 1)
       g ? fg_root<NL, true>(R, rw, q) : fg_root<NL, false>(R, rw, q);
     else
@@ -668,7 +668,7 @@ __device__ __forceinline__ void fg_any(RQ& R, PL& S, bool g, uint32_t k, const u
   }
 #define POLAR_FG(K)                                                         \
   case K:                                                                   \
-    if constexpr (K < NL) {                                                 \
+    if constexpr (K < NL && K >= KLO && K <= KHI) {                         \
       if constexpr (L == 1)                                                 \
         g ? fg_reg<K, true>(R, q) : fg_reg<K, false>(R, q);                 \
       else                                                                  \
@@ -679,13 +679,13 @@ __device__ __forceinline__ void fg_any(RQ& R, PL& S, bool g, uint32_t k, const u
 #undef POLAR_FG
 }
 
-template <int NL, int L>
+template <int NL, int L, int KLO, int KHI>
 __device__ __forceinline__ void h_any(RQ& R, PL& S, uint32_t k, uint32_t q) {
   // the root's h is left out: the codeword is read from the root's left
   // sums and the last right child's sums at the end of the stage
 #define POLAR_H(K)                       \
   case K:                                \
-    if constexpr (K < NL) {              \
+    if constexpr (K < NL && K >= KLO && K <= KHI) { \
       if constexpr (L == 1)              \
         h_step<K>(R, q);                 \
       else                               \
@@ -696,12 +696,12 @@ __device__ __forceinline__ void h_any(RQ& R, PL& S, uint32_t k, uint32_t q) {
 #undef POLAR_H
 }
 
-template <int NL, int L>
+template <int NL, int L, int KLO, int KHI>
 __device__ __forceinline__ void node_any(RQ& R, PL& S, const Geo& G, uint32_t opc, uint32_t k,
                                          uint32_t& a) {
 #define POLAR_N(K)                        \
   case K:                                 \
-    if constexpr (K < NL) {               \
+    if constexpr (K < NL && K >= KLO && K <= KHI) { \
       if constexpr (L == 1)               \
         node1<K>(R, opc, G.q);            \
       else                                \
@@ -711,10 +711,12 @@ __device__ __forceinline__ void node_any(RQ& R, PL& S, const Geo& G, uint32_t op
   switch (k) {
     POLAR_LEVELS(POLAR_N)
     default:
-      if constexpr (L == 1)
-        node1<0>(R, opc, G.q);
-      else
-        nodeL<0, L>(R, S, G, opc, a);
+      if constexpr (KLO == 0) {
+        if constexpr (L == 1)
+          node1<0>(R, opc, G.q);
+        else
+          nodeL<0, L>(R, S, G, opc, a);
+      }
       break;
   }
 #undef POLAR_N
@@ -746,19 +748,107 @@ __device__ __forceinline__ void fused_step(RQ& R, PL& S, const Geo& G, uint32_t 
       h_stepL<K>(R, S, G.q);
   }
 }
-template <int NL, int L, bool GNH>
+template <int NL, int L, int KLO, int KHI, bool GNH>
 __device__ __forceinline__ void fused_any(RQ& R, PL& S, const Geo& G, uint32_t sub, uint32_t k,
                                           const uint32_t* rw, uint32_t& a) {
   // the child has at most 64 positions: K <= 7
-  switch (k) {
-    case 7: if constexpr (7 <= NL) fused_step<NL, L, 7, GNH>(R, S, G, sub, rw, a); break;
-    case 6: if constexpr (6 <= NL) fused_step<NL, L, 6, GNH>(R, S, G, sub, rw, a); break;
-    case 5: fused_step<NL, L, 5, GNH>(R, S, G, sub, rw, a); break;
-    case 4: fused_step<NL, L, 4, GNH>(R, S, G, sub, rw, a); break;
-    case 3: fused_step<NL, L, 3, GNH>(R, S, G, sub, rw, a); break;
-    case 2: fused_step<NL, L, 2, GNH>(R, S, G, sub, rw, a); break;
-    default: fused_step<NL, L, 1, GNH>(R, S, G, sub, rw, a); break;
+#define POLAR_FU(K)                                                         \
+  case K:                                                                   \
+    if constexpr (K <= NL && K >= KLO && K <= KHI)                          \
+      fused_step<NL, L, K, GNH>(R, S, G, sub, rw, a);                       \
+    break;
+  switch (k) { POLAR_FU(7) POLAR_FU(6) POLAR_FU(5) POLAR_FU(4) POLAR_FU(3) POLAR_FU(2) POLAR_FU(1) default: break; }
+#undef POLAR_FU
+}
+
+// The switch key of a step: opcode, depth and fused child opcode (the node
+// offset masked out), so that one switch picks the step's whole code.
+template <int NL>
+constexpr uint32_t skey(uint32_t opc, int K, uint32_t sub = 0) {
+  return opc | ((uint32_t)(NL - K) << 4) | (sub << 24);
+}
+
+// One step of a list of one whose level lies in [KLO, KHI], through a single
+// switch over every (opcode, level, fused child) the programs use: one
+// binary search, then straight code.  Dedicated REP nodes have levels 1..5,
+// SPC nodes 2..5 (at least four positions), leaves level 0, and fused steps
+// levels <= 7; other keys select nothing.
+template <int NL, int KLO, int KHI>
+__device__ __forceinline__ void step1(RQ& R, PL& S, const Geo& G, uint32_t w, const uint32_t* rw,
+                                      uint32_t& a) {
+  Geo Go = G;
+  asm volatile("" : "+v"(Go.q));
+  const uint32_t q = Go.q;
+#define POLAR_C_FG(K)                                                                   \
+  case skey<NL>(OP_F, K): if constexpr (K >= KLO && K <= KHI && K < NL) fg_reg<K, false>(R, q); break; \
+  case skey<NL>(OP_G, K): if constexpr (K >= KLO && K <= KHI && K < NL) fg_reg<K, true>(R, q); break;  \
+  case skey<NL>(OP_H, K): if constexpr (K >= KLO && K <= KHI && K < NL) h_step<K>(R, q); break;
+#define POLAR_C_N(K, O) \
+  case skey<NL>(O, K): if constexpr (K >= KLO && K <= KHI && K < NL) node1<K>(R, O, q); break;
+#define POLAR_C_NODES(K) POLAR_C_N(K, OP_R0) POLAR_C_N(K, OP_R1)
+#define POLAR_C_NODES5(K) POLAR_C_NODES(K) POLAR_C_N(K, OP_REP) POLAR_C_N(K, OP_SPC)
+#define POLAR_C_FU(K, O)                                                                 \
+  case skey<NL>(OP_FN, K, O):                                                            \
+    if constexpr (K >= KLO && K <= KHI && K <= NL) fused_step<NL, 1, K, false>(R, S, Go, O, rw, a); \
+    break;                                                                               \
+  case skey<NL>(OP_GNH, K, O):                                                           \
+    if constexpr (K >= KLO && K <= KHI && K <= NL) fused_step<NL, 1, K, true>(R, S, Go, O, rw, a);  \
+    break;
+#define POLAR_C_FU4(K) POLAR_C_FU(K, OP_R0) POLAR_C_FU(K, OP_R1)
+#define POLAR_C_FU6(K) POLAR_C_FU4(K) POLAR_C_FU(K, OP_REP) POLAR_C_FU(K, OP_SPC)
+  switch (w & 0x0F0000FFu) {
+    case skey<NL>(OP_F, NL):
+      if constexpr (KHI >= NL) fg_root<NL, false>(R, rw, q);
+      break;
+    case skey<NL>(OP_G, NL):
+      if constexpr (KHI >= NL) fg_root<NL, true>(R, rw, q);
+      break;
+    POLAR_C_FG(10) POLAR_C_FG(9) POLAR_C_FG(8) POLAR_C_FG(7) POLAR_C_FG(6)
+    POLAR_C_FG(5) POLAR_C_FG(4) POLAR_C_FG(3) POLAR_C_FG(2) POLAR_C_FG(1)
+    POLAR_C_NODES(10) POLAR_C_NODES(9) POLAR_C_NODES(8) POLAR_C_NODES(7) POLAR_C_NODES(6)
+    POLAR_C_NODES5(5) POLAR_C_NODES5(4) POLAR_C_NODES5(3) POLAR_C_NODES5(2) POLAR_C_NODES(1)
+    POLAR_C_N(1, OP_REP)
+    POLAR_C_N(0, OP_LF) POLAR_C_N(0, OP_LI)
+    // fused: f or g at level K with a child of level K - 1 (REP / SPC
+    // children of level <= 5, leaves below level 1)
+    POLAR_C_FU4(7) POLAR_C_FU6(6) POLAR_C_FU6(5) POLAR_C_FU6(4) POLAR_C_FU6(3)
+    POLAR_C_FU(2, OP_R0) POLAR_C_FU(2, OP_R1) POLAR_C_FU(2, OP_REP)
+    POLAR_C_FU(1, OP_LF) POLAR_C_FU(1, OP_LI)
+    default: break;
   }
+#undef POLAR_C_FG
+#undef POLAR_C_N
+#undef POLAR_C_NODES
+#undef POLAR_C_NODES5
+#undef POLAR_C_FU
+#undef POLAR_C_FU4
+#undef POLAR_C_FU6
+}
+
+// One step of the node program whose level lies in [KLO, KHI]; fused
+// steps have levels <= 7 and lie in the lower range of any split at 8.
+template <int NL, int L, int KLO, int KHI>
+__device__ __forceinline__ void step(RQ& R, PL& S, const Geo& G, uint32_t w, const uint32_t* rw,
+                                     uint32_t& a) {
+  const uint32_t opc = op_code(w), k = (uint32_t)NL - op_depth(w);
+  // the lane index is made opaque at every step, so that nothing derived
+  // from it (element indices, addresses) is hoisted out of the walk and
+  // held in registers for its whole length
+  Geo Go = G;
+  if constexpr (L == 1)
+    asm volatile("" : "+v"(Go.q));
+  else
+    asm volatile("" : "+v"(Go.lane), "+v"(Go.q), "+v"(Go.Q), "+v"(Go.r), "+v"(Go.g0), "+v"(Go.fl));
+  if (opc == OP_F || opc == OP_G)
+    fg_any<NL, L, KLO, KHI>(R, S, opc == OP_G, k, rw, Go.q, Go.Q);
+  else if (opc == OP_H)
+    h_any<NL, L, KLO, KHI>(R, S, k, Go.q);
+  else if (opc == OP_FN)
+    fused_any<NL, L, KLO, KHI, false>(R, S, Go, op_sub(w), k, rw, a);
+  else if (opc == OP_GNH)
+    fused_any<NL, L, KLO, KHI, true>(R, S, Go, op_sub(w), k, rw, a);
+  else
+    node_any<NL, L, KLO, KHI>(R, S, Go, opc, k, a);
 }
 
 }  // namespace
@@ -773,6 +863,7 @@ __device__ __forceinline__ void fused_any(RQ& R, PL& S, const Geo& G, uint32_t s
 template <int NL, int L>
 __global__ __launch_bounds__(64, 2) void k_rq(KArgs A, uint32_t* state, const uint32_t* xl) {
   constexpr uint32_t FW = 16u / L;          // frames per wave
+  constexpr int KB = L == 1 ? 8 : 0;        // the walk's split level (0: none)
   constexpr int CWW = 2 * nwords(NL - 1);  // codeword words per lane
   constexpr int W10 = nwords(NL - 1);
   __shared__ uint32_t cw[16][CWW][4];  // codeword estimate of each quad's path
@@ -796,7 +887,10 @@ __global__ __launch_bounds__(64, 2) void k_rq(KArgs A, uint32_t* state, const ui
   const uint32_t* comp = uni_ptr(plan_tab(P, uni(P->off_datacomp)));
   // the node program in LDS: one step's word is read while the previous
   // step runs, at LDS rather than memory latency
-  for (uint32_t i = G.lane; i < n_ops; i += 64u) prog_s[i] = prog[i];
+  // followed by a step at the root's level that is never run: the walk
+  // reads one step ahead without a bounds check, and the loop below level
+  // KB ends on it
+  for (uint32_t i = G.lane; i <= n_ops; i += 64u) prog_s[i] = i < n_ops ? prog[i] : op_make(OP_H, 0, 0);
   __syncthreads();
   uint32_t count = A.n_frames;
   if constexpr (L > 1) {
@@ -830,28 +924,33 @@ __global__ __launch_bounds__(64, 2) void k_rq(KArgs A, uint32_t* state, const ui
     S.sb = G.Q * 0x1111u;
     uint32_t a = 1;
     uint32_t w_next = prog_s[0];
-    for (uint32_t pc = 0; pc < n_ops; ++pc) {
-      const uint32_t w = uni(w_next);
-      if (pc + 1 < n_ops) w_next = prog_s[pc + 1];
-      const uint32_t opc = op_code(w), k = (uint32_t)NL - op_depth(w);
-      // the lane index is made opaque at every step, so that nothing derived
-      // from it (element indices, addresses) is hoisted out of the walk and
-      // held in registers for its whole length
-      Geo Go = G;
+    uint32_t pc = 0;
+    while (pc < n_ops) {
+      uint32_t w = uni(w_next);
+      w_next = prog_s[pc + 1];
+      if constexpr (KB > 0) {
+        if ((uint32_t)NL - op_depth(w) < (uint32_t)KB) {
+          // a subtree below level KB, walked by a loop of its own: its steps
+          // touch only the registers of levels < KB, so the larger levels'
+          // registers pass through it untouched
+          for (;;) {
+            if constexpr (L == 1)
+              step1<NL, 0, KB - 1>(R, S, G, w, rw, a);
+            else
+              step<NL, L, 0, KB - 1>(R, S, G, w, rw, a);
+            ++pc;
+            w = uni(w_next);
+            if ((uint32_t)NL - op_depth(w) >= (uint32_t)KB) break;
+            w_next = prog_s[pc + 1];  // pc < n_ops: w is not the end step
+          }
+          continue;
+        }
+      }
       if constexpr (L == 1)
-        asm volatile("" : "+v"(Go.q));
+        step1<NL, KB, NL>(R, S, G, w, rw, a);
       else
-        asm volatile("" : "+v"(Go.lane), "+v"(Go.q), "+v"(Go.Q), "+v"(Go.r), "+v"(Go.g0), "+v"(Go.fl));
-      if (opc == OP_F || opc == OP_G)
-        fg_any<NL, L>(R, S, opc == OP_G, k, rw, Go.q, Go.Q);
-      else if (opc == OP_H)
-        h_any<NL, L>(R, S, k, Go.q);
-      else if (opc == OP_FN)
-        fused_any<NL, L, false>(R, S, Go, op_sub(w), k, rw, a);
-      else if (opc == OP_GNH)
-        fused_any<NL, L, true>(R, S, Go, op_sub(w), k, rw, a);
-      else
-        node_any<NL, L>(R, S, Go, opc, k, a);
+        step<NL, L, KB, NL>(R, S, G, w, rw, a);
+      ++pc;
     }
     // ---- codeword estimate of each path to LDS: word v of lane q of quad
     // Q at cw[Q][v][q], so that a codeword word's four lane bytes are
@@ -970,7 +1069,7 @@ __global__ __launch_bounds__(64, 2) void k_rq(KArgs A, uint32_t* state, const ui
 
 int launch_decode_rq1(const KArgs& A, uint32_t n_ops, uint32_t grid, uint32_t* state,
                       hipStream_t s) {
-  hipLaunchKernelGGL((k_rq<11, 1>), dim3(grid > 0 ? grid : 1), dim3(64), (n_ops + 3u) / 4u * 16u,
+  hipLaunchKernelGGL((k_rq<11, 1>), dim3(grid > 0 ? grid : 1), dim3(64), (n_ops + 4u) / 4u * 16u,
                      s, A, state, (const uint32_t*)nullptr);
   return hipGetLastError() == hipSuccess ? POLAR_OK : POLAR_EHIP;
 }
@@ -980,7 +1079,7 @@ int launch_decode_rqL(uint32_t L, const KArgs& A, uint32_t n_ops, uint32_t grid,
   int rc = launch_gather(A.n_frames, L, state, xl, s);
   if (rc) return rc;
   const dim3 gr(grid > 0 ? grid : 1), bl(64);
-  const uint32_t lds = (n_ops + 3u) / 4u * 16u;
+  const uint32_t lds = (n_ops + 4u) / 4u * 16u;
   const uint32_t* x = xl;
   switch (L) {
     case 2: hipLaunchKernelGGL((k_rq<11, 2>), gr, bl, lds, s, A, state, x); break;
