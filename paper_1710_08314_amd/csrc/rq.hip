@@ -654,72 +654,33 @@ __device__ __forceinline__ void h_stepL(RQ& R, PL& S, uint32_t q) {
 }
 
 // ------------------------------------------------------------- dispatch
-#define POLAR_LEVELS(M) M(10) M(9) M(8) M(7) M(6) M(5) M(4) M(3) M(2) M(1)
-
-template <int NL, int L, int KLO, int KHI>
-__device__ __forceinline__ void fg_any(RQ& R, PL& S, bool g, uint32_t k, const uint32_t* rw,
-                                       uint32_t q, uint32_t Q) {
-  if (KHI >= NL && k == (uint32_t)NL) {
+// Single-path and list versions of each kind of step
+template <int NL, int L, int K, bool G>
+__device__ __forceinline__ void fg_x(RQ& R, PL& S, const uint32_t* rw, uint32_t q, uint32_t Q) {
+  if constexpr (K == NL) {
     if constexpr (L == 1)
-      g ? fg_root<NL, true>(R, rw, q) : fg_root<NL, false>(R, rw, q);
+      fg_root<NL, G>(R, rw, q);
     else
-      g ? fg_rootL<NL, true>(R, S, rw, q, Q) : fg_rootL<NL, false>(R, S, rw, q, Q);
-    return;
+      fg_rootL<NL, G>(R, S, rw, q, Q);
+  } else if constexpr (L == 1) {
+    fg_reg<K, G>(R, q);
+  } else {
+    fg_regL<K, G>(R, S, q, Q);
   }
-#define POLAR_FG(K)                                                         \
-  case K:                                                                   \
-    if constexpr (K < NL && K >= KLO && K <= KHI) {                         \
-      if constexpr (L == 1)                                                 \
-        g ? fg_reg<K, true>(R, q) : fg_reg<K, false>(R, q);                 \
-      else                                                                  \
-        g ? fg_regL<K, true>(R, S, q, Q) : fg_regL<K, false>(R, S, q, Q);   \
-    }                                                                       \
-    break;
-  switch (k) { POLAR_LEVELS(POLAR_FG) default: break; }
-#undef POLAR_FG
 }
-
-template <int NL, int L, int KLO, int KHI>
-__device__ __forceinline__ void h_any(RQ& R, PL& S, uint32_t k, uint32_t q) {
-  // the root's h is left out: the codeword is read from the root's left
-  // sums and the last right child's sums at the end of the stage
-#define POLAR_H(K)                       \
-  case K:                                \
-    if constexpr (K < NL && K >= KLO && K <= KHI) { \
-      if constexpr (L == 1)              \
-        h_step<K>(R, q);                 \
-      else                               \
-        h_stepL<K>(R, S, q);             \
-    }                                    \
-    break;
-  switch (k) { POLAR_LEVELS(POLAR_H) default: break; }
-#undef POLAR_H
+template <int L, int K>
+__device__ __forceinline__ void h_x(RQ& R, PL& S, uint32_t q) {
+  if constexpr (L == 1)
+    h_step<K>(R, q);
+  else
+    h_stepL<K>(R, S, q);
 }
-
-template <int NL, int L, int KLO, int KHI>
-__device__ __forceinline__ void node_any(RQ& R, PL& S, const Geo& G, uint32_t opc, uint32_t k,
-                                         uint32_t& a) {
-#define POLAR_N(K)                        \
-  case K:                                 \
-    if constexpr (K < NL && K >= KLO && K <= KHI) { \
-      if constexpr (L == 1)               \
-        node1<K>(R, opc, G.q);            \
-      else                                \
-        nodeL<K, L>(R, S, G, opc, a);     \
-    }                                     \
-    break;
-  switch (k) {
-    POLAR_LEVELS(POLAR_N)
-    default:
-      if constexpr (KLO == 0) {
-        if constexpr (L == 1)
-          node1<0>(R, opc, G.q);
-        else
-          nodeL<0, L>(R, S, G, opc, a);
-      }
-      break;
-  }
-#undef POLAR_N
+template <int L, int K>
+__device__ __forceinline__ void node_x(RQ& R, PL& S, const Geo& G, uint32_t opc, uint32_t& a) {
+  if constexpr (L == 1)
+    node1<K>(R, opc, G.q);
+  else
+    nodeL<K, L>(R, S, G, opc, a);
 }
 
 // Fused steps of the node program: f at level K and the left child (a node
@@ -727,38 +688,9 @@ __device__ __forceinline__ void node_any(RQ& R, PL& S, const Geo& G, uint32_t op
 template <int NL, int L, int K, bool GNH>
 __device__ __forceinline__ void fused_step(RQ& R, PL& S, const Geo& G, uint32_t sub,
                                            const uint32_t* rw, uint32_t& a) {
-  if constexpr (K == NL) {
-    if constexpr (L == 1)
-      fg_root<NL, GNH>(R, rw, G.q);
-    else
-      fg_rootL<NL, GNH>(R, S, rw, G.q, G.Q);
-  } else if constexpr (L == 1) {
-    fg_reg<K, GNH>(R, G.q);
-  } else {
-    fg_regL<K, GNH>(R, S, G.q, G.Q);
-  }
-  if constexpr (L == 1)
-    node1<K - 1>(R, sub, G.q);
-  else
-    nodeL<K - 1, L>(R, S, G, sub, a);
-  if constexpr (GNH && K < NL) {
-    if constexpr (L == 1)
-      h_step<K>(R, G.q);
-    else
-      h_stepL<K>(R, S, G.q);
-  }
-}
-template <int NL, int L, int KLO, int KHI, bool GNH>
-__device__ __forceinline__ void fused_any(RQ& R, PL& S, const Geo& G, uint32_t sub, uint32_t k,
-                                          const uint32_t* rw, uint32_t& a) {
-  // the child has at most 64 positions: K <= 7
-#define POLAR_FU(K)                                                         \
-  case K:                                                                   \
-    if constexpr (K <= NL && K >= KLO && K <= KHI)                          \
-      fused_step<NL, L, K, GNH>(R, S, G, sub, rw, a);                       \
-    break;
-  switch (k) { POLAR_FU(7) POLAR_FU(6) POLAR_FU(5) POLAR_FU(4) POLAR_FU(3) POLAR_FU(2) POLAR_FU(1) default: break; }
-#undef POLAR_FU
+  fg_x<NL, L, K, GNH>(R, S, rw, G.q, G.Q);
+  node_x<L, K - 1>(R, S, G, sub, a);
+  if constexpr (GNH && K < NL) h_x<L, K>(R, S, G.q);
 }
 
 // The switch key of a step: opcode, depth and fused child opcode (the node
@@ -768,40 +700,47 @@ constexpr uint32_t skey(uint32_t opc, int K, uint32_t sub = 0) {
   return opc | ((uint32_t)(NL - K) << 4) | (sub << 24);
 }
 
-// One step of a list of one whose level lies in [KLO, KHI], through a single
-// switch over every (opcode, level, fused child) the programs use: one
-// binary search, then straight code.  Dedicated REP nodes have levels 1..5,
-// SPC nodes 2..5 (at least four positions), leaves level 0, and fused steps
-// levels <= 7; other keys select nothing.
-template <int NL, int KLO, int KHI>
-__device__ __forceinline__ void step1(RQ& R, PL& S, const Geo& G, uint32_t w, const uint32_t* rw,
-                                      uint32_t& a) {
+// One step whose level lies in [KLO, KHI], through a single switch over
+// every (opcode, level, fused child) the programs use: one binary search,
+// then straight code.  Dedicated REP nodes have levels 1..5, SPC nodes
+// 2..5 (at least four positions), leaves level 0, and fused steps levels
+// <= 7; other keys select nothing (the root's h among them: the codeword
+// is read from the root's left sums and the last right child's sums).
+template <int NL, int L, int KLO, int KHI>
+__device__ __forceinline__ void step(RQ& R, PL& S, const Geo& G, uint32_t w, const uint32_t* rw,
+                                     uint32_t& a) {
+  // the lane index is made opaque at every step, so that nothing derived
+  // from it (element indices, addresses) is hoisted out of the walk and
+  // held in registers for its whole length
   Geo Go = G;
-  asm volatile("" : "+v"(Go.q));
-  const uint32_t q = Go.q;
+  if constexpr (L == 1)
+    asm volatile("" : "+v"(Go.q));
+  else
+    asm volatile("" : "+v"(Go.lane), "+v"(Go.q), "+v"(Go.Q), "+v"(Go.r), "+v"(Go.g0), "+v"(Go.fl));
+  const uint32_t q = Go.q, Q = Go.Q;
 #define POLAR_C_FG(K)                                                                   \
-  case skey<NL>(OP_F, K): if constexpr (K >= KLO && K <= KHI && K < NL) fg_reg<K, false>(R, q); break; \
-  case skey<NL>(OP_G, K): if constexpr (K >= KLO && K <= KHI && K < NL) fg_reg<K, true>(R, q); break;  \
-  case skey<NL>(OP_H, K): if constexpr (K >= KLO && K <= KHI && K < NL) h_step<K>(R, q); break;
+  case skey<NL>(OP_F, K): if constexpr (K >= KLO && K <= KHI && K < NL) fg_x<NL, L, K, false>(R, S, rw, q, Q); break; \
+  case skey<NL>(OP_G, K): if constexpr (K >= KLO && K <= KHI && K < NL) fg_x<NL, L, K, true>(R, S, rw, q, Q); break;  \
+  case skey<NL>(OP_H, K): if constexpr (K >= KLO && K <= KHI && K < NL) h_x<L, K>(R, S, q); break;
 #define POLAR_C_N(K, O) \
-  case skey<NL>(O, K): if constexpr (K >= KLO && K <= KHI && K < NL) node1<K>(R, O, q); break;
+  case skey<NL>(O, K): if constexpr (K >= KLO && K <= KHI && K < NL) node_x<L, K>(R, S, Go, O, a); break;
 #define POLAR_C_NODES(K) POLAR_C_N(K, OP_R0) POLAR_C_N(K, OP_R1)
 #define POLAR_C_NODES5(K) POLAR_C_NODES(K) POLAR_C_N(K, OP_REP) POLAR_C_N(K, OP_SPC)
 #define POLAR_C_FU(K, O)                                                                 \
   case skey<NL>(OP_FN, K, O):                                                            \
-    if constexpr (K >= KLO && K <= KHI && K <= NL) fused_step<NL, 1, K, false>(R, S, Go, O, rw, a); \
+    if constexpr (K >= KLO && K <= KHI && K <= NL) fused_step<NL, L, K, false>(R, S, Go, O, rw, a); \
     break;                                                                               \
   case skey<NL>(OP_GNH, K, O):                                                           \
-    if constexpr (K >= KLO && K <= KHI && K <= NL) fused_step<NL, 1, K, true>(R, S, Go, O, rw, a);  \
+    if constexpr (K >= KLO && K <= KHI && K <= NL) fused_step<NL, L, K, true>(R, S, Go, O, rw, a);  \
     break;
 #define POLAR_C_FU4(K) POLAR_C_FU(K, OP_R0) POLAR_C_FU(K, OP_R1)
 #define POLAR_C_FU6(K) POLAR_C_FU4(K) POLAR_C_FU(K, OP_REP) POLAR_C_FU(K, OP_SPC)
   switch (w & 0x0F0000FFu) {
     case skey<NL>(OP_F, NL):
-      if constexpr (KHI >= NL) fg_root<NL, false>(R, rw, q);
+      if constexpr (KHI >= NL) fg_x<NL, L, NL, false>(R, S, rw, q, Q);
       break;
     case skey<NL>(OP_G, NL):
-      if constexpr (KHI >= NL) fg_root<NL, true>(R, rw, q);
+      if constexpr (KHI >= NL) fg_x<NL, L, NL, true>(R, S, rw, q, Q);
       break;
     POLAR_C_FG(10) POLAR_C_FG(9) POLAR_C_FG(8) POLAR_C_FG(7) POLAR_C_FG(6)
     POLAR_C_FG(5) POLAR_C_FG(4) POLAR_C_FG(3) POLAR_C_FG(2) POLAR_C_FG(1)
@@ -825,31 +764,6 @@ __device__ __forceinline__ void step1(RQ& R, PL& S, const Geo& G, uint32_t w, co
 #undef POLAR_C_FU6
 }
 
-// One step of the node program whose level lies in [KLO, KHI]; fused
-// steps have levels <= 7 and lie in the lower range of any split at 8.
-template <int NL, int L, int KLO, int KHI>
-__device__ __forceinline__ void step(RQ& R, PL& S, const Geo& G, uint32_t w, const uint32_t* rw,
-                                     uint32_t& a) {
-  const uint32_t opc = op_code(w), k = (uint32_t)NL - op_depth(w);
-  // the lane index is made opaque at every step, so that nothing derived
-  // from it (element indices, addresses) is hoisted out of the walk and
-  // held in registers for its whole length
-  Geo Go = G;
-  if constexpr (L == 1)
-    asm volatile("" : "+v"(Go.q));
-  else
-    asm volatile("" : "+v"(Go.lane), "+v"(Go.q), "+v"(Go.Q), "+v"(Go.r), "+v"(Go.g0), "+v"(Go.fl));
-  if (opc == OP_F || opc == OP_G)
-    fg_any<NL, L, KLO, KHI>(R, S, opc == OP_G, k, rw, Go.q, Go.Q);
-  else if (opc == OP_H)
-    h_any<NL, L, KLO, KHI>(R, S, k, Go.q);
-  else if (opc == OP_FN)
-    fused_any<NL, L, KLO, KHI, false>(R, S, Go, op_sub(w), k, rw, a);
-  else if (opc == OP_GNH)
-    fused_any<NL, L, KLO, KHI, true>(R, S, Go, op_sub(w), k, rw, a);
-  else
-    node_any<NL, L, KLO, KHI>(R, S, Go, opc, k, a);
-}
 
 }  // namespace
 
@@ -934,10 +848,7 @@ __global__ __launch_bounds__(64, 2) void k_rq(KArgs A, uint32_t* state, const ui
           // touch only the registers of levels < KB, so the larger levels'
           // registers pass through it untouched
           for (;;) {
-            if constexpr (L == 1)
-              step1<NL, 0, KB - 1>(R, S, G, w, rw, a);
-            else
-              step<NL, L, 0, KB - 1>(R, S, G, w, rw, a);
+            step<NL, L, 0, KB - 1>(R, S, G, w, rw, a);
             ++pc;
             w = uni(w_next);
             if ((uint32_t)NL - op_depth(w) >= (uint32_t)KB) break;
@@ -946,10 +857,7 @@ __global__ __launch_bounds__(64, 2) void k_rq(KArgs A, uint32_t* state, const ui
           continue;
         }
       }
-      if constexpr (L == 1)
-        step1<NL, KB, NL>(R, S, G, w, rw, a);
-      else
-        step<NL, L, KB, NL>(R, S, G, w, rw, a);
+      step<NL, L, KB, NL>(R, S, G, w, rw, a);
       ++pc;
     }
     // ---- codeword estimate of each path to LDS: word v of lane q of quad
