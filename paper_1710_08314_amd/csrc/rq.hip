@@ -362,20 +362,40 @@ __device__ __forceinline__ uint32_t nib_set(uint32_t v, int i, uint32_t x) {
   return (v & ~(15u << (4 * i))) | (x << (4 * i));
 }
 
-// minimum over the quads of a frame (4 L lanes, aligned)
-template <int L>
-__device__ __forceinline__ uint32_t frame_min(uint32_t v, uint32_t lane) {
-#pragma unroll
-  for (uint32_t d = 4; d < 4u * L; d <<= 1) v = min(v, bperm(v, lane ^ d));
-  return v;
-}
-
-// the value of lane (lane ^ d) for d = 1, 2 (DPP) or a larger power of two
+// the value of lane (lane ^ D), D a power of two below 64, without the LDS
+// crossbar: quad permutes for 1 and 2; in a row of 16 lanes, a rotation by
+// 8 for 8, and rotations by 12 (lane + 4) and 4 (lane - 4) for 4; the
+// 16-lane and 32-lane swaps of gfx950 for 16 and 32 (their first result
+// holds the lower block in both blocks, the second the upper)
+constexpr int kRowRor4 = 0x124, kRowRor8 = 0x128, kRowRor12 = 0x12C;
 template <uint32_t D>
 __device__ __forceinline__ uint32_t xchg(uint32_t v, uint32_t lane) {
-  if constexpr (D == 1) return dpp<kQX1>(v);
-  else if constexpr (D == 2) return dpp<kQX2>(v);
-  else return bperm(v, lane ^ D);
+  if constexpr (D == 1) {
+    return dpp<kQX1>(v);
+  } else if constexpr (D == 2) {
+    return dpp<kQX2>(v);
+  } else if constexpr (D == 4) {
+    const uint32_t up = dpp<kRowRor12>(v), dn = dpp<kRowRor4>(v);
+    return (lane & 4u) ? dn : up;
+  } else if constexpr (D == 8) {
+    return dpp<kRowRor8>(v);
+  } else if constexpr (D == 16) {
+    const auto p = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+    return (lane & 16u) ? p[0] : p[1];
+  } else {
+    static_assert(D == 32, "lane distance");
+    const auto p = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+    return (lane & 32u) ? p[0] : p[1];
+  }
+}
+
+// minimum over the quads of a frame (4 L lanes, aligned)
+template <int L, uint32_t D = 4>
+__device__ __forceinline__ uint32_t frame_min(uint32_t v, uint32_t lane) {
+  if constexpr (D < 4u * L)
+    return frame_min<L, 2 * D>(min(v, xchg<D>(v, lane)), lane);
+  else
+    return v;
 }
 
 // Ascending bitonic sort of a frame's candidate keys: 4 L elements, one per
