@@ -552,7 +552,7 @@ int plan_tiers(const Batch& b, polar::TierPlan* out) {
         if (small && h.n == 11) {
           const uint32_t g16 = (n_frames + 15) / 16, capq = 8u * (uint32_t)cus;
           tp.sc_q = 1;
-          tp.n_ops = h.n_sc_ops;
+          tp.n_ops = h.n_sc_ops;  // LDS for the longer program (the lists' is shorter)
           tp.grid_q = g16 < capq ? (g16 ? g16 : 1u) : capq;
         }
         if (stage2 && small) {

@@ -239,6 +239,21 @@ int make_plan(const polar_plan_desc& d, HostPlan& hp) {
     }
     hp.sc_prog.push_back(w);
   }
+  // ---- and with an f-and-left-child step merged into the g, right-child and
+  // h step of the same node that follows it (the register stages' program)
+  hp.q_prog.clear();
+  for (size_t i = 0; i < hp.sc_prog.size(); ++i) {
+    const uint32_t w = hp.sc_prog[i];
+    if (op_code(w) == OP_FN && i + 1 < hp.sc_prog.size()) {
+      const uint32_t nx = hp.sc_prog[i + 1];
+      if (op_code(nx) == OP_GNH && op_depth(nx) == op_depth(w)) {
+        hp.q_prog.push_back(op_make(OP_PAIR, op_depth(w), (op_sub(w) << 8) | (op_sub(nx) << 12)));
+        i += 1;
+        continue;
+      }
+    }
+    hp.q_prog.push_back(w);
+  }
 
   // ---- CRC syndrome columns.  CRC(data) is the remainder of data(x) x^c
   // by g(x) (MSB first, init 0, no final xor), linear in the data bits: data
@@ -307,6 +322,9 @@ int make_plan(const polar_plan_desc& d, HostPlan& hp) {
   h.n_sc_ops = uint32_t(hp.sc_prog.size());
   h.off_sc_prog = off;
   off += h.n_sc_ops;
+  h.n_q_ops = uint32_t(hp.q_prog.size());
+  h.off_q_prog = off;
+  off += h.n_q_ops;
   h.off_infomask = off;
   off += bw;
   h.off_datamask = off;
@@ -327,6 +345,7 @@ int make_plan(const polar_plan_desc& d, HostPlan& hp) {
   std::copy_n(reinterpret_cast<const uint32_t*>(&h), sizeof(DevPlan) / 4, hp.blob.begin());
   std::copy(hp.prog.begin(), hp.prog.end(), hp.blob.begin() + h.off_prog);
   std::copy(hp.sc_prog.begin(), hp.sc_prog.end(), hp.blob.begin() + h.off_sc_prog);
+  std::copy(hp.q_prog.begin(), hp.q_prog.end(), hp.blob.begin() + h.off_q_prog);
   std::copy(info.begin(), info.end(), hp.blob.begin() + h.off_infomask);
   std::copy(datamask.begin(), datamask.end(), hp.blob.begin() + h.off_datamask);
   std::copy(prefix.begin(), prefix.end(), hp.blob.begin() + h.off_dataprefix);

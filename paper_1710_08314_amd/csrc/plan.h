@@ -19,6 +19,7 @@ struct HostPlan {
   std::vector<uint32_t> blob;    // header + tables (32-bit words)
   std::vector<uint32_t> prog;    // node program
   std::vector<uint32_t> sc_prog;  // node program with fused steps (single-path tier)
+  std::vector<uint32_t> q_prog;   // the same with OP_PAIR steps (register stages)
   std::vector<uint32_t> frozen;  // frozen mask, bw words
   NodeCounts counts;
 };

@@ -43,6 +43,11 @@ enum Op : uint32_t {
   // by the single-path tier): the node's opcode in bits 24..27.
   OP_FN = 9,    // f at depth d, then the left child: a node (size <= 64)
   OP_GNH = 10,  // g at depth d, the right child: a node (size <= 64), then h at d
+  // The register stages' program merges an OP_FN and the OP_GNH of the same
+  // node that follows it: the left child's opcode in bits 16..19, the right
+  // child's in bits 20..23 (in place of the node offset, which those stages
+  // do not read), bits 24..31 zero.
+  OP_PAIR = 11,
 };
 
 POLAR_HD inline uint32_t op_make(uint32_t op, uint32_t d, uint32_t o) {
@@ -52,6 +57,8 @@ POLAR_HD inline uint32_t op_code(uint32_t w) { return w & 15u; }
 POLAR_HD inline uint32_t op_depth(uint32_t w) { return (w >> 4) & 15u; }
 POLAR_HD inline uint32_t op_off(uint32_t w) { return (w >> 8) & 0xFFFFu; }
 POLAR_HD inline uint32_t op_sub(uint32_t w) { return (w >> 24) & 15u; }
+POLAR_HD inline uint32_t pair_left(uint32_t w) { return (w >> 16) & 15u; }
+POLAR_HD inline uint32_t pair_right(uint32_t w) { return (w >> 20) & 15u; }
 
 // ---------------------------------------------------------------------------
 // Device plan blob: a header followed by tables, all 32-bit words, offsets
@@ -78,7 +85,9 @@ struct DevPlan {
   uint32_t off_datacomp;  // bw x 8 words, for word w: its data mask, the five move
                           // masks that gather the mask's bits to the low end, the
                           // data positions before w and the data positions in w
-  uint32_t pad[4];
+  uint32_t off_q_prog;    // n_q_ops words: the fused program with OP_PAIR steps
+  uint32_t n_q_ops;       // (the register stages)
+  uint32_t pad[2];
 };
 static_assert(sizeof(DevPlan) == 32 * 4, "DevPlan header is 32 words");
 

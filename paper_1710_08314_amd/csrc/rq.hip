@@ -713,8 +713,34 @@ __device__ __forceinline__ void fused_step(RQ& R, PL& S, const Geo& G, uint32_t 
   if constexpr (GNH && K < NL) h_x<L, K>(R, S, G.q);
 }
 
+// A dedicated child of level K of a paired step: R0 or R1 (levels >= 1),
+// REP (1..5), SPC (2..5) or a leaf (level 0)
+template <int L, int K>
+__device__ __forceinline__ void node_sub(RQ& R, PL& S, const Geo& G, uint32_t sub, uint32_t& a) {
+  switch (sub) {
+    case OP_R0: if constexpr (K >= 1) node_x<L, K>(R, S, G, OP_R0, a); break;
+    case OP_R1: if constexpr (K >= 1) node_x<L, K>(R, S, G, OP_R1, a); break;
+    case OP_REP: if constexpr (K >= 1 && K <= 5) node_x<L, K>(R, S, G, OP_REP, a); break;
+    case OP_SPC: if constexpr (K >= 2 && K <= 5) node_x<L, K>(R, S, G, OP_SPC, a); break;
+    case OP_LF: if constexpr (K == 0) node_x<L, K>(R, S, G, OP_LF, a); break;
+    case OP_LI: if constexpr (K == 0) node_x<L, K>(R, S, G, OP_LI, a); break;
+    default: break;
+  }
+}
+// A paired step of level K: f, the left child, g, the right child, h
+template <int NL, int L, int K>
+__device__ __forceinline__ void pair_step(RQ& R, PL& S, const Geo& G, uint32_t w, const uint32_t* rw,
+                                          uint32_t& a) {
+  fg_x<NL, L, K, false>(R, S, rw, G.q, G.Q);
+  node_sub<L, K - 1>(R, S, G, pair_left(w), a);
+  fg_x<NL, L, K, true>(R, S, rw, G.q, G.Q);
+  node_sub<L, K - 1>(R, S, G, pair_right(w), a);
+  if constexpr (K < NL) h_x<L, K>(R, S, G.q);
+}
+
 // The switch key of a step: opcode, depth and fused child opcode (the node
-// offset masked out), so that one switch picks the step's whole code.
+// offset, or a paired step's child opcodes, masked out), so that one switch
+// picks the step's code.
 template <int NL>
 constexpr uint32_t skey(uint32_t opc, int K, uint32_t sub = 0) {
   return opc | ((uint32_t)(NL - K) << 4) | (sub << 24);
@@ -722,10 +748,12 @@ constexpr uint32_t skey(uint32_t opc, int K, uint32_t sub = 0) {
 
 // One step whose level lies in [KLO, KHI], through a single switch over
 // every (opcode, level, fused child) the programs use: one binary search,
-// then straight code.  Dedicated REP nodes have levels 1..5, SPC nodes
-// 2..5 (at least four positions), leaves level 0, and fused steps levels
-// <= 7; other keys select nothing (the root's h among them: the codeword
-// is read from the root's left sums and the last right child's sums).
+// then straight code (a paired step picks its two children's code by two
+// small switches).  Dedicated REP nodes have levels 1..5, SPC nodes 2..5
+// (at least four positions), leaves level 0, and fused and paired steps
+// levels <= 7; other keys select nothing (the root's h among them: the
+// codeword is read from the root's left sums and the last right child's
+// sums).
 template <int NL, int L, int KLO, int KHI>
 __device__ __forceinline__ void step(RQ& R, PL& S, const Geo& G, uint32_t w, const uint32_t* rw,
                                      uint32_t& a) {
@@ -753,6 +781,10 @@ __device__ __forceinline__ void step(RQ& R, PL& S, const Geo& G, uint32_t w, con
   case skey<NL>(OP_GNH, K, O):                                                           \
     if constexpr (K >= KLO && K <= KHI && K <= NL) fused_step<NL, L, K, true>(R, S, Go, O, rw, a);  \
     break;
+#define POLAR_C_PAIR(K)                                                                  \
+  case skey<NL>(OP_PAIR, K):                                                             \
+    if constexpr (L > 1 && K >= KLO && K <= KHI && K <= NL) pair_step<NL, L, K>(R, S, Go, w, rw, a); \
+    break;
 #define POLAR_C_FU4(K) POLAR_C_FU(K, OP_R0) POLAR_C_FU(K, OP_R1)
 #define POLAR_C_FU6(K) POLAR_C_FU4(K) POLAR_C_FU(K, OP_REP) POLAR_C_FU(K, OP_SPC)
   switch (w & 0x0F0000FFu) {
@@ -773,6 +805,9 @@ __device__ __forceinline__ void step(RQ& R, PL& S, const Geo& G, uint32_t w, con
     POLAR_C_FU4(7) POLAR_C_FU6(6) POLAR_C_FU6(5) POLAR_C_FU6(4) POLAR_C_FU6(3)
     POLAR_C_FU(2, OP_R0) POLAR_C_FU(2, OP_R1) POLAR_C_FU(2, OP_REP)
     POLAR_C_FU(1, OP_LF) POLAR_C_FU(1, OP_LI)
+    // paired: both children dedicated nodes or leaves
+    POLAR_C_PAIR(7) POLAR_C_PAIR(6) POLAR_C_PAIR(5) POLAR_C_PAIR(4) POLAR_C_PAIR(3)
+    POLAR_C_PAIR(2) POLAR_C_PAIR(1)
     default: break;
   }
 #undef POLAR_C_FG
@@ -782,6 +817,7 @@ __device__ __forceinline__ void step(RQ& R, PL& S, const Geo& G, uint32_t w, con
 #undef POLAR_C_FU
 #undef POLAR_C_FU4
 #undef POLAR_C_FU6
+#undef POLAR_C_PAIR
 }
 
 
@@ -797,7 +833,7 @@ __device__ __forceinline__ void step(RQ& R, PL& S, const Geo& G, uint32_t w, con
 template <int NL, int L>
 __global__ __launch_bounds__(64, 2) void k_rq(KArgs A, uint32_t* state, const uint32_t* xl) {
   constexpr uint32_t FW = 16u / L;          // frames per wave
-  constexpr int KB = L == 1 ? 8 : 0;        // the walk's split level (0: none)
+  constexpr int KB = L == 1 ? 6 : 0;        // the walk's split level (0: none)
   constexpr int CWW = 2 * nwords(NL - 1);  // codeword words per lane
   constexpr int W10 = nwords(NL - 1);
   __shared__ uint32_t cw[16][CWW][4];  // codeword estimate of each quad's path
@@ -812,10 +848,12 @@ __global__ __launch_bounds__(64, 2) void k_rq(KArgs A, uint32_t* state, const ui
   G.fl = G.lane & (4u * L - 1u);
   const uint32_t gi = G.Q / L;
   const DevPlan* P = uni_ptr(A.plans[0]);
-  // the program with fused steps (f or g merged with an adjacent child node)
-  const uint32_t n_ops = uni(P->n_sc_ops);
+  // the program with fused steps (f or g merged with an adjacent child node);
+  // the lists' with paired steps as well (for a single path the paired code
+  // costs more register moves than the dispatch it saves)
+  const uint32_t n_ops = uni(L == 1 ? P->n_sc_ops : P->n_q_ops);
   const uint32_t iw = uni(A.info_words), L_max = uni(P->L_max), c_len = uni(P->c);
-  const uint32_t* prog = uni_ptr(plan_tab(P, uni(P->off_sc_prog)));
+  const uint32_t* prog = uni_ptr(plan_tab(P, uni(L == 1 ? P->off_sc_prog : P->off_q_prog)));
   const uint32_t* imask = uni_ptr(plan_tab(P, uni(P->off_infomask)));
   const uint32_t* nib = uni_ptr(plan_tab(P, uni(P->off_crcnib)));
   const uint32_t* comp = uni_ptr(plan_tab(P, uni(P->off_datacomp)));
