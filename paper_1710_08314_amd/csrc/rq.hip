@@ -104,6 +104,14 @@ __device__ __forceinline__ uint32_t& X(RQ& R, int j) {
   else return R.x0;
 }
 
+// the LLR words of level K made opaque to the optimiser (no instruction)
+template <int K>
+__device__ __forceinline__ void opaque_level(RQ& R) {
+  constexpr int W = K >= 4 ? (1 << (K - 4)) : (K == 3 ? 2 : 1);
+#pragma unroll
+  for (int j = 0; j < W; ++j) asm volatile("" : "+v"(X<K>(R, j)));
+}
+
 // partial-sum bits a lane holds for a node of level K, and their words
 constexpr int nbits(int K) { return K >= 4 ? (1 << (K - 2)) : (1 << K); }
 constexpr int nwords(int K) { return nbits(K) >= 32 ? nbits(K) / 32 : 1; }
@@ -906,6 +914,12 @@ __global__ __launch_bounds__(64, 2) void k_rq(KArgs A, uint32_t* state, const ui
           // touch only the registers of levels < KB, so the larger levels'
           // registers pass through it untouched
           for (;;) {
+            // the subtree's root LLRs, which no step of the subtree writes,
+            // made opaque at every step: otherwise every computation that
+            // depends on them alone (f and g at the subtree's root, the
+            // statistics of a dedicated node there) is hoisted out of the
+            // loop and run on every entry, used or not
+            opaque_level<KB - 1>(R);
             step<NL, L, 0, KB - 1>(R, S, G, w, rw, a);
             ++pc;
             w = uni(w_next);
