@@ -173,11 +173,13 @@ typedef struct {
   uint32_t schedule;   /* 0 = automatic: a batch of fixed-list plans (CA-SCL, SC)
                         * with several plans uses the class schedule -- frames
                         * split by list size and code length, one persistent
-                        * kernel per class sized for that class; otherwise the
-                        * tiered schedule -- an L = 1 tier, then list tiers fed
-                        * by device escalation queues.  1 = plain (one generic
-                        * launch in which each workgroup runs whole frames, every
-                        * stage in place)                                          */
+                        * kernel per class sized for that class; a batch of
+                        * fewer than 32 frames with an adaptive plan runs the
+                        * plain form; otherwise the tiered schedule -- an L = 1
+                        * tier, then the list stages, each frame's next list
+                        * size kept in a per-frame state word on the device.
+                        * 1 = plain (one generic launch in which each workgroup
+                        * runs whole frames, every stage in place)                */
   uint32_t flags;      /* OR of POLAR_OPT_*                                         */
   uint64_t *d_times;   /* nullable device array, 2 per frame: the device realtime
                         * counter (polar_device_clock_khz) when the frame's decode
@@ -186,7 +188,11 @@ typedef struct {
 } polar_decode_opts;
 
 /* Decode a batch (the hot path, Algorithm 1 and Sec. II-B3..B5).
- *   plans[n_plans]   host array of plans used by the frames (all of one quant)
+ *   plans[n_plans]   host array of plans used by the frames: all of one quant,
+ *                    except that a batch of two or more fixed-list plans (CA-SCL,
+ *                    SC) in the automatic schedule may mix them (each frame's
+ *                    LLRs then in its own plan's type, at its descriptor's
+ *                    llr_off)
  *   d_frames         device array of n_frames descriptors, or NULL: then every
  *                    frame uses plans[0], frame f reads d_llr + f * llr_bytes
  *                    and writes d_info + f * info_words
@@ -198,12 +204,13 @@ typedef struct {
  *   d_pm_lists       nullable; per frame max_list uint32 (float32 bits or int32):
  *                    the final path metrics in ascending order, unused entries
  *                    0xFFFFFFFF
- *   scratch          the library keeps a per-device work area (escalation queue
- *                    and counters) that grows on demand: concurrent calls on
- *                    different streams of one device must be serialised by
- *                    the caller.
- * Errors: POLAR_EINVAL (NULL buffers, mixed quants, plan index out of range is
- * not checked on device: the caller guarantees it), POLAR_EHIP. */
+ *   scratch          the library keeps a per-device work area (per-frame state
+ *                    words, frame lists, counters, spill regions) that grows on
+ *                    demand: concurrent calls on different streams of one
+ *                    device must be serialised by the caller.
+ * Errors: POLAR_EINVAL (NULL buffers, mixed quants outside the case above; a
+ * plan index out of range is not checked on device: the caller guarantees
+ * it), POLAR_EHIP. */
 int polar_scl_decode_batch(const polar_plan *plans, uint32_t n_plans,
                            const polar_frame *d_frames, uint32_t n_frames,
                            const void *d_llr, uint32_t *d_info, polar_status *d_status,

@@ -147,6 +147,16 @@ def test_served_equals_alone(quant):
     _served_case(quant, alone_schedule=1)
 
 
+@pytest.mark.skip(reason="one-frame batches through the tiered schedule hung once on the GPU "
+                         "(escalation queues, since replaced by per-frame state words); the cause "
+                         "was not shown, so the case stays off the GPU: the automatic schedule now "
+                         "runs adaptive batches of fewer than 32 frames in the plain form, and no "
+                         "schedule value sends them through the tiers")
+@pytest.mark.parametrize("quant", ["i8"])
+def test_served_equals_alone_tiered(quant):
+    _served_case(quant, alone_schedule=0)
+
+
 @pytest.mark.parametrize("quant", ["i8"])
 def test_served_equals_alone_automatic(quant):
     """Requests decoded alone with the automatic schedule.  A batch of fewer
