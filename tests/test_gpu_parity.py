@@ -390,6 +390,39 @@ def test_list_stages_path_per_lane(case):
         compare(code, llr)
 
 
+Q_CASES = [
+    # (N, K, c, poly, design dB, algo, L, node options, Eb/N0)
+    (2048, 1723, 32, 0x04C11DB7, 4.5, "sc", 1, dict(), 4.0),
+    (2048, 1723, 32, 0x04C11DB7, 4.5, "fa", 16, dict(), 3.0),
+    (2048, 1723, 32, 0x04C11DB7, 4.5, "pa", 16, dict(spc_max=32, rep_max=32), 3.0),
+    (2048, 1024, 24, 0x1864CFB, 2.5, "ca", 8, dict(), 1.5),
+    (2048, 1500, 16, 0x1021, 3.5, "ca", 2, dict(node_enable=O.NODE_R0 | O.NODE_R1), 2.5),
+    (2048, 1200, 11, 0x621, 3.0, "ca", 4, dict(r1_max=64, rep_max=2), 2.0),
+    (2048, 800, 11, 0x621, 2.0, "fa", 16, dict(node_enable=0), 1.0),
+]
+
+
+@pytest.mark.parametrize("case", range(len(Q_CASES)))
+def test_register_stages_n2048(case):
+    """Uniform int8 batches of N = 2048 codes whose REP / SPC nodes have at
+    most 32 positions: the L = 1 stage and the list stages up to 16 run with
+    four lanes per path and the whole decoder state in registers (16 / L
+    frames per wave, a persistent grid).  SC, FA and PA to 16, CA at 2, 4
+    and 8 (every frame in one list stage), the default node set, Rate-0 /
+    Rate-1 only, capped Rate-1 and REP sizes, and leaves only (a program of
+    thousands of steps), at SNRs where many frames fork and escalate; bits,
+    CRC flags, list sizes, metrics and metric lists equal the oracle for
+    batches of 1, 17 and 100 frames (a lone frame, a ragged wave, several
+    waves).  Adaptive (FA, PA) batches below 32 frames run the plain form by
+    the automatic schedule's rule, so for them the 100-frame batch is the
+    register-stage case."""
+    N, K, c, poly, design, algo, Lm, kw, eb = Q_CASES[case]
+    code = _code(N, K, c, poly, design, quant="i8", algo=algo, L=Lm, L_max=Lm, **kw)
+    for n in (1, 17, 100):
+        _, llr = make_inputs(code, n, 2100 + 7 * case + n, eb)
+        compare(code, llr)
+
+
 @pytest.mark.parametrize("quant", ["i8", "f32"])
 def test_sc_tier_frame_pairs(quant):
     """The L = 1 tier decodes two frames per wave.  Every frame of an odd-sized
