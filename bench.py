@@ -492,6 +492,116 @@ def bench_pruning(args):
     return out
 
 
+QUANT_SWEEP = {"N": 1024, "K": 512, "crc_len": 24, "crc_poly": 0x1864CFB, "design": 2.5, "L": 8,
+               "points": [1.0, 1.5, 2.0, 2.5, 3.0, 3.5, 4.0]}
+
+
+def quant_oracle_leg(quant, points, frames, threads):
+    """The cpu_baseline leg of the quantisation sweep: the oracle as it
+    stands on a host-made sample of each point (decode time only), giving its
+    frame and bit error counts for the matched-FER check."""
+    import oracle as O
+    from paper_1710_08314_amd import synth
+
+    Q = QUANT_SWEEP
+    oq = {"f32": O.F32, "i16": O.I16, "i8": O.I8}[quant]
+    frac = {"f32": 0, "i16": 3, "i8": 2}[quant]
+    fz = O.construct(Q["N"], Q["K"], 0, Q["crc_len"], Q["design"])
+    code = O.Code(Q["N"], Q["K"], fz, Q["crc_len"], Q["crc_poly"], quant=oq, algo=O.CA_SCL, L=Q["L"])
+    out, secs, bits = {}, 0.0, 0
+    for i, eb in enumerate(points):
+        data, noise = synth.frames(9000 + i, 0, frames, code.k_data, code.n_tx)
+        x = np.zeros((frames, code.N), np.uint8)
+        for f in range(frames):
+            x[f] = O.encode(fz, O.attach_crc(data[f], code.crc_len, code.crc_poly))
+        llr = O.make_llr(code, x, noise, synth.sigma_for(eb, code.k_data, code.n_tx), frac)
+        t0 = time.perf_counter()
+        r = O.decode(code, llr, threads=threads)
+        secs += time.perf_counter() - t0
+        bits += frames * code.k_data
+        wrong = r.info != data
+        out[eb] = (int(wrong.any(axis=1).sum()), int(wrong.sum()))
+    return out, bits / secs / 1e6
+
+
+def bench_quant(args):
+    """The quantisation sweep at scale (the fixed-point study of Sec. III-B3):
+    the (1024, 488 + CRC-24) code, Bhattacharyya design at 2.5 dB, CA-SCL
+    L = 8, float32 / saturated int16 / saturated int8 LLRs at Eb/N0 = 1.0 ...
+    4.0 dB, `--quant-frames` frames per point (10^7 by default) generated on
+    the device in chunks (data, systematic encoding, BPSK / AWGN, the plan's
+    quantiser), decoded, and their frame and bit errors counted on the
+    device.  Beside each point the oracle decodes a host-made sample
+    (`--quant-oracle` frames) and the GPU's FER must lie in the oracle's 95%
+    interval or the two intervals overlap."""
+    import torch
+
+    from paper_1710_08314_amd import polar as P
+
+    torch.cuda.set_device(0)
+    Q = QUANT_SWEEP
+    F, C = args.quant_frames, 1 << 20
+    stream = torch.cuda.current_stream()
+    pop = torch.tensor([bin(i).count("1") for i in range(256)], dtype=torch.int64, device="cuda")
+    rows, oracle_mbps = {}, {}
+    for quant, pq in (("f32", P.F32), ("i16", P.I16), ("i8", P.I8)):
+        plan = P.Plan(Q["N"], Q["K"], Q["crc_len"], Q["crc_poly"], design_ebn0_db=Q["design"],
+                      algo=P.CA_SCL, L=Q["L"], quant=pq)
+        kd = plan.info.k_data
+        pts = {}
+        for i, eb in enumerate(Q["points"]):
+            fe, be, ms = 0, 0, 0.0
+            for f0 in range(0, F, C):
+                n = min(C, F - f0)
+                data = P.gen_data(plan, 5000 + i, f0, n)
+                llr = P.channel(plan, P.encode(plan, data), eb, 6000 + i, f0)
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                info, _, _ = P.decode_batch(plan, llr, stream=stream)
+                e1.record(stream)
+                x = torch.bitwise_xor(info, data)
+                fe += int((x != 0).any(dim=1).sum().item())
+                be += int(pop[x.contiguous().view(torch.uint8).long()].sum().item())
+                ms += e0.elapsed_time(e1)
+                del data, llr, info, x
+            fer, ber = fe / F, be / (F * kd)
+            pts[str(eb)] = {"frames": F, "frame_errors": fe, "bit_errors": be, "fer": fer, "ber": ber,
+                            "fer_ci95": list(wilson(fe, F)), "decode_ms": round(ms, 1),
+                            "info_mbps": round(F * kd / (ms / 1e3) / 1e6, 1),
+                            "coded_mbps": round(F * Q["N"] / (ms / 1e3) / 1e6, 1)}
+            print(f"quant {quant} {eb} dB: {pts[str(eb)]}", file=sys.stderr, flush=True)
+        rec = {"points": pts}
+        if not args.no_cpu and args.quant_oracle > 0:
+            errs, mbps = quant_oracle_leg(quant, Q["points"], args.quant_oracle, host_cores())
+            oracle_mbps[quant] = round(mbps, 3)
+            for eb in Q["points"]:
+                pp = pts[str(eb)]
+                ofe, obe = errs[eb]
+                lo, hi = wilson(ofe, args.quant_oracle)
+                pp["oracle_frame_errors"], pp["oracle_bit_errors"] = ofe, obe
+                pp["oracle_fer_ci95"] = [lo, hi]
+                glo, ghi = pp["fer_ci95"]
+                pp["fer_matched"] = bool(lo <= pp["fer"] <= hi or (glo <= hi and lo <= ghi))
+        rows[quant] = rec
+    tot_bits = sum(p["frames"] * (Q["K"] - Q["crc_len"]) for r in rows.values() for p in r["points"].values())
+    tot_ms = sum(p["decode_ms"] for r in rows.values() for p in r["points"].values())
+    cpu = None
+    if oracle_mbps:
+        cpu = {"value": round(sum(oracle_mbps.values()) / len(oracle_mbps), 3), "unit": "Mb/s",
+               "cores": host_cores(), "kind": "oracle", "cpu_model": cpu_model(),
+               "sample": f"{args.quant_oracle} host-generated frames per Eb/N0 point and LLR type, "
+                         f"frame-parallel over {host_cores()} threads; decode time only; the mean "
+                         f"of the three types' rates",
+               "per_quant_mbps": oracle_mbps}
+    return {"metric": "info Mb/s per MI355X at matched FER + p50/p99 decode latency, batched vs plain",
+            "value": round(tot_bits / (tot_ms / 1e3) / 1e6, 1), "unit": "Mb/s", "n_gpus": 1,
+            "steps": 1, "warmup": 0, "ms_per_step": round(tot_ms, 1), "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f32/i16/i8", "data": "synthetic",
+            "cpu_baseline": cpu,
+            "config": {"workload": "quant_sweep_n1024_k512_crc24_ca_l8", "frames_per_point": F,
+                       "ebn0_db": Q["points"], "quants": rows}}
+
+
 def headline(args):
     """The headline workload: FA-SSCL on the (2048, 1723) code at three Eb/N0
     points; returns the JSON record (value, per-point figures, roofline)."""
@@ -736,9 +846,14 @@ def main():
     ap.add_argument("--calib-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (HBM counter calibration)")
     ap.add_argument("--workload", default="headline",
-                    choices=["headline", "uneven", "served", "pruning"],
+                    choices=["headline", "uneven", "served", "pruning", "quant"],
                     help="uneven: the batched uneven launch (2^20 frames of mixed codes); "
-                         "served: Poisson arrivals of mixed-size requests through the serving loop")
+                         "served: Poisson arrivals of mixed-size requests through the serving loop; "
+                         "quant: the quantisation sweep at scale")
+    ap.add_argument("--quant-frames", type=int, default=10_000_000,
+                    help="quant workload: frames per Eb/N0 point and LLR type")
+    ap.add_argument("--quant-oracle", type=int, default=10_000,
+                    help="quant workload: oracle sample per point (0: none)")
     args = ap.parse_args()
     if args.calib_copy:
         calib_copy(args.calib_copy)
@@ -747,8 +862,9 @@ def main():
         print("bench.py runs on one GPU: the decoder shards frames across GPUs with no "
               "collective, so only --gpus 1 is measured", file=sys.stderr)
         sys.exit(2)
-    if args.workload in ("uneven", "served", "pruning"):
-        r = {"uneven": bench_uneven, "served": bench_served, "pruning": bench_pruning}[args.workload](args)
+    if args.workload in ("uneven", "served", "pruning", "quant"):
+        r = {"uneven": bench_uneven, "served": bench_served, "pruning": bench_pruning,
+             "quant": bench_quant}[args.workload](args)
         print(json.dumps(r))
         return
 
