@@ -507,7 +507,9 @@ def quant_oracle_leg(quant, points, frames, threads):
     oq = {"f32": O.F32, "i16": O.I16, "i8": O.I8}[quant]
     frac = {"f32": 0, "i16": 3, "i8": 2}[quant]
     fz = O.construct(Q["N"], Q["K"], 0, Q["crc_len"], Q["design"])
-    code = O.Code(Q["N"], Q["K"], fz, Q["crc_len"], Q["crc_poly"], quant=oq, algo=O.CA_SCL, L=Q["L"])
+    # the GPU plan's node options: REP nodes of at most 8 positions in int8, any size otherwise
+    code = O.Code(Q["N"], Q["K"], fz, Q["crc_len"], Q["crc_poly"], quant=oq, algo=O.CA_SCL, L=Q["L"],
+                  rep_max=8 if quant == "i8" else 0, spc_max=4)
     out, secs, bits = {}, 0.0, 0
     for i, eb in enumerate(points):
         data, noise = synth.frames(9000 + i, 0, frames, code.k_data, code.n_tx)
@@ -546,7 +548,7 @@ def bench_quant(args):
     rows, oracle_mbps = {}, {}
     for quant, pq in (("f32", P.F32), ("i16", P.I16), ("i8", P.I8)):
         plan = P.Plan(Q["N"], Q["K"], Q["crc_len"], Q["crc_poly"], design_ebn0_db=Q["design"],
-                      algo=P.CA_SCL, L=Q["L"], quant=pq)
+                      algo=P.CA_SCL, L=Q["L"], quant=pq, rep_max=8 if quant == "i8" else 0, spc_max=4)
         kd = plan.info.k_data
         pts = {}
         for i, eb in enumerate(Q["points"]):
