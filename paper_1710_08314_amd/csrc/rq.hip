@@ -463,16 +463,34 @@ __device__ __forceinline__ void fork(RQ& R, PL& S, const Geo& G, uint32_t k0, ui
                                      bool rep) {
   constexpr int NW = nwords(K);
   constexpr uint32_t full = lowmask(nbits(K));
-  sort_all<L, TWO, 2>(k0, k1, G.fl, G.lane);
-  const uint32_t fb = G.lane - G.fl;  // the frame's first lane
-  uint32_t kr;
-  if constexpr (TWO) {
-    const uint32_t x0 = bperm(k0, fb + (G.r >> 1)), x1 = bperm(k1, fb + (G.r >> 1));
-    kr = (G.r & 1u) ? x1 : x0;
+  uint32_t kr, kf;
+  if constexpr (L == 2) {
+    // the two smallest keys of the frame on every lane of it: sorted pairs
+    // merged by a butterfly over its 8 lanes (the smallest of two pairs is
+    // the smaller first; the second is the smaller of the larger first and
+    // the smaller second)
+    uint32_t m1 = TWO ? min(k0, k1) : k0, m2 = TWO ? max(k0, k1) : 0xFFFFFFFFu;
+    const auto merge = [&](uint32_t o1, uint32_t o2) {
+      const uint32_t n2 = min(max(m1, o1), min(m2, o2));
+      m1 = min(m1, o1);
+      m2 = n2;
+    };
+    merge(xchg<1>(m1, G.lane), xchg<1>(m2, G.lane));
+    merge(xchg<2>(m1, G.lane), xchg<2>(m2, G.lane));
+    merge(xchg<4>(m1, G.lane), xchg<4>(m2, G.lane));
+    kr = G.r ? m2 : m1;
+    kf = m1;
   } else {
-    kr = bperm(k0, fb + G.r);
+    sort_all<L, TWO, 2>(k0, k1, G.fl, G.lane);
+    const uint32_t fb = G.lane - G.fl;  // the frame's first lane
+    if constexpr (TWO) {
+      const uint32_t x0 = bperm(k0, fb + (G.r >> 1)), x1 = bperm(k1, fb + (G.r >> 1));
+      kr = (G.r & 1u) ? x1 : x0;
+    } else {
+      kr = bperm(k0, fb + G.r);
+    }
+    kf = bperm(k0, fb);
   }
-  const uint32_t kf = bperm(k0, fb);
   const uint32_t an = min((uint32_t)L, a * C);
   const bool alive = G.r < an;
   const uint32_t p = alive ? (kr >> 4) & 15u : G.r, local = alive ? kr & 15u : 0u;
