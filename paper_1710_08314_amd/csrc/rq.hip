@@ -406,38 +406,70 @@ __device__ __forceinline__ uint32_t frame_min(uint32_t v, uint32_t lane) {
     return v;
 }
 
-// Ascending bitonic sort of a frame's candidate keys: 4 L elements, one per
-// lane (fl = lane within the frame), or 8 L with two per lane (element
-// 2 fl + t in k[t]).
+// Ascending sort of a frame's candidate keys: 4 L elements, one per lane
+// (element fl in lane fl of the frame), or 8 L with two per lane (element
+// 2 fl + t in k[t]).  A bitonic network in its mirrored form: every merge
+// first compares element e with e ^ (S - 1) (the block of S reversed), then
+// halves the distance; the lower element of each pair keeps the minimum, so
+// every block is ascending after its merge and runs that arrive sorted
+// (RUN elements, aligned) skip the stages below them.
+constexpr int kQMirror = 0x1B;                      // quad_perm [3, 2, 1, 0]
+constexpr int kRowHalfMirror = 0x141, kRowMirror = 0x140;
+// the value of lane (lane ^ (M - 1)), M a power of two from 2 to 64
+template <uint32_t M>
+__device__ __forceinline__ uint32_t mirror(uint32_t v, uint32_t lane) {
+  if constexpr (M == 2) return dpp<kQX1>(v);
+  else if constexpr (M == 4) return dpp<kQMirror>(v);
+  else if constexpr (M == 8) return dpp<kRowHalfMirror>(v);
+  else if constexpr (M == 16) return dpp<kRowMirror>(v);
+  else if constexpr (M == 32) return xchg<16>(dpp<kRowMirror>(v), lane);
+  else return xchg<32>(xchg<16>(dpp<kRowMirror>(v), lane), lane);
+}
+__device__ __forceinline__ uint32_t cx(uint32_t k, uint32_t p, bool keep_min) {
+  return keep_min ? min(k, p) : max(k, p);
+}
 template <int L, bool TWO, uint32_t S, uint32_t D>
-__device__ __forceinline__ void sort_step(uint32_t& k0, uint32_t& k1, uint32_t fl, uint32_t lane) {
+__device__ __forceinline__ void sort_half(uint32_t& k0, uint32_t& k1, uint32_t fl, uint32_t lane) {
   if constexpr (TWO && D == 1) {
-    const bool asc = ((2u * fl) & S) == 0u;
     const uint32_t lo = min(k0, k1), hi = max(k0, k1);
-    k0 = asc ? lo : hi;
-    k1 = asc ? hi : lo;
+    k0 = lo;
+    k1 = hi;
   } else {
     constexpr uint32_t DL = TWO ? D / 2 : D;  // lane distance
-    const uint32_t e = TWO ? 2u * fl : fl;
-    const bool keep_min = ((e & D) == 0u) == ((e & S) == 0u);
+    const bool keep = (fl & DL) == 0u;
     const uint32_t p0 = xchg<DL>(k0, lane);
-    k0 = keep_min ? min(k0, p0) : max(k0, p0);
+    k0 = cx(k0, p0, keep);
     if constexpr (TWO) {
       const uint32_t p1 = xchg<DL>(k1, lane);
-      k1 = keep_min ? min(k1, p1) : max(k1, p1);
+      k1 = cx(k1, p1, keep);
     }
   }
-}
-template <int L, bool TWO, uint32_t S, uint32_t D>
-__device__ __forceinline__ void sort_merge(uint32_t& k0, uint32_t& k1, uint32_t fl, uint32_t lane) {
-  sort_step<L, TWO, S, D>(k0, k1, fl, lane);
-  if constexpr (D > 1) sort_merge<L, TWO, S, D / 2>(k0, k1, fl, lane);
+  if constexpr (D > 1) sort_half<L, TWO, S, D / 2>(k0, k1, fl, lane);
 }
 template <int L, bool TWO, uint32_t S>
-__device__ __forceinline__ void sort_all(uint32_t& k0, uint32_t& k1, uint32_t fl, uint32_t lane) {
+__device__ __forceinline__ void sort_from(uint32_t& k0, uint32_t& k1, uint32_t fl, uint32_t lane) {
   constexpr uint32_t E = TWO ? 8u * L : 4u * L;
-  sort_merge<L, TWO, S, S / 2>(k0, k1, fl, lane);
-  if constexpr (S < E) sort_all<L, TWO, 2 * S>(k0, k1, fl, lane);
+  if constexpr (TWO) {
+    if constexpr (S == 2) {
+      const uint32_t lo = min(k0, k1), hi = max(k0, k1);
+      k0 = lo;
+      k1 = hi;
+    } else {
+      const bool keep = (fl & (S / 4)) == 0u;
+      const uint32_t p0 = mirror<S / 2>(k1, lane), p1 = mirror<S / 2>(k0, lane);
+      k0 = cx(k0, p0, keep);
+      k1 = cx(k1, p1, keep);
+    }
+  } else {
+    const bool keep = (fl & (S / 2)) == 0u;
+    k0 = cx(k0, mirror<S>(k0, lane), keep);
+  }
+  if constexpr (S >= 4) sort_half<L, TWO, S, S / 4>(k0, k1, fl, lane);
+  if constexpr (S < E) sort_from<L, TWO, 2 * S>(k0, k1, fl, lane);
+}
+template <int L, bool TWO, uint32_t RUN>
+__device__ __forceinline__ void sort_all(uint32_t& k0, uint32_t& k1, uint32_t fl, uint32_t lane) {
+  sort_from<L, TWO, 2 * RUN>(k0, k1, fl, lane);
 }
 
 // candidate key: (metric, parent rank, local index) as one integer
@@ -457,7 +489,7 @@ struct Geo {
 // whole small-level LLRs and packed left sums are copied; the node's partial
 // sums are the parent's hard decisions with the candidate's flips (or all v
 // for REP and information leaves).
-template <int K, int L, bool TWO, int T>
+template <int K, int L, bool TWO, int T, uint32_t RUN>
 __device__ __forceinline__ void fork(RQ& R, PL& S, const Geo& G, uint32_t k0, uint32_t k1, uint32_t C,
                                      uint32_t& a, const uint32_t (&hd)[nwords(K)], uint32_t pos,
                                      bool rep) {
@@ -481,7 +513,7 @@ __device__ __forceinline__ void fork(RQ& R, PL& S, const Geo& G, uint32_t k0, ui
     kr = G.r ? m2 : m1;
     kf = m1;
   } else {
-    sort_all<L, TWO, 2>(k0, k1, G.fl, G.lane);
+    sort_all<L, TWO, RUN>(k0, k1, G.fl, G.lane);
     const uint32_t fb = G.lane - G.fl;  // the frame's first lane
     if constexpr (TWO) {
       const uint32_t x0 = bperm(k0, fb + (G.r >> 1)), x1 = bperm(k1, fb + (G.r >> 1));
@@ -607,7 +639,10 @@ __device__ __forceinline__ void nodeL(RQ& R, PL& S, const Geo& G, uint32_t opc, 
     }
     if constexpr (K <= 5) {
       const uint32_t k0 = act && G.q < 2u ? ckey(S.pm, G.q ? p1 : p0, G.r, G.q) : 0xFFFFFFFFu;
-      fork<K, L, false, 2>(R, S, G, k0, 0u, 2u, a, hd, 0u, true);
+      // each quad's two candidates in order (lanes 2, 3 hold none): the
+      // quad is a sorted run of four
+      const uint32_t o = xchg<1>(k0, G.lane);
+      fork<K, L, false, 2, 4>(R, S, G, (G.q & 1u) ? max(k0, o) : min(k0, o), 0u, 2u, a, hd, 0u, true);
     }
     return;
   }
@@ -619,7 +654,9 @@ __device__ __forceinline__ void nodeL(RQ& R, PL& S, const Geo& G, uint32_t opc, 
     const uint32_t pos = (s2[0] & 0xFFFu) | ((s2[1] & 0xFFFu) << 16);
     const int pen = ((G.q & 1u) ? m0 : 0) + ((G.q & 2u) ? m1 : 0);
     const uint32_t k0 = act ? ckey(S.pm, pen, G.r, G.q) : 0xFFFFFFFFu;
-    fork<K, L, false, 2>(R, S, G, k0, 0u, 4u, a, hd, pos, false);
+    // the quad's four keys ascend with q (penalties 0, m0, m1, m0 + m1 with
+    // m0 <= m1, then the local index): a sorted run of four
+    fork<K, L, false, 2, 4>(R, S, G, k0, 0u, 4u, a, hd, pos, false);
     return;
   }
   if constexpr (K <= 5 && K >= 2) {
@@ -646,7 +683,7 @@ __device__ __forceinline__ void nodeL(RQ& R, PL& S, const Geo& G, uint32_t opc, 
         if ((mk >> u) & 1u) pen += (int)(s4[u] >> 12);
       kk[t] = act ? ckey(S.pm, pen, G.r, mk) : 0xFFFFFFFFu;
     }
-    fork<K, L, true, 4>(R, S, G, kk[0], kk[1], 8u, a, hd, pos, false);
+    fork<K, L, true, 4, 1>(R, S, G, kk[0], kk[1], 8u, a, hd, pos, false);
   }
 }
 
