@@ -17,11 +17,13 @@ CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libpolar_scl.so")
 BUILD_DIR = os.path.join(PKG, "_build")
 
-HIP_SOURCES = ["decode.hip", "sc.hip", "scx.hip", "rq.hip", "gen.hip", "noalloc.hip"]
+HIP_SOURCES = ["decode.hip", "sc.hip", "scx.hip", "rq.hip", "rq10.hip", "rq9.hip", "gen.hip",
+               "noalloc.hip"]
 # Per-file flags.  rq.hip keeps a path's whole state in registers, reached
 # through a switch over tree levels; merging the cases' common stores would
 # turn those registers into stack memory.
-EXTRA = {"rq.hip": ["-mllvm", "-simplifycfg-sink-common=false"]}
+_RQ_FLAGS = ["-mllvm", "-simplifycfg-sink-common=false"]
+EXTRA = {"rq.hip": _RQ_FLAGS, "rq10.hip": _RQ_FLAGS, "rq9.hip": _RQ_FLAGS}
 CPP_SOURCES = ["plan.cpp", "capi.cpp", "server.cpp"]
 
 ARCH = os.environ.get("POLAR_OFFLOAD_ARCH", "gfx950")

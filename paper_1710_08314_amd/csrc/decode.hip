@@ -1322,7 +1322,7 @@ static int launch_tiered_t(const KArgs& A, const TierPlan& tp, uint32_t* state, 
   hipLaunchKernelGGL(k_state_init, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, s, A, state);
   if (ev) (void)hipEventRecord(ev[0], s);
   if (tp.run_sc && tp.sc_q) {
-    const int rc = launch_decode_rq1(A, tp.n_ops, tp.grid_q, state, s);
+    const int rc = launch_decode_rq1(tp.sc_q, A, tp.n_ops, tp.grid_q, state, s);
     if (rc) return rc;
   } else if (tp.run_sc && tp.sc_x) {
     KArgs As = A;
@@ -1357,7 +1357,7 @@ static int launch_tiered_t(const KArgs& A, const TierPlan& tp, uint32_t* state, 
     Ap.spill_stride = tp.spill_p;
     for (uint32_t i = 0; i < tp.n_p; ++i) {
       const int rc = tp.sc_q && tp.p_stage[i] <= 16
-                         ? launch_decode_rqL(tp.p_stage[i], A, tp.n_ops, tp.grid_ql[i], state, xl, s)
+                         ? launch_decode_rqL(tp.sc_q, tp.p_stage[i], A, tp.n_ops, tp.grid_ql[i], state, xl, s)
                          : launch_decode_listp(tp.p_stage[i], Ap, tp.grid_p[i], state, xl, s);
       if (rc) return rc;
     }

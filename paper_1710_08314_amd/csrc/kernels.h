@@ -63,8 +63,9 @@ struct TierPlan {
                               // (k_listp) in place of list tiers A and B
   uint32_t p_stage[5], grid_p[5], n_p;  // those stages in order and their grids (waves)
   uint64_t spill_p;           // region bytes per wave (scx_region_bytes)
-  uint32_t sc_q;              // the L = 1 stage runs four lanes per frame, its state in
-                              // registers (k_rq1, N = 2048), in place of k_scx
+  uint32_t sc_q;              // nonzero: log2 N (9, 10 or 11); the L = 1 stage runs four
+                              // lanes per frame, its state in registers (k_rq), in
+                              // place of k_scx
   uint32_t grid_q;            // its persistent grid (waves)
   uint32_t n_ops;             // program words of the batch's plan (uniform batches)
   uint32_t grid_ql[5];        // with sc_q: grids of the list stages L <= 16, which then run
@@ -127,18 +128,28 @@ int launch_decode_listp(uint32_t L, const KArgs& A, uint32_t grid, uint32_t* sta
                         hipStream_t s);
 int launch_decode_scx(const KArgs& A, uint32_t grid, uint32_t* state, hipStream_t s);
 // The L = 1 stage with four lanes per frame and the decoder state in
-// registers (rq.hip), for the batches of k_scx with N = 2048 whose REP and
-// SPC nodes have at most 32 positions: 16 frames per wave, a persistent grid
-// of `grid` waves, no spill region; the plan's program (n_ops words) is
-// staged in LDS.
-int launch_decode_rq1(const KArgs& A, uint32_t n_ops, uint32_t grid, uint32_t* state,
+// registers (rq.hip), for the batches of k_scx with N = 2^nl, nl = 9, 10 or
+// 11, whose REP and SPC nodes have at most 32 positions: 16 frames per wave,
+// a persistent grid of `grid` waves, no spill region; the plan's program
+// (n_ops words) is staged in LDS.
+int launch_decode_rq1(uint32_t nl, const KArgs& A, uint32_t n_ops, uint32_t grid, uint32_t* state,
                       hipStream_t s);
 // The list stage of size L = 2, 4, 8 or 16 the same way (rq.hip), 16 / L
 // frames per wave, for the frames whose next stage is L (listed in xl by
 // launch_gather first).  Finished frames get state 0, the others their next
 // stage.
-int launch_decode_rqL(uint32_t L, const KArgs& A, uint32_t n_ops, uint32_t grid, uint32_t* state,
-                      uint32_t* xl, hipStream_t s);
+int launch_decode_rqL(uint32_t nl, uint32_t L, const KArgs& A, uint32_t n_ops, uint32_t grid,
+                      uint32_t* state, uint32_t* xl, hipStream_t s);
+// the same per code length (rq9.hip, rq10.hip, rq.hip)
+int launch_rq1_n9(const KArgs& A, uint32_t n_ops, uint32_t grid, uint32_t* state, hipStream_t s);
+int launch_rq1_n10(const KArgs& A, uint32_t n_ops, uint32_t grid, uint32_t* state, hipStream_t s);
+int launch_rq1_n11(const KArgs& A, uint32_t n_ops, uint32_t grid, uint32_t* state, hipStream_t s);
+int launch_rqL_n9(uint32_t L, const KArgs& A, uint32_t n_ops, uint32_t grid, uint32_t* state,
+                  uint32_t* xl, hipStream_t s);
+int launch_rqL_n10(uint32_t L, const KArgs& A, uint32_t n_ops, uint32_t grid, uint32_t* state,
+                   uint32_t* xl, hipStream_t s);
+int launch_rqL_n11(uint32_t L, const KArgs& A, uint32_t n_ops, uint32_t grid, uint32_t* state,
+                   uint32_t* xl, hipStream_t s);
 // The frames whose next stage is L, listed in xl (xl[0] = count, then their
 // indices in no set order; scx.hip).
 int launch_gather(uint32_t n_frames, uint32_t L, const uint32_t* state, uint32_t* xl, hipStream_t s);

@@ -808,6 +808,14 @@ template <int NL>
 constexpr uint32_t skey(uint32_t opc, int K, uint32_t sub = 0) {
   return opc | ((uint32_t)(NL - K) << 4) | (sub << 24);
 }
+// the key of a case that exists for some code lengths only: for a level the
+// code does not have (K > KMAX) a distinct key no program word matches (bits
+// 28..31 are never set under the key mask)
+template <int NL, int KMAX>
+constexpr uint32_t rkey(uint32_t opc, int K, uint32_t sub = 0) {
+  return K <= KMAX ? skey<NL>(opc, K, sub)
+                   : (0xF0000000u | opc | ((uint32_t)K << 4) | (sub << 12));
+}
 
 // One step whose level lies in [KLO, KHI], through a single switch over
 // every (opcode, level, fused child) the programs use: one binary search,
@@ -830,22 +838,22 @@ __device__ __forceinline__ void step(RQ& R, PL& S, const Geo& G, uint32_t w, con
     asm volatile("" : "+v"(Go.lane), "+v"(Go.q), "+v"(Go.Q), "+v"(Go.r), "+v"(Go.g0), "+v"(Go.fl));
   const uint32_t q = Go.q, Q = Go.Q;
 #define POLAR_C_FG(K)                                                                   \
-  case skey<NL>(OP_F, K): if constexpr (K >= KLO && K <= KHI && K < NL) fg_x<NL, L, K, false>(R, S, rw, q, Q); break; \
-  case skey<NL>(OP_G, K): if constexpr (K >= KLO && K <= KHI && K < NL) fg_x<NL, L, K, true>(R, S, rw, q, Q); break;  \
-  case skey<NL>(OP_H, K): if constexpr (K >= KLO && K <= KHI && K < NL) h_x<L, K>(R, S, q); break;
+  case rkey<NL, NL - 1>(OP_F, K): if constexpr (K >= KLO && K <= KHI && K < NL) fg_x<NL, L, K, false>(R, S, rw, q, Q); break; \
+  case rkey<NL, NL - 1>(OP_G, K): if constexpr (K >= KLO && K <= KHI && K < NL) fg_x<NL, L, K, true>(R, S, rw, q, Q); break;  \
+  case rkey<NL, NL - 1>(OP_H, K): if constexpr (K >= KLO && K <= KHI && K < NL) h_x<L, K>(R, S, q); break;
 #define POLAR_C_N(K, O) \
-  case skey<NL>(O, K): if constexpr (K >= KLO && K <= KHI && K < NL) node_x<L, K>(R, S, Go, O, a); break;
+  case rkey<NL, NL - 1>(O, K): if constexpr (K >= KLO && K <= KHI && K < NL) node_x<L, K>(R, S, Go, O, a); break;
 #define POLAR_C_NODES(K) POLAR_C_N(K, OP_R0) POLAR_C_N(K, OP_R1)
 #define POLAR_C_NODES5(K) POLAR_C_NODES(K) POLAR_C_N(K, OP_REP) POLAR_C_N(K, OP_SPC)
 #define POLAR_C_FU(K, O)                                                                 \
-  case skey<NL>(OP_FN, K, O):                                                            \
+  case rkey<NL, NL>(OP_FN, K, O):                                                            \
     if constexpr (K >= KLO && K <= KHI && K <= NL) fused_step<NL, L, K, false>(R, S, Go, O, rw, a); \
     break;                                                                               \
-  case skey<NL>(OP_GNH, K, O):                                                           \
+  case rkey<NL, NL>(OP_GNH, K, O):                                                           \
     if constexpr (K >= KLO && K <= KHI && K <= NL) fused_step<NL, L, K, true>(R, S, Go, O, rw, a);  \
     break;
 #define POLAR_C_PAIR(K)                                                                  \
-  case skey<NL>(OP_PAIR, K):                                                             \
+  case rkey<NL, NL>(OP_PAIR, K):                                                             \
     if constexpr (L > 1 && K >= KLO && K <= KHI && K <= NL) pair_step<NL, L, K>(R, S, Go, w, rw, a); \
     break;
 #define POLAR_C_FU4(K) POLAR_C_FU(K, OP_R0) POLAR_C_FU(K, OP_R1)
@@ -1102,28 +1110,85 @@ __global__ __launch_bounds__(64, 2) void k_rq(KArgs A, uint32_t* state, const ui
   }
 }
 
-int launch_decode_rq1(const KArgs& A, uint32_t n_ops, uint32_t grid, uint32_t* state,
-                      hipStream_t s) {
-  hipLaunchKernelGGL((k_rq<11, 1>), dim3(grid > 0 ? grid : 1), dim3(64), (n_ops + 4u) / 4u * 16u,
+// Launchers of the stages for codes of length 2^NL.  This file builds the
+// kernels of NL = POLAR_RQ_NL (11 unless the including unit says otherwise:
+// rq9.hip and rq10.hip build NL = 9 and 10 in units of their own, which
+// compile in parallel), and for NL = 11 also the dispatch over NL.
+template <int NL>
+int launch_rq1_t(const KArgs& A, uint32_t n_ops, uint32_t grid, uint32_t* state, hipStream_t s) {
+  hipLaunchKernelGGL((k_rq<NL, 1>), dim3(grid > 0 ? grid : 1), dim3(64), (n_ops + 4u) / 4u * 16u,
                      s, A, state, (const uint32_t*)nullptr);
   return hipGetLastError() == hipSuccess ? POLAR_OK : POLAR_EHIP;
 }
 
-int launch_decode_rqL(uint32_t L, const KArgs& A, uint32_t n_ops, uint32_t grid, uint32_t* state,
-                      uint32_t* xl, hipStream_t s) {
+template <int NL>
+int launch_rqL_t(uint32_t L, const KArgs& A, uint32_t n_ops, uint32_t grid, uint32_t* state,
+                 uint32_t* xl, hipStream_t s) {
   int rc = launch_gather(A.n_frames, L, state, xl, s);
   if (rc) return rc;
   const dim3 gr(grid > 0 ? grid : 1), bl(64);
   const uint32_t lds = (n_ops + 4u) / 4u * 16u;
   const uint32_t* x = xl;
   switch (L) {
-    case 2: hipLaunchKernelGGL((k_rq<11, 2>), gr, bl, lds, s, A, state, x); break;
-    case 4: hipLaunchKernelGGL((k_rq<11, 4>), gr, bl, lds, s, A, state, x); break;
-    case 8: hipLaunchKernelGGL((k_rq<11, 8>), gr, bl, lds, s, A, state, x); break;
-    case 16: hipLaunchKernelGGL((k_rq<11, 16>), gr, bl, lds, s, A, state, x); break;
+    case 2: hipLaunchKernelGGL((k_rq<NL, 2>), gr, bl, lds, s, A, state, x); break;
+    case 4: hipLaunchKernelGGL((k_rq<NL, 4>), gr, bl, lds, s, A, state, x); break;
+    case 8: hipLaunchKernelGGL((k_rq<NL, 8>), gr, bl, lds, s, A, state, x); break;
+    case 16: hipLaunchKernelGGL((k_rq<NL, 16>), gr, bl, lds, s, A, state, x); break;
     default: return POLAR_EINVAL;
   }
   return hipGetLastError() == hipSuccess ? POLAR_OK : POLAR_EHIP;
 }
+
+#ifndef POLAR_RQ_NL
+#define POLAR_RQ_NL 11
+#endif
+
+#if POLAR_RQ_NL == 11
+int launch_rq1_n11(const KArgs& A, uint32_t n_ops, uint32_t grid, uint32_t* state, hipStream_t s) {
+  return launch_rq1_t<11>(A, n_ops, grid, state, s);
+}
+int launch_rqL_n11(uint32_t L, const KArgs& A, uint32_t n_ops, uint32_t grid, uint32_t* state,
+                   uint32_t* xl, hipStream_t s) {
+  return launch_rqL_t<11>(L, A, n_ops, grid, state, xl, s);
+}
+
+int launch_decode_rq1(uint32_t nl, const KArgs& A, uint32_t n_ops, uint32_t grid, uint32_t* state,
+                      hipStream_t s) {
+  switch (nl) {
+    case 9: return launch_rq1_n9(A, n_ops, grid, state, s);
+    case 10: return launch_rq1_n10(A, n_ops, grid, state, s);
+    case 11: return launch_rq1_n11(A, n_ops, grid, state, s);
+    default: return POLAR_EINVAL;
+  }
+}
+
+int launch_decode_rqL(uint32_t nl, uint32_t L, const KArgs& A, uint32_t n_ops, uint32_t grid,
+                      uint32_t* state, uint32_t* xl, hipStream_t s) {
+  switch (nl) {
+    case 9: return launch_rqL_n9(L, A, n_ops, grid, state, xl, s);
+    case 10: return launch_rqL_n10(L, A, n_ops, grid, state, xl, s);
+    case 11: return launch_rqL_n11(L, A, n_ops, grid, state, xl, s);
+    default: return POLAR_EINVAL;
+  }
+}
+#elif POLAR_RQ_NL == 10
+int launch_rq1_n10(const KArgs& A, uint32_t n_ops, uint32_t grid, uint32_t* state, hipStream_t s) {
+  return launch_rq1_t<10>(A, n_ops, grid, state, s);
+}
+int launch_rqL_n10(uint32_t L, const KArgs& A, uint32_t n_ops, uint32_t grid, uint32_t* state,
+                   uint32_t* xl, hipStream_t s) {
+  return launch_rqL_t<10>(L, A, n_ops, grid, state, xl, s);
+}
+#elif POLAR_RQ_NL == 9
+int launch_rq1_n9(const KArgs& A, uint32_t n_ops, uint32_t grid, uint32_t* state, hipStream_t s) {
+  return launch_rq1_t<9>(A, n_ops, grid, state, s);
+}
+int launch_rqL_n9(uint32_t L, const KArgs& A, uint32_t n_ops, uint32_t grid, uint32_t* state,
+                  uint32_t* xl, hipStream_t s) {
+  return launch_rqL_t<9>(L, A, n_ops, grid, state, xl, s);
+}
+#else
+#error "register stages are built for NL = 9, 10 and 11"
+#endif
 
 }  // namespace polar

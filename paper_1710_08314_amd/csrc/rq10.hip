@@ -1,0 +1,4 @@
+// The register stages for codes of length 2^10, built in a unit of their own
+// (the kernels and launchers are those of rq.hip).
+#define POLAR_RQ_NL 10
+#include "rq.hip"
