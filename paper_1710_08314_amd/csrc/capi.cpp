@@ -548,10 +548,11 @@ int plan_tiers(const Batch& b, polar::TierPlan* out) {
         // stage of the plan
         const uint32_t cap2 = 12u * (uint32_t)cus;
         // N = 512, 1024 or 2048 with REP / SPC nodes in the register levels:
-        // four lanes per frame, the state in registers (2 waves per SIMD: its
-        // registers)
+        // four lanes per frame, the state in registers (waves per SIMD that
+        // its registers allow: 2 at N = 2048, 3 below)
         if (small && h.n >= 9 && h.n <= 11) {
-          const uint32_t g16 = (n_frames + 15) / 16, capq = 8u * (uint32_t)cus;
+          const uint32_t g16 = (n_frames + 15) / 16;
+          const uint32_t capq = (h.n <= 10 ? 12u : 8u) * (uint32_t)cus;
           tp.sc_q = h.n;
           tp.n_ops = h.n_sc_ops;  // LDS for the longer program (the lists' is shorter)
           tp.grid_q = g16 < capq ? (g16 ? g16 : 1u) : capq;

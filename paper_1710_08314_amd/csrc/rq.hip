@@ -901,8 +901,15 @@ __device__ __forceinline__ void step(RQ& R, PL& S, const Geo& G, uint32_t w, con
 // are finished); L > 1 decodes the frames listed in xl (finished frames get
 // state 0, the others their next stage).  Lanes past the batch or list
 // decode a frame already taken and drop the result.
+// Waves per SIMD the registers allow: a path's state is 157 words at N = 2048
+// (two waves), about half of that less at N <= 1024 for a single path (three).
 template <int NL, int L>
-__global__ __launch_bounds__(64, 2) void k_rq(KArgs A, uint32_t* state, const uint32_t* xl) {
+constexpr int rq_waves() {
+  return NL <= 10 && L == 1 ? 3 : 2;
+}
+
+template <int NL, int L>
+__global__ __launch_bounds__(64, (rq_waves<NL, L>())) void k_rq(KArgs A, uint32_t* state, const uint32_t* xl) {
   constexpr uint32_t FW = 16u / L;          // frames per wave
   constexpr int KB = L == 1 ? 6 : 0;        // the walk's split level (0: none)
   constexpr int CWW = 2 * nwords(NL - 1);  // codeword words per lane
