@@ -399,18 +399,24 @@ Q_CASES = [
     (2048, 1500, 16, 0x1021, 3.5, "ca", 2, dict(node_enable=O.NODE_R0 | O.NODE_R1), 2.5),
     (2048, 1200, 11, 0x621, 3.0, "ca", 4, dict(r1_max=64, rep_max=2), 2.0),
     (2048, 800, 11, 0x621, 2.0, "fa", 16, dict(node_enable=0), 1.0),
+    (1024, 512, 24, 0x1864CFB, 2.5, "fa", 16, dict(), 1.5),
+    (1024, 512, 24, 0x1864CFB, 2.5, "ca", 8, dict(), 1.5),
+    (512, 300, 11, 0x621, 2.5, "pa", 16, dict(spc_max=32, rep_max=32), 1.5),
+    (512, 256, 16, 0x1021, 2.0, "sc", 1, dict(), 3.0),
 ]
 
 
 @pytest.mark.parametrize("case", range(len(Q_CASES)))
-def test_register_stages_n2048(case):
-    """Uniform int8 batches of N = 2048 codes whose REP / SPC nodes have at
-    most 32 positions: the L = 1 stage and the list stages up to 16 run with
-    four lanes per path and the whole decoder state in registers (16 / L
-    frames per wave, a persistent grid).  SC, FA and PA to 16, CA at 2, 4
-    and 8 (every frame in one list stage), the default node set, Rate-0 /
-    Rate-1 only, capped Rate-1 and REP sizes, and leaves only (a program of
-    thousands of steps), at SNRs where many frames fork and escalate; bits,
+def test_register_stages(case):
+    """Uniform int8 batches of N = 512, 1024 and 2048 codes whose REP / SPC
+    nodes have at most 32 positions: the L = 1 stage and the list stages up
+    to 16 run with four lanes per path and the whole decoder state in
+    registers (16 / L frames per wave, a persistent grid; three waves per
+    SIMD for the single path below N = 2048).  SC, FA and PA to 16, CA at 2,
+    4 and 8 (every frame in one list stage), the default node set, Rate-0 /
+    Rate-1 only, capped Rate-1 and REP sizes, REP / SPC up to 32 positions,
+    and leaves only (a program of thousands of steps), at SNRs where many
+    frames fork and escalate; bits,
     CRC flags, list sizes, metrics and metric lists equal the oracle for
     batches of 1, 17 and 100 frames (a lone frame, a ragged wave, several
     waves).  Adaptive (FA, PA) batches below 32 frames run the plain form by
