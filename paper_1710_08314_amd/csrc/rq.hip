@@ -18,8 +18,18 @@
 //     4 (i >> 4) + (i & 3); smaller nodes are held whole by every lane;
 //   * the left child's partial sums of every split node on the current path
 //     wait in registers until the node's h consumes them.
-// An int8 frame of N = 2048 needs about 160 registers per lane, no LDS and
-// no global memory besides its channel LLRs and outputs.
+// A path of an int8 code of N = 2048 holds 157 words per lane (two waves
+// per SIMD); below N = 2048 a single path fits three waves per SIMD.  Beside
+// the registers a wave uses LDS only for a copy of the node program and to
+// stage each path's codeword for the CRC and the output, and global memory
+// only for the channel LLRs, the plan's tables and the outputs.
+//
+// Lists keep, per level, the quad whose registers hold a path's node (index
+// indirection: a fork moves slot numbers and the small levels, never the
+// large levels' LLRs).  Candidate keys are sorted with lane exchanges (DPP,
+// row rotations and mirrors, the 16- and 32-lane swaps); a node's words in
+// another quad, a survivor's key (L >= 4) and its parent's registers come
+// by ds_bpermute.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
