@@ -565,7 +565,7 @@ int plan_tiers(const Batch& b, polar::TierPlan* out) {
         }
         // list stages: one path per lane when each of them is 2, 4, 8, 16 or
         // 32 (then also in place of the frame-per-lane L = 2 stage; waves per
-        // CU that the registers allow: 4 per SIMD at L <= 8, 3 above)
+        // CU that the registers allow: 4 per SIMD at L <= 8 and 32, 3 at 16)
         uint32_t st = h.first_stage, np = 0, pst[5] = {0, 0, 0, 0, 0};
         bool fits = small;
         for (int guard = 0; guard < 8; ++guard) {
@@ -583,10 +583,17 @@ int plan_tiers(const Batch& b, polar::TierPlan* out) {
           tp.run_p = 1;
           tp.n_p = np;
           tp.spill_p = polar::scx_region_bytes(h.N);
+          // the L = 32 stage's short lists: the region in LDS, as many waves
+          // per CU as its LDS holds (1 at N = 2048, 2 at N = 1024)
+          const uint32_t lds_w = (uint32_t)tp.spill_p + polar::listp_static_lds();
+          if (lds_w <= polar::kLdsLimit) {
+            tp.lds_pl = (uint32_t)tp.spill_p;
+            tp.grid_pl = (polar::kLdsLimit / lds_w) * (uint32_t)cus;
+          }
           for (uint32_t i = 0; i < np; ++i) {
             const uint32_t fw = 64u / pst[i];
             const uint32_t need = (n_frames + fw - 1) / fw;
-            const uint32_t capp = (pst[i] <= 8 ? 16u : 12u) * (uint32_t)cus;
+            const uint32_t capp = (pst[i] <= 8 || pst[i] == 32 ? 16u : 12u) * (uint32_t)cus;
             tp.p_stage[i] = pst[i];
             tp.grid_p[i] = polar::cap_grid(need < capp ? (need ? need : 1u) : capp, tp.spill_p,
                                            b.spill_cap);

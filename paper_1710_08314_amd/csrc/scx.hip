@@ -1488,11 +1488,15 @@ int launch_decode_listx(const KArgs& A, uint32_t grid, uint32_t* state, uint32_t
 // The stage of size L >= 2 of the listed frames, 64 / L per wave
 // (persistent grid, wave q takes the groups q, q + G, ...).  A frame whose
 // CRC passes, or whose plan ends at L, is finished (bits, status, metric
-// list, end stamp; state 0); the others get their next stage.
-template <int L>
-__global__ __launch_bounds__(64) void k_listp(KArgs A, uint32_t* state, const uint32_t* xl) {
-  __shared__ uint4 lds6p[4 * 64];  // level 6: 4 chunks per lane
-  __shared__ uint32_t selp[64];
+// list, end stamp; state 0); the others get their next stage.  `region` is
+// the wave's region (levels 7 .. n-1 and the partial sums): global memory,
+// or LDS in the form for short lists (LR).  Of the two forms launched for a
+// stage, the LDS one takes the list when it has at most lr_groups groups and
+// the global one otherwise; the other returns at once.
+template <int L, bool LR>
+__device__ __forceinline__ void listp_run(const KArgs& A, uint32_t* state, const uint32_t* xl,
+                                          char* region, uint4* lds6p, uint32_t* selp,
+                                          uint32_t lr_groups) {
   constexpr uint32_t FW = 64u / L;  // frames per wave
   const uint32_t lane = threadIdx.x, gi = lane / L, r = lane % L, g0 = lane - r;
   const DevPlan* P = uni_ptr(A.plans[0]);
@@ -1502,7 +1506,6 @@ __global__ __launch_bounds__(64) void k_listp(KArgs A, uint32_t* state, const ui
   const uint32_t* imask = uni_ptr(plan_tab(P, uni(P->off_infomask)));
   const uint32_t* nib = uni_ptr(plan_tab(P, uni(P->off_crcnib)));
   const uint32_t* dmask = uni_ptr(plan_tab(P, uni(P->off_datamask)));
-  char* region = A.spill + (size_t)blockIdx.x * A.spill_stride;
   // the count through a vector load at device scope, not the scalar cache;
   // a list never holds more frames than the batch, and the list's capacity
   // is the batch size, so a count above it is never trusted
@@ -1510,6 +1513,7 @@ __global__ __launch_bounds__(64) void k_listp(KArgs A, uint32_t* state, const ui
       uni(__hip_atomic_load(&xl[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
   const uint32_t count = count0 < A.n_frames ? count0 : A.n_frames;
   const uint32_t n_groups = (count + FW - 1u) / FW;
+  if (LR ? n_groups > lr_groups : n_groups <= lr_groups) return;
   for (uint32_t q = blockIdx.x; q < n_groups; q += gridDim.x) {
     const uint32_t idx = FW * q + gi;
     const bool valid = idx < count;
@@ -1626,6 +1630,39 @@ __global__ __launch_bounds__(64) void k_listp(KArgs A, uint32_t* state, const ui
   }
 }
 
+// L = 32 is held to 128 VGPRs (4 waves per SIMD): at the busiest point its
+// frames then fit the chip in one pass.
+template <int L>
+__global__ __launch_bounds__(64, (L == 32 ? 4 : 1)) void k_listp(KArgs A, uint32_t* state,
+                                                                 const uint32_t* xl,
+                                                                 uint32_t lr_groups) {
+  __shared__ uint4 lds6p[4 * 64];  // level 6: 4 chunks per lane
+  __shared__ uint32_t selp[64];
+  listp_run<L, false>(A, state, xl, A.spill + (size_t)blockIdx.x * A.spill_stride, lds6p, selp,
+                      lr_groups);
+}
+
+// The same stage with the wave's region in dynamic LDS (scx_region_bytes(N)
+// bytes): for short lists, whose few waves would otherwise wait on global
+// memory at every level >= 7.
+template <int L>
+__global__ __launch_bounds__(64, 1) void k_listp_lds(KArgs A, uint32_t* state, const uint32_t* xl,
+                                                     uint32_t lr_groups) {
+  __shared__ uint4 lds6p[4 * 64];
+  __shared__ uint32_t selp[64];
+  extern __shared__ uint4 lds_region[];
+  listp_run<L, true>(A, state, xl, reinterpret_cast<char*>(lds_region), lds6p, selp, lr_groups);
+}
+
+uint32_t listp_static_lds() { return (uint32_t)(4 * 64 * sizeof(uint4) + 64 * sizeof(uint32_t)); }
+
+int listp_set_attributes(uint32_t lds) {
+  return hipFuncSetAttribute((const void*)k_listp_lds<32>,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) == hipSuccess
+             ? POLAR_OK
+             : POLAR_EHIP;
+}
+
 int launch_gather(uint32_t n_frames, uint32_t L, const uint32_t* state, uint32_t* xl, hipStream_t s) {
   const uint32_t gb = (n_frames + 255u) / 256u < 1024u ? (n_frames + 255u) / 256u : 1024u;
   hipLaunchKernelGGL(k_xreset, dim3(1), dim3(64), 0, s, xl);
@@ -1633,23 +1670,29 @@ int launch_gather(uint32_t n_frames, uint32_t L, const uint32_t* state, uint32_t
   return hipGetLastError() == hipSuccess ? POLAR_OK : POLAR_EHIP;
 }
 
-int launch_decode_listp(uint32_t L, const KArgs& A, uint32_t grid, uint32_t* state, uint32_t* xl,
-                        hipStream_t s) {
+int launch_decode_listp(uint32_t L, const KArgs& A, uint32_t grid, uint32_t grid_lds,
+                        uint32_t lds, uint32_t* state, uint32_t* xl, hipStream_t s) {
   const uint32_t gb = (A.n_frames + 255u) / 256u < 1024u ? (A.n_frames + 255u) / 256u : 1024u;
   hipLaunchKernelGGL(k_xreset, dim3(1), dim3(64), 0, s, xl);
   hipLaunchKernelGGL(k_gather, dim3(gb > 0 ? gb : 1), dim3(256), 0, s, A.n_frames, L,
                      (const uint32_t*)state, xl);
   const dim3 gr(grid > 0 ? grid : 1);
+  // the LDS form (L = 32 only) takes lists of up to one group per wave of its grid
+  const bool lr = L == 32 && grid_lds > 0 && lds > 0;
+  const uint32_t lr_groups = lr ? grid_lds : 0u;
+  if (lr)
+    hipLaunchKernelGGL(k_listp_lds<32>, dim3(grid_lds), dim3(64), lds, s, A, state,
+                       (const uint32_t*)xl, lr_groups);
   if (L == 2)
-    hipLaunchKernelGGL(k_listp<2>, gr, dim3(64), 0, s, A, state, (const uint32_t*)xl);
+    hipLaunchKernelGGL(k_listp<2>, gr, dim3(64), 0, s, A, state, (const uint32_t*)xl, lr_groups);
   else if (L == 4)
-    hipLaunchKernelGGL(k_listp<4>, gr, dim3(64), 0, s, A, state, (const uint32_t*)xl);
+    hipLaunchKernelGGL(k_listp<4>, gr, dim3(64), 0, s, A, state, (const uint32_t*)xl, lr_groups);
   else if (L == 8)
-    hipLaunchKernelGGL(k_listp<8>, gr, dim3(64), 0, s, A, state, (const uint32_t*)xl);
+    hipLaunchKernelGGL(k_listp<8>, gr, dim3(64), 0, s, A, state, (const uint32_t*)xl, lr_groups);
   else if (L == 16)
-    hipLaunchKernelGGL(k_listp<16>, gr, dim3(64), 0, s, A, state, (const uint32_t*)xl);
+    hipLaunchKernelGGL(k_listp<16>, gr, dim3(64), 0, s, A, state, (const uint32_t*)xl, lr_groups);
   else
-    hipLaunchKernelGGL(k_listp<32>, gr, dim3(64), 0, s, A, state, (const uint32_t*)xl);
+    hipLaunchKernelGGL(k_listp<32>, gr, dim3(64), 0, s, A, state, (const uint32_t*)xl, lr_groups);
   return hipGetLastError() == hipSuccess ? POLAR_OK : POLAR_EHIP;
 }
 

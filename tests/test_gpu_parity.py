@@ -390,6 +390,21 @@ def test_list_stages_path_per_lane(case):
         compare(code, llr)
 
 
+@pytest.mark.parametrize("n", [500, 700])
+def test_list32_stage_lds_and_global_forms(n):
+    """The L = 32 stage of the headline FA schedule at 2.5 dB, where nearly 9
+    frames in 10 reach it and about one in six of those passes its CRC.  A
+    list of at most one group (two frames) per wave of the stage's LDS form
+    (256 groups on a 256-CU device at N = 2048) runs with each wave's region
+    in LDS; a longer list runs with the regions in global memory.  Batches
+    of 500 frames (about 440 at L = 32: the LDS form) and 700 (about 620:
+    the global form) equal the oracle element by element."""
+    code = _code(2048, 1723, 32, 0x04C11DB7, 4.5, quant="i8", algo="fa", L_max=32)
+    _, llr = make_inputs(code, n, 3100 + n, 2.5)
+    rep = compare(code, llr)
+    assert rep["escalated"] > 0.8 * n
+
+
 Q_CASES = [
     # (N, K, c, poly, design dB, algo, L, node options, Eb/N0)
     (2048, 1723, 32, 0x04C11DB7, 4.5, "sc", 1, dict(), 4.0),
