@@ -597,6 +597,11 @@ int plan_tiers(const Batch& b, polar::TierPlan* out) {
             tp.p_stage[i] = pst[i];
             tp.grid_p[i] = polar::cap_grid(need < capp ? (need ? need : 1u) : capp, tp.spill_p,
                                            b.spill_cap);
+            if (pst[i] == 32) {
+              // lists of up to 3 waves per SIMD: the form with no register bound
+              const uint32_t cm = 12u * (uint32_t)cus;
+              tp.grid_pm = tp.grid_p[i] < cm ? tp.grid_p[i] : cm;
+            }
             // four lanes per path: 16 / L frames per wave, 2 waves per SIMD
             const uint32_t nq = (n_frames + 16u / pst[i] - 1u) / (16u / pst[i] < 1u ? 1u : 16u / pst[i]);
             const uint32_t capq = 8u * (uint32_t)cus;

@@ -1359,8 +1359,8 @@ static int launch_tiered_t(const KArgs& A, const TierPlan& tp, uint32_t* state, 
     for (uint32_t i = 0; i < tp.n_p; ++i) {
       const int rc = tp.sc_q && tp.p_stage[i] <= 16
                          ? launch_decode_rqL(tp.sc_q, tp.p_stage[i], A, tp.n_ops, tp.grid_ql[i], state, xl, s)
-                         : launch_decode_listp(tp.p_stage[i], Ap, tp.grid_p[i], tp.grid_pl, tp.lds_pl,
-                                               state, xl, s);
+                         : launch_decode_listp(tp.p_stage[i], Ap, tp.grid_p[i], tp.grid_pm, tp.grid_pl,
+                                               tp.lds_pl, state, xl, s);
       if (rc) return rc;
     }
   } else if (tp.run_b) {

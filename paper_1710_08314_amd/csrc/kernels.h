@@ -65,6 +65,7 @@ struct TierPlan {
   uint64_t spill_p;           // region bytes per wave (scx_region_bytes)
   uint32_t grid_pl, lds_pl;   // the L = 32 stage's LDS form for short lists: grid (waves)
                               // and region bytes in LDS (0: not used)
+  uint32_t grid_pm;           // its unbounded-register form for lists up to one pass
   uint32_t sc_q;              // nonzero: log2 N (9, 10 or 11); the L = 1 stage runs four
                               // lanes per frame, its state in registers (k_rq), in
                               // place of k_scx
@@ -125,12 +126,16 @@ int launch_decode_listx(const KArgs& A, uint32_t grid, uint32_t* state, uint32_t
 // The stages of size L = 2, 4, 8, 16, 32 with one path per lane (scx.hip), 64 / L
 // frames per wave, for the same batches: the frames whose next stage is L
 // are listed in xl as above, then decoded by a persistent grid of `grid`
-// waves, each with a region of scx_region_bytes(N).  With grid_lds > 0 and
-// lds > 0 (L = 32 only), a list of at most grid_lds groups is decoded instead
-// by grid_lds waves whose regions are `lds` bytes of dynamic LDS
-// (scx_region_bytes(N) <= lds, lds + listp_static_lds() <= the LDS of a CU).
-int launch_decode_listp(uint32_t L, const KArgs& A, uint32_t grid, uint32_t grid_lds,
-                        uint32_t lds, uint32_t* state, uint32_t* xl, hipStream_t s);
+// waves, each with a region of scx_region_bytes(N).  At L = 32 the list's
+// group count picks one of three forms: with grid_lds > 0 and lds > 0, up to
+// grid_lds groups go to grid_lds waves whose regions are `lds` bytes of
+// dynamic LDS (scx_region_bytes(N) <= lds, lds + listp_static_lds() <= the
+// LDS of a CU); then up to grid_mid groups to grid_mid waves with no register
+// bound (grid_mid <= grid: their regions are the first grid_mid of the
+// global ones); longer lists to the `grid` waves held to 4 per SIMD.
+int launch_decode_listp(uint32_t L, const KArgs& A, uint32_t grid, uint32_t grid_mid,
+                        uint32_t grid_lds, uint32_t lds, uint32_t* state, uint32_t* xl,
+                        hipStream_t s);
 uint32_t listp_static_lds();
 int listp_set_attributes(uint32_t lds);
 int launch_decode_scx(const KArgs& A, uint32_t grid, uint32_t* state, hipStream_t s);

@@ -1490,13 +1490,13 @@ int launch_decode_listx(const KArgs& A, uint32_t grid, uint32_t* state, uint32_t
 // CRC passes, or whose plan ends at L, is finished (bits, status, metric
 // list, end stamp; state 0); the others get their next stage.  `region` is
 // the wave's region (levels 7 .. n-1 and the partial sums): global memory,
-// or LDS in the form for short lists (LR).  Of the two forms launched for a
-// stage, the LDS one takes the list when it has at most lr_groups groups and
-// the global one otherwise; the other returns at once.
-template <int L, bool LR>
+// or LDS in the form for short lists.  Of the forms launched for a stage,
+// the one whose range lo < groups <= hi holds the list's group count takes
+// it; the others return at once.
+template <int L>
 __device__ __forceinline__ void listp_run(const KArgs& A, uint32_t* state, const uint32_t* xl,
                                           char* region, uint4* lds6p, uint32_t* selp,
-                                          uint32_t lr_groups) {
+                                          uint32_t lo, uint32_t hi) {
   constexpr uint32_t FW = 64u / L;  // frames per wave
   const uint32_t lane = threadIdx.x, gi = lane / L, r = lane % L, g0 = lane - r;
   const DevPlan* P = uni_ptr(A.plans[0]);
@@ -1513,7 +1513,7 @@ __device__ __forceinline__ void listp_run(const KArgs& A, uint32_t* state, const
       uni(__hip_atomic_load(&xl[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
   const uint32_t count = count0 < A.n_frames ? count0 : A.n_frames;
   const uint32_t n_groups = (count + FW - 1u) / FW;
-  if (LR ? n_groups > lr_groups : n_groups <= lr_groups) return;
+  if (n_groups <= lo || n_groups > hi) return;
   for (uint32_t q = blockIdx.x; q < n_groups; q += gridDim.x) {
     const uint32_t idx = FW * q + gi;
     const bool valid = idx < count;
@@ -1634,12 +1634,22 @@ __device__ __forceinline__ void listp_run(const KArgs& A, uint32_t* state, const
 // frames then fit the chip in one pass.
 template <int L>
 __global__ __launch_bounds__(64, (L == 32 ? 4 : 1)) void k_listp(KArgs A, uint32_t* state,
-                                                                 const uint32_t* xl,
-                                                                 uint32_t lr_groups) {
+                                                                 const uint32_t* xl, uint32_t lo,
+                                                                 uint32_t hi) {
   __shared__ uint4 lds6p[4 * 64];  // level 6: 4 chunks per lane
   __shared__ uint32_t selp[64];
-  listp_run<L, false>(A, state, xl, A.spill + (size_t)blockIdx.x * A.spill_stride, lds6p, selp,
-                      lr_groups);
+  listp_run<L>(A, state, xl, A.spill + (size_t)blockIdx.x * A.spill_stride, lds6p, selp, lo, hi);
+}
+
+// The same stage with no register bound (160 VGPRs at L = 32, 3 waves per
+// SIMD): for lists that fit the chip in one pass at that occupancy, where
+// each wave's own latency sets the time.
+template <int L>
+__global__ __launch_bounds__(64) void k_listp_mid(KArgs A, uint32_t* state, const uint32_t* xl,
+                                                  uint32_t lo, uint32_t hi) {
+  __shared__ uint4 lds6p[4 * 64];
+  __shared__ uint32_t selp[64];
+  listp_run<L>(A, state, xl, A.spill + (size_t)blockIdx.x * A.spill_stride, lds6p, selp, lo, hi);
 }
 
 // The same stage with the wave's region in dynamic LDS (scx_region_bytes(N)
@@ -1647,11 +1657,11 @@ __global__ __launch_bounds__(64, (L == 32 ? 4 : 1)) void k_listp(KArgs A, uint32
 // memory at every level >= 7.
 template <int L>
 __global__ __launch_bounds__(64, 1) void k_listp_lds(KArgs A, uint32_t* state, const uint32_t* xl,
-                                                     uint32_t lr_groups) {
+                                                     uint32_t lo, uint32_t hi) {
   __shared__ uint4 lds6p[4 * 64];
   __shared__ uint32_t selp[64];
   extern __shared__ uint4 lds_region[];
-  listp_run<L, true>(A, state, xl, reinterpret_cast<char*>(lds_region), lds6p, selp, lr_groups);
+  listp_run<L>(A, state, xl, reinterpret_cast<char*>(lds_region), lds6p, selp, lo, hi);
 }
 
 uint32_t listp_static_lds() { return (uint32_t)(4 * 64 * sizeof(uint4) + 64 * sizeof(uint32_t)); }
@@ -1670,29 +1680,38 @@ int launch_gather(uint32_t n_frames, uint32_t L, const uint32_t* state, uint32_t
   return hipGetLastError() == hipSuccess ? POLAR_OK : POLAR_EHIP;
 }
 
-int launch_decode_listp(uint32_t L, const KArgs& A, uint32_t grid, uint32_t grid_lds,
-                        uint32_t lds, uint32_t* state, uint32_t* xl, hipStream_t s) {
+int launch_decode_listp(uint32_t L, const KArgs& A, uint32_t grid, uint32_t grid_mid,
+                        uint32_t grid_lds, uint32_t lds, uint32_t* state, uint32_t* xl,
+                        hipStream_t s) {
   const uint32_t gb = (A.n_frames + 255u) / 256u < 1024u ? (A.n_frames + 255u) / 256u : 1024u;
   hipLaunchKernelGGL(k_xreset, dim3(1), dim3(64), 0, s, xl);
   hipLaunchKernelGGL(k_gather, dim3(gb > 0 ? gb : 1), dim3(256), 0, s, A.n_frames, L,
                      (const uint32_t*)state, xl);
   const dim3 gr(grid > 0 ? grid : 1);
-  // the LDS form (L = 32 only) takes lists of up to one group per wave of its grid
-  const bool lr = L == 32 && grid_lds > 0 && lds > 0;
-  const uint32_t lr_groups = lr ? grid_lds : 0u;
-  if (lr)
-    hipLaunchKernelGGL(k_listp_lds<32>, dim3(grid_lds), dim3(64), lds, s, A, state,
-                       (const uint32_t*)xl, lr_groups);
-  if (L == 2)
-    hipLaunchKernelGGL(k_listp<2>, gr, dim3(64), 0, s, A, state, (const uint32_t*)xl, lr_groups);
-  else if (L == 4)
-    hipLaunchKernelGGL(k_listp<4>, gr, dim3(64), 0, s, A, state, (const uint32_t*)xl, lr_groups);
-  else if (L == 8)
-    hipLaunchKernelGGL(k_listp<8>, gr, dim3(64), 0, s, A, state, (const uint32_t*)xl, lr_groups);
-  else if (L == 16)
-    hipLaunchKernelGGL(k_listp<16>, gr, dim3(64), 0, s, A, state, (const uint32_t*)xl, lr_groups);
-  else
-    hipLaunchKernelGGL(k_listp<32>, gr, dim3(64), 0, s, A, state, (const uint32_t*)xl, lr_groups);
+  const uint32_t* cxl = xl;
+  if (L != 32) {
+    const uint32_t lo = 0, hi = 0xFFFFFFFFu;
+    if (L == 2)
+      hipLaunchKernelGGL(k_listp<2>, gr, dim3(64), 0, s, A, state, cxl, lo, hi);
+    else if (L == 4)
+      hipLaunchKernelGGL(k_listp<4>, gr, dim3(64), 0, s, A, state, cxl, lo, hi);
+    else if (L == 8)
+      hipLaunchKernelGGL(k_listp<8>, gr, dim3(64), 0, s, A, state, cxl, lo, hi);
+    else
+      hipLaunchKernelGGL(k_listp<16>, gr, dim3(64), 0, s, A, state, cxl, lo, hi);
+    return hipGetLastError() == hipSuccess ? POLAR_OK : POLAR_EHIP;
+  }
+  // L = 32: up to grid_lds groups in LDS (one pass), then up to grid_mid
+  // (the one-pass capacity at 3 waves per SIMD) unbounded, the rest bounded
+  const uint32_t h_lds = grid_lds > 0 && lds > 0 ? grid_lds : 0u;
+  const uint32_t h_mid = grid_mid > h_lds ? grid_mid : h_lds;
+  if (h_lds)
+    hipLaunchKernelGGL(k_listp_lds<32>, dim3(grid_lds), dim3(64), lds, s, A, state, cxl, 0u,
+                       h_lds);
+  if (h_mid > h_lds)
+    hipLaunchKernelGGL(k_listp_mid<32>, dim3(grid_mid), dim3(64), 0, s, A, state, cxl, h_lds,
+                       h_mid);
+  hipLaunchKernelGGL(k_listp<32>, gr, dim3(64), 0, s, A, state, cxl, h_mid, 0xFFFFFFFFu);
   return hipGetLastError() == hipSuccess ? POLAR_OK : POLAR_EHIP;
 }
 

@@ -390,15 +390,17 @@ def test_list_stages_path_per_lane(case):
         compare(code, llr)
 
 
-@pytest.mark.parametrize("n", [500, 700])
+@pytest.mark.parametrize("n", [500, 700, 8000])
 def test_list32_stage_lds_and_global_forms(n):
     """The L = 32 stage of the headline FA schedule at 2.5 dB, where nearly 9
-    frames in 10 reach it and about one in six of those passes its CRC.  A
-    list of at most one group (two frames) per wave of the stage's LDS form
-    (256 groups on a 256-CU device at N = 2048) runs with each wave's region
-    in LDS; a longer list runs with the regions in global memory.  Batches
-    of 500 frames (about 440 at L = 32: the LDS form) and 700 (about 620:
-    the global form) equal the oracle element by element."""
+    frames in 10 reach it and about one in six of those passes its CRC.  The
+    list's group count (two frames a group) picks the form: up to one group
+    per wave of the LDS form (256 groups on a 256-CU device at N = 2048) runs
+    with each wave's region in LDS; up to 3 waves per SIMD (3,072 groups) with
+    the regions in global memory and no register bound; a longer list held to
+    4 waves per SIMD.  Batches of 500 frames (about 440 at L = 32), 700
+    (about 620) and 8,000 (about 7,000) take the three forms and equal the
+    oracle element by element."""
     code = _code(2048, 1723, 32, 0x04C11DB7, 4.5, quant="i8", algo="fa", L_max=32)
     _, llr = make_inputs(code, n, 3100 + n, 2.5)
     rep = compare(code, llr)
