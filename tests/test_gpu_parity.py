@@ -407,6 +407,30 @@ def test_list32_stage_lds_and_global_forms(n):
     assert rep["escalated"] > 0.8 * n
 
 
+L32_FORM_CASES = [
+    # (N, K, c, poly, design dB, node options, Eb/N0, frames)
+    (1024, 512, 24, 0x1864CFB, 2.5, dict(), 1.0, 100),
+    (512, 256, 11, 0x621, 2.0, dict(node_enable=O.NODE_R0 | O.NODE_R1), 0.0, 3000),
+    (512, 256, 11, 0x621, 2.0, dict(node_enable=O.NODE_R0 | O.NODE_R1), 0.0, 8000),
+]
+
+
+@pytest.mark.parametrize("case", range(len(L32_FORM_CASES)))
+def test_list32_stage_forms_shorter_codes(case):
+    """The three forms of the L = 32 stage below N = 2048, where the LDS form
+    holds more waves per CU (two at N = 1024, four at 512) and so takes
+    longer lists.  FA to 32 at N = 1024 with a short list (LDS form); at
+    N = 512, Rate-0 / Rate-1 only at 0 dB, where about 86% of frames reach
+    L = 32: 3,000 frames (about 1,300 groups, beyond the 1,024 of the LDS
+    form on 256 CUs: the unbounded form) and 8,000 (about 3,400 groups: the
+    128-VGPR form).  Bits, CRC flags, list sizes, metrics and metric lists
+    equal the oracle."""
+    N, K, c, poly, design, kw, eb, n = L32_FORM_CASES[case]
+    code = _code(N, K, c, poly, design, quant="i8", algo="fa", L=32, L_max=32, **kw)
+    _, llr = make_inputs(code, n, 3300 + 7 * case, eb)
+    compare(code, llr)
+
+
 Q_CASES = [
     # (N, K, c, poly, design dB, algo, L, node options, Eb/N0)
     (2048, 1723, 32, 0x04C11DB7, 4.5, "sc", 1, dict(), 4.0),
