@@ -36,17 +36,22 @@ VALU_PEAK_OPS = 256 * 128 * 2.4e9
 HBM_PEAK_BYTES = 8.0e12  # MI355X HBM3E
 PAPER_CONTEXT_MBPS = {3.5: 24.4, 4.0: 227.3, 4.5: 425.9}  # one i5-6600K core, 8-bit FA
 # counter summaries (HBM bytes per launch) and the sources each kernel is built from
-LIST_KERNELS = ["k_rq<11,2>", "k_rq<11,4>", "k_rq<11,8>", "k_rq<11,16>", "k_listp<32>"]
+LIST_KERNELS = ["k_rq<11,2>", "k_rq<11,4>", "k_rq<11,8>", "k_rq<11,16>", "k_listp<32>",
+                "k_listp_lds<32>"]
 TRAFFIC_FILES = {"k_rq<11,1>": "hbm_traffic_k_rq1_fa2048_i8.md",
                  "k_rq<11,2>": "hbm_traffic_k_rq2_fa2048_i8.md",
                  "k_rq<11,4>": "hbm_traffic_k_rq4_fa2048_i8.md",
                  "k_rq<11,8>": "hbm_traffic_k_rq8_fa2048_i8.md",
                  "k_rq<11,16>": "hbm_traffic_k_rq16_fa2048_i8.md",
-                 "k_listp<32>": "hbm_traffic_k_listp32_fa2048_i8.md"}
+                 "k_listp<32>": "hbm_traffic_k_listp32_fa2048_i8.md",
+                 "k_listp_lds<32>": "hbm_traffic_k_listp32_lds_fa2048_i8.md"}
 _RQ_SRC = ["rq.hip", "device_common.h", "kernels.h", "polar_internal.h"]
+_LISTP_SRC = ["scx.hip", "device_common.h", "kernels.h", "polar_internal.h"]
 KERNEL_SOURCES = {"k_rq<11,1>": _RQ_SRC, "k_rq<11,2>": _RQ_SRC, "k_rq<11,4>": _RQ_SRC,
                   "k_rq<11,8>": _RQ_SRC, "k_rq<11,16>": _RQ_SRC,
-                  "k_listp<32>": ["scx.hip", "device_common.h", "kernels.h", "polar_internal.h"]}
+                  "k_listp<32>": _LISTP_SRC, "k_listp_lds<32>": _LISTP_SRC}
+# issue counters of the same profiled run (VALU busy per kernel)
+ISSUE_FILE = "counters_issue_lds_fa2048_i8.md"
 
 
 def wilson(k, n, z=1.96):
@@ -176,6 +181,42 @@ def measured_traffic(kernel):
         return int(vals["traffic_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
+
+
+def measured_valu_busy(kernel):
+    """VALU busy fraction of `kernel` (wave64 VALU instructions x 4 cycles
+    over the SIMDs' cycles) from the committed issue-counter summary, or None
+    when there is none or the kernel's traffic summary (taken in the same
+    run) no longer matches its sources.  A tier of several kernels takes the
+    time-weighted mean of theirs."""
+    names = kernel.split(" + ")
+    if any(measured_traffic(k) is None for k in names):
+        return None
+    path = os.path.join(ROOT, "profiles", ISSUE_FILE)
+    if not os.path.exists(path):
+        return None
+    rows = {}
+    with open(path) as fh:
+        for line in fh:
+            cells = [c.strip() for c in line.strip().strip("|").split("|")]
+            if len(cells) >= 8 and cells[0].startswith("`"):
+                try:
+                    rows[cells[0].strip("`")] = (float(cells[6]), float(cells[7].rstrip("%")) / 100)
+                except ValueError:
+                    pass
+    if any(k not in rows for k in names):
+        return None
+    ms = sum(rows[k][0] for k in names)
+    return sum(rows[k][0] * rows[k][1] for k in names) / ms if ms > 0 else None
+
+
+def tier_bound(hbm_frac, valu_busy, op_frac):
+    """A kernel's bound from its own counters: "hbm" when its measured HBM
+    rate is a larger fraction of the HBM peak than its VALU busy fraction
+    (or, without issue counters, its algorithmic-op fraction of the issue
+    peak), else "alu"."""
+    issue = valu_busy if valu_busy is not None else op_frac
+    return "hbm" if (hbm_frac or 0.0) > issue else "alu"
 
 
 def bench_uneven(args):
@@ -711,6 +752,9 @@ def headline(args):
     # launch stream around each tier) and each tier's algorithmic work
     tier_ms = {t: 0.0 for t in ("sc", "list_a", "list_b")}
     tier_work = {t: 0 for t in tier_ms}
+    tier_bytes = {t: 0 for t in tier_ms}
+    # algorithmic HBM bytes of a frame-stage: its LLRs in, its data bits and status out
+    alg_bytes = W["N"] + 4 * ((kd + 31) // 32) + 8
     for (eb, data, llr), (info, status) in zip(batches, outs):
         P.decode_batch(plan, llr, schedule=args.schedule, stream=stream, tier_timing=True)
         torch.cuda.synchronize()
@@ -725,6 +769,7 @@ def headline(args):
             # list interval (the first stays empty)
             tier = "sc" if l == 1 else "list_b"
             tier_work[tier] += reached * plan.stage_work(l)
+            tier_bytes[tier] += reached * alg_bytes
 
     # ---- latency of the automatic schedule: per-frame decode time from
     # device realtime stamps
@@ -767,14 +812,19 @@ def headline(args):
                         "work_per_launch_ops": int(tier_work[t] / len(points)),
                         "achieved": round(ach / 1e12, 5), "frac": round(ach / VALU_PEAK_OPS, 6)}
             # measured HBM bytes per launch (counter summary), against the 8 TB/s peak
+            tiers[t]["alg_bytes_per_launch"] = int(tier_bytes[t] / len(points))
             tb = measured_traffic(kernel_names[t])
             if tb:
                 rate = tb / (tier_ms[t] / len(points) / 1e3)
                 tiers[t].update({"traffic": tb, "hbm_tbs": round(rate / 1e12, 3),
                                  "hbm_frac": round(rate / HBM_PEAK_BYTES, 4)})
-            # the bound: the larger of the issue and the memory fractions
-            tiers[t]["bound"] = ("hbm" if tiers[t].get("hbm_frac", 0.0) > tiers[t]["frac"]
-                                 else "alu")
+            # the bound, from the kernels' own counters: memory when the measured
+            # HBM rate is the larger fraction of its peak than VALU busy is of
+            # the issue rate (the algorithmic-op fraction where no counters are)
+            busy = measured_valu_busy(kernel_names[t])
+            if busy is not None:
+                tiers[t]["valu_busy"] = round(busy, 4)
+            tiers[t]["bound"] = tier_bound(tiers[t].get("hbm_frac"), busy, tiers[t]["frac"])
     # the dominant kernel: the single kernel with the longest average launch
     # (the L = 1 stage; each list stage runs as a launch of its own, shorter
     # on average over the points)
@@ -786,8 +836,10 @@ def headline(args):
                 "work_per_launch_ops": tiers[dom]["work_per_launch_ops"],
                 "launch_ms": tiers[dom]["launch_ms"], "tiers": tiers}
     if roofline["bound"] == "hbm":
-        roofline.update({"achieved": tiers[dom]["hbm_tbs"] * 1e3, "peak": HBM_PEAK_BYTES / 1e9,
-                         "unit": "GB/s", "frac": tiers[dom]["hbm_frac"]})
+        # algorithmic bytes per launch over the launch time (the counters' bytes are `traffic`)
+        ab = tiers[dom]["alg_bytes_per_launch"] / (tiers[dom]["launch_ms"] / 1e3)
+        roofline.update({"achieved": round(ab / 1e9, 1), "peak": HBM_PEAK_BYTES / 1e9,
+                         "unit": "GB/s", "frac": round(ab / HBM_PEAK_BYTES, 4)})
 
     return {
         "metric": "info Mb/s per MI355X at matched FER + p50/p99 decode latency, batched vs plain",
