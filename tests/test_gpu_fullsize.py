@@ -1,10 +1,12 @@
 """Full-size parity of the headline workload in the launch configuration the
 benchmark times: 10^6 host-made frames of the (2048, 1723 incl. CRC-32) code
-at 3.5 dB (the point with the most list escalation), fully adaptive L = 1 ->
-32, int8, decoded in one tiered batch.  Sampled frames (random ones and every
-frame that needed L >= 8, up to a cap) are compared with the oracle element by
-element; the error rates of the whole batch and of an oracle-decoded subset
-must agree within Monte-Carlo 95% intervals."""
+at 3.5 dB (the point with the most list escalation; its L = 32 list takes the
+128-VGPR form) and at 4.0 dB (a short L = 32 list: the LDS form), fully
+adaptive L = 1 -> 32, int8, decoded in one tiered batch.  Sampled frames
+(random ones, frames that needed L >= 8 and frames that reached L = 32, up to
+caps) are compared with the oracle element by element; the error rates of the
+whole batch and of an oracle-decoded subset must agree within Monte-Carlo 95%
+intervals."""
 import concurrent.futures as cf
 import math
 import os
@@ -20,7 +22,6 @@ pytestmark = pytest.mark.gpu
 
 F = 1_000_000
 CHUNK = 16384
-EBN0 = 3.5
 
 
 def wilson(k, n, z=1.96):
@@ -31,15 +32,16 @@ def wilson(k, n, z=1.96):
     return max(0.0, c - h), min(1.0, c + h)
 
 
-@pytest.fixture(scope="module")
-def workload():
+@pytest.fixture(scope="module", params=[3.5, 4.0])
+def workload(request):
     import torch
 
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     fz = O.construct(2048, 1723, 0, 32, 4.5)
     code = oracle_code(2048, 1723, 32, 0x04C11DB7, fz, quant="i8", algo="fa", L_max=32)
-    sigma = synth.sigma_for(EBN0, code.k_data, code.n_tx)
+    ebn0 = request.param
+    sigma = synth.sigma_for(ebn0, code.k_data, code.n_tx)
     data = np.zeros((F, code.k_data), dtype=np.uint8)
     llr = np.zeros((F, code.n_tx), dtype=np.int8)
 
@@ -51,7 +53,7 @@ def workload():
 
     with cf.ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
         list(ex.map(chunk, range((F + CHUNK - 1) // CHUNK)))
-    print(f"generated {F} frames", flush=True)
+    print(f"generated {F} frames at {ebn0} dB", flush=True)
     return code, data, llr
 
 
@@ -74,6 +76,7 @@ def test_headline_full_size(workload):
     sample = set(rng.choice(F, 1500, replace=False).tolist())
     deep = np.nonzero(st["L_used"] >= 8)[0]
     sample |= set(deep[:600].tolist())
+    sample |= set(np.nonzero(st["L_used"] == 32)[0][:200].tolist())
     sample |= set(np.nonzero(st["crc_ok"] == 0)[0][:100].tolist())
     idx = np.array(sorted(sample))
     ref = O.decode(code, llr[idx], threads=min(16, os.cpu_count() or 1))
