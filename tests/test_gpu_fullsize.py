@@ -1,8 +1,9 @@
 """Full-size parity of the headline workload in the launch configuration the
 benchmark times: 10^6 host-made frames of the (2048, 1723 incl. CRC-32) code
-at 3.5 dB (the point with the most list escalation; its L = 32 list takes the
-128-VGPR form) and at 4.0 dB (a short L = 32 list: the LDS form), fully
-adaptive L = 1 -> 32, int8, decoded in one tiered batch.  Sampled frames
+at each of its three points: 3.5 dB (the most list escalation; its L = 32 list
+takes the 128-VGPR form), 4.0 dB (a short L = 32 list: the LDS form) and
+4.5 dB (a few frames in each of the stages L = 2 .. 16); fully adaptive
+L = 1 -> 32, int8, decoded in one tiered batch.  Sampled frames
 (random ones, frames that needed L >= 8 and frames that reached L = 32, up to
 caps) are compared with the oracle element by element; the error rates of the
 whole batch and of an oracle-decoded subset must agree within Monte-Carlo 95%
@@ -32,7 +33,7 @@ def wilson(k, n, z=1.96):
     return max(0.0, c - h), min(1.0, c + h)
 
 
-@pytest.fixture(scope="module", params=[3.5, 4.0])
+@pytest.fixture(scope="module", params=[3.5, 4.0, 4.5])
 def workload(request):
     import torch
 
